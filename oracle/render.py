@@ -1,0 +1,167 @@
+"""Oracle: per-pixel front-to-back alpha blending (FP64). Test infrastructure only.
+
+Section 3.1 "Rasterization" and Section 4.2 (Eq. 3): for a pixel, every
+projected Gaussian i is visited in depth order (nearest first); its
+transmittance is alpha_i = min(0.99, theta_i e^rho_i) with the power decay
+rho_i = -1/2 d^T conic_i d at the pixel (d = pixel centre - mean2D); a Gaussian
+with alpha_i < alpha* does not take part in the blend, the others contribute
+alpha_i T c_i and multiply T by (1 - alpha_i).
+
+Readings where the paper is silent: alpha* = 1/255 (the paper's effective rho
+range [-5.55, 0] ends at ln(1/255)); blending stops, without blending the
+Gaussian, once T (1 - alpha_i) would fall below 1e-4; rho is clamped to <= 0;
+equal depths are ordered by node id; background black unless given; pixel
+(i, j) is sampled at its centre (i + 0.5, j + 0.5). No tiles, no preemptive
+filter and no LUT: every valid Gaussian is a candidate, pruned only by the
+exact radius bound of oracle.project (plus 2 px slack, which cannot change the
+result because the pruned alphas are below alpha* there).
+
+Ambiguity accounting (for comparison with a float32 renderer): a pixel is
+flagged when a decision that float32 rounding could flip is within a margin:
+|ln alpha - ln alpha*| <= amb_alpha for a Gaussian visited up to termination,
+|T(1 - alpha) - 1e-4| <= amb_t * 1e-4 at a blend, two consecutive contributors
+with depths within amb_depth (relative), or a contributor within 1e-6
+(relative) of the near plane.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+ALPHA_MIN = 1.0 / 255.0
+ALPHA_MAX = 0.99
+T_MIN = 1e-4
+SLACK = 2.0
+
+
+def depth_order(proj):
+    """Indices of valid Gaussians sorted by (depth, node id)."""
+    v = np.nonzero(proj["valid"])[0]
+    o = np.lexsort((proj["ids"][v], proj["depth"][v]))
+    return v[o]
+
+
+def render_pixels(proj, px, py, bg=(0.0, 0.0, 0.0), order=None, amb_alpha=2e-4, amb_t=2e-4, amb_depth=1e-6,
+                  chunk=2048):
+    """Blend pixels with integer coordinates (px, py) (1-D arrays).
+
+    Returns dict(rgb (P, 3), T (P,), n_contrib (P,), ambiguous (P,) bool)."""
+    if order is None:
+        order = depth_order(proj)
+    px = np.asarray(px, np.int64)
+    py = np.asarray(py, np.int64)
+    P = len(px)
+    cxp = px + 0.5
+    cyp = py + 0.5
+    m = proj["mean2d"][order]
+    r = proj["radius"][order] + SLACK
+    # candidates: squares intersecting the pixels' bounding box
+    if P:
+        x0, x1, y0, y1 = cxp.min(), cxp.max(), cyp.min(), cyp.max()
+        keep = (m[:, 0] + r >= x0) & (m[:, 0] - r <= x1) & (m[:, 1] + r >= y0) & (m[:, 1] - r <= y1)
+    else:
+        keep = np.zeros(len(order), bool)
+    cand = order[keep]
+    mc, rc = m[keep], r[keep]
+    con = proj["conic"][cand]
+    th = proj["theta"][cand]
+    rgb_g = proj["rgb"][cand]
+    dep = proj["depth"][cand]
+    nearm = proj["near_margin"][cand]
+    T = np.ones(P)
+    C = np.zeros((P, 3))
+    done = np.zeros(P, bool)
+    ncon = np.zeros(P, np.int64)
+    amb = np.zeros(P, bool)
+    prev_depth = np.full(P, np.nan)
+    ln_amin = math.log(ALPHA_MIN)
+    for s in range(0, len(cand), chunk):
+        e = min(len(cand), s + chunk)
+        dx = cxp[:, None] - mc[None, s:e, 0]
+        dy = cyp[:, None] - mc[None, s:e, 1]
+        inside = (np.abs(dx) <= rc[None, s:e]) & (np.abs(dy) <= rc[None, s:e])
+        Q = con[None, s:e, 0] * dx * dx + 2.0 * con[None, s:e, 1] * dx * dy + con[None, s:e, 2] * dy * dy
+        rho = np.minimum(0.0, -0.5 * Q)
+        alpha = np.minimum(ALPHA_MAX, th[None, s:e] * np.exp(rho))
+        alpha = np.where(inside, alpha, 0.0)
+        use = inside & (alpha >= ALPHA_MIN) & ~done[:, None]
+        a = np.where(use, alpha, 0.0)
+        Tafter = T[:, None] * np.cumprod(1.0 - a, axis=1)
+        Tbefore = np.concatenate([T[:, None], Tafter[:, :-1]], axis=1)
+        stop = Tafter < T_MIN                       # monotone along the row
+        first_stop = stop & ~np.concatenate([np.zeros((P, 1), bool), stop[:, :-1]], axis=1)
+        active = use & ~stop                        # blended
+        w = np.where(active, a * Tbefore, 0.0)
+        C += w @ rgb_g[s:e]
+        ncon += active.sum(axis=1)
+        relevant = (~stop | first_stop) & inside & ~done[:, None]
+        with np.errstate(divide="ignore"):
+            la = np.log(np.where(alpha > 0, alpha, 1e-300))
+        amb |= np.any(relevant & (np.abs(la - ln_amin) <= amb_alpha), axis=1)
+        amb |= np.any(use & relevant & (np.abs(Tafter - T_MIN) <= amb_t * T_MIN), axis=1)
+        amb |= np.any(active & (nearm[None, s:e] <= 1e-6), axis=1)
+        # depth ties between consecutive contributors
+        idx = np.where(active, np.arange(e - s)[None, :], -1)
+        last = np.maximum.accumulate(idx, axis=1)
+        prev_idx = np.concatenate([np.full((P, 1), -1), last[:, :-1]], axis=1)
+        d_here = dep[None, s:e]
+        d_prev = np.where(prev_idx >= 0, dep[s:e][np.maximum(prev_idx, 0)], prev_depth[:, None])
+        tie = active & np.isfinite(d_prev) & (np.abs(d_here - d_prev) <= amb_depth * np.abs(d_here))
+        amb |= np.any(tie, axis=1)
+        has = last[:, -1] >= 0
+        prev_depth = np.where(has, dep[s:e][np.maximum(last[:, -1], 0)], prev_depth)
+        # carry state
+        any_stop = stop.any(axis=1)
+        T = np.where(any_stop, np.where(first_stop, Tbefore, 0.0).sum(axis=1), Tafter[:, -1])
+        done |= any_stop
+    bgv = np.asarray(bg, np.float64)
+    return dict(rgb=C + T[:, None] * bgv[None, :], T=T, n_contrib=ncon, ambiguous=amb)
+
+
+def render_image(proj, width, height, bg=(0.0, 0.0, 0.0), tiles=None, tile=16, **kw):
+    """Whole image (3, H, W) (or only the given tile indices, others NaN), plus
+    T_final, n_contrib and the ambiguity mask (H, W)."""
+    order = depth_order(proj)
+    img = np.full((3, height, width), np.nan)
+    Tf = np.full((height, width), np.nan)
+    nc = np.full((height, width), -1, np.int64)
+    amb = np.zeros((height, width), bool)
+    tx_n = (width + tile - 1) // tile
+    ty_n = (height + tile - 1) // tile
+    all_tiles = range(tx_n * ty_n) if tiles is None else tiles
+    for t in all_tiles:
+        ty, tx = divmod(int(t), tx_n)
+        xs = np.arange(tx * tile, min(width, (tx + 1) * tile))
+        ys = np.arange(ty * tile, min(height, (ty + 1) * tile))
+        PX, PY = np.meshgrid(xs, ys)
+        r = render_pixels(proj, PX.ravel(), PY.ravel(), bg=bg, order=order, **kw)
+        img[:, PY.ravel(), PX.ravel()] = r["rgb"].T
+        Tf[PY.ravel(), PX.ravel()] = r["T"]
+        nc[PY.ravel(), PX.ravel()] = r["n_contrib"]
+        amb[PY.ravel(), PX.ravel()] = r["ambiguous"]
+    return dict(image=img, T=Tf, n_contrib=nc, ambiguous=amb)
+
+
+def render_pixel_loop(proj, px: int, py: int, bg=(0.0, 0.0, 0.0)):
+    """The definition as a plain loop over every valid Gaussian (one pixel,
+    no pruning). Slow; used to pin render_pixels on tiny inputs."""
+    order = depth_order(proj)
+    T = 1.0
+    C = np.zeros(3)
+    n = 0
+    for i in order.tolist():
+        dx = px + 0.5 - proj["mean2d"][i, 0]
+        dy = py + 0.5 - proj["mean2d"][i, 1]
+        A, B, Cc = proj["conic"][i]
+        rho = min(0.0, -0.5 * (A * dx * dx + 2 * B * dx * dy + Cc * dy * dy))
+        alpha = min(ALPHA_MAX, proj["theta"][i] * math.exp(rho))
+        if alpha < ALPHA_MIN:
+            continue
+        t_next = T * (1.0 - alpha)
+        if t_next < T_MIN:
+            break
+        C += alpha * T * proj["rgb"][i]
+        T = t_next
+        n += 1
+    return C + T * np.asarray(bg, np.float64), T, n
