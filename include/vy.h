@@ -1,0 +1,247 @@
+/*
+ * vy.h - C ABI of the Voyager MI355X per-frame hot path.
+ *
+ * The library renders a 3D Gaussian Splatting scene stored as a level-of-detail
+ * (LoD) tree, following "Voyager: Real-Time City-Scale 3D Gaussian Splatting on
+ * Resource-Constrained Devices" (arXiv 2506.02774):
+ *
+ *   vy_lod_cut  - Section 3.1 "Cut Finding" and Section 4.1: the LoD cut, by a
+ *                 full top-down search or by the temporal-aware search of
+ *                 Algorithm 1 seeded with the previous frame's cut;
+ *   vy_render   - Section 3.1 "Culling & Projection", "Sorting" and
+ *                 "Rasterization", optionally with the preemptive alpha-filtering
+ *                 of Section 4.2 (Eq. 3 and Eq. 4 moved to culling/projection).
+ *
+ * Conventions
+ *   - Every entry point returns VY_OK (0) or a negative VY_ERR_* code; the
+ *     message of the last error on the calling thread is vy_last_error().
+ *   - "device" pointers are HIP device memory (for example torch CUDA tensors
+ *     on ROCm); "host" pointers are ordinary memory. The library never
+ *     allocates device memory: every device buffer comes from the caller,
+ *     sized by the matching *_workspace_bytes() query (alignment 256 bytes).
+ *   - `stream` is a hipStream_t (NULL = the null stream). All vy_lod_cut and
+ *     vy_render work is enqueued asynchronously on it; only the functions that
+ *     say so synchronise the stream.
+ *   - Handles (vy_scene, vy_cut, vy_render_ctx) are host objects created by the
+ *     library and released with their *_free(); they reference, but do not own,
+ *     the caller's device buffers, which must outlive them. Calls that use one
+ *     vy_cut or vy_render_ctx must not overlap; distinct handles may be used
+ *     concurrently on distinct streams.
+ *   - Camera: x_cam = R (x_world - pos), OpenCV axes (+x right, +y down,
+ *     +z forward); pixel (i, j) is sampled at (i + 0.5, j + 0.5); pixel
+ *     coordinates u = fx x/z + cx, v = fy y/z + cy.
+ */
+#ifndef VY_H
+#define VY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  VY_OK = 0,
+  VY_ERR_ARG = -1,      /* invalid argument (NULL handle, bad size, mismatched scene) */
+  VY_ERR_HIP = -2,      /* a HIP runtime call failed */
+  VY_ERR_CAPACITY = -3, /* a buffer was too small for this frame (output incomplete) */
+  VY_ERR_STATE = -4,    /* handle used in an invalid state (e.g. empty previous cut) */
+  VY_ERR_DEVICE = -5    /* a device-side consistency check failed */
+};
+
+const char* vy_last_error(void);
+const char* vy_version(void);
+
+/* Camera. R is row-major; rows are the camera's x (right), y (down) and
+ * z (forward) axes in world coordinates. `pos` is the camera centre. */
+typedef struct vy_camera {
+  float R[9];
+  float pos[3];
+  float fx, fy, cx, cy;
+  int32_t width, height;
+  float znear; /* near plane (0.2 m in the reference workloads) */
+} vy_camera;
+
+/* ------------------------------------------------------------------------ */
+/* Scene                                                                     */
+/* ------------------------------------------------------------------------ */
+
+/* LoD tree (Section 3.1 "LoD Tree"): each node holds one Gaussian and a
+ * contiguous range of children [first_child, first_child + child_count).
+ * All arrays are DEVICE pointers, node-major, length n_nodes. Node 0 is the
+ * root (parent -1); leaves have first_child = -1, child_count = 0.
+ * Requirement (checked by vy_scene_validate): AABB(child) is contained in
+ * AABB(parent) in float32, which makes the cut predicate monotone. */
+typedef struct vy_scene_desc {
+  int64_t n_nodes;
+  const int32_t* parent;      /* [n] */
+  const int32_t* first_child; /* [n] */
+  const int32_t* child_count; /* [n] */
+  const float* aabb_lo;       /* [n][3] */
+  const float* aabb_hi;       /* [n][3] */
+  const float* mean;          /* [n][3] */
+  const float* log_scale;     /* [n][3] natural log of the per-axis std-dev */
+  const float* quat;          /* [n][4] rotation (w, x, y, z), any norm > 0 */
+  const float* opacity_logit; /* [n]    theta = sigmoid(logit) */
+  const float* sh;            /* [n][16][3] SH degree-3 coefficients, index l*l+l+m;
+                                 BORROWED: must stay valid while the scene lives */
+} vy_scene_desc;
+
+typedef struct vy_scene vy_scene;
+
+/* Bytes of device workspace vy_scene_upload needs for n_nodes nodes. */
+size_t vy_scene_workspace_bytes(int64_t n_nodes);
+
+/* Packs the node arrays into the library's device layout in `workspace`
+ * (caller-owned, >= vy_scene_workspace_bytes) and precomputes theta and
+ * log(theta) per Gaussian (Section 4.2: log theta is computed once and stored).
+ * Enqueued on `stream`; the desc arrays other than `sh` may be released once
+ * the stream has passed this call. Errors: VY_ERR_ARG for NULL pointers,
+ * n_nodes < 1 or a short workspace; VY_ERR_HIP on a launch failure. */
+int vy_scene_upload(const vy_scene_desc* desc, void* workspace, size_t workspace_bytes, void* stream,
+                    vy_scene** out);
+
+/* Device-side structural check (synchronises `stream`): counts nodes whose
+ * parent/child links disagree or whose AABB is not inside the parent's.
+ * Returns VY_OK with *n_bad = 0 for a valid tree. */
+int vy_scene_validate(const vy_scene* scene, int64_t* n_bad, void* stream);
+int64_t vy_scene_num_nodes(const vy_scene* scene);
+int vy_scene_free(vy_scene* scene);
+
+/* ------------------------------------------------------------------------ */
+/* LoD cut (Section 3.1 "Cut Finding"; Section 4.1, Algorithm 1)             */
+/* ------------------------------------------------------------------------ */
+
+/* A cut handle holds, on the device, the frontier F (every non-expanded node
+ * whose ancestors all expand, including nodes outside the view frustum) and
+ * the cut C = F restricted to visible nodes, both as ascending int32 node ids.
+ * F is the state the temporal search starts from in the next frame. */
+typedef struct vy_cut vy_cut;
+
+size_t vy_cut_workspace_bytes(int64_t n_nodes);
+int vy_cut_create(const vy_scene* scene, void* workspace, size_t workspace_bytes, vy_cut** out);
+int vy_cut_free(vy_cut* cut);
+
+enum {
+  VY_CUT_FRONTIER = 0, /* full search: top-down traversal from the root that visits
+                          only expanded nodes and their children (Section 4.1,
+                          "Fully-Streaming LoD Tree Traversal") */
+  VY_CUT_FLAT = 1      /* full search: exhaustive test of every node (the baseline
+                          exhaustive search of Section 3.2 "Cut Finding") */
+};
+
+/* Computes the cut for `cam` at LoD granularity `tau` (pixels).
+ * Predicate (Section 3.1): node n expands iff it has children, its AABB is not
+ * outside the view frustum (4 side planes through the camera centre and the
+ * near plane), and fx * ext(n) > tau * dist(n), where ext is the longest AABB
+ * side and dist the distance from the camera centre to the AABB.
+ *   prev == NULL : full search, method `full_mode` (VY_CUT_FRONTIER/FLAT).
+ *   prev != NULL : temporal search (Algorithm 1) seeded with prev's frontier;
+ *                  prev must hold a cut of the same scene (VY_ERR_STATE if it
+ *                  has never been computed, VY_ERR_ARG for another scene).
+ *                  prev == out is allowed. The result is identical, bit for
+ *                  bit, to the full search.
+ * Enqueued on `stream`. */
+int vy_lod_cut(const vy_scene* scene, const vy_camera* cam, float tau, vy_cut* prev, vy_cut* out,
+               int full_mode, void* stream);
+
+/* Synchronises `stream`; returns |F| and |C| of the last computed cut, and
+ * VY_ERR_DEVICE if a device-side bound was hit while computing it. */
+int vy_cut_counts(const vy_cut* cut, int64_t* n_frontier, int64_t* n_cut, void* stream);
+
+/* Device pointers to the ascending id arrays of the last computed cut (valid
+ * until the next vy_lod_cut writing this handle) and to the device int32
+ * counters {|F|, |C|}. Any pointer argument may be NULL. */
+int vy_cut_arrays(const vy_cut* cut, const int32_t** frontier, const int32_t** cut_ids,
+                  const int32_t** counts);
+
+/* Replace the frontier of `cut` with `n` caller-given node ids (device,
+ * ascending, forming a valid frontier: one node on every root-to-leaf path),
+ * e.g. to seed the temporal search from an arbitrary state. Enqueued. */
+int vy_cut_set_frontier(vy_cut* cut, const int32_t* ids, int64_t n, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Rendering (Section 3.1 Culling & Projection, Sorting, Rasterization;     */
+/* Section 4.2 preemptive alpha-filtering)                                   */
+/* ------------------------------------------------------------------------ */
+
+typedef struct vy_render_opts {
+  int32_t alpha_filter; /* 0: plain pipeline. 1: preemptive alpha-filtering
+                           (Eq. 4 applied per Gaussian, per Gaussian-tile pair at
+                           binning and per pixel before the exponential). The
+                           image is bitwise identical either way. */
+  float bg[3];          /* background colour (default black) */
+  int32_t save_state;   /* 1: also write the per-pixel final transmittance and
+                           contributor count (needed by the backward pass) */
+} vy_render_opts;
+
+typedef struct vy_render_ctx vy_render_ctx;
+
+/* Workspace for rendering cuts of at most max_gaussians nodes into images of
+ * at most max_width x max_height with at most max_pairs Gaussian-tile pairs. */
+size_t vy_render_workspace_bytes(int64_t max_gaussians, int32_t max_width, int32_t max_height,
+                                 int64_t max_pairs);
+int vy_render_ctx_create(int64_t max_gaussians, int32_t max_width, int32_t max_height, int64_t max_pairs,
+                         void* workspace, size_t workspace_bytes, vy_render_ctx** out);
+int vy_render_ctx_free(vy_render_ctx* ctx);
+
+/* Renders the cut C of `cut` seen from `cam` into `image` (DEVICE, float32,
+ * planar [3][height][width], caller-owned). Stages: EWA projection with SH
+ * colour; 16x16-tile binning (with the pair-level alpha filter when enabled);
+ * a stable radix sort by (tile, depth) with depth ties in node-id order;
+ * per-tile front-to-back blending with alpha = min(0.99, theta e^rho) (Eq. 3),
+ * skipping alpha < 1/255 and stopping before T falls below 1e-4.
+ * Enqueued on `stream`. VY_ERR_ARG if the camera exceeds the context's image
+ * size or the cut belongs to another scene. A pair overflow is reported by
+ * vy_render_status (the image is then incomplete). */
+int vy_render(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, const vy_render_opts* opts,
+              float* image, vy_render_ctx* ctx, void* stream);
+
+/* Synchronises `stream`; returns the last frame's pair count and number of
+ * projected (non-culled) Gaussians, VY_ERR_CAPACITY if the pairs exceeded
+ * max_pairs (then *n_pairs is the number required), VY_ERR_DEVICE if a
+ * device-side wait bound was hit. */
+int vy_render_status(vy_render_ctx* ctx, int64_t* n_pairs, int64_t* n_visible, void* stream);
+
+/* Device pointers into the context's saved state of the last frame: per-pixel
+ * final transmittance [H][W] and contributor count [H][W] (written only with
+ * save_state = 1), and the projected Gaussians' 2D means [n][2] (cut order). */
+int vy_render_saved(const vy_render_ctx* ctx, const float** T_final, const int32_t** n_contrib,
+                    const float** mean2d);
+
+/* ------------------------------------------------------------------------ */
+/* Stage timing (HIP events recorded around every kernel launch)            */
+/* ------------------------------------------------------------------------ */
+
+enum {
+  VY_STAGE_LOD_SETUP = 0,
+  VY_STAGE_LOD_FLAT,
+  VY_STAGE_LOD_CLASSIFY,
+  VY_STAGE_LOD_TRAVERSE,
+  VY_STAGE_LOD_COMPACT,
+  VY_STAGE_RENDER_SETUP,
+  VY_STAGE_PROJECT,
+  VY_STAGE_DEPTH_SORT,
+  VY_STAGE_PAIR_SCAN,
+  VY_STAGE_EMIT,
+  VY_STAGE_TILE_SORT,
+  VY_STAGE_RANGES,
+  VY_STAGE_BLEND,
+  VY_NUM_STAGES
+};
+
+/* Starts recording (capacity = max number of launches to record). While
+ * recording, each launch by this thread is bracketed by HIP events on its
+ * stream. */
+int vy_profile_begin(int64_t capacity);
+/* Stops recording, synchronises the recorded events and writes the summed
+ * milliseconds and launch counts per stage (arrays of VY_NUM_STAGES). */
+int vy_profile_end(double* stage_ms, int64_t* stage_launches);
+const char* vy_stage_name(int stage);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VY_H */

@@ -1,0 +1,334 @@
+"""Voyager on MI355X: Python binding of the C-ABI library ``libvoyager.so``.
+
+Argument marshalling only: every step of the per-frame path (LoD cut,
+projection, binning, sorting, blending) runs in the library's HIP kernels.
+PyTorch provides device memory (tensors) and the HIP stream. There is no CPU
+fallback: importing the binding raises if the library has not been built, and
+every call raises ``VoyagerError`` on a non-zero status.
+
+The function names follow the C ABI in include/vy.h (vy_scene_upload,
+vy_lod_cut, vy_render, ...); ``Scene``, ``Cut`` and ``RenderContext`` are small
+owners that keep the device buffers alive for the handles that borrow them.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvoyager.so")
+
+VY_OK, VY_ERR_ARG, VY_ERR_HIP, VY_ERR_CAPACITY, VY_ERR_STATE, VY_ERR_DEVICE = 0, -1, -2, -3, -4, -5
+VY_CUT_FRONTIER, VY_CUT_FLAT = 0, 1
+STAGES = ["lod_setup", "lod_flat", "lod_classify", "lod_traverse", "lod_compact", "render_setup", "project",
+          "depth_sort", "pair_scan", "emit", "tile_sort", "ranges", "blend"]
+
+
+class VoyagerError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class vy_camera(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_float * 9), ("pos", ctypes.c_float * 3), ("fx", ctypes.c_float),
+                ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("znear", ctypes.c_float)]
+
+
+class vy_scene_desc(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int64)] + [(k, ctypes.c_void_p) for k in (
+        "parent", "first_child", "child_count", "aabb_lo", "aabb_hi", "mean", "log_scale", "quat",
+        "opacity_logit", "sh")]
+
+
+class vy_render_opts(ctypes.Structure):
+    _fields_ = [("alpha_filter", ctypes.c_int32), ("bg", ctypes.c_float * 3), ("save_state", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libvoyager.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2506_02774_amd.build.build() "
+                          "(there is no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I64, I32, F32, SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_float, ctypes.c_size_t
+    sig = {
+        "vy_last_error": ([], ctypes.c_char_p),
+        "vy_version": ([], ctypes.c_char_p),
+        "vy_scene_workspace_bytes": ([I64], SZ),
+        "vy_scene_upload": ([ctypes.POINTER(vy_scene_desc), P, SZ, P, ctypes.POINTER(P)], ctypes.c_int),
+        "vy_scene_validate": ([P, ctypes.POINTER(I64), P], ctypes.c_int),
+        "vy_scene_num_nodes": ([P], I64),
+        "vy_scene_free": ([P], ctypes.c_int),
+        "vy_cut_workspace_bytes": ([I64], SZ),
+        "vy_cut_create": ([P, P, SZ, ctypes.POINTER(P)], ctypes.c_int),
+        "vy_cut_free": ([P], ctypes.c_int),
+        "vy_lod_cut": ([P, ctypes.POINTER(vy_camera), F32, P, P, ctypes.c_int, P], ctypes.c_int),
+        "vy_cut_counts": ([P, ctypes.POINTER(I64), ctypes.POINTER(I64), P], ctypes.c_int),
+        "vy_cut_arrays": ([P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P)], ctypes.c_int),
+        "vy_cut_set_frontier": ([P, P, I64, P], ctypes.c_int),
+        "vy_render_workspace_bytes": ([I64, I32, I32, I64], SZ),
+        "vy_render_ctx_create": ([I64, I32, I32, I64, P, SZ, ctypes.POINTER(P)], ctypes.c_int),
+        "vy_render_ctx_free": ([P], ctypes.c_int),
+        "vy_render": ([P, P, ctypes.POINTER(vy_camera), ctypes.POINTER(vy_render_opts), P, P, P], ctypes.c_int),
+        "vy_render_status": ([P, ctypes.POINTER(I64), ctypes.POINTER(I64), P], ctypes.c_int),
+        "vy_render_saved": ([P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P)], ctypes.c_int),
+        "vy_profile_begin": ([I64], ctypes.c_int),
+        "vy_profile_end": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)], ctypes.c_int),
+        "vy_stage_name": ([ctypes.c_int], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def check(rc, what=""):
+    if rc != VY_OK:
+        msg = lib().vy_last_error().decode(errors="replace")
+        raise VoyagerError(rc, f"{what}: {msg}" if what else msg)
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def make_camera(cam) -> vy_camera:
+    """vy_camera from any object with R, pos, fx, fy, cx, cy, width, height, near."""
+    c = vy_camera()
+    R = np.asarray(cam.R, np.float32).reshape(9)
+    for i in range(9):
+        c.R[i] = float(R[i])
+    p = np.asarray(cam.pos, np.float32)
+    for i in range(3):
+        c.pos[i] = float(p[i])
+    c.fx, c.fy, c.cx, c.cy = (float(np.float32(v)) for v in (cam.fx, cam.fy, cam.cx, cam.cy))
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.znear = float(np.float32(getattr(cam, "near", 0.2)))
+    return c
+
+
+def _dev(a, dtype, device):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dtype)
+
+
+class Scene:
+    """Device copy of a hierarchy (scenegen.Scene or any object with the same
+    arrays) plus the library's packed workspace (vy_scene_upload)."""
+
+    def __init__(self, host_scene, device="cuda", stream=None):
+        import torch
+        L = lib()
+        self.n = int(host_scene.parent.shape[0])
+        self.host = host_scene
+        i32, f32 = torch.int32, torch.float32
+        self.arrays = dict(
+            parent=_dev(host_scene.parent, i32, device), first_child=_dev(host_scene.first_child, i32, device),
+            child_count=_dev(host_scene.child_count, i32, device),
+            aabb_lo=_dev(host_scene.aabb_lo, f32, device), aabb_hi=_dev(host_scene.aabb_hi, f32, device),
+            mean=_dev(host_scene.mean, f32, device), log_scale=_dev(host_scene.log_scale, f32, device),
+            quat=_dev(host_scene.quat, f32, device), opacity_logit=_dev(host_scene.opacity_logit, f32, device),
+            sh=_dev(host_scene.sh.reshape(self.n, 48), f32, device))
+        d = vy_scene_desc()
+        d.n_nodes = self.n
+        for k, t in self.arrays.items():
+            setattr(d, k, t.data_ptr())
+        nb = L.vy_scene_workspace_bytes(self.n)
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p()
+        check(L.vy_scene_upload(ctypes.byref(d), ctypes.c_void_p(self.ws.data_ptr()), nb, _stream(stream),
+                                ctypes.byref(h)), "vy_scene_upload")
+        self.handle = h
+        # the packed copy replaces the per-attribute arrays (except sh, which is borrowed)
+        torch.cuda.current_stream().synchronize()
+        keep = self.arrays["sh"]
+        self.arrays = {"sh": keep}
+
+    def validate(self, stream=None) -> int:
+        nb = ctypes.c_int64()
+        check(lib().vy_scene_validate(self.handle, ctypes.byref(nb), _stream(stream)), "vy_scene_validate")
+        return int(nb.value)
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                lib().vy_scene_free(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+
+class Cut:
+    """A cut handle (frontier + cut ids on the device)."""
+
+    def __init__(self, scene: Scene, device="cuda"):
+        import torch
+        L = lib()
+        self.scene = scene
+        nb = L.vy_cut_workspace_bytes(scene.n)
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p()
+        check(L.vy_cut_create(scene.handle, ctypes.c_void_p(self.ws.data_ptr()), nb, ctypes.byref(h)),
+              "vy_cut_create")
+        self.handle = h
+
+    def counts(self, stream=None):
+        nf, nc = ctypes.c_int64(), ctypes.c_int64()
+        check(lib().vy_cut_counts(self.handle, ctypes.byref(nf), ctypes.byref(nc), _stream(stream)),
+              "vy_cut_counts")
+        return int(nf.value), int(nc.value)
+
+    def ids(self, stream=None):
+        """(frontier, cut) as int64 numpy arrays (synchronises)."""
+        import torch
+        nf, nc = self.counts(stream)
+        pf, pc, pn = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        check(lib().vy_cut_arrays(self.handle, ctypes.byref(pf), ctypes.byref(pc), ctypes.byref(pn)),
+              "vy_cut_arrays")
+        F = np.empty(nf, np.int32)
+        C = np.empty(nc, np.int32)
+        if nf:
+            _copy_d2h(F, pf.value)
+        if nc:
+            _copy_d2h(C, pc.value)
+        return F.astype(np.int64), C.astype(np.int64)
+
+    def set_frontier(self, ids, stream=None):
+        import torch
+        t = torch.as_tensor(np.asarray(ids, np.int32), device="cuda")
+        check(lib().vy_cut_set_frontier(self.handle, ctypes.c_void_p(t.data_ptr()), int(t.numel()),
+                                        _stream(stream)), "vy_cut_set_frontier")
+        torch.cuda.current_stream().synchronize()
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                lib().vy_cut_free(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+
+class _DevView:
+    """Zero-copy view of library-owned device memory for torch.as_tensor."""
+
+    def __init__(self, ptr: int, shape, typestr: str):
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr, "data": (int(ptr), False),
+                                         "version": 2, "strides": None}
+
+
+def device_view(ptr: int, shape, dtype=np.int32):
+    """torch tensor aliasing `ptr` (device memory owned by the library)."""
+    import torch
+    typestr = np.dtype(dtype).str
+    return torch.as_tensor(_DevView(ptr, shape, typestr), device="cuda")
+
+
+def _copy_d2h(dst: np.ndarray, src_ptr: int):
+    import torch
+    torch.cuda.current_stream().synchronize()
+    dst[...] = device_view(src_ptr, dst.shape, dst.dtype).cpu().numpy()
+
+
+class RenderContext:
+    def __init__(self, max_gaussians, max_width, max_height, max_pairs, device="cuda"):
+        import torch
+        L = lib()
+        nb = L.vy_render_workspace_bytes(int(max_gaussians), int(max_width), int(max_height), int(max_pairs))
+        if nb == 0:
+            raise VoyagerError(VY_ERR_ARG, "vy_render_workspace_bytes: invalid sizes")
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p()
+        check(L.vy_render_ctx_create(int(max_gaussians), int(max_width), int(max_height), int(max_pairs),
+                                     ctypes.c_void_p(self.ws.data_ptr()), nb, ctypes.byref(h)),
+              "vy_render_ctx_create")
+        self.handle = h
+        self.max_width, self.max_height, self.max_pairs = int(max_width), int(max_height), int(max_pairs)
+
+    def status(self, stream=None):
+        n_pairs, n_vis = ctypes.c_int64(), ctypes.c_int64()
+        rc = lib().vy_render_status(self.handle, ctypes.byref(n_pairs), ctypes.byref(n_vis), _stream(stream))
+        return rc, int(n_pairs.value), int(n_vis.value)
+
+    def saved(self, width, height):
+        """(T_final, n_contrib) of the last frame rendered with save_state (synchronises)."""
+        pt, pn, pm = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        check(lib().vy_render_saved(self.handle, ctypes.byref(pt), ctypes.byref(pn), ctypes.byref(pm)),
+              "vy_render_saved")
+        T = np.empty((height, width), np.float32)
+        N = np.empty((height, width), np.int32)
+        _copy_d2h(T, pt.value)
+        _copy_d2h(N, pn.value)
+        return T, N
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                lib().vy_render_ctx_free(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+
+# ----------------------------------------------------------------------------
+# C-ABI-named entry points
+# ----------------------------------------------------------------------------
+
+def vy_scene_upload(host_scene, device="cuda", stream=None) -> Scene:
+    return Scene(host_scene, device, stream)
+
+
+def vy_lod_cut(scene: Scene, cam, tau: float, prev: Cut | None = None, out: Cut | None = None,
+               mode: int = VY_CUT_FRONTIER, stream=None) -> Cut:
+    """Enqueue the LoD cut; returns `out` (a new Cut when None)."""
+    if out is None:
+        out = Cut(scene)
+    c = make_camera(cam)
+    check(lib().vy_lod_cut(scene.handle, ctypes.byref(c), float(tau), prev.handle if prev is not None else None,
+                           out.handle, int(mode), _stream(stream)), "vy_lod_cut")
+    return out
+
+
+def vy_render(scene: Scene, cut: Cut, cam, ctx: RenderContext, image=None, alpha_filter=False,
+              bg=(0.0, 0.0, 0.0), save_state=False, stream=None):
+    """Enqueue rendering of `cut` into `image` (torch float32 [3, H, W] on the device)."""
+    import torch
+    if image is None:
+        image = torch.empty((3, int(cam.height), int(cam.width)), dtype=torch.float32, device="cuda")
+    if image.dtype != torch.float32 or not image.is_contiguous() or tuple(image.shape) != (3, cam.height, cam.width):
+        raise VoyagerError(VY_ERR_ARG, "image must be a contiguous float32 tensor of shape (3, H, W)")
+    o = vy_render_opts()
+    o.alpha_filter = 1 if alpha_filter else 0
+    for i in range(3):
+        o.bg[i] = float(bg[i])
+    o.save_state = 1 if save_state else 0
+    c = make_camera(cam)
+    check(lib().vy_render(scene.handle, cut.handle, ctypes.byref(c), ctypes.byref(o),
+                          ctypes.c_void_p(image.data_ptr()), ctx.handle, _stream(stream)), "vy_render")
+    return image
+
+
+def profile_begin(capacity=1 << 16):
+    check(lib().vy_profile_begin(int(capacity)), "vy_profile_begin")
+
+
+def profile_end():
+    ms = (ctypes.c_double * len(STAGES))()
+    n = (ctypes.c_int64 * len(STAGES))()
+    check(lib().vy_profile_end(ms, n), "vy_profile_end")
+    return {STAGES[i]: (float(ms[i]), int(n[i])) for i in range(len(STAGES))}

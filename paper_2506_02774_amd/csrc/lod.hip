@@ -1,0 +1,530 @@
+// LoD cut kernels (gfx950).
+//
+// Section 3.1 "Cut Finding": a node is selected when its projected size is
+// below tau while its parent's is above. Section 4.1: a full search that visits
+// only expanded nodes and their children ("fully-streaming traversal", with
+// work dispatched dynamically to whichever wave is free) and the
+// temporal-aware search of Algorithm 1, which starts from the previous frame's
+// cut and moves each node up (TOP signal) or down (BOTTOM signal) only as far
+// as the new camera requires.
+//
+// Predicate (one device function, compiled without FP contraction so every
+// kernel computes the same bits for a node):
+//   vis(n)    : the AABB is not entirely outside any of the 4 side planes
+//               through the camera centre or the near plane (positive-vertex
+//               test on n.(v - pos) >= d);
+//   expand(n) : n has children && vis(n) && (fx*ext)^2 > tau^2 * dist^2,
+//               ext = longest AABB side, dist = camera centre to AABB.
+// Every step of vis and expand is a monotone float32 operation of the AABB
+// bounds, so AABB(child) inside AABB(parent) gives expand(child) =>
+// expand(parent) exactly; the frontier is then well defined and the temporal
+// search reproduces the full search bit for bit.
+//
+// State kept per cut: the frontier F (non-expanded nodes whose ancestors all
+// expand, frustum-culled ones included) and C = F with vis. New F/C are
+// collected as bitmaps and compacted to ascending ids (canonical order).
+#include <cstdlib>
+#include <cstring>
+
+#include "vy_common.hpp"
+
+#pragma clang fp contract(off)
+
+namespace {
+
+using namespace vyd;
+
+struct LodCam {
+  float4 pl[5];  // world normal (x, y, z) and offset w: inside iff n.(v - pos) >= w
+  float px, py, pz, fx, tau2;
+};
+
+VY_DEV bool lod_vis(const float4 a, const float4 b, const LodCam& c) {
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const float4 n = c.pl[k];
+    const float vx = n.x >= 0.f ? b.x : a.x;
+    const float vy = n.y >= 0.f ? b.y : a.y;
+    const float vz = n.z >= 0.f ? b.z : a.z;
+    const float s = (n.x * (vx - c.px) + n.y * (vy - c.py)) + n.z * (vz - c.pz);
+    if (!(s >= n.w)) return false;
+  }
+  return true;
+}
+
+// a = {lo.xyz, first_child bits}, b = {hi.xyz, parent bits}
+VY_DEV bool lod_expand(const float4 a, const float4 b, const LodCam& c, bool& vis) {
+  vis = lod_vis(a, b, c);
+  const float ext = fmaxf(fmaxf(b.x - a.x, b.y - a.y), b.z - a.z);
+  const float dx = fmaxf(fmaxf(a.x - c.px, c.px - b.x), 0.f);
+  const float dy = fmaxf(fmaxf(a.y - c.py, c.py - b.y), 0.f);
+  const float dz = fmaxf(fmaxf(a.z - c.pz, c.pz - b.z), 0.f);
+  const float d2 = (dx * dx + dy * dy) + dz * dz;
+  const float fe = c.fx * ext;
+  return __float_as_int(a.w) >= 0 && vis && (fe * fe > c.tau2 * d2);
+}
+
+VY_DEV void emit_node(int32_t n, bool vis, uint32_t* fbits, uint32_t* cbits) {
+  const uint32_t bit = 1u << (n & 31);
+  atomicOr(fbits + (n >> 5), bit);
+  if (vis) atomicOr(cbits + (n >> 5), bit);
+}
+
+// ctr layout
+constexpr int kHead = 0, kTail = 1, kPending = 2, kErr = 3, kTicket = 4;
+
+__global__ void lod_setup(uint32_t* ctr, int32_t* items, int seed_root) {
+  if (threadIdx.x == 0) {
+    ctr[kHead] = 0;
+    ctr[kTail] = seed_root ? 1u : 0u;
+    ctr[kPending] = seed_root ? 1u : 0u;
+    ctr[kErr] = 0;
+    ctr[kTicket] = 0;
+    if (seed_root) items[0] = 0;
+  }
+}
+
+// Exhaustive baseline: every node tests itself and its parent.
+// Each wave owns 64 consecutive nodes = 2 whole bitmap words.
+__global__ __launch_bounds__(256) void lod_flat(int64_t n, const float4* __restrict__ lod, LodCam cam,
+                                                uint32_t* __restrict__ fbits, uint32_t* __restrict__ cbits) {
+  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t wv = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); wv * 64 < n; wv += nwaves) {
+    const int64_t i = wv * 64 + lane();
+    bool inF = false, vis = false;
+    if (i < n) {
+      const float4 a = lod[2 * i], b = lod[2 * i + 1];
+      const bool e = lod_expand(a, b, cam, vis);
+      bool pe = true;
+      const int32_t par = __float_as_int(b.w);
+      if (par >= 0) {
+        bool pvis;
+        pe = lod_expand(lod[2 * (int64_t)par], lod[2 * (int64_t)par + 1], cam, pvis);
+      }
+      inF = !e && pe;
+    }
+    const uint64_t mf = ballot(inF), mc = ballot(inF && vis);
+    if (lane() == 0) {
+      fbits[2 * wv] = (uint32_t)mf;
+      cbits[2 * wv] = (uint32_t)mc;
+    } else if (lane() == 32) {
+      fbits[2 * wv + 1] = (uint32_t)(mf >> 32);
+      cbits[2 * wv + 1] = (uint32_t)(mc >> 32);
+    }
+  }
+}
+
+// Block-aggregated push of `push` children (first id fc) per thread onto the
+// worklist. Pending is raised before the items become visible, so it never
+// reaches zero while work remains.
+VY_DEV void push_children(uint32_t push, int32_t fc, int32_t* items, uint32_t* ctr, uint32_t cap,
+                          uint32_t* s_scan, uint32_t* s_tail) {
+  uint32_t total;
+  const uint32_t off = block_excl_scan256(push, s_scan, &total);
+  if (total == 0) return;
+  if (threadIdx.x == 0) {
+    const uint32_t t0 = fetch_add(ctr + kTail, total);
+    uint32_t fits = t0 >= cap ? 0u : (cap - t0 < total ? cap - t0 : total);
+    if (fits < total) fetch_add(ctr + kErr, 1u);
+    if (fits) (void)__hip_atomic_fetch_add(ctr + kPending, fits, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+    s_tail[0] = t0;
+  }
+  __syncthreads();
+  const uint32_t t0 = s_tail[0];
+  for (uint32_t k = 0; k < push; ++k) {
+    const uint32_t pos = t0 + off + k;
+    if (pos < cap) st_rel(items + pos, fc + (int32_t)k);
+  }
+  __syncthreads();
+}
+
+// Temporal step (Algorithm 1) for every node of the previous frontier:
+//   expand(n)                          -> BOTTOM: descend (children go to the worklist)
+//   n != root && !expand(parent(n))    -> TOP: climb to the highest ancestor a with
+//                                         !expand(parent(a)) (or the root), emit a
+//   otherwise                          -> n stays on the frontier.
+__global__ __launch_bounds__(256) void lod_classify(const int32_t* __restrict__ Fprev, const int32_t* n_prev_ptr,
+                                                    const float4* __restrict__ lod,
+                                                    const int32_t* __restrict__ ccount, LodCam cam,
+                                                    int32_t* items, uint32_t* ctr, uint32_t cap,
+                                                    uint32_t* fbits, uint32_t* cbits) {
+  __shared__ uint32_t s_scan[8], s_tail[1];
+  const int64_t n_prev = *n_prev_ptr;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // uniform trip count so that every thread reaches the block barriers
+  const int64_t trips = (n_prev + stride - 1) / stride;
+  for (int64_t t = 0; t < trips; ++t) {
+    const int64_t i = t * stride + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    uint32_t push = 0;
+    int32_t fc = 0;
+    const int32_t nd = i < n_prev ? Fprev[i] : -1;
+    const bool ok = nd >= 0 && (uint32_t)nd < cap;
+    if (i < n_prev && !ok) fetch_add(ctr + kErr, 1u);
+    if (ok) {
+      const float4 a = lod[2 * (int64_t)nd], b = lod[2 * (int64_t)nd + 1];
+      bool vis;
+      if (lod_expand(a, b, cam, vis)) {
+        fc = __float_as_int(a.w);
+        push = (uint32_t)ccount[nd];
+      } else {
+        int32_t p = __float_as_int(b.w);
+        int32_t cur = nd;
+        bool cur_vis = vis;
+        // climb while the parent does not expand (bounded by the tree depth limit)
+        for (int depth = 0; p >= 0; ++depth) {
+          if (depth >= 256) {
+            fetch_add(ctr + kErr, 1u);
+            break;
+          }
+          const float4 pa = lod[2 * (int64_t)p], pb = lod[2 * (int64_t)p + 1];
+          bool pvis;
+          if (lod_expand(pa, pb, cam, pvis)) break;
+          cur = p;
+          cur_vis = pvis;
+          p = __float_as_int(pb.w);
+        }
+        emit_node(cur, cur_vis, fbits, cbits);
+      }
+    }
+    push_children(push, fc, items, ctr, cap, s_scan, s_tail);
+  }
+}
+
+// Dynamic worklist traversal. Each block takes a ticket of 256 consecutive
+// slots; a thread waits for its slot to be filled, tests the node, emits it
+// or pushes its children. The traversal is over when `pending` (pushed but
+// unprocessed items) is zero; every wait is bounded (error flag on timeout).
+constexpr uint32_t kIdleLimit = 1u << 20;
+
+__global__ __launch_bounds__(256) void lod_traverse(const float4* __restrict__ lod,
+                                                    const int32_t* __restrict__ ccount, LodCam cam,
+                                                    int32_t* items, uint32_t* ctr, uint32_t cap,
+                                                    uint32_t* fbits, uint32_t* cbits) {
+  __shared__ uint32_t s_scan[8], s_tail[1], s_base, s_flag, s_poll;
+  const uint32_t tid = threadIdx.x;
+  for (;;) {
+    if (tid == 0) s_base = fetch_add(ctr + kHead, 256u);
+    __syncthreads();
+    // slots at or beyond the capacity are never filled: nothing left for this block
+    if (s_base >= cap) break;
+    const uint32_t slot = s_base + tid;
+    bool resolved = slot >= cap;
+    uint32_t idle = 0;
+    bool finished = false;
+    for (;;) {
+      if (tid == 0) s_poll = ld_acq(ctr + kTail) > s_base ? 1u : 0u;
+      __syncthreads();
+      int32_t item = -1;
+      if (!resolved && s_poll) {
+        item = ld_acq(items + slot);
+        if (item >= 0) {
+          st_rel(items + slot, (int32_t)-1);
+          resolved = true;
+        }
+      }
+      uint32_t push = 0;
+      int32_t fc = 0;
+      if (item >= 0) {
+        const float4 a = lod[2 * (int64_t)item], b = lod[2 * (int64_t)item + 1];
+        bool vis;
+        if (lod_expand(a, b, cam, vis)) {
+          fc = __float_as_int(a.w);
+          push = (uint32_t)ccount[item];
+        } else {
+          emit_node(item, vis, fbits, cbits);
+        }
+      }
+      const uint32_t got = (uint32_t)__syncthreads_count(item >= 0);
+      push_children(push, fc, items, ctr, cap, s_scan, s_tail);
+      if (tid == 0 && got) (void)__hip_atomic_fetch_add(ctr + kPending, (uint32_t)(0u - got), __ATOMIC_SEQ_CST,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+      if (__syncthreads_and(resolved)) break;
+      if (got == 0) {
+        if (tid == 0) {
+          __builtin_amdgcn_s_sleep(8);
+          uint32_t f = ld_acq(ctr + kPending) == 0 ? 1u : 0u;
+          if (!f && ++idle > kIdleLimit) {
+            fetch_add(ctr + kErr, 1u);
+            f = 1;
+          }
+          s_flag = f;
+        }
+        __syncthreads();
+        if (s_flag) {
+          finished = true;
+          break;
+        }
+      } else {
+        idle = 0;
+      }
+    }
+    if (finished) break;
+    __syncthreads();
+  }
+}
+
+// Compaction of the F and C bitmaps into ascending ids (decoupled look-back
+// scan over partitions of 1024 words), zeroing the bitmaps as they are read.
+constexpr int kWordsPerThread = 4, kWordsPerPart = 256 * kWordsPerThread;
+
+__global__ __launch_bounds__(256) void lod_compact(int64_t n_words, uint32_t* __restrict__ fbits,
+                                                   uint32_t* __restrict__ cbits, int32_t* __restrict__ Fout,
+                                                   int32_t* __restrict__ Cout, int32_t* counts, int f_slot,
+                                                   uint32_t* ctr, uint64_t* status, uint32_t epoch,
+                                                   uint32_t n_parts) {
+  __shared__ uint32_t s_scan[8], s_part;
+  __shared__ uint64_t s_ex[2];
+  if (threadIdx.x == 0) s_part = fetch_add(ctr + kTicket, 1u);
+  __syncthreads();
+  const uint32_t part = s_part;
+  if (part >= n_parts) return;
+  const int64_t w0 = (int64_t)part * kWordsPerPart + threadIdx.x * kWordsPerThread;
+  uint32_t fw[kWordsPerThread], cw[kWordsPerThread];
+  uint32_t fc = 0, cc = 0;
+#pragma unroll
+  for (int k = 0; k < kWordsPerThread; ++k) {
+    const int64_t w = w0 + k;
+    fw[k] = w < n_words ? fbits[w] : 0u;
+    cw[k] = w < n_words ? cbits[w] : 0u;
+    fc += __popc(fw[k]);
+    cc += __popc(cw[k]);
+  }
+  uint32_t ftot, ctot;
+  const uint32_t foff = block_excl_scan256(fc, s_scan, &ftot);
+  const uint32_t coff = block_excl_scan256(cc, s_scan, &ctot);
+  if (threadIdx.x == 0) s_ex[0] = lookback(status, part, 2, epoch, ftot, ctr + kErr);
+  if (threadIdx.x == 64) s_ex[1] = lookback(status + 1, part, 2, epoch, ctot, ctr + kErr);
+  __syncthreads();
+  int64_t fo = (int64_t)s_ex[0] + foff, co = (int64_t)s_ex[1] + coff;
+#pragma unroll
+  for (int k = 0; k < kWordsPerThread; ++k) {
+    const int64_t w = w0 + k;
+    uint32_t f = fw[k], c = cw[k];
+    while (f) {
+      const int b = __ffs(f) - 1;
+      f &= f - 1;
+      Fout[fo++] = (int32_t)(w * 32 + b);
+    }
+    while (c) {
+      const int b = __ffs(c) - 1;
+      c &= c - 1;
+      Cout[co++] = (int32_t)(w * 32 + b);
+    }
+    if (w < n_words) {
+      if (fw[k]) fbits[w] = 0u;
+      if (cw[k]) cbits[w] = 0u;
+    }
+  }
+  if (part == n_parts - 1 && threadIdx.x == 255) {
+    counts[f_slot] = (int32_t)fo;
+    counts[2] = (int32_t)co;
+  }
+}
+
+__global__ void fill_i32(int32_t* p, int64_t n, int32_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void set_count(int32_t* p, int32_t v) {
+  if (threadIdx.x == 0) p[0] = v;
+}
+
+LodCam make_cam(const vy_camera* c, float tau) {
+  LodCam L;
+  const float* R = c->R;
+  const float W = (float)c->width, H = (float)c->height;
+  const float nc[5][3] = {{c->fx, 0.f, c->cx}, {-c->fx, 0.f, W - c->cx}, {0.f, c->fy, c->cy},
+                          {0.f, -c->fy, H - c->cy}, {0.f, 0.f, 1.f}};
+  for (int p = 0; p < 5; ++p) {
+    float n[3];
+    for (int k = 0; k < 3; ++k) n[k] = (nc[p][0] * R[0 + k] + nc[p][1] * R[3 + k]) + nc[p][2] * R[6 + k];
+    L.pl[p] = make_float4(n[0], n[1], n[2], p == 4 ? c->znear : 0.f);
+  }
+  L.px = c->pos[0];
+  L.py = c->pos[1];
+  L.pz = c->pos[2];
+  L.fx = c->fx;
+  L.tau2 = tau * tau;
+  return L;
+}
+
+}  // namespace
+
+using namespace vy;
+
+extern "C" {
+
+size_t vy_cut_workspace_bytes(int64_t n) {
+  if (n < 1) return 0;
+  const int64_t n_words = (n + 31) / 32 + 64;
+  const int64_t n_parts = (n_words + kWordsPerPart - 1) / kWordsPerPart;
+  return (size_t)n * 4 * 4        // F[2], C, items
+         + (size_t)n_words * 4 * 2 // bitmaps
+         + 64 * 4 + 64 * 4         // counts, ctr
+         + (size_t)n_parts * 16    // status
+         + 16 * 256;               // alignment slack
+}
+
+int vy_cut_create(const vy_scene* scene, void* ws, size_t ws_bytes, vy_cut** out) {
+  const Scene* s = (const Scene*)scene;
+  if (!s || s->magic != kSceneMagic || !ws || !out) return fail(VY_ERR_ARG, "vy_cut_create: bad argument");
+  if (ws_bytes < vy_cut_workspace_bytes(s->n))
+    return fail(VY_ERR_ARG, "vy_cut_create: workspace %zu < %zu bytes", ws_bytes, vy_cut_workspace_bytes(s->n));
+  Cut* c = (Cut*)calloc(1, sizeof(Cut));
+  if (!c) return fail(VY_ERR_ARG, "vy_cut_create: out of host memory");
+  Carver cv(ws, ws_bytes);
+  c->magic = kCutMagic;
+  c->scene = s;
+  c->n = s->n;
+  c->n_words = (s->n + 31) / 32 + 64;
+  c->n_parts = (c->n_words + kWordsPerPart - 1) / kWordsPerPart;
+  c->F[0] = cv.take<int32_t>(s->n);
+  c->F[1] = cv.take<int32_t>(s->n);
+  c->C = cv.take<int32_t>(s->n);
+  c->items = cv.take<int32_t>(s->n);
+  c->fbits = cv.take<uint32_t>(c->n_words);
+  c->cbits = cv.take<uint32_t>(c->n_words);
+  c->counts = cv.take<int32_t>(64);
+  c->ctr = cv.take<uint32_t>(64);
+  c->status = cv.take<uint64_t>(2 * c->n_parts);
+  c->cur = -1;
+  c->epoch = 0;
+  if (!cv.ok()) {
+    free(c);
+    return fail(VY_ERR_ARG, "vy_cut_create: workspace layout overflow");
+  }
+  // one-time initialisation (synchronous): bitmaps zero, worklist slots -1
+  hipError_t e = hipMemset(c->fbits, 0, sizeof(uint32_t) * c->n_words);
+  if (e == hipSuccess) e = hipMemset(c->cbits, 0, sizeof(uint32_t) * c->n_words);
+  if (e == hipSuccess) e = hipMemset(c->counts, 0, 64 * 4);
+  if (e == hipSuccess) e = hipMemset(c->ctr, 0, 64 * 4);
+  if (e == hipSuccess) e = hipMemset(c->status, 0, 16 * c->n_parts);
+  if (e == hipSuccess) {
+    fill_i32<<<1024, 256>>>(c->items, s->n, -1);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    free(c);
+    return fail(VY_ERR_HIP, "vy_cut_create: %s", hipGetErrorString(e));
+  }
+  *out = (vy_cut*)c;
+  return VY_OK;
+}
+
+int vy_cut_free(vy_cut* cut) {
+  Cut* c = (Cut*)cut;
+  if (!c) return VY_OK;
+  if (c->magic != kCutMagic) return fail(VY_ERR_ARG, "vy_cut_free: not a cut");
+  c->magic = 0;
+  free(c);
+  return VY_OK;
+}
+
+int vy_lod_cut(const vy_scene* scene, const vy_camera* cam, float tau, vy_cut* prev, vy_cut* out, int full_mode,
+               void* stream) {
+  const Scene* s = (const Scene*)scene;
+  Cut* o = (Cut*)out;
+  Cut* p = (Cut*)prev;
+  if (!s || s->magic != kSceneMagic || !cam || !o || o->magic != kCutMagic)
+    return fail(VY_ERR_ARG, "vy_lod_cut: bad argument");
+  if (o->scene != s) return fail(VY_ERR_ARG, "vy_lod_cut: output cut belongs to another scene");
+  if (!(tau >= 0.f) || cam->width < 1 || cam->height < 1 || !(cam->fx > 0.f) || !(cam->fy > 0.f))
+    return fail(VY_ERR_ARG, "vy_lod_cut: invalid tau or camera");
+  if (p) {
+    if (p->magic != kCutMagic) return fail(VY_ERR_ARG, "vy_lod_cut: prev is not a cut");
+    if (p->scene != s) return fail(VY_ERR_ARG, "vy_lod_cut: prev cut belongs to another scene");
+    if (p->cur < 0) return fail(VY_ERR_STATE, "vy_lod_cut: prev cut has no frontier yet");
+  } else if (full_mode != VY_CUT_FRONTIER && full_mode != VY_CUT_FLAT) {
+    return fail(VY_ERR_ARG, "vy_lod_cut: unknown full_mode %d", full_mode);
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const LodCam L = make_cam(cam, tau);
+  const uint32_t cap = (uint32_t)s->n;
+  // destination frontier buffer: never the one we read from
+  const int src = p ? p->cur : -1;
+  const int dst = (p == o) ? 1 - src : (o->cur < 0 ? 0 : 1 - o->cur);
+  const bool flat = !p && full_mode == VY_CUT_FLAT;
+  {
+    ProfScope ps(VY_STAGE_LOD_SETUP, st);
+    lod_setup<<<1, 64, 0, st>>>(o->ctr, o->items, (!p && !flat) ? 1 : 0);
+    VY_LAUNCHED();
+  }
+  if (flat) {
+    ProfScope ps(VY_STAGE_LOD_FLAT, st);
+    const int64_t waves = (s->n + 63) / 64;
+    const int64_t blocks = (waves + 3) / 4 < 65536 ? (waves + 3) / 4 : 65536;
+    lod_flat<<<(int)blocks, 256, 0, st>>>(s->n, s->lod, L, o->fbits, o->cbits);
+    VY_LAUNCHED();
+  } else {
+    if (p) {
+      ProfScope ps(VY_STAGE_LOD_CLASSIFY, st);
+      // Cut::counts[src] holds |F_prev|; if p != o the worklist of o is used
+      lod_classify<<<2048, 256, 0, st>>>(p->F[src], p->counts + src, s->lod, s->ccount, L, o->items, o->ctr, cap,
+                                         o->fbits, o->cbits);
+      VY_LAUNCHED();
+    }
+    ProfScope ps(VY_STAGE_LOD_TRAVERSE, st);
+    lod_traverse<<<1024, 256, 0, st>>>(s->lod, s->ccount, L, o->items, o->ctr, cap, o->fbits, o->cbits);
+    VY_LAUNCHED();
+  }
+  {
+    ProfScope ps(VY_STAGE_LOD_COMPACT, st);
+    const uint32_t ep = next_epoch(o->epoch);
+    if (ep == 1) VY_HIP(hipMemsetAsync(o->status, 0, 16 * o->n_parts, st));
+    lod_compact<<<(int)o->n_parts, 256, 0, st>>>(o->n_words, o->fbits, o->cbits, o->F[dst], o->C, o->counts, dst,
+                                                 o->ctr, o->status, ep, (uint32_t)o->n_parts);
+    VY_LAUNCHED();
+  }
+  o->cur = dst;
+  return VY_OK;
+}
+
+int vy_cut_counts(const vy_cut* cut, int64_t* n_frontier, int64_t* n_cut, void* stream) {
+  const Cut* c = (const Cut*)cut;
+  if (!c || c->magic != kCutMagic) return fail(VY_ERR_ARG, "vy_cut_counts: bad argument");
+  if (c->cur < 0) return fail(VY_ERR_STATE, "vy_cut_counts: no cut computed yet");
+  int32_t h[4];
+  uint32_t e[4];
+  hipStream_t st = (hipStream_t)stream;
+  VY_HIP(hipMemcpyAsync(h, c->counts, sizeof(h), hipMemcpyDeviceToHost, st));
+  VY_HIP(hipMemcpyAsync(e, c->ctr, sizeof(e), hipMemcpyDeviceToHost, st));
+  VY_HIP(hipStreamSynchronize(st));
+  if (n_frontier) *n_frontier = h[c->cur];
+  if (n_cut) *n_cut = h[2];
+  if (e[kErr]) return fail(VY_ERR_DEVICE, "vy_lod_cut: device-side bound hit (%u)", e[kErr]);
+  return VY_OK;
+}
+
+int vy_cut_arrays(const vy_cut* cut, const int32_t** frontier, const int32_t** cut_ids, const int32_t** counts) {
+  const Cut* c = (const Cut*)cut;
+  if (!c || c->magic != kCutMagic) return fail(VY_ERR_ARG, "vy_cut_arrays: bad argument");
+  if (c->cur < 0) return fail(VY_ERR_STATE, "vy_cut_arrays: no cut computed yet");
+  if (frontier) *frontier = c->F[c->cur];
+  if (cut_ids) *cut_ids = c->C;
+  if (counts) *counts = c->counts;
+  return VY_OK;
+}
+
+int vy_cut_set_frontier(vy_cut* cut, const int32_t* ids, int64_t n, void* stream) {
+  Cut* c = (Cut*)cut;
+  if (!c || c->magic != kCutMagic || (!ids && n > 0)) return fail(VY_ERR_ARG, "vy_cut_set_frontier: bad argument");
+  if (n < 1 || n > c->n) return fail(VY_ERR_ARG, "vy_cut_set_frontier: n %lld out of range", (long long)n);
+  hipStream_t st = (hipStream_t)stream;
+  const int dst = c->cur < 0 ? 0 : 1 - c->cur;
+  VY_HIP(hipMemcpyAsync(c->F[dst], ids, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
+  set_count<<<1, 64, 0, st>>>(c->counts + dst, (int32_t)n);
+  VY_LAUNCHED();
+  c->cur = dst;
+  return VY_OK;
+}
+
+}  // extern "C"
+
+// Accessors for the render stage (same library).
+namespace vy {
+const int32_t* cut_ids_dev(const Cut* c) { return c->C; }
+const int32_t* cut_count_dev(const Cut* c) { return c->counts + 2; }
+}  // namespace vy

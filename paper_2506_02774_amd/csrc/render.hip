@@ -1,0 +1,745 @@
+// Splatting kernels (gfx950): Section 3.1 "Culling & Projection", "Sorting"
+// and "Rasterization", with the preemptive alpha-filtering of Section 4.2.
+//
+//   render_setup  zero the frame's counters, digit histograms and tile ranges
+//   project       EWA projection + SH colour per cut Gaussian, tile rect,
+//                 pair count (alpha filter: Eq. 4 per Gaussian / rect / tile),
+//                 depth key + its 4 digit histograms
+//   depth sort    4 stable onesweep passes over 8-bit digits of the depth bits
+//                 (values = cut positions, so equal depths keep node-id order)
+//   pair_scan     exclusive scan of the pair counts in depth order
+//   emit          Gaussian-tile pairs in depth order (tile key + cut position)
+//                 + the tile digit histograms
+//   tile sort     2 stable onesweep passes on the tile id: afterwards pairs are
+//                 ordered by (tile, depth, node id) - an LSD radix sort by
+//                 (tile, depth) whose depth digits were sorted before the
+//                 Gaussians were replicated into pairs
+//   ranges        [start, end) of every tile in the sorted pairs
+//   blend         one 256-thread workgroup per 16x16 tile, Gaussians staged in
+//                 LDS in batches of 256, front-to-back alpha blending (Eq. 3)
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+
+#include "sort.hpp"
+#include "vy_common.hpp"
+
+#pragma clang fp contract(off)
+
+namespace vy {
+const int32_t* cut_ids_dev(const Cut* c);
+const int32_t* cut_count_dev(const Cut* c);
+}  // namespace vy
+
+namespace {
+
+using namespace vyd;
+
+constexpr int kTileSize = 16;
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kAlphaMax = 0.99f;
+constexpr float kTMin = 1e-4f;
+constexpr float kLowpass = 0.3f;
+constexpr float kClamp = 1.3f;
+constexpr float kRadiusK = 3.3290f;      // >= sqrt(2 ln 255)
+constexpr float kFilterDelta = 1e-3f;    // margin of the preemptive check (keeps it lossless)
+
+// ctr layout
+enum {
+  C_NVIS = 0,      // Gaussians that produce at least one pair
+  C_NPAIRS = 1,    // pairs stored (clamped to capacity)
+  C_NPAIRS_RAW = 2,
+  C_ERR = 3,
+  C_TICKET0 = 4,   // 4..9 sort passes, 10 scan
+  C_SCAN_TICKET = 10,
+  C_OVERFLOW = 11,
+  C_NCUT = 12,
+  C_COUNT = 32
+};
+
+struct RCam {
+  float R[9];
+  float px, py, pz;
+  float fx, fy, cx, cy;
+  float near;
+  float ulo, uhi, vlo, vhi;  // clamp range of x/z and y/z
+  int W, H, tiles_x, tiles_y;
+  float bg[3];
+  float ln_amin;             // log(1/255)
+};
+
+__global__ void render_setup(uint32_t* ctr, uint32_t* hist, uint2* ranges, int ntiles) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int stride = gridDim.x * blockDim.x;
+  for (int i = t; i < C_COUNT; i += stride) ctr[i] = 0;
+  for (int i = t; i < 6 * 256; i += stride) hist[i] = 0;
+  for (int i = t; i < ntiles; i += stride) ranges[i] = make_uint2(0, 0);
+}
+
+// Real SH, degree <= 3, orthonormal, no Condon-Shortley phase; index l*l+l+m.
+VY_DEV float3 sh_colour(const float* __restrict__ c, float x, float y, float z) {
+  const float C0 = 0.28209479177387814f;
+  const float C1 = 0.4886025119029199f;
+  const float C2a = 1.0925484305920792f;   // xy, yz, xz
+  const float C20 = 0.31539156525252005f;  // 3z^2 - 1
+  const float C22 = 0.5462742152960396f;   // x^2 - y^2
+  const float C33 = 0.5900435899266435f;   // y(3x^2 - y^2), x(x^2 - 3y^2)
+  const float C32 = 2.890611442640554f;    // xyz
+  const float C31 = 0.4570457994644658f;   // y(5z^2 - 1), x(5z^2 - 1)
+  const float C30 = 0.3731763325901154f;   // z(5z^2 - 3)
+  const float C32p = 1.445305721320277f;   // z(x^2 - y^2)
+  const float xx = x * x, yy = y * y, zz = z * z;
+  float Y[16];
+  Y[0] = C0;
+  Y[1] = C1 * y;
+  Y[2] = C1 * z;
+  Y[3] = C1 * x;
+  Y[4] = C2a * (x * y);
+  Y[5] = C2a * (y * z);
+  Y[6] = C20 * (3.f * zz - 1.f);
+  Y[7] = C2a * (x * z);
+  Y[8] = C22 * (xx - yy);
+  Y[9] = C33 * y * (3.f * xx - yy);
+  Y[10] = C32 * (x * y) * z;
+  Y[11] = C31 * y * (5.f * zz - 1.f);
+  Y[12] = C30 * z * (5.f * zz - 3.f);
+  Y[13] = C31 * x * (5.f * zz - 1.f);
+  Y[14] = C32p * z * (xx - yy);
+  Y[15] = C33 * x * (xx - 3.f * yy);
+  float r = 0.f, g = 0.f, b = 0.f;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    r = fmaf(Y[k], c[3 * k + 0], r);
+    g = fmaf(Y[k], c[3 * k + 1], g);
+    b = fmaf(Y[k], c[3 * k + 2], b);
+  }
+  return make_float3(fminf(fmaxf(r + 0.5f, 0.f), 1.f), fminf(fmaxf(g + 0.5f, 0.f), 1.f),
+                     fminf(fmaxf(b + 0.5f, 0.f), 1.f));
+}
+
+// Upper bound of rho = -1/2 d^T A d over pixel centres of tile (tx, ty):
+// exact maximum over the continuous rectangle spanned by the centres
+// (0 if the mean is inside, else the best of the four clamped edges).
+VY_DEV float tile_rho_max(float mx, float my, float a, float b, float c, int tx, int ty, int W, int H) {
+  const float x0 = tx * kTileSize + 0.5f, y0 = ty * kTileSize + 0.5f;
+  const float x1 = fminf((float)(tx * kTileSize + kTileSize), (float)W) - 0.5f;
+  const float y1 = fminf((float)(ty * kTileSize + kTileSize), (float)H) - 0.5f;
+  if (mx >= x0 && mx <= x1 && my >= y0 && my <= y1) return 0.f;
+  const float dx0 = x0 - mx, dx1 = x1 - mx, dy0 = y0 - my, dy1 = y1 - my;
+  float best = -INFINITY;
+  // vertical edges (dx fixed): maximise over dy in [dy0, dy1]
+  for (int e = 0; e < 2; ++e) {
+    const float dx = e ? dx1 : dx0;
+    float dy = -b * dx / c;
+    dy = fminf(fmaxf(dy, dy0), dy1);
+    const float q = -0.5f * (a * dx * dx + c * dy * dy) - b * dx * dy;
+    best = fmaxf(best, q);
+  }
+  for (int e = 0; e < 2; ++e) {
+    const float dy = e ? dy1 : dy0;
+    float dx = -b * dy / a;
+    dx = fminf(fmaxf(dx, dx0), dx1);
+    const float q = -0.5f * (a * dx * dx + c * dy * dy) - b * dx * dy;
+    best = fmaxf(best, q);
+  }
+  return fminf(best, 0.f);
+}
+
+// Pair-level preemptive test (Section 4.2 moved to binning): keep tile t unless
+// every pixel centre in it has rho below thr. `relax` (>= 0) loosens the test
+// for ill-conditioned conics so that float32 rounding of the per-pixel rho can
+// never make a dropped pair matter.
+VY_DEV bool tile_keep(const float4 p0, const float4 p1, float relax, int tx, int ty, int W, int H) {
+  const float rm = tile_rho_max(p0.x, p0.y, p0.z, p0.w, p1.x, tx, ty, W, H);
+  return rm * (1.f - relax) >= p1.z;
+}
+
+template <bool FILTER>
+__global__ __launch_bounds__(256) void project(const int32_t* __restrict__ cut, const int32_t* n_cut_ptr,
+                                               const float4* __restrict__ gauss, const float* __restrict__ sh,
+                                               RCam cam, float4* __restrict__ pg0, float4* __restrict__ pg1,
+                                               float4* __restrict__ pg2, uint32_t* __restrict__ prect,
+                                               uint32_t* __restrict__ prect2, float* __restrict__ prelax,
+                                               uint32_t* __restrict__ pcount, uint32_t* __restrict__ dkey,
+                                               uint32_t* ctr, uint32_t* hist, int64_t n_nodes) {
+  __shared__ uint32_t s_hist[4][256];
+  for (int i = threadIdx.x; i < 4 * 256; i += blockDim.x) (&s_hist[0][0])[i] = 0;
+  __syncthreads();
+  const int64_t n = *n_cut_ptr;
+  uint32_t nvis = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    int32_t node = cut[i];
+    if (node < 0 || node >= n_nodes) node = 0;
+    const float4 g0 = gauss[3 * (int64_t)node], g1 = gauss[3 * (int64_t)node + 1], g2 = gauss[3 * (int64_t)node + 2];
+    const float dxw = g0.x - cam.px, dyw = g0.y - cam.py, dzw = g0.z - cam.pz;
+    const float x = (cam.R[0] * dxw + cam.R[1] * dyw) + cam.R[2] * dzw;
+    const float y = (cam.R[3] * dxw + cam.R[4] * dyw) + cam.R[5] * dzw;
+    const float z = (cam.R[6] * dxw + cam.R[7] * dyw) + cam.R[8] * dzw;
+    bool valid = z > cam.near;
+    uint32_t count = 0, key = 0xFFFFFFFFu;
+    float4 o0 = make_float4(0, 0, 0, 0), o1 = make_float4(0, 0, 0, 0), o2 = make_float4(0, 0, 0, 0);
+    uint32_t r0 = 0, r1 = 0;
+    float relax = 0.f;
+    if (valid) {
+      // Sigma3 = M M^T with M = Rq diag(s)
+      const float qw = g2.x, qx = g2.y, qy = g2.z, qz = g2.w;
+      const float Rq[9] = {1.f - 2.f * (qy * qy + qz * qz), 2.f * (qx * qy - qw * qz), 2.f * (qx * qz + qw * qy),
+                           2.f * (qx * qy + qw * qz), 1.f - 2.f * (qx * qx + qz * qz), 2.f * (qy * qz - qw * qx),
+                           2.f * (qx * qz - qw * qy), 2.f * (qy * qz + qw * qx), 1.f - 2.f * (qx * qx + qy * qy)};
+      const float s[3] = {g1.x, g1.y, g1.z};
+      const float iz = 1.f / z;
+      const float u = fminf(fmaxf(x * iz, cam.ulo), cam.uhi);
+      const float v = fminf(fmaxf(y * iz, cam.vlo), cam.vhi);
+      // T = J R (2x3): rows fx/z (R0 - u R2), fy/z (R1 - v R2)
+      float T0[3], T1[3];
+      for (int k = 0; k < 3; ++k) {
+        T0[k] = (cam.fx * iz) * (cam.R[k] - u * cam.R[6 + k]);
+        T1[k] = (cam.fy * iz) * (cam.R[3 + k] - v * cam.R[6 + k]);
+      }
+      // V = T M (2x3); Sigma2 = V V^T + lowpass
+      float V0[3], V1[3];
+      for (int j = 0; j < 3; ++j) {
+        const float m0 = Rq[0 + j] * s[j], m1 = Rq[3 + j] * s[j], m2 = Rq[6 + j] * s[j];
+        V0[j] = (T0[0] * m0 + T0[1] * m1) + T0[2] * m2;
+        V1[j] = (T1[0] * m0 + T1[1] * m1) + T1[2] * m2;
+      }
+      const float a = ((V0[0] * V0[0] + V0[1] * V0[1]) + V0[2] * V0[2]) + kLowpass;
+      const float b = (V0[0] * V1[0] + V0[1] * V1[1]) + V0[2] * V1[2];
+      const float c = ((V1[0] * V1[0] + V1[1] * V1[1]) + V1[2] * V1[2]) + kLowpass;
+      const float det = fmaf(a, c, -b * b);
+      valid = det > 0.f;
+      if (valid) {
+        const float idet = 1.f / det;
+        const float ca = c * idet, cb = -b * idet, cc = a * idet;
+        const float mx = cam.fx * x * iz + cam.cx, my = cam.fy * y * iz + cam.cy;
+        const float mid = 0.5f * (a + c);
+        const float lmax = mid + sqrtf(fmaxf(0.f, mid * mid - det));
+        const float lmin = fmaxf(det / lmax, 1e-30f);
+        float r = ceilf(kRadiusK * sqrtf(lmax));
+        const float theta = g1.w, log_theta = g0.w;
+        const float thr = cam.ln_amin - log_theta - kFilterDelta;
+        // relative rounding bound of rho for this conic (condition number based)
+        relax = 1e-6f * (lmax / lmin);
+        if (FILTER) {
+          if (thr > 0.f) valid = false;      // theta below alpha*: never blended
+          if (valid && relax < 0.25f) {
+            // beyond r_f every pixel has rho < thr (with margin for rounding)
+            const float rf2 = 2.f * (-thr) * lmax * ((1.f + relax) / (1.f - relax)) * 1.001f + 2.f;
+            const float rf = ceilf(sqrtf(rf2));
+            r = fminf(r, rf);
+          }
+        }
+        if (valid) {
+          int x0 = (int)floorf((mx - r) / kTileSize), x1 = (int)floorf((mx + r) / kTileSize);
+          int y0 = (int)floorf((my - r) / kTileSize), y1 = (int)floorf((my + r) / kTileSize);
+          x0 = max(x0, 0);
+          y0 = max(y0, 0);
+          x1 = min(x1, cam.tiles_x - 1);
+          y1 = min(y1, cam.tiles_y - 1);
+          if (x0 > x1 || y0 > y1 || !(r > 0.f)) valid = false;
+          if (valid) {
+            o0 = make_float4(mx, my, ca, cb);
+            o1 = make_float4(cc, theta, thr, z);
+            const float dn = 1.f / sqrtf((dxw * dxw + dyw * dyw) + dzw * dzw);
+            const float3 rgb = sh_colour(sh + 48 * (int64_t)node, dxw * dn, dyw * dn, dzw * dn);
+            o2 = make_float4(rgb.x, rgb.y, rgb.z, 0.f);
+            r0 = (uint32_t)x0 | ((uint32_t)y0 << 16);
+            r1 = (uint32_t)x1 | ((uint32_t)y1 << 16);
+            if (FILTER && relax < 0.25f) {
+              for (int ty = y0; ty <= y1; ++ty)
+                for (int tx = x0; tx <= x1; ++tx) count += tile_keep(o0, o1, relax, tx, ty, cam.W, cam.H) ? 1u : 0u;
+            } else {
+              count = (uint32_t)(x1 - x0 + 1) * (uint32_t)(y1 - y0 + 1);
+            }
+            if (count == 0) valid = false;
+            else key = __float_as_uint(z);
+          }
+        }
+      }
+    }
+    if (!valid) count = 0;
+    pg0[i] = o0;
+    pg1[i] = o1;
+    pg2[i] = o2;
+    prect[i] = r0;
+    prect2[i] = r1;
+    prelax[i] = relax;
+    pcount[i] = count;
+    dkey[i] = key;
+    nvis += count > 0 ? 1u : 0u;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255u], 1u);
+  }
+  // block totals
+  for (int o = 32; o > 0; o >>= 1) nvis += __shfl_xor(nvis, o, 64);
+  if (lane() == 0 && nvis) atomicAdd(ctr + C_NVIS, nvis);
+  __syncthreads();
+  for (int i = threadIdx.x; i < 4 * 256; i += blockDim.x) {
+    const uint32_t v = (&s_hist[0][0])[i];
+    if (v) atomicAdd(hist + i, v);
+  }
+}
+
+// Exclusive scan of pcount[sorted_val[r]] for r < n_vis -> offsets[r]; the
+// total goes to C_NPAIRS_RAW, min(total, cap) to C_NPAIRS.
+constexpr int kScanItems = 16, kScanTile = 256 * kScanItems;
+
+__global__ __launch_bounds__(256) void pair_scan(const uint32_t* __restrict__ sorted_val,
+                                                 const uint32_t* __restrict__ pcount,
+                                                 uint32_t* __restrict__ offsets, uint32_t* ctr, uint64_t* status,
+                                                 uint32_t epoch, uint32_t cap, uint32_t n_g) {
+  __shared__ uint32_t s_v[kScanTile];
+  __shared__ uint32_t s_scan[8], s_part;
+  __shared__ uint64_t s_ex;
+  const uint32_t n = ctr[C_NVIS];
+  const uint32_t n_parts = (n + kScanTile - 1) / kScanTile;
+  for (;;) {
+    if (threadIdx.x == 0) s_part = fetch_add(ctr + C_SCAN_TICKET, 1u);
+    __syncthreads();
+    const uint32_t part = s_part;
+    if (part >= n_parts) break;
+    const uint32_t base = part * kScanTile;
+    for (int k = 0; k < kScanItems; ++k) {
+      const uint32_t i = base + k * 256 + threadIdx.x;
+      uint32_t v = 0;
+      if (i < n) {
+        const uint32_t g = sorted_val[i];
+        v = g < n_g ? pcount[g] : 0u;
+      }
+      s_v[k * 256 + threadIdx.x] = v;
+    }
+    __syncthreads();
+    uint32_t loc[kScanItems], sum = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+      loc[k] = sum;
+      sum += s_v[threadIdx.x * kScanItems + k];
+    }
+    uint32_t tot;
+    const uint32_t off = block_excl_scan256(sum, s_scan, &tot);
+    if (threadIdx.x == 0) s_ex = lookback(status, part, 1, epoch, tot, ctr + C_ERR);
+    __syncthreads();
+    const uint64_t ex = s_ex;
+    for (int k = 0; k < kScanItems; ++k) s_v[threadIdx.x * kScanItems + k] = (uint32_t)(ex + off + loc[k]);
+    __syncthreads();
+    for (int k = 0; k < kScanItems; ++k) {
+      const uint32_t i = base + k * 256 + threadIdx.x;
+      if (i < n) offsets[i] = s_v[k * 256 + threadIdx.x];
+    }
+    if (part == n_parts - 1 && threadIdx.x == 0) {
+      const uint64_t total = ex + tot;
+      ctr[C_NPAIRS_RAW] = (uint32_t)(total > 0xFFFFFFFFull ? 0xFFFFFFFFull : total);
+      ctr[C_NPAIRS] = (uint32_t)(total > cap ? cap : total);
+      if (total > cap) ctr[C_OVERFLOW] = 1;
+    }
+    __syncthreads();
+  }
+}
+
+template <bool FILTER>
+__global__ __launch_bounds__(256) void emit_pairs(const uint32_t* __restrict__ sorted_val,
+                                                  const uint32_t* __restrict__ offsets,
+                                                  const float4* __restrict__ pg0, const float4* __restrict__ pg1,
+                                                  const uint32_t* __restrict__ prect,
+                                                  const uint32_t* __restrict__ prect2,
+                                                  const float* __restrict__ prelax, int W, int H, int tiles_x,
+                                                  int bits0, uint32_t* __restrict__ tkey, uint32_t* __restrict__ tval,
+                                                  uint32_t* ctr, uint32_t* hist, uint32_t cap, uint32_t n_g) {
+  __shared__ uint32_t s_hist[2][256];
+  for (int i = threadIdx.x; i < 512; i += blockDim.x) (&s_hist[0][0])[i] = 0;
+  __syncthreads();
+  const uint32_t n = ctr[C_NVIS];
+  const uint32_t m0 = (1u << bits0) - 1u;
+  for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+    const uint32_t g = sorted_val[r];
+    if (g >= n_g) continue;
+    uint32_t o = offsets[r];
+    const uint32_t a = prect[g], b = prect2[g];
+    const int x0 = a & 0xFFFF, y0 = a >> 16, x1 = b & 0xFFFF, y1 = b >> 16;
+    const float relax = prelax[g];
+    float4 p0, p1;
+    if (FILTER) {
+      p0 = pg0[g];
+      p1 = pg1[g];
+    }
+    for (int ty = y0; ty <= y1; ++ty)
+      for (int tx = x0; tx <= x1; ++tx) {
+        if (FILTER && relax < 0.25f && !tile_keep(p0, p1, relax, tx, ty, W, H)) continue;
+        const uint32_t t = (uint32_t)(ty * tiles_x + tx);
+        if (o < cap) {
+          tkey[o] = t;
+          tval[o] = g;
+          atomicAdd(&s_hist[0][t & m0], 1u);
+          atomicAdd(&s_hist[1][(t >> bits0) & 255u], 1u);
+        }
+        ++o;
+      }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 512; i += blockDim.x) {
+    const uint32_t v = (&s_hist[0][0])[i];
+    if (v) atomicAdd(hist + 4 * 256 + i, v);
+  }
+}
+
+__global__ __launch_bounds__(256) void tile_ranges(const uint32_t* __restrict__ key, const uint32_t* ctr,
+                                                   uint2* __restrict__ ranges, uint32_t ntiles) {
+  const uint32_t n = ctr[C_NPAIRS];
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const uint32_t t = key[i];
+    if (t >= ntiles) continue;
+    if (i == 0 || key[i - 1] != t) ranges[t].x = i;
+    if (i + 1 == n || key[i + 1] != t) ranges[t].y = i + 1;
+  }
+}
+
+// One workgroup per tile; tiles are handed to XCDs in contiguous bands
+// (workgroup i runs on XCD i % 8) so that neighbouring tiles, which share
+// Gaussians, share an L2.
+template <bool FILTER, bool SAVE>
+__global__ __launch_bounds__(256) void blend(const uint2* __restrict__ ranges, const uint32_t* __restrict__ tval,
+                                             const float4* __restrict__ pg0, const float4* __restrict__ pg1,
+                                             const float4* __restrict__ pg2, RCam cam, int ntiles, int per_xcd,
+                                             uint32_t n_g, uint32_t n_pairs_cap,
+                                             float* __restrict__ img, float* __restrict__ Tout,
+                                             int32_t* __restrict__ Nout) {
+  __shared__ float4 s0[256], s1[256], s2[256];
+  const int tile = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (tile >= ntiles) return;
+  const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
+  const int px = tx * kTileSize + (threadIdx.x & 15), py = ty * kTileSize + (threadIdx.x >> 4);
+  const bool inside = px < cam.W && py < cam.H;
+  const float fxp = px + 0.5f, fyp = py + 0.5f;
+  uint2 rg = ranges[tile];
+  if (rg.y > n_pairs_cap) rg.y = n_pairs_cap;
+  if (rg.x > rg.y) rg.x = rg.y;
+  float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f;
+  int32_t ncon = 0;
+  bool done = !inside;
+  for (uint32_t b0 = rg.x; b0 < rg.y; b0 += 256) {
+    if (__syncthreads_count(done) == 256) break;
+    const uint32_t idx = b0 + threadIdx.x;
+    if (idx < rg.y) {
+      uint32_t g = tval[idx];
+      if (g >= n_g) g = 0;
+      s0[threadIdx.x] = pg0[g];
+      s1[threadIdx.x] = pg1[g];
+      s2[threadIdx.x] = pg2[g];
+    }
+    __syncthreads();
+    const int cnt = (int)min(256u, rg.y - b0);
+    if (!done) {
+      for (int j = 0; j < cnt; ++j) {
+        const float4 p0 = s0[j];
+        const float4 p1 = s1[j];
+        const float dx = p0.x - fxp, dy = p0.y - fyp;
+        float power = -0.5f * (p0.z * dx * dx + p1.x * dy * dy) - p0.w * dx * dy;
+        power = fminf(power, 0.f);
+        if (FILTER && power < p1.z) continue;   // Eq. 4: log(a*) - log(theta) >= rho, no exp needed
+        const float alpha = fminf(kAlphaMax, p1.y * __expf(power));
+        if (alpha < kAlphaMin) continue;
+        const float Tn = T * (1.f - alpha);
+        if (Tn < kTMin) {
+          done = true;
+          break;
+        }
+        const float4 p2 = s2[j];
+        const float wgt = alpha * T;
+        cr = fmaf(wgt, p2.x, cr);
+        cg = fmaf(wgt, p2.y, cg);
+        cb = fmaf(wgt, p2.z, cb);
+        T = Tn;
+        ++ncon;
+      }
+    }
+    __syncthreads();
+  }
+  if (inside) {
+    const size_t hw = (size_t)cam.W * cam.H, o = (size_t)py * cam.W + px;
+    img[o] = fmaf(T, cam.bg[0], cr);
+    img[hw + o] = fmaf(T, cam.bg[1], cg);
+    img[2 * hw + o] = fmaf(T, cam.bg[2], cb);
+    if (SAVE) {
+      Tout[o] = T;
+      Nout[o] = ncon;
+    }
+  }
+}
+
+RCam make_rcam(const vy_camera* c, const vy_render_opts* opt) {
+  RCam r;
+  for (int i = 0; i < 9; ++i) r.R[i] = c->R[i];
+  r.px = c->pos[0];
+  r.py = c->pos[1];
+  r.pz = c->pos[2];
+  r.fx = c->fx;
+  r.fy = c->fy;
+  r.cx = c->cx;
+  r.cy = c->cy;
+  r.near = c->znear;
+  r.W = c->width;
+  r.H = c->height;
+  r.ulo = -kClamp * c->cx / c->fx;
+  r.uhi = kClamp * ((float)c->width - c->cx) / c->fx;
+  r.vlo = -kClamp * c->cy / c->fy;
+  r.vhi = kClamp * ((float)c->height - c->cy) / c->fy;
+  r.tiles_x = (c->width + kTileSize - 1) / kTileSize;
+  r.tiles_y = (c->height + kTileSize - 1) / kTileSize;
+  for (int k = 0; k < 3; ++k) r.bg[k] = opt ? opt->bg[k] : 0.f;
+  r.ln_amin = logf(kAlphaMin);
+  return r;
+}
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int imin(int64_t a, int64_t b) { return (int)(a < b ? a : b); }
+
+}  // namespace
+
+using namespace vy;
+
+extern "C" {
+
+static int64_t status_words_for(int64_t max_g, int64_t max_pairs) {
+  const int64_t a = cdiv(max_pairs, vysort::kTile), b = cdiv(max_g, vysort::kTile);
+  return (a > b ? a : b) * 256 + 256;
+}
+
+size_t vy_render_workspace_bytes(int64_t max_g, int32_t max_w, int32_t max_h, int64_t max_pairs) {
+  if (max_g < 1 || max_w < 1 || max_h < 1 || max_pairs < 1) return 0;
+  const int64_t tiles = cdiv(max_w, kTileSize) * cdiv(max_h, kTileSize);
+  size_t b = 0;
+  b += (size_t)max_g * (16 * 3 + 4 * 9);  // pg0..2, rect x2, count, relax, offsets, dkey x2, dval x2
+  b += (size_t)max_pairs * 4 * 4;                          // tkey x2, tval x2
+  b += (size_t)tiles * 8;
+  b += 64 * 4 + 6 * 256 * 4;
+  b += (size_t)status_words_for(max_g, max_pairs) * 8;
+  b += (size_t)max_w * max_h * 8;                          // saved T, n_contrib
+  b += 32 * 256;
+  return b;
+}
+
+int vy_render_ctx_create(int64_t max_g, int32_t max_w, int32_t max_h, int64_t max_pairs, void* ws, size_t bytes,
+                         vy_render_ctx** out) {
+  if (!ws || !out || max_g < 1 || max_w < 1 || max_h < 1 || max_pairs < 1 || max_pairs > 0x7FFFFFFF ||
+      max_g > 0x7FFFFFFF || max_w > 32768 || max_h > 32768)
+    return fail(VY_ERR_ARG, "vy_render_ctx_create: bad argument");
+  if (cdiv(max_w, kTileSize) * cdiv(max_h, kTileSize) > 65536)
+    return fail(VY_ERR_ARG, "vy_render_ctx_create: more than 65536 tiles (16-bit tile keys)");
+  if (bytes < vy_render_workspace_bytes(max_g, max_w, max_h, max_pairs))
+    return fail(VY_ERR_ARG, "vy_render_ctx_create: workspace %zu < %zu bytes", bytes,
+                vy_render_workspace_bytes(max_g, max_w, max_h, max_pairs));
+  RenderCtx* c = (RenderCtx*)calloc(1, sizeof(RenderCtx));
+  if (!c) return fail(VY_ERR_ARG, "vy_render_ctx_create: out of host memory");
+  Carver cv(ws, bytes);
+  c->magic = kCtxMagic;
+  c->max_g = max_g;
+  c->max_pairs = max_pairs;
+  c->max_w = max_w;
+  c->max_h = max_h;
+  c->max_tiles = cdiv(max_w, kTileSize) * cdiv(max_h, kTileSize);
+  c->pg0 = cv.take<float4>(max_g);
+  c->pg1 = cv.take<float4>(max_g);
+  c->pg2 = cv.take<float4>(max_g);
+  c->prect = cv.take<uint32_t>(max_g);
+  c->prect2 = cv.take<uint32_t>(max_g);
+  c->pcount = cv.take<uint32_t>(max_g);
+  c->prelax = cv.take<float>(max_g);
+  c->offsets = cv.take<uint32_t>(max_g);
+  c->dkey[0] = cv.take<uint32_t>(max_g);
+  c->dkey[1] = cv.take<uint32_t>(max_g);
+  c->dval[0] = cv.take<uint32_t>(max_g);
+  c->dval[1] = cv.take<uint32_t>(max_g);
+  c->tkey[0] = cv.take<uint32_t>(max_pairs);
+  c->tkey[1] = cv.take<uint32_t>(max_pairs);
+  c->tval[0] = cv.take<uint32_t>(max_pairs);
+  c->tval[1] = cv.take<uint32_t>(max_pairs);
+  c->ranges = cv.take<uint2>(c->max_tiles);
+  c->ctr = cv.take<uint32_t>(64);
+  c->hist = cv.take<uint32_t>(6 * 256);
+  c->status_words = status_words_for(max_g, max_pairs);
+  c->status = cv.take<uint64_t>(c->status_words);
+  c->T_final = cv.take<float>((size_t)max_w * max_h);
+  c->n_contrib = cv.take<int32_t>((size_t)max_w * max_h);
+  if (!cv.ok()) {
+    free(c);
+    return fail(VY_ERR_ARG, "vy_render_ctx_create: workspace layout overflow");
+  }
+  hipError_t e = hipMemset(c->status, 0, sizeof(uint64_t) * c->status_words);
+  if (e == hipSuccess) e = hipMemset(c->ctr, 0, 64 * 4);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    free(c);
+    return fail(VY_ERR_HIP, "vy_render_ctx_create: %s", hipGetErrorString(e));
+  }
+  c->epoch = 0;
+  *out = (vy_render_ctx*)c;
+  return VY_OK;
+}
+
+int vy_render_ctx_free(vy_render_ctx* ctx) {
+  RenderCtx* c = (RenderCtx*)ctx;
+  if (!c) return VY_OK;
+  if (c->magic != kCtxMagic) return fail(VY_ERR_ARG, "vy_render_ctx_free: not a render context");
+  c->magic = 0;
+  free(c);
+  return VY_OK;
+}
+
+static int epoch_for(RenderCtx* c, hipStream_t st, uint32_t* ep) {
+  *ep = next_epoch(c->epoch);
+  if (*ep == 1) VY_HIP(hipMemsetAsync(c->status, 0, sizeof(uint64_t) * c->status_words, st));
+  return VY_OK;
+}
+
+int vy_render(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, const vy_render_opts* opts,
+              float* image, vy_render_ctx* ctx, void* stream) {
+  const Scene* s = (const Scene*)scene;
+  const Cut* ct = (const Cut*)cut;
+  RenderCtx* c = (RenderCtx*)ctx;
+  if (!s || s->magic != kSceneMagic || !ct || ct->magic != kCutMagic || !c || c->magic != kCtxMagic || !cam ||
+      !image)
+    return fail(VY_ERR_ARG, "vy_render: bad argument");
+  if (ct->scene != s) return fail(VY_ERR_ARG, "vy_render: cut belongs to another scene");
+  if (ct->cur < 0) return fail(VY_ERR_STATE, "vy_render: cut has not been computed");
+  if (cam->width < 1 || cam->height < 1 || cam->width > c->max_w || cam->height > c->max_h)
+    return fail(VY_ERR_ARG, "vy_render: image %dx%d exceeds the context (%dx%d)", cam->width, cam->height,
+                c->max_w, c->max_h);
+  if (!(cam->fx > 0.f) || !(cam->fy > 0.f) || !(cam->znear > 0.f))
+    return fail(VY_ERR_ARG, "vy_render: invalid camera intrinsics");
+  if (c->max_g < s->n)
+    return fail(VY_ERR_ARG, "vy_render: context max_gaussians %lld < scene nodes %lld", (long long)c->max_g,
+                (long long)s->n);
+  const bool filter = opts && opts->alpha_filter;
+  const bool save = opts && opts->save_state;
+  hipStream_t st = (hipStream_t)stream;
+  const RCam rc = make_rcam(cam, opts);
+  const int ntiles = rc.tiles_x * rc.tiles_y;
+  const int32_t* cut_ids = cut_ids_dev(ct);
+  const uint32_t* n_cut = (const uint32_t*)cut_count_dev(ct);
+  const uint32_t gcap = (uint32_t)c->max_g, pcap = (uint32_t)c->max_pairs;
+  int tile_bits = 1;
+  while ((1 << tile_bits) < ntiles) ++tile_bits;
+  const int bits0 = (tile_bits + 1) / 2, bits1 = tile_bits - bits0;
+  {
+    ProfScope ps(VY_STAGE_RENDER_SETUP, st);
+    render_setup<<<16, 256, 0, st>>>(c->ctr, c->hist, c->ranges, ntiles);
+    VY_LAUNCHED();
+  }
+  {
+    ProfScope ps(VY_STAGE_PROJECT, st);
+    const int blocks = imin(cdiv(c->max_g, 256), 2048);
+    if (filter)
+      project<true><<<blocks, 256, 0, st>>>(cut_ids, (const int32_t*)n_cut, s->gauss, s->sh, rc, c->pg0, c->pg1,
+                                            c->pg2, c->prect, c->prect2, c->prelax, c->pcount, c->dkey[0], c->ctr,
+                                            c->hist, s->n);
+    else
+      project<false><<<blocks, 256, 0, st>>>(cut_ids, (const int32_t*)n_cut, s->gauss, s->sh, rc, c->pg0, c->pg1,
+                                             c->pg2, c->prect, c->prect2, c->prelax, c->pcount, c->dkey[0], c->ctr,
+                                             c->hist, s->n);
+    VY_LAUNCHED();
+  }
+  {
+    // depth sort of all cut entries (culled ones carry key 0xFFFFFFFF and sort last)
+    ProfScope ps(VY_STAGE_DEPTH_SORT, st);
+    const int blocks = imin(cdiv(c->max_g, vysort::kTile), 1024);
+    for (int p = 0; p < 4; ++p) {
+      uint32_t ep;
+      if (int rcode = epoch_for(c, st, &ep)) return rcode;
+      const uint32_t* kin = c->dkey[p & 1];
+      const uint32_t* vin = p == 0 ? nullptr : c->dval[p & 1];
+      vysort::onesweep_pass<<<blocks, vysort::kThreads, 0, st>>>(
+          kin, vin, c->dkey[(p + 1) & 1], c->dval[(p + 1) & 1], n_cut, gcap, 8 * p, 255u, 8, c->hist + 256 * p,
+          c->status, ep, c->ctr + C_TICKET0 + p, c->ctr + C_ERR);
+      VY_LAUNCHED();
+    }
+  }
+  // sorted order now in dkey[0] / dval[0]; the first C_NVIS entries are the visible Gaussians
+  {
+    ProfScope ps(VY_STAGE_PAIR_SCAN, st);
+    uint32_t ep;
+    if (int rcode = epoch_for(c, st, &ep)) return rcode;
+    const int blocks = imin(cdiv(c->max_g, kScanTile), 1024);
+    pair_scan<<<blocks, 256, 0, st>>>(c->dval[0], c->pcount, c->offsets, c->ctr, c->status, ep, pcap, gcap);
+    VY_LAUNCHED();
+  }
+  {
+    ProfScope ps(VY_STAGE_EMIT, st);
+    const int blocks = imin(cdiv(c->max_g, 256), 2048);
+    if (filter)
+      emit_pairs<true><<<blocks, 256, 0, st>>>(c->dval[0], c->offsets, c->pg0, c->pg1, c->prect, c->prect2,
+                                               c->prelax, rc.W, rc.H, rc.tiles_x, bits0, c->tkey[0], c->tval[0],
+                                               c->ctr, c->hist, pcap, gcap);
+    else
+      emit_pairs<false><<<blocks, 256, 0, st>>>(c->dval[0], c->offsets, c->pg0, c->pg1, c->prect, c->prect2,
+                                                c->prelax, rc.W, rc.H, rc.tiles_x, bits0, c->tkey[0], c->tval[0],
+                                                c->ctr, c->hist, pcap, gcap);
+    VY_LAUNCHED();
+  }
+  {
+    ProfScope ps(VY_STAGE_TILE_SORT, st);
+    const int blocks = imin(cdiv(c->max_pairs, vysort::kTile), 1024);
+    const uint32_t* np = c->ctr + C_NPAIRS;
+    for (int p = 0; p < 2; ++p) {
+      uint32_t ep;
+      if (int rcode = epoch_for(c, st, &ep)) return rcode;
+      const int shift = p == 0 ? 0 : bits0;
+      const int nb = p == 0 ? bits0 : bits1;
+      const uint32_t mask = nb > 0 ? ((1u << nb) - 1u) : 0u;
+      vysort::onesweep_pass<<<blocks, vysort::kThreads, 0, st>>>(
+          c->tkey[p & 1], c->tval[p & 1], c->tkey[(p + 1) & 1], c->tval[(p + 1) & 1], np, pcap, shift, mask, nb,
+          c->hist + 256 * (4 + p), c->status, ep, c->ctr + C_TICKET0 + 4 + p, c->ctr + C_ERR);
+      VY_LAUNCHED();
+    }
+  }
+  {
+    ProfScope ps(VY_STAGE_RANGES, st);
+    const int blocks = imin(cdiv(c->max_pairs, 256), 4096);
+    tile_ranges<<<blocks, 256, 0, st>>>(c->tkey[0], c->ctr, c->ranges, (uint32_t)ntiles);
+    VY_LAUNCHED();
+  }
+  {
+    ProfScope ps(VY_STAGE_BLEND, st);
+    const int per_xcd = (int)cdiv(ntiles, 8);
+    const int blocks = per_xcd * 8;
+#define VY_BLEND(F, S)                                                                                      \
+  blend<F, S><<<blocks, 256, 0, st>>>(c->ranges, c->tval[0], c->pg0, c->pg1, c->pg2, rc, ntiles, per_xcd, gcap, pcap, image, \
+                                      c->T_final, c->n_contrib)
+    if (filter) {
+      if (save) VY_BLEND(true, true); else VY_BLEND(true, false);
+    } else {
+      if (save) VY_BLEND(false, true); else VY_BLEND(false, false);
+    }
+#undef VY_BLEND
+    VY_LAUNCHED();
+  }
+  return VY_OK;
+}
+
+int vy_render_status(vy_render_ctx* ctx, int64_t* n_pairs, int64_t* n_visible, void* stream) {
+  RenderCtx* c = (RenderCtx*)ctx;
+  if (!c || c->magic != kCtxMagic) return fail(VY_ERR_ARG, "vy_render_status: bad argument");
+  uint32_t h[16];
+  hipStream_t st = (hipStream_t)stream;
+  VY_HIP(hipMemcpyAsync(h, c->ctr, sizeof(h), hipMemcpyDeviceToHost, st));
+  VY_HIP(hipStreamSynchronize(st));
+  if (n_visible) *n_visible = h[C_NVIS];
+  if (h[C_OVERFLOW]) {
+    if (n_pairs) *n_pairs = h[C_NPAIRS_RAW];
+    return fail(VY_ERR_CAPACITY, "vy_render: %u pairs exceed max_pairs %lld", h[C_NPAIRS_RAW],
+                (long long)c->max_pairs);
+  }
+  if (n_pairs) *n_pairs = h[C_NPAIRS];
+  if (h[C_ERR]) return fail(VY_ERR_DEVICE, "vy_render: device-side bound hit (%u)", h[C_ERR]);
+  return VY_OK;
+}
+
+int vy_render_saved(const vy_render_ctx* ctx, const float** T_final, const int32_t** n_contrib,
+                    const float** mean2d) {
+  const RenderCtx* c = (const RenderCtx*)ctx;
+  if (!c || c->magic != kCtxMagic) return fail(VY_ERR_ARG, "vy_render_saved: bad argument");
+  if (T_final) *T_final = c->T_final;
+  if (n_contrib) *n_contrib = c->n_contrib;
+  if (mean2d) *mean2d = (const float*)c->pg0;
+  return VY_OK;
+}
+
+}  // extern "C"

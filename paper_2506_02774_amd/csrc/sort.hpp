@@ -1,0 +1,132 @@
+// Stable LSD radix sort passes (onesweep: one scatter launch per digit with
+// decoupled look-back across partitions) and a single-pass exclusive scan,
+// for uint32 keys and uint32 values on gfx950 (wave64, LDS staging).
+//
+// Included by render.hip only.
+#pragma once
+
+#include "vy_common.hpp"
+
+namespace vysort {
+
+using namespace vyd;
+
+constexpr int kThreads = 256;
+constexpr int kItems = 16;                    // keys per thread per partition
+constexpr int kTile = kThreads * kItems;      // 4096 keys per partition
+constexpr int kWaves = kThreads / 64;
+
+// One stable scatter pass on digit (key >> shift) & mask (mask <= 255).
+// `ghist` holds this digit's global histogram (256 counts of the n keys).
+// vals_in == nullptr means value = input index. n = min(*n_ptr, n_cap).
+__global__ __launch_bounds__(kThreads) void onesweep_pass(const uint32_t* __restrict__ keys_in,
+                                                          const uint32_t* __restrict__ vals_in,
+                                                          uint32_t* __restrict__ keys_out,
+                                                          uint32_t* __restrict__ vals_out, const uint32_t* n_ptr,
+                                                          uint32_t n_cap, int shift, uint32_t mask, int nbits,
+                                                          const uint32_t* __restrict__ ghist, uint64_t* status,
+                                                          uint32_t epoch, uint32_t* ticket, uint32_t* err) {
+  __shared__ uint32_t s_keys[kTile];
+  __shared__ uint32_t s_vals[kTile];
+  __shared__ uint32_t s_whist[kWaves][256];
+  __shared__ uint32_t s_dstart[256];
+  __shared__ uint32_t s_gofs[256];
+  __shared__ uint32_t s_gstart[256];
+  __shared__ uint32_t s_scan[8];
+  __shared__ uint32_t s_part;
+
+  const uint32_t tid = threadIdx.x, w = tid >> 6, l = lane();
+  uint32_t n = *n_ptr;
+  if (n > n_cap) n = n_cap;
+  const uint32_t n_parts = (n + kTile - 1) / kTile;
+  {
+    uint32_t tot;
+    const uint32_t g = ghist[tid];
+    s_gstart[tid] = block_excl_scan256(g, s_scan, &tot);
+  }
+  for (;;) {
+    if (tid == 0) s_part = fetch_add(ticket, 1u);
+    s_whist[w][l] = 0;
+    s_whist[w][l + 64] = 0;
+    s_whist[w][l + 128] = 0;
+    s_whist[w][l + 192] = 0;
+    __syncthreads();
+    const uint32_t part = s_part;
+    if (part >= n_parts) break;
+    const uint32_t base = part * kTile;
+    const uint32_t cnt = (n - base) < (uint32_t)kTile ? (n - base) : (uint32_t)kTile;
+    uint32_t key[kItems], val[kItems], rnk[kItems];
+    // load: wave w round r covers partition items w*1024 + r*64 + lane (ranking order)
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      const uint32_t li = w * (64 * kItems) + r * 64 + l;
+      const bool ok = li < cnt;
+      key[r] = ok ? keys_in[base + li] : 0xFFFFFFFFu;
+      val[r] = ok ? (vals_in ? vals_in[base + li] : base + li) : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      const uint32_t li = w * (64 * kItems) + r * 64 + l;
+      const bool ok = li < cnt;
+      const uint32_t d = (key[r] >> shift) & mask;
+      uint64_t peers = ballot(ok);
+      for (int b = 0; b < nbits; ++b) {
+        const uint64_t bb = ballot(((d >> b) & 1u) != 0);
+        peers &= ((d >> b) & 1u) ? bb : ~bb;
+      }
+      const uint32_t before = s_whist[w][d];
+      const uint32_t rk = (uint32_t)__popcll(peers & lanemask_lt());
+      rnk[r] = before + rk;
+      const bool leader = ok && rk == 0;
+      // all lanes read the running count before the leader updates it (same wave, in order)
+      __builtin_amdgcn_wave_barrier();
+      if (leader) s_whist[w][d] = before + (uint32_t)__popcll(peers);
+      __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    // per digit: wave exclusive offsets and the block total
+    uint32_t dtot = 0;
+    {
+      const uint32_t d = tid;
+      uint32_t run = 0;
+#pragma unroll
+      for (int ww = 0; ww < kWaves; ++ww) {
+        const uint32_t c = s_whist[ww][d];
+        s_whist[ww][d] = run;
+        run += c;
+      }
+      dtot = run;
+    }
+    uint32_t btot;
+    const uint32_t dstart = block_excl_scan256(dtot, s_scan, &btot);
+    s_dstart[tid] = dstart;
+    {
+      const uint64_t ex = lookback(status + tid, part, 256, epoch, dtot, err);
+      s_gofs[tid] = s_gstart[tid] + (uint32_t)ex - dstart;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      const uint32_t li = w * (64 * kItems) + r * 64 + l;
+      if (li < cnt) {
+        const uint32_t d = (key[r] >> shift) & mask;
+        const uint32_t pos = s_dstart[d] + s_whist[w][d] + rnk[r];
+        s_keys[pos] = key[r];
+        s_vals[pos] = val[r];
+      }
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < cnt; i += kThreads) {
+      const uint32_t k = s_keys[i];
+      const uint32_t d = (k >> shift) & mask;
+      const uint32_t o = s_gofs[d] + i;
+      if (o < n) {   // always true unless a look-back wait timed out
+        keys_out[o] = k;
+        vals_out[o] = s_vals[i];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace vysort

@@ -1,0 +1,224 @@
+// Shared internals of the Voyager HIP library (gfx950): handle layouts, error
+// reporting, launch timing and wave64 device primitives.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/vy.h"
+
+namespace vy {
+
+// ---------------------------------------------------------------- errors ----
+
+void set_error(const char* fmt, ...);
+int fail(int code, const char* fmt, ...);
+
+#define VY_HIP(call)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      return ::vy::fail(VY_ERR_HIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),    \
+                        __FILE__, __LINE__);                                                  \
+  } while (0)
+
+#define VY_LAUNCHED()                                                                         \
+  do {                                                                                        \
+    hipError_t e_ = hipGetLastError();                                                        \
+    if (e_ != hipSuccess)                                                                     \
+      return ::vy::fail(VY_ERR_HIP, "kernel launch failed: %s (%s:%d)", hipGetErrorString(e_), \
+                        __FILE__, __LINE__);                                                  \
+  } while (0)
+
+// ---------------------------------------------------------------- timing ----
+
+// Brackets a launch with HIP events when vy_profile_begin() is active.
+void prof_mark(int stage, hipStream_t s, bool end);
+struct ProfScope {
+  int stage;
+  hipStream_t s;
+  ProfScope(int st, hipStream_t str) : stage(st), s(str) { prof_mark(stage, s, false); }
+  ~ProfScope() { prof_mark(stage, s, true); }
+};
+
+// ------------------------------------------------------------- workspace ----
+
+struct Carver {
+  uintptr_t base, cur, end;
+  explicit Carver(void* p, size_t bytes) : base((uintptr_t)p), cur((uintptr_t)p), end((uintptr_t)p + bytes) {}
+  template <class T>
+  T* take(size_t count) {
+    cur = (cur + 255) & ~uintptr_t(255);
+    T* r = reinterpret_cast<T*>(cur);
+    cur += count * sizeof(T);
+    return r;
+  }
+  size_t used() const { return cur - base; }
+  bool ok() const { return cur <= end; }
+};
+
+// ----------------------------------------------------------------- handles ----
+
+constexpr uint32_t kSceneMagic = 0x56595343u, kCutMagic = 0x56594355u, kCtxMagic = 0x56595243u;
+
+struct Scene {
+  uint32_t magic;
+  int64_t n;
+  // LoD record: {lo.x, lo.y, lo.z, first_child}, {hi.x, hi.y, hi.z, parent} (ints stored as bits)
+  float4* lod;
+  int32_t* ccount;   // child counts
+  // Gaussian record: {mean.xyz, log theta}, {scale.xyz, theta}, {unit quaternion w,x,y,z}
+  float4* gauss;
+  const float* sh;   // borrowed [n][48]
+  int32_t* scratch;  // small device scratch for validate
+};
+
+struct Cut {
+  uint32_t magic;
+  const Scene* scene;
+  int64_t n;
+  int32_t* F[2];        // frontier buffers (double-buffered so prev == out works)
+  int cur;              // index of the buffer holding the latest frontier (-1: none yet)
+  int32_t* C;           // cut ids
+  int32_t* counts;      // device: [0] |F| of buffer 0, [1] |F| of buffer 1, [2] |C|, [3] |C| copy
+  uint32_t* fbits;      // frontier bitmap (kept zero between calls)
+  uint32_t* cbits;      // cut bitmap
+  int64_t n_words;
+  int32_t* items;       // worklist slots (kept at -1 between calls)
+  uint32_t* ctr;        // device counters: [0] head [1] tail [2] pending [3] error
+                        //   [4] compaction ticket
+  uint64_t* status;     // look-back status of the compaction scan (2 per partition)
+  int64_t n_parts;      // compaction partitions
+  uint32_t epoch;
+};
+
+struct RenderCtx {
+  uint32_t magic;
+  int64_t max_g, max_pairs;
+  int32_t max_w, max_h;
+  int64_t max_tiles;
+  // projected Gaussians (cut order)
+  float4* pg0;          // {mean2d.x, mean2d.y, conic.a, conic.b}
+  float4* pg1;          // {conic.c, theta, rho threshold (filter), depth}
+  float4* pg2;          // {r, g, b, 0}
+  uint32_t* prect;      // packed tile rect x0 | y0 << 16, (x1, y1) in prect2
+  uint32_t* prect2;
+  uint32_t* pcount;     // pairs per Gaussian
+  float* prelax;        // per-Gaussian rounding allowance of the tile test
+  // depth sort
+  uint32_t* dkey[2];
+  uint32_t* dval[2];
+  uint32_t* offsets;    // exclusive scan of counts in depth order
+  // pairs
+  uint32_t* tkey[2];
+  uint32_t* tval[2];
+  uint2* ranges;        // per tile [start, end)
+  // per-frame counters, histograms, tickets: zeroed by the setup kernel
+  uint32_t* ctr;        // see render.hip for the layout
+  uint32_t* hist;       // 6 passes x 256 bins
+  uint64_t* status;     // look-back status words (sort passes and scans)
+  int64_t status_words;
+  uint32_t epoch;
+  float* T_final;
+  int32_t* n_contrib;
+};
+
+uint32_t next_epoch(uint32_t& epoch);   // 24-bit epochs, never 0
+
+}  // namespace vy
+
+// --------------------------------------------------------- device helpers ----
+
+#define VY_DEV __device__ __forceinline__
+
+namespace vyd {
+
+VY_DEV uint32_t lane() { return __lane_id(); }
+VY_DEV uint64_t ballot(bool p) { return __ballot(p); }
+VY_DEV uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
+
+template <class T>
+VY_DEV T ld_acq(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+VY_DEV void st_rel(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+VY_DEV T fetch_add(T* p, T v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Look-back status word: [63:40] epoch (24 bit) | [39:38] flag | [37:0] value.
+constexpr uint64_t kFlagAgg = 1, kFlagInc = 2;
+VY_DEV uint64_t pack_status(uint32_t epoch, uint64_t flag, uint64_t v) {
+  return (uint64_t(epoch) << 40) | (flag << 38) | (v & ((1ull << 38) - 1));
+}
+
+// Maximum number of polls of a look-back predecessor before giving up (the
+// kernel then records an error and continues, so it always terminates).
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+// Decoupled look-back (single thread): publishes `aggregate` for partition
+// `part`, sums predecessors' values back to the nearest inclusive prefix, and
+// publishes the inclusive prefix. Returns the exclusive prefix.
+VY_DEV uint64_t lookback(uint64_t* status, uint32_t part, uint32_t stride, uint32_t epoch, uint64_t aggregate,
+                         uint32_t* err) {
+  uint64_t* me = status + (uint64_t)part * stride;
+  if (part == 0) {
+    st_rel(me, pack_status(epoch, kFlagInc, aggregate));
+    return 0;
+  }
+  st_rel(me, pack_status(epoch, kFlagAgg, aggregate));
+  uint64_t excl = 0;
+  int64_t j = (int64_t)part - 1;
+  uint32_t spins = 0;
+  while (j >= 0) {
+    uint64_t w = ld_acq(status + (uint64_t)j * stride);
+    uint64_t flag = (w >> 38) & 3ull;
+    if ((uint32_t)(w >> 40) != epoch || flag == 0) {
+      if (++spins > kSpinLimit) {
+        fetch_add(err, 1u);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    excl += w & ((1ull << 38) - 1);
+    if (flag == kFlagInc) break;
+    --j;
+  }
+  st_rel(me, pack_status(epoch, kFlagInc, excl + aggregate));
+  return excl;
+}
+
+// Block-wide exclusive scan of one uint32 per thread (blockDim == 256).
+// `sh` needs 4 (waves) + 1 words. Returns the exclusive prefix; *total = sum.
+VY_DEV uint32_t block_excl_scan256(uint32_t v, uint32_t* sh, uint32_t* total) {
+  const uint32_t l = lane(), w = threadIdx.x >> 6;
+  // wave inclusive scan via DPP-free shuffles
+  uint32_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = __shfl_up(x, o, 64);
+    if (l >= (uint32_t)o) x += y;
+  }
+  if (l == 63) sh[w] = x;
+  __syncthreads();
+  uint32_t wbase = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    uint32_t s = sh[i];
+    if (i < (int)w) wbase += s;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return wbase + x - v;
+}
+
+}  // namespace vyd

@@ -1,0 +1,119 @@
+"""GPU parity of the LoD cut (through the C ABI): the full search (worklist
+traversal and exhaustive flat) against the FP64 brute-force oracle, and the
+temporal search (Algorithm 1) bitwise equal to the full search from any seed."""
+import numpy as np
+import pytest
+
+import scenegen
+from oracle import lod as olod
+
+from gpu_util import random_cameras, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tiny(tiny_scene):
+    vy = require_gpu()
+    return vy, vy.Scene(tiny_scene), tiny_scene
+
+
+def test_scene_validates(tiny):
+    vy, sc, host = tiny
+    assert sc.validate() == 0
+
+
+def test_full_cut_matches_oracle_walkthrough(tiny, tiny_cams):
+    vy, sc, host = tiny
+    for i, cam in enumerate(tiny_cams):
+        for mode in (vy.VY_CUT_FRONTIER, vy.VY_CUT_FLAT):
+            cut = vy.vy_lod_cut(sc, cam, 2.0, mode=mode)
+            F, C = cut.ids()
+            res = olod.compare_cut(host, cam, 2.0, F, C)
+            print(f"frame {i} mode {mode}: {res}", flush=True)
+            assert res["ok"], res
+            assert olod.check_frontier(host, F)
+
+
+def test_flat_equals_frontier_bitwise(tiny):
+    vy, sc, host = tiny
+    for cam in random_cameras(scenegen.CONFIGS["tiny"], 6, 21):
+        for tau in (0.0, 0.7, 2.0, 16.0):
+            a = vy.vy_lod_cut(sc, cam, tau, mode=vy.VY_CUT_FRONTIER).ids()
+            b = vy.vy_lod_cut(sc, cam, tau, mode=vy.VY_CUT_FLAT).ids()
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_temporal_equals_full_along_walkthrough(tiny, tiny_cams):
+    vy, sc, host = tiny
+    state = vy.vy_lod_cut(sc, tiny_cams[0], 2.0)
+    for cam in tiny_cams[1:]:
+        state = vy.vy_lod_cut(sc, cam, 2.0, prev=state, out=state)     # prev == out
+        full = vy.vy_lod_cut(sc, cam, 2.0)
+        a, b = state.ids(), full.ids()
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_temporal_from_arbitrary_frontiers(tiny):
+    vy, sc, host = tiny
+    rng = np.random.default_rng(5)
+    leaves = np.nonzero(host.child_count == 0)[0]
+    seeds = {"root": np.array([0]), "leaves": leaves}
+    # random valid frontier: cut of a random camera at a random tau
+    cams = random_cameras(scenegen.CONFIGS["tiny"], 4, 33)
+    seeds["other_camera"] = vy.vy_lod_cut(sc, cams[0], 7.0).ids()[0]
+    for name, F0 in seeds.items():
+        for cam in cams[1:]:
+            for tau in (0.5, 2.0, 9.0):
+                st = vy.Cut(sc)
+                st.set_frontier(F0)
+                out = vy.Cut(sc)
+                vy.vy_lod_cut(sc, cam, tau, prev=st, out=out)
+                full = vy.vy_lod_cut(sc, cam, tau)
+                a, b = out.ids(), full.ids()
+                assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), (name, tau)
+
+
+def test_cut_edge_cases(tiny):
+    vy, sc, host = tiny
+    # camera far above looking away (sky): nothing visible, F = {root} or a culled frontier
+    cam = scenegen.look_camera([0.0, 0.0, 5000.0], 0.0, 1.2, 64, 64)
+    F, C = vy.vy_lod_cut(sc, cam, 2.0).ids()
+    res = olod.compare_cut(host, cam, 2.0, F, C)
+    assert res["ok"] and len(C) == 0
+    # tau = 0 from the street: visible leaves
+    cam = scenegen.walkthrough(scenegen.CONFIGS["tiny"])[0]
+    F, C = vy.vy_lod_cut(sc, cam, 0.0).ids()
+    assert np.all(host.child_count[C] == 0)
+    assert olod.compare_cut(host, cam, 0.0, F, C)["ok"]
+    # huge tau from outside the root box: the root alone
+    cam = scenegen.look_camera([0.0, 0.0, 5000.0], 0.0, -1.2, 64, 64)
+    F, C = vy.vy_lod_cut(sc, cam, 1e30).ids()
+    assert F.tolist() == [0] and C.tolist() == [0]
+
+
+def test_single_node_scene():
+    vy = require_gpu()
+    host = scenegen.tree_from_arrays([-1], [-1], [0], [[-1, -1, 4]], [[1, 1, 6]], mean=[[0, 0, 5]])
+    sc = vy.Scene(host)
+    cam = scenegen.identity_camera(32, 32)
+    F, C = vy.vy_lod_cut(sc, cam, 1.0).ids()
+    assert F.tolist() == [0] and C.tolist() == [0]
+    st = vy.vy_lod_cut(sc, cam, 1.0)
+    F2, C2 = vy.vy_lod_cut(sc, cam, 1.0, prev=st, out=st).ids()
+    assert F2.tolist() == [0] and C2.tolist() == [0]
+
+
+def test_errors(tiny):
+    vy, sc, host = tiny
+    fresh = vy.Cut(sc)
+    cam = scenegen.identity_camera(32, 32)
+    with pytest.raises(vy.VoyagerError) as e:
+        vy.vy_lod_cut(sc, cam, 1.0, prev=fresh)
+    assert e.value.code == vy.VY_ERR_STATE
+    other = vy.Scene(scenegen.make_city(scenegen.scaled_config("tiny", 500)))
+    with pytest.raises(vy.VoyagerError) as e:
+        vy.vy_lod_cut(other, cam, 1.0, out=vy.Cut(sc))
+    assert e.value.code == vy.VY_ERR_ARG
+    with pytest.raises(vy.VoyagerError):
+        vy.vy_lod_cut(sc, cam, -1.0)

@@ -1,0 +1,105 @@
+"""GPU parity of splatting (through the C ABI): images against the FP64
+oracle within max-abs 2e-3 (non-ambiguous pixels) and mean-abs 1e-4, and the
+alpha-filtered image bitwise equal to the unfiltered one."""
+import numpy as np
+import pytest
+
+import scenegen
+from oracle import project as oproj, render as orender
+
+from gpu_util import image_parity, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tiny(tiny_scene):
+    vy = require_gpu()
+    sc = vy.Scene(tiny_scene)
+    ctx = vy.RenderContext(sc.n, 256, 256, 1 << 22)
+    return vy, sc, tiny_scene, ctx
+
+
+def _render_both(vy, sc, cut, cam, ctx, bg=(0.0, 0.0, 0.0)):
+    a = vy.vy_render(sc, cut, cam, ctx, alpha_filter=False, bg=bg).cpu().numpy()
+    rc, npairs_a, nvis_a = ctx.status()
+    vy.check(rc)
+    b = vy.vy_render(sc, cut, cam, ctx, alpha_filter=True, bg=bg).cpu().numpy()
+    rc, npairs_b, nvis_b = ctx.status()
+    vy.check(rc)
+    return a, b, npairs_a, npairs_b
+
+
+def test_walkthrough_images_match_oracle(tiny, tiny_cams):
+    vy, sc, host, ctx = tiny
+    state = None
+    for i, cam in enumerate(tiny_cams):
+        state = vy.vy_lod_cut(sc, cam, 2.0, prev=state, out=state) if state is not None else \
+            vy.vy_lod_cut(sc, cam, 2.0)
+        F, C = state.ids()
+        a, b, pa, pb = _render_both(vy, sc, state, cam, ctx)
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), f"frame {i}: filtered != unfiltered"
+        assert pb <= pa
+        ref = orender.render_image(oproj.project(host, C, cam), cam.width, cam.height)
+        res = image_parity(a, ref)
+        print(f"frame {i}: |C|={len(C)} pairs {pa} -> {pb} (filtered) {res}", flush=True)
+        assert res["ok"], res
+
+
+def test_random_gaussians_ragged_image():
+    vy = require_gpu()
+    W, H = 100, 37
+    leaves = scenegen.random_gaussians(3000, 4, W, H, depth_range=(1.0, 40.0), scale_range=(-3.5, 0.5))
+    L = dict(mean=leaves.mean, log_scale=leaves.log_scale, quat=leaves.quat,
+             opacity_logit=leaves.opacity_logit, sh=leaves.sh)
+    host = scenegen.build_hierarchy(L)
+    sc = vy.Scene(host)
+    cam = scenegen.identity_camera(W, H)
+    ctx = vy.RenderContext(sc.n, W, H, 1 << 22)
+    cut = vy.vy_lod_cut(sc, cam, 0.0)
+    F, C = cut.ids()
+    assert np.all(host.child_count[C] == 0) and len(C) > 1000
+    for bg in [(0.0, 0.0, 0.0), (0.25, 0.5, 1.0)]:
+        a, b, pa, pb = _render_both(vy, sc, cut, cam, ctx, bg=bg)
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+        ref = orender.render_image(oproj.project(host, C, cam), W, H, bg=bg)
+        res = image_parity(a, ref)
+        print(bg, res, pa, pb, flush=True)
+        assert res["ok"], res
+
+
+def test_empty_cut_gives_background(tiny):
+    vy, sc, host, ctx = tiny
+    cam = scenegen.look_camera([0.0, 0.0, 5000.0], 0.0, 1.2, 64, 48)
+    cut = vy.vy_lod_cut(sc, cam, 2.0)
+    img = vy.vy_render(sc, cut, cam, ctx, bg=(0.1, 0.2, 0.3)).cpu().numpy()
+    rc, npairs, nvis = ctx.status()
+    vy.check(rc)
+    assert npairs == 0 and nvis == 0
+    assert np.all(img[0] == np.float32(0.1)) and np.all(img[2] == np.float32(0.3))
+
+
+def test_tiny_images(tiny, tiny_cams):
+    vy, sc, host, ctx = tiny
+    cam0 = tiny_cams[2]
+    for W, H in [(1, 1), (17, 3), (16, 16), (33, 250)]:
+        cam = scenegen.look_camera(cam0.pos, 0.3, 0.0, W, H)
+        cut = vy.vy_lod_cut(sc, cam, 2.0)
+        F, C = cut.ids()
+        a, b, pa, pb = _render_both(vy, sc, cut, cam, ctx)
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+        ref = orender.render_image(oproj.project(host, C, cam), W, H)
+        res = image_parity(a, ref)
+        assert res["ok"], (W, H, res)
+
+
+def test_pair_overflow_reported(tiny, tiny_cams):
+    vy, sc, host, _ = tiny
+    ctx = vy.RenderContext(sc.n, 256, 256, 1000)
+    cam = tiny_cams[0]
+    cut = vy.vy_lod_cut(sc, cam, 2.0)
+    vy.vy_render(sc, cut, cam, ctx)
+    rc, need, nvis = ctx.status()
+    assert rc == vy.VY_ERR_CAPACITY and need > 1000
+    with pytest.raises(vy.VoyagerError):
+        vy.vy_render(sc, cut, scenegen.identity_camera(512, 512), ctx)
