@@ -11,7 +11,7 @@ splatting constants) are:
   clamped to 1.3x the image's half-extent in normalised coordinates;
 * Sigma2 = J R Sigma3 R^T J^T + 0.3 I (low-pass), conic = Sigma2^-1;
 * mean2D = (fx x/z + cx, fy y/z + cy); depth = z;
-* radius r = ceil(3.3290 sqrt(lambda_max(Sigma2))) pixels: beyond it
+* radius r = ceil(3.33 sqrt(lambda_max(Sigma2))) pixels: beyond it
   rho < -ln 255, so alpha = theta e^rho < 1/255 for any theta <= 1 (an exact
   pruning bound, not an approximation);
 * theta = sigmoid(opacity logit), log theta precomputed (Section 4.2, Eq. 4);
@@ -25,7 +25,7 @@ from . import sh as _sh
 
 LOWPASS = 0.3
 CLAMP = 1.3
-RADIUS_K = 3.3290   # >= sqrt(2 ln 255) = 3.32898...
+RADIUS_K = 3.33     # > sqrt(2 ln 255) = 3.329043...; 3.3290 would fall short of the bound
 
 
 def quat_to_rot(q: np.ndarray) -> np.ndarray:

@@ -25,7 +25,7 @@ def test_isotropic_on_axis_closed_form():
         np.testing.assert_allclose(p["cov2d"][0], [v, 0.0, v], rtol=1e-6, atol=1e-9)
         np.testing.assert_allclose(p["conic"][0], [1 / v, 0.0, 1 / v], rtol=1e-6, atol=1e-12)
         np.testing.assert_allclose(p["mean2d"][0], [128.0, 128.0], atol=1e-12)
-        assert p["radius"][0] == math.ceil(3.3290 * math.sqrt(v))
+        assert p["radius"][0] == math.ceil(3.33 * math.sqrt(v))
         assert p["depth"][0] == z and p["valid"][0]
 
 
@@ -81,3 +81,14 @@ def test_near_plane_and_opacity():
     assert p["valid"][0]
     th = 1 / (1 + math.exp(-float(np.float32(1.3))))
     assert abs(p["theta"][0] - th) < 1e-15 and abs(p["log_theta"][0] - math.log(th)) < 1e-15
+
+
+def test_radius_bound_is_exact():
+    """Beyond the pruning radius alpha < 1/255 even for theta = 1: the radius
+    constant must be at least sqrt(2 ln 255) (3.3290 is not)."""
+    assert project.RADIUS_K >= math.sqrt(2 * math.log(255.0))
+    assert 3.3290 < math.sqrt(2 * math.log(255.0))
+    for lam in (0.3, 2.0, 17.5, 1e4):
+        r = project.RADIUS_K * math.sqrt(lam)            # before the ceil: the tightest case
+        alpha = math.exp(-0.5 * r * r / lam)             # along the major axis, theta = 1
+        assert alpha < 1 / 255
