@@ -1,0 +1,325 @@
+#!/usr/bin/env python3
+"""Walkthrough benchmark of the Voyager per-frame hot path on one MI355X.
+
+A step is one frame: the LoD cut (temporal search seeded with the previous
+frame's frontier, or a full search) followed by rendering (projection, binning
+with or without the preemptive alpha filter, sort, blend). The default
+workload is the city-scale walkthrough: 1.8e7 leaf Gaussians (3.6e7 hierarchy
+nodes), 1920x1080, 300 frames, tau = 2 px, seeded synthetic scene and path.
+
+Prints ONE JSON line: FPS of temporal LoD + alpha filter (the method), with
+p50/p99 frame times, the plain full-search + unfiltered renderer on the same
+frames, the 2x2 ablation for tau in {1, 2, 4}, bitwise gates (temporal cut ==
+full cut, filtered image == unfiltered image, every frame), per-stage times,
+the roofline of the dominant kernel, and the FP64 oracle timed on the host.
+Progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+T0 = time.time()
+
+
+def log(msg):
+    print(f"[bench {time.time() - T0:7.1f}s] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300, help="timed frames (the walkthrough length)")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="full", help="tiny | med | full")
+    ap.add_argument("--tau", type=float, default=2.0, help="tau of the headline number")
+    ap.add_argument("--no-ablation", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-tiles", type=int, default=16, help="tiles the oracle renders for the CPU baseline")
+    ap.add_argument("--max-pairs", type=int, default=96 << 20)
+    return ap.parse_args()
+
+
+def frame_loop(vy, torch, scene, cams, tau, temporal, filt, state, full_cut, ctx, img, per_frame=True):
+    """Run the frames; returns per-frame ms (events on torch's current stream)."""
+    ev = []
+    for i, cam in enumerate(cams):
+        if per_frame:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+        if temporal:
+            if i == 0:
+                vy.vy_lod_cut(scene, cam, tau, out=state)
+            else:
+                vy.vy_lod_cut(scene, cam, tau, prev=state, out=state)
+            cut = state
+        else:
+            vy.vy_lod_cut(scene, cam, tau, out=full_cut)
+            cut = full_cut
+        vy.vy_render(scene, cut, cam, ctx, image=img, alpha_filter=filt)
+        if per_frame:
+            e1.record()
+            ev.append((e0, e1))
+    return ev
+
+
+def timed(vy, torch, scene, cams, tau, temporal, filt, state, full_cut, ctx, img):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev = frame_loop(vy, torch, scene, cams, tau, temporal, filt, state, full_cut, ctx, img)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = np.array([a.elapsed_time(b) for a, b in ev])
+    rc, npairs, nvis = ctx.status()
+    vy.check(rc, "vy_render_status")
+    return dict(fps=len(cams) / wall, ms_per_step=1e3 * wall / len(cams), p50_ms=float(np.percentile(ms, 50)),
+                p99_ms=float(np.percentile(ms, 99)), p99_ms_frames_1_on=float(np.percentile(ms[1:], 99))
+                if len(ms) > 1 else float(ms[0]), mean_event_ms=float(ms.mean()))
+
+
+def stage_bytes(stage, c):
+    """Algorithmic HBM bytes of one frame's launches of `stage` (from counts)."""
+    F, C, V, P, T, N, px = c["F"], c["C"], c["V"], c["P"], c["tiles"], c["N"], c["px"]
+    return {
+        "lod_classify": (4 + 32 + 16) * F + 4 * (F + C),
+        "lod_compact": 2 * (N / 8) + 4 * (F + C),
+        "lod_flat": 32 * N + 16 * N + N / 4,
+        "project": (4 + 48 + 192 + 68) * C,
+        "depth_sort": 60 * C,
+        "pair_scan": 12 * V,
+        "emit": (16 + (36 if c["filter"] else 0)) * V + 8 * P,
+        "tile_sort": 32 * P,
+        "ranges": 4 * P + 8 * T,
+        "blend": (4 + 48) * P + 8 * T + 12 * px,
+    }.get(stage, 0.0)
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU: the per-frame path is measured on one "
+                                   "MI355X; see DESIGN.md for how it would shard", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    import scenegen
+    import paper_2506_02774_amd as vy
+    if not os.path.exists(vy.LIB_PATH):
+        from paper_2506_02774_amd import build as _b
+        _b.build(force=True)
+    vy.lib()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    cfg = scenegen.CONFIGS[args.config]
+    K, W = args.steps, args.warmup
+    log(f"generating scene '{cfg.name}' ({cfg.n_leaf} leaves)")
+    host = scenegen.make_city(cfg)
+    log(f"scene: {host.n_nodes} nodes, {len(host.level_start) - 1} levels; uploading")
+    scene = vy.Scene(host)
+    nbad = scene.validate()
+    assert nbad == 0, f"scene validation failed: {nbad}"
+    cams = scenegen.walkthrough(cfg, frames=K)
+    warm = scenegen.walkthrough(cfg, seed=cfg.path_seed + 100, frames=max(W, 1))
+    Wd, Hd = cfg.width, cfg.height
+    ctx = vy.RenderContext(scene.n, Wd, Hd, args.max_pairs)
+    state, full_cut, aux = vy.Cut(scene), vy.Cut(scene), vy.Cut(scene)
+    img = torch.empty((3, Hd, Wd), dtype=torch.float32, device="cuda")
+    img2 = torch.empty_like(img)
+    ntiles = ((Wd + 15) // 16) * ((Hd + 15) // 16)
+    log(f"GPU memory in use: {torch.cuda.memory_allocated() / 2**30:.1f} GiB")
+
+    # ---------------------------------------------------------------- warmup
+    for temporal, filt in ((True, True), (False, False)):
+        frame_loop(vy, torch, scene, warm[:W] if W else warm[:1], args.tau, temporal, filt, state, full_cut, ctx,
+                   img, per_frame=False)
+    torch.cuda.synchronize()
+    rc, np_w, nv_w = ctx.status()
+    vy.check(rc, "warmup")
+    log("warmup done")
+
+    # ------------------------------------------------------------ headline
+    head = timed(vy, torch, scene, cams, args.tau, True, True, state, full_cut, ctx, img)
+    log(f"temporal + alpha filter: {head['fps']:.1f} FPS, p50 {head['p50_ms']:.3f} ms, p99 {head['p99_ms']:.3f} ms")
+    base = timed(vy, torch, scene, cams, args.tau, False, False, state, full_cut, ctx, img)
+    log(f"full + unfiltered: {base['fps']:.1f} FPS, p50 {base['p50_ms']:.3f} ms, p99 {base['p99_ms']:.3f} ms")
+
+    # ------------------------------------------------------------ ablation
+    ablation = {}
+    if not args.no_ablation:
+        for tau in cfg.taus:
+            row = {}
+            for temporal in (False, True):
+                for filt in (False, True):
+                    r = timed(vy, torch, scene, cams, tau, temporal, filt, state, full_cut, ctx, img)
+                    row[("temporal" if temporal else "full") + ("+filter" if filt else "")] = {
+                        k: round(v, 4) for k, v in r.items() if k in ("fps", "p50_ms", "p99_ms")}
+            ablation[f"tau={tau:g}"] = row
+            log(f"ablation tau={tau:g}: " + ", ".join(f"{k} {v['fps']:.0f}" for k, v in row.items()))
+
+    # ------------------------------------------------ gates + per-frame counts
+    log("verification pass (temporal cut == full cut, filtered == unfiltered, every frame)")
+    gates = dict(frames=0, cut_mismatch=0, image_mismatch=0)
+    counts = dict(F=0.0, C=0.0, V=0.0, P=0.0, P_unf=0.0)
+    tst = vy.Cut(scene)
+    for i, cam in enumerate(cams):
+        if i == 0:
+            vy.vy_lod_cut(scene, cam, args.tau, out=tst)
+        else:
+            vy.vy_lod_cut(scene, cam, args.tau, prev=tst, out=tst)
+        vy.vy_lod_cut(scene, cam, args.tau, out=full_cut)
+        nf_t, nc_t = tst.counts()
+        nf_f, nc_f = full_cut.counts()
+        same = (nf_t, nc_t) == (nf_f, nc_f)
+        if same:
+            pt = [ctypes_ptr(vy, tst, k) for k in (0, 1)]
+            pf = [ctypes_ptr(vy, full_cut, k) for k in (0, 1)]
+            same = bool(torch.equal(vy.device_view(pt[0], (nf_t,)), vy.device_view(pf[0], (nf_f,)))) and \
+                bool(torch.equal(vy.device_view(pt[1], (nc_t,)), vy.device_view(pf[1], (nc_f,))))
+        gates["cut_mismatch"] += 0 if same else 1
+        vy.vy_render(scene, full_cut, cam, ctx, image=img, alpha_filter=False)
+        rc, p_unf, _ = ctx.status()
+        vy.check(rc)
+        vy.vy_render(scene, tst, cam, ctx, image=img2, alpha_filter=True)
+        rc, p_f, v_f = ctx.status()
+        vy.check(rc)
+        if not torch.equal(img.view(torch.int32), img2.view(torch.int32)):
+            gates["image_mismatch"] += 1
+        gates["frames"] += 1
+        counts["F"] += nf_t
+        counts["C"] += nc_t
+        counts["V"] += v_f
+        counts["P"] += p_f
+        counts["P_unf"] += p_unf
+    nfr = max(1, gates["frames"])
+    avg = {k: v / nfr for k, v in counts.items()}
+    log(f"gates: {gates}; mean |F| {avg['F']:.0f} |C| {avg['C']:.0f} visible {avg['V']:.0f} "
+        f"pairs {avg['P']:.0f} (unfiltered {avg['P_unf']:.0f})")
+
+    # ------------------------------------------------------- stage profile
+    prof = {}
+    for name, temporal, filt in (("temporal+filter", True, True), ("full", False, False)):
+        vy.profile_begin(64 * K + 64)
+        frame_loop(vy, torch, scene, cams, args.tau, temporal, filt, state, full_cut, ctx, img, per_frame=False)
+        torch.cuda.synchronize()
+        prof[name] = vy.profile_end()
+    stages = prof["temporal+filter"]
+    tot_ms = sum(ms for ms, n in stages.values())
+    log("stage ms/frame (temporal+filter): " + ", ".join(
+        f"{k} {ms / K:.3f}" for k, (ms, n) in stages.items() if n))
+    cnt = dict(F=avg["F"], C=avg["C"], V=avg["V"], P=avg["P"], tiles=ntiles, N=scene.n, px=Wd * Hd, filter=True)
+    per_stage = {}
+    for k, (ms, n) in stages.items():
+        if not n:
+            continue
+        b = stage_bytes(k, cnt)
+        per_stage[k] = dict(ms_per_frame=round(ms / K, 5), launches_per_frame=n / K,
+                            algorithmic_GBps=round(b / (ms / K * 1e-3) / 1e9, 1) if ms > 0 else None)
+    dom = max(((k, ms) for k, (ms, n) in stages.items() if n), key=lambda t: t[1])[0]
+    dom_ms, dom_n = stages[dom]
+    launch_ms = dom_ms / dom_n
+    bytes_per_launch = stage_bytes(dom, cnt) * K / dom_n
+    achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
+    roofline = dict(kernel=dom, bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    launch_ms=round(launch_ms, 5), bytes_per_launch=round(bytes_per_launch))
+    log(f"dominant kernel {dom}: {launch_ms:.4f} ms/launch, {achieved:.0f} GB/s algorithmic")
+
+    # ------------------------------------------------------ oracle on CPU
+    cpu = None
+    parity = dict(gates)
+    if not args.no_cpu_baseline:
+        cpu, par = cpu_baseline(vy, torch, host, scene, cams, args.tau, ctx, img, args.cpu_tiles, state)
+        parity.update(par)
+
+    out = {
+        "metric": "FPS, 18M-Gaussian 1080p walkthrough (temporal vs full LoD); p99 frame ms",
+        "value": round(head["fps"], 2), "unit": "FPS", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": round(head["ms_per_step"], 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"city-{cfg.name}: {cfg.n_leaf} leaves ({scene.n} nodes), {Wd}x{Hd}, "
+                               f"{K}-frame walkthrough, tau={args.tau:g} px, temporal LoD + alpha filter",
+                   "leaves": cfg.n_leaf, "nodes": scene.n, "width": Wd, "height": Hd, "frames": K, "tau": args.tau},
+        "p50_ms": round(head["p50_ms"], 4), "p99_ms": round(head["p99_ms"], 4),
+        "p99_ms_frames_1_on": round(head["p99_ms_frames_1_on"], 4),
+        "full_unfiltered": {k: round(v, 4) for k, v in base.items()},
+        "speedup_vs_full_unfiltered": round(head["fps"] / base["fps"], 3),
+        "ablation": ablation,
+        "mean_counts": {k: round(v) for k, v in avg.items()},
+        "stages": per_stage,
+        "stages_full_unfiltered_ms_per_frame": {k: round(ms / K, 5) for k, (ms, n) in prof["full"].items() if n},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "parity": parity,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def ctypes_ptr(vy, cut, which):
+    import ctypes
+    pf, pc, pn = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+    vy.check(vy.lib().vy_cut_arrays(cut.handle, ctypes.byref(pf), ctypes.byref(pc), ctypes.byref(pn)))
+    return (pf.value, pc.value)[which]
+
+
+def cpu_baseline(vy, torch, host, scene, cams, tau, ctx, img, n_tiles, state):
+    """The FP64 oracle on a bounded sample of the same workload: the brute-force
+    cut of frame 0 over every node plus n_tiles 16x16 tiles of its image.
+    Also checks the GPU against it (cut and sampled tiles)."""
+    from oracle import lod as olod, project as oproj, render as orender
+    cam = cams[0]
+    W, H = cam.width, cam.height
+    tx_n, ty_n = (W + 15) // 16, (H + 15) // 16
+    log("cpu baseline: oracle brute-force cut over every node")
+    t0 = time.perf_counter()
+    F_or, C_or, P = olod.cut_bruteforce(host, cam, tau)
+    t_cut = time.perf_counter() - t0
+    # GPU frame 0 (full search) for parity
+    g = vy.vy_lod_cut(scene, cam, tau, out=state)
+    F, C = g.ids()
+    cut_cmp = olod.compare_cut(host, cam, tau, F, C, oracle=(F_or, C_or, P))
+    vy.vy_render(scene, g, cam, ctx, image=img, alpha_filter=True)
+    torch.cuda.synchronize()
+    gimg = img.cpu().numpy().astype(np.float64)
+    log(f"cpu baseline: cut {t_cut:.1f}s, |C| {len(C_or)}; projecting")
+    t0 = time.perf_counter()
+    proj = oproj.project(host, C, cam)
+    t_proj = time.perf_counter() - t0
+    # evenly spread tiles, including the horizon rows where the work concentrates
+    rng = np.random.default_rng(7)
+    tiles = sorted(set(int(t) for t in rng.choice(tx_n * ty_n, size=min(n_tiles, tx_n * ty_n), replace=False)))
+    t0 = time.perf_counter()
+    ref = orender.render_image(proj, W, H, tiles=tiles)
+    t_tiles = time.perf_counter() - t0
+    mask = ~np.isnan(ref["image"][0])
+    err = np.abs(gimg - np.nan_to_num(ref["image"]))[:, mask]
+    amb = ref["ambiguous"][mask]
+    max_err = float(err[:, ~amb].max()) if (~amb).any() else 0.0
+    frame_s = t_cut + t_proj + t_tiles * (tx_n * ty_n) / len(tiles)
+    cpu = dict(value=round(1.0 / frame_s, 6), unit="FPS", cores=1, kind="oracle",
+               sample=f"frame 0: brute-force cut over all {host.n_nodes} nodes ({t_cut:.1f}s), projection of "
+                      f"{len(C)} cut Gaussians ({t_proj:.1f}s), {len(tiles)} of {tx_n * ty_n} tiles blended "
+                      f"({t_tiles:.1f}s), scaled to a whole frame; single process FP64 numpy",
+               seconds=round(t_cut + t_proj + t_tiles, 2))
+    par = dict(oracle_cut_ok=bool(cut_cmp["ok"]), oracle_cut_near_threshold=cut_cmp["expand_diff"],
+               oracle_tiles=len(tiles), oracle_max_abs=round(max_err, 6), oracle_mean_abs=float(err.mean()),
+               oracle_ambiguous_px=int(amb.sum()), oracle_px=int(mask.sum()),
+               oracle_image_ok=bool(max_err <= 2e-3 and float(err.mean()) <= 1e-4))
+    log(f"cpu baseline: {cpu['value']:.5f} FPS equivalent; parity {par}")
+    return cpu, par
+
+
+if __name__ == "__main__":
+    main()

@@ -95,10 +95,12 @@ size_t vy_scene_workspace_bytes(int64_t n_nodes);
 
 /* Packs the node arrays into the library's device layout in `workspace`
  * (caller-owned, >= vy_scene_workspace_bytes) and precomputes theta and
- * log(theta) per Gaussian (Section 4.2: log theta is computed once and stored).
- * Enqueued on `stream`; the desc arrays other than `sh` may be released once
- * the stream has passed this call. Errors: VY_ERR_ARG for NULL pointers,
- * n_nodes < 1 or a short workspace; VY_ERR_HIP on a launch failure. */
+ * log(theta) per Gaussian (Section 4.2: log theta is computed once and stored),
+ * and measures the tree depth (which sets the number of traversal launches).
+ * Runs on `stream` and synchronises it; afterwards the desc arrays other than
+ * `sh` may be released. Errors: VY_ERR_ARG for NULL pointers, n_nodes < 1, a
+ * short workspace, or parent links that do not form a tree of depth < 1024;
+ * VY_ERR_HIP on a HIP failure. */
 int vy_scene_upload(const vy_scene_desc* desc, void* workspace, size_t workspace_bytes, void* stream,
                     vy_scene** out);
 

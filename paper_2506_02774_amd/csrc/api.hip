@@ -34,30 +34,39 @@ uint32_t next_epoch(uint32_t& epoch) {
 
 struct ProfRec {
   int stage;
-  hipEvent_t a, b;
+  int slot;
 };
 
+// Events are created once by vy_profile_begin (2 per launch slot), so that a
+// recorded launch costs two hipEventRecord calls and nothing else.
 static thread_local bool g_prof_on = false;
 static thread_local std::vector<ProfRec>* g_prof = nullptr;
+static thread_local std::vector<hipEvent_t>* g_events = nullptr;
 static thread_local int64_t g_prof_cap = 0;
-static thread_local hipEvent_t g_pending_start = nullptr;
+static thread_local int g_open_slot = -1;
 
 void prof_mark(int stage, hipStream_t s, bool end) {
-  if (!g_prof_on || !g_prof) return;
+  if (!g_prof_on || !g_prof || !g_events) return;
   if (!end) {
-    if ((int64_t)g_prof->size() >= g_prof_cap) { g_pending_start = nullptr; return; }
-    hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) { g_pending_start = nullptr; return; }
-    hipEventRecord(e, s);
-    g_pending_start = e;
+    g_open_slot = -1;
+    if ((int64_t)g_prof->size() >= g_prof_cap) return;
+    const int slot = (int)g_prof->size();
+    if (hipEventRecord((*g_events)[2 * slot], s) != hipSuccess) return;
+    g_open_slot = slot;
   } else {
-    if (!g_pending_start) return;
-    hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) { hipEventDestroy(g_pending_start); g_pending_start = nullptr; return; }
-    hipEventRecord(e, s);
-    g_prof->push_back({stage, g_pending_start, e});
-    g_pending_start = nullptr;
+    if (g_open_slot < 0) return;
+    if (hipEventRecord((*g_events)[2 * g_open_slot + 1], s) == hipSuccess) g_prof->push_back({stage, g_open_slot});
+    g_open_slot = -1;
   }
+}
+
+static void prof_release() {
+  if (g_events) {
+    for (hipEvent_t e : *g_events) (void)hipEventDestroy(e);
+    g_events->clear();
+  }
+  if (g_prof) g_prof->clear();
+  g_prof_cap = 0;
 }
 
 }  // namespace vy
@@ -79,11 +88,20 @@ const char* vy_stage_name(int stage) {
 }
 
 int vy_profile_begin(int64_t capacity) {
-  if (capacity <= 0) return fail(VY_ERR_ARG, "vy_profile_begin: capacity must be > 0");
+  if (capacity <= 0 || capacity > (1 << 22)) return fail(VY_ERR_ARG, "vy_profile_begin: capacity out of range");
   if (!g_prof) g_prof = new std::vector<ProfRec>();
-  for (auto& r : *g_prof) { hipEventDestroy(r.a); hipEventDestroy(r.b); }
-  g_prof->clear();
+  if (!g_events) g_events = new std::vector<hipEvent_t>();
+  prof_release();
   g_prof->reserve((size_t)capacity);
+  g_events->reserve(2 * (size_t)capacity);
+  for (int64_t i = 0; i < 2 * capacity; ++i) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) {
+      prof_release();
+      return fail(VY_ERR_HIP, "vy_profile_begin: hipEventCreate failed");
+    }
+    g_events->push_back(e);
+  }
   g_prof_cap = capacity;
   g_prof_on = true;
   return VY_OK;
@@ -98,15 +116,14 @@ int vy_profile_end(double* stage_ms, int64_t* stage_launches) {
   }
   int rc = VY_OK;
   for (auto& r : *g_prof) {
-    if (hipEventSynchronize(r.b) != hipSuccess) rc = fail(VY_ERR_HIP, "hipEventSynchronize failed");
+    hipEvent_t a = (*g_events)[2 * r.slot], b = (*g_events)[2 * r.slot + 1];
+    if (hipEventSynchronize(b) != hipSuccess) rc = fail(VY_ERR_HIP, "hipEventSynchronize failed");
     float ms = 0;
-    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) ms = 0;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) ms = 0;
     if (stage_ms) stage_ms[r.stage] += ms;
     if (stage_launches) stage_launches[r.stage] += 1;
-    hipEventDestroy(r.a);
-    hipEventDestroy(r.b);
   }
-  g_prof->clear();
+  prof_release();
   return rc;
 }
 

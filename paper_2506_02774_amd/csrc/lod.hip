@@ -70,17 +70,42 @@ VY_DEV void emit_node(int32_t n, bool vis, uint32_t* fbits, uint32_t* cbits) {
   if (vis) atomicOr(cbits + (n >> 5), bit);
 }
 
-// ctr layout
-constexpr int kHead = 0, kTail = 1, kPending = 2, kErr = 3, kTicket = 4;
+// Wave-cooperative emission for (mostly ascending) node ids: runs of lanes
+// that hit the same bitmap word are OR-reduced with a segmented shuffle scan
+// and written by one atomic per run. Every lane of the wave must call it;
+// lanes with active == false contribute nothing.
+VY_DEV void emit_wave(bool active, int32_t n, bool vis, uint32_t* fbits, uint32_t* cbits) {
+  const int32_t word = active ? (n >> 5) : -1;
+  uint32_t fv = active ? (1u << (n & 31)) : 0u;
+  uint32_t cv = (active && vis) ? fv : 0u;
+  const uint32_t l = lane();
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t ow = __shfl_down(word, off, 64);
+    const uint32_t of = __shfl_down(fv, off, 64), oc = __shfl_down(cv, off, 64);
+    if (l + off < 64 && ow == word) {
+      fv |= of;
+      cv |= oc;
+    }
+  }
+  const int32_t prev = __shfl_up(word, 1, 64);
+  if (active && (l == 0 || prev != word)) {
+    atomicOr(fbits + word, fv);
+    if (cv) atomicOr(cbits + word, cv);
+  }
+}
 
-__global__ void lod_setup(uint32_t* ctr, int32_t* items, int seed_root) {
+// ctr layout: [0..2] rotating level-queue counters, [3] error count, [4] compaction ticket
+constexpr int kQ0 = 0, kErr = 3, kTicket = 4;
+
+__global__ void lod_setup(uint32_t* ctr, int32_t* q0, int seed_root) {
   if (threadIdx.x == 0) {
-    ctr[kHead] = 0;
-    ctr[kTail] = seed_root ? 1u : 0u;
-    ctr[kPending] = seed_root ? 1u : 0u;
+    ctr[kQ0] = seed_root ? 1u : 0u;
+    ctr[kQ0 + 1] = 0;
+    ctr[kQ0 + 2] = 0;
     ctr[kErr] = 0;
     ctr[kTicket] = 0;
-    if (seed_root) items[0] = 0;
+    if (seed_root) q0[0] = 0;
   }
 }
 
@@ -114,27 +139,20 @@ __global__ __launch_bounds__(256) void lod_flat(int64_t n, const float4* __restr
   }
 }
 
-// Block-aggregated push of `push` children (first id fc) per thread onto the
-// worklist. Pending is raised before the items become visible, so it never
-// reaches zero while work remains.
-VY_DEV void push_children(uint32_t push, int32_t fc, int32_t* items, uint32_t* ctr, uint32_t cap,
+// Block-aggregated append of `push` consecutive ids starting at fc (per
+// thread) to a queue: one atomic per block.
+VY_DEV void push_children(uint32_t push, int32_t fc, int32_t* q, uint32_t* qcnt, uint32_t cap, uint32_t* err,
                           uint32_t* s_scan, uint32_t* s_tail) {
   uint32_t total;
   const uint32_t off = block_excl_scan256(push, s_scan, &total);
   if (total == 0) return;
-  if (threadIdx.x == 0) {
-    const uint32_t t0 = fetch_add(ctr + kTail, total);
-    uint32_t fits = t0 >= cap ? 0u : (cap - t0 < total ? cap - t0 : total);
-    if (fits < total) fetch_add(ctr + kErr, 1u);
-    if (fits) (void)__hip_atomic_fetch_add(ctr + kPending, fits, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
-    s_tail[0] = t0;
-  }
+  if (threadIdx.x == 0) s_tail[0] = fetch_add(qcnt, total);
   __syncthreads();
   const uint32_t t0 = s_tail[0];
   for (uint32_t k = 0; k < push; ++k) {
     const uint32_t pos = t0 + off + k;
-    if (pos < cap) st_rel(items + pos, fc + (int32_t)k);
+    if (pos < cap) q[pos] = fc + (int32_t)k;
+    else fetch_add(err, 1u);
   }
   __syncthreads();
 }
@@ -147,7 +165,7 @@ VY_DEV void push_children(uint32_t push, int32_t fc, int32_t* items, uint32_t* c
 __global__ __launch_bounds__(256) void lod_classify(const int32_t* __restrict__ Fprev, const int32_t* n_prev_ptr,
                                                     const float4* __restrict__ lod,
                                                     const int32_t* __restrict__ ccount, LodCam cam,
-                                                    int32_t* items, uint32_t* ctr, uint32_t cap,
+                                                    int32_t* q0, uint32_t* ctr, uint32_t cap,
                                                     uint32_t* fbits, uint32_t* cbits) {
   __shared__ uint32_t s_scan[8], s_tail[1];
   const int64_t n_prev = *n_prev_ptr;
@@ -161,6 +179,8 @@ __global__ __launch_bounds__(256) void lod_classify(const int32_t* __restrict__ 
     const int32_t nd = i < n_prev ? Fprev[i] : -1;
     const bool ok = nd >= 0 && (uint32_t)nd < cap;
     if (i < n_prev && !ok) fetch_add(ctr + kErr, 1u);
+    bool em = false, em_vis = false;
+    int32_t em_id = 0;
     if (ok) {
       const float4 a = lod[2 * (int64_t)nd], b = lod[2 * (int64_t)nd + 1];
       bool vis;
@@ -184,82 +204,94 @@ __global__ __launch_bounds__(256) void lod_classify(const int32_t* __restrict__ 
           cur_vis = pvis;
           p = __float_as_int(pb.w);
         }
-        emit_node(cur, cur_vis, fbits, cbits);
+        em = true;
+        em_id = cur;
+        em_vis = cur_vis;
       }
     }
-    push_children(push, fc, items, ctr, cap, s_scan, s_tail);
+    emit_wave(em, em_id, em_vis, fbits, cbits);
+    push_children(push, fc, q0, ctr + kQ0, cap, ctr + kErr, s_scan, s_tail);
   }
 }
 
-// Dynamic worklist traversal. Each block takes a ticket of 256 consecutive
-// slots; a thread waits for its slot to be filled, tests the node, emits it
-// or pushes its children. The traversal is over when `pending` (pushed but
-// unprocessed items) is zero; every wait is bounded (error flag on timeout).
-constexpr uint32_t kIdleLimit = 1u << 20;
+// Level launches of the top-down traversal (Section 4.1 "Fully-Streaming LoD
+// Tree Traversal": only expanded nodes and their children are visited). Each
+// thread takes one queued node and descends up to kLocalLevels levels on its
+// own (a small DFS stack), emitting frontier nodes to the bitmaps; nodes one
+// level deeper are handed to the next launch through an LDS buffer that the
+// block appends to the output queue with a single atomic. ceil(levels /
+// kLocalLevels) launches cover any tree depth; launches with an empty input
+// queue return at once. Queue counters rotate over three slots: launch j
+// reads cnt[j % 3], appends to cnt[(j + 1) % 3] and clears cnt[(j + 2) % 3].
+constexpr int kLocalLevels = 4;
+constexpr int kStack = 16;
+constexpr int kOutPerBlock = 256 * 16;
 
-__global__ __launch_bounds__(256) void lod_traverse(const float4* __restrict__ lod,
-                                                    const int32_t* __restrict__ ccount, LodCam cam,
-                                                    int32_t* items, uint32_t* ctr, uint32_t cap,
-                                                    uint32_t* fbits, uint32_t* cbits) {
-  __shared__ uint32_t s_scan[8], s_tail[1], s_base, s_flag, s_poll;
-  const uint32_t tid = threadIdx.x;
-  for (;;) {
-    if (tid == 0) s_base = fetch_add(ctr + kHead, 256u);
+__global__ __launch_bounds__(256) void lod_level(const int32_t* __restrict__ in_q, uint32_t* cnt3, int j,
+                                                 int32_t* __restrict__ out_q, const float4* __restrict__ lod,
+                                                 const int32_t* __restrict__ ccount, LodCam cam, uint32_t cap,
+                                                 uint32_t* fbits, uint32_t* cbits, uint32_t* err) {
+  __shared__ int32_t s_out[kOutPerBlock];
+  __shared__ uint32_t s_n, s_base;
+  const uint32_t n_in = ld_acq(cnt3 + (j % 3));
+  if (blockIdx.x == 0 && threadIdx.x == 0) cnt3[(j + 2) % 3] = 0;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  const uint32_t trips = (n_in + stride - 1) / stride;
+  uint32_t* out_cnt = cnt3 + ((j + 1) % 3);
+  for (uint32_t t = 0; t < trips; ++t) {
+    if (threadIdx.x == 0) s_n = 0;
     __syncthreads();
-    // slots at or beyond the capacity are never filled: nothing left for this block
-    if (s_base >= cap) break;
-    const uint32_t slot = s_base + tid;
-    bool resolved = slot >= cap;
-    uint32_t idle = 0;
-    bool finished = false;
-    for (;;) {
-      if (tid == 0) s_poll = ld_acq(ctr + kTail) > s_base ? 1u : 0u;
-      __syncthreads();
-      int32_t item = -1;
-      if (!resolved && s_poll) {
-        item = ld_acq(items + slot);
-        if (item >= 0) {
-          st_rel(items + slot, (int32_t)-1);
-          resolved = true;
-        }
-      }
-      uint32_t push = 0;
-      int32_t fc = 0;
-      if (item >= 0) {
-        const float4 a = lod[2 * (int64_t)item], b = lod[2 * (int64_t)item + 1];
-        bool vis;
-        if (lod_expand(a, b, cam, vis)) {
-          fc = __float_as_int(a.w);
-          push = (uint32_t)ccount[item];
-        } else {
-          emit_node(item, vis, fbits, cbits);
-        }
-      }
-      const uint32_t got = (uint32_t)__syncthreads_count(item >= 0);
-      push_children(push, fc, items, ctr, cap, s_scan, s_tail);
-      if (tid == 0 && got) (void)__hip_atomic_fetch_add(ctr + kPending, (uint32_t)(0u - got), __ATOMIC_SEQ_CST,
-                                                         __HIP_MEMORY_SCOPE_AGENT);
-      if (__syncthreads_and(resolved)) break;
-      if (got == 0) {
-        if (tid == 0) {
-          __builtin_amdgcn_s_sleep(8);
-          uint32_t f = ld_acq(ctr + kPending) == 0 ? 1u : 0u;
-          if (!f && ++idle > kIdleLimit) {
-            fetch_add(ctr + kErr, 1u);
-            f = 1;
-          }
-          s_flag = f;
-        }
-        __syncthreads();
-        if (s_flag) {
-          finished = true;
-          break;
-        }
+    const uint32_t i = t * stride + blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t stk[kStack];
+    int32_t dep[kStack];
+    int sp = 0;
+    if (i < n_in) {
+      const int32_t nd = in_q[i];
+      if (nd >= 0 && (uint32_t)nd < cap) {
+        stk[0] = nd;
+        dep[0] = 0;
+        sp = 1;
       } else {
-        idle = 0;
+        fetch_add(err, 1u);
       }
     }
-    if (finished) break;
+    while (sp > 0) {
+      --sp;
+      const int32_t n = stk[sp], d = dep[sp];
+      const float4 a = lod[2 * (int64_t)n], b = lod[2 * (int64_t)n + 1];
+      bool vis;
+      if (!lod_expand(a, b, cam, vis)) {
+        emit_node(n, vis, fbits, cbits);
+        continue;
+      }
+      const int32_t fc = __float_as_int(a.w), cc = ccount[n];
+      for (int k = cc - 1; k >= 0; --k) {
+        const int32_t ch = fc + k;
+        if (d + 1 < kLocalLevels && sp < kStack) {
+          stk[sp] = ch;
+          dep[sp] = d + 1;
+          ++sp;
+        } else {
+          const uint32_t slot = atomicAdd(&s_n, 1u);
+          if (slot < (uint32_t)kOutPerBlock) {
+            s_out[slot] = ch;
+          } else {
+            const uint32_t g = fetch_add(out_cnt, 1u);
+            if (g < cap) out_q[g] = ch;
+            else fetch_add(err, 1u);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    const uint32_t nl = s_n < (uint32_t)kOutPerBlock ? s_n : (uint32_t)kOutPerBlock;
+    if (threadIdx.x == 0) s_base = nl ? fetch_add(out_cnt, nl) : 0u;
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < nl; k += blockDim.x) {
+      const uint32_t pos = s_base + k;
+      if (pos < cap) out_q[pos] = s_out[k];
+      else fetch_add(err, 1u);
+    }
     __syncthreads();
   }
 }
@@ -360,7 +392,7 @@ size_t vy_cut_workspace_bytes(int64_t n) {
   if (n < 1) return 0;
   const int64_t n_words = (n + 31) / 32 + 64;
   const int64_t n_parts = (n_words + kWordsPerPart - 1) / kWordsPerPart;
-  return (size_t)n * 4 * 4        // F[2], C, items
+  return (size_t)n * 4 * 5        // F[2], C, two level queues
          + (size_t)n_words * 4 * 2 // bitmaps
          + 64 * 4 + 64 * 4         // counts, ctr
          + (size_t)n_parts * 16    // status
@@ -383,7 +415,8 @@ int vy_cut_create(const vy_scene* scene, void* ws, size_t ws_bytes, vy_cut** out
   c->F[0] = cv.take<int32_t>(s->n);
   c->F[1] = cv.take<int32_t>(s->n);
   c->C = cv.take<int32_t>(s->n);
-  c->items = cv.take<int32_t>(s->n);
+  c->q[0] = cv.take<int32_t>(s->n);
+  c->q[1] = cv.take<int32_t>(s->n);
   c->fbits = cv.take<uint32_t>(c->n_words);
   c->cbits = cv.take<uint32_t>(c->n_words);
   c->counts = cv.take<int32_t>(64);
@@ -401,10 +434,6 @@ int vy_cut_create(const vy_scene* scene, void* ws, size_t ws_bytes, vy_cut** out
   if (e == hipSuccess) e = hipMemset(c->counts, 0, 64 * 4);
   if (e == hipSuccess) e = hipMemset(c->ctr, 0, 64 * 4);
   if (e == hipSuccess) e = hipMemset(c->status, 0, 16 * c->n_parts);
-  if (e == hipSuccess) {
-    fill_i32<<<1024, 256>>>(c->items, s->n, -1);
-    e = hipGetLastError();
-  }
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     free(c);
@@ -449,7 +478,7 @@ int vy_lod_cut(const vy_scene* scene, const vy_camera* cam, float tau, vy_cut* p
   const bool flat = !p && full_mode == VY_CUT_FLAT;
   {
     ProfScope ps(VY_STAGE_LOD_SETUP, st);
-    lod_setup<<<1, 64, 0, st>>>(o->ctr, o->items, (!p && !flat) ? 1 : 0);
+    lod_setup<<<1, 64, 0, st>>>(o->ctr, o->q[0], (!p && !flat) ? 1 : 0);
     VY_LAUNCHED();
   }
   if (flat) {
@@ -462,13 +491,19 @@ int vy_lod_cut(const vy_scene* scene, const vy_camera* cam, float tau, vy_cut* p
     if (p) {
       ProfScope ps(VY_STAGE_LOD_CLASSIFY, st);
       // Cut::counts[src] holds |F_prev|; if p != o the worklist of o is used
-      lod_classify<<<2048, 256, 0, st>>>(p->F[src], p->counts + src, s->lod, s->ccount, L, o->items, o->ctr, cap,
+      lod_classify<<<2048, 256, 0, st>>>(p->F[src], p->counts + src, s->lod, s->ccount, L, o->q[0], o->ctr, cap,
                                          o->fbits, o->cbits);
       VY_LAUNCHED();
     }
-    ProfScope ps(VY_STAGE_LOD_TRAVERSE, st);
-    lod_traverse<<<1024, 256, 0, st>>>(s->lod, s->ccount, L, o->items, o->ctr, cap, o->fbits, o->cbits);
-    VY_LAUNCHED();
+    // enough level launches for the deepest possible descent
+    const int launches = (s->levels + kLocalLevels - 1) / kLocalLevels;
+    const int blocks = (int)((s->n + 255) / 256 < 1024 ? (s->n + 255) / 256 : 1024);
+    for (int j = 0; j < launches; ++j) {
+      ProfScope ps(VY_STAGE_LOD_TRAVERSE, st);
+      lod_level<<<blocks, 256, 0, st>>>(o->q[j & 1], o->ctr + kQ0, j, o->q[(j + 1) & 1], s->lod, s->ccount, L,
+                                        cap, o->fbits, o->cbits, o->ctr + kErr);
+      VY_LAUNCHED();
+    }
   }
   {
     ProfScope ps(VY_STAGE_LOD_COMPACT, st);

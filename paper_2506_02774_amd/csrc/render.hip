@@ -41,7 +41,8 @@ constexpr float kAlphaMax = 0.99f;
 constexpr float kTMin = 1e-4f;
 constexpr float kLowpass = 0.3f;
 constexpr float kClamp = 1.3f;
-constexpr float kRadiusK = 3.3290f;      // >= sqrt(2 ln 255)
+constexpr float kRadiusK = 3.33f;        // > sqrt(2 ln 255) = 3.32904: alpha < 1/255 beyond it
+constexpr uint32_t kBigArea = 32;        // rects with more tiles are binned by a whole workgroup
 constexpr float kFilterDelta = 1e-3f;    // margin of the preemptive check (keeps it lossless)
 
 // ctr layout
@@ -53,7 +54,7 @@ enum {
   C_TICKET0 = 4,   // 4..9 sort passes, 10 scan
   C_SCAN_TICKET = 10,
   C_OVERFLOW = 11,
-  C_NCUT = 12,
+  C_NBIG = 12,     // Gaussians whose rect exceeds kBigArea tiles
   C_COUNT = 32
 };
 
@@ -117,38 +118,35 @@ VY_DEV float3 sh_colour(const float* __restrict__ c, float x, float y, float z) 
                      fminf(fmaxf(b + 0.5f, 0.f), 1.f));
 }
 
-// Upper bound of rho = -1/2 d^T A d over pixel centres of tile (tx, ty):
-// exact maximum over the continuous rectangle spanned by the centres
-// (0 if the mean is inside, else the best of the four clamped edges).
-VY_DEV float tile_rho_max(float mx, float my, float a, float b, float c, int tx, int ty, int W, int H) {
+// Maximum of rho(d) = A d_x^2 + B d_x d_y + C d_y^2 (A, C < 0: the power of a
+// Gaussian, d = pixel centre - mean) over the pixel centres of tile (tx, ty):
+// the exact maximum over the continuous rectangle spanned by those centres
+// (0 if the mean is inside, else the best of the four edges, each a 1-D
+// concave quadratic maximised at its clamped vertex).
+VY_DEV float tile_rho_max(float mx, float my, float A, float B, float C, int tx, int ty, int W, int H) {
   const float x0 = tx * kTileSize + 0.5f, y0 = ty * kTileSize + 0.5f;
   const float x1 = fminf((float)(tx * kTileSize + kTileSize), (float)W) - 0.5f;
   const float y1 = fminf((float)(ty * kTileSize + kTileSize), (float)H) - 0.5f;
   if (mx >= x0 && mx <= x1 && my >= y0 && my <= y1) return 0.f;
   const float dx0 = x0 - mx, dx1 = x1 - mx, dy0 = y0 - my, dy1 = y1 - my;
   float best = -INFINITY;
-  // vertical edges (dx fixed): maximise over dy in [dy0, dy1]
-  for (int e = 0; e < 2; ++e) {
+  for (int e = 0; e < 2; ++e) {  // edges with d_x fixed
     const float dx = e ? dx1 : dx0;
-    float dy = -b * dx / c;
-    dy = fminf(fmaxf(dy, dy0), dy1);
-    const float q = -0.5f * (a * dx * dx + c * dy * dy) - b * dx * dy;
-    best = fmaxf(best, q);
+    const float dy = fminf(fmaxf(-B * dx / (2.f * C), dy0), dy1);
+    best = fmaxf(best, (A * dx * dx + C * dy * dy) + B * dx * dy);
   }
-  for (int e = 0; e < 2; ++e) {
+  for (int e = 0; e < 2; ++e) {  // edges with d_y fixed
     const float dy = e ? dy1 : dy0;
-    float dx = -b * dy / a;
-    dx = fminf(fmaxf(dx, dx0), dx1);
-    const float q = -0.5f * (a * dx * dx + c * dy * dy) - b * dx * dy;
-    best = fmaxf(best, q);
+    const float dx = fminf(fmaxf(-B * dy / (2.f * A), dx0), dx1);
+    best = fmaxf(best, (A * dx * dx + C * dy * dy) + B * dx * dy);
   }
   return fminf(best, 0.f);
 }
 
-// Pair-level preemptive test (Section 4.2 moved to binning): keep tile t unless
-// every pixel centre in it has rho below thr. `relax` (>= 0) loosens the test
-// for ill-conditioned conics so that float32 rounding of the per-pixel rho can
-// never make a dropped pair matter.
+// Pair-level preemptive test (Eq. 4 moved to binning, Section 4.2): keep tile t
+// unless every pixel centre in it has rho below thr. `relax` >= 0 is a relative
+// allowance for float32 rounding of the per-pixel rho (grows with the conic's
+// condition number) so that a dropped pair could never have been blended.
 VY_DEV bool tile_keep(const float4 p0, const float4 p1, float relax, int tx, int ty, int W, int H) {
   const float rm = tile_rho_max(p0.x, p0.y, p0.z, p0.w, p1.x, tx, ty, W, H);
   return rm * (1.f - relax) >= p1.z;
@@ -161,7 +159,8 @@ __global__ __launch_bounds__(256) void project(const int32_t* __restrict__ cut, 
                                                float4* __restrict__ pg2, uint32_t* __restrict__ prect,
                                                uint32_t* __restrict__ prect2, float* __restrict__ prelax,
                                                uint32_t* __restrict__ pcount, uint32_t* __restrict__ dkey,
-                                               uint32_t* ctr, uint32_t* hist, int64_t n_nodes) {
+                                               uint32_t* ctr, uint32_t* hist, int64_t n_nodes,
+                                               uint32_t* __restrict__ big) {
   __shared__ uint32_t s_hist[4][256];
   for (int i = threadIdx.x; i < 4 * 256; i += blockDim.x) (&s_hist[0][0])[i] = 0;
   __syncthreads();
@@ -238,18 +237,25 @@ __global__ __launch_bounds__(256) void project(const int32_t* __restrict__ cut, 
           y1 = min(y1, cam.tiles_y - 1);
           if (x0 > x1 || y0 > y1 || !(r > 0.f)) valid = false;
           if (valid) {
-            o0 = make_float4(mx, my, ca, cb);
-            o1 = make_float4(cc, theta, thr, z);
+            // rho = A dx^2 + B dx dy + C dy^2 with (A, B, C) = (-a/2, -b, -c/2) of the conic
+            o0 = make_float4(mx, my, -0.5f * ca, -cb);
+            o1 = make_float4(-0.5f * cc, theta, thr, z);
             const float dn = 1.f / sqrtf((dxw * dxw + dyw * dyw) + dzw * dzw);
             const float3 rgb = sh_colour(sh + 48 * (int64_t)node, dxw * dn, dyw * dn, dzw * dn);
-            o2 = make_float4(rgb.x, rgb.y, rgb.z, 0.f);
+            o2 = make_float4(rgb.x, rgb.y, rgb.z, r);
             r0 = (uint32_t)x0 | ((uint32_t)y0 << 16);
             r1 = (uint32_t)x1 | ((uint32_t)y1 << 16);
-            if (FILTER && relax < 0.25f) {
+            const uint32_t area = (uint32_t)(x1 - x0 + 1) * (uint32_t)(y1 - y0 + 1);
+            if (area > kBigArea) {
+              // binned by a whole workgroup (big_count / emit_big); with the filter
+              // the count is provisional until big_count applies the tile test
+              count = area;
+              big[fetch_add(ctr + C_NBIG, 1u)] = (uint32_t)i;
+            } else if (FILTER && relax < 0.25f) {
               for (int ty = y0; ty <= y1; ++ty)
                 for (int tx = x0; tx <= x1; ++tx) count += tile_keep(o0, o1, relax, tx, ty, cam.W, cam.H) ? 1u : 0u;
             } else {
-              count = (uint32_t)(x1 - x0 + 1) * (uint32_t)(y1 - y0 + 1);
+              count = area;
             }
             if (count == 0) valid = false;
             else key = __float_as_uint(z);
@@ -280,8 +286,38 @@ __global__ __launch_bounds__(256) void project(const int32_t* __restrict__ cut, 
   }
 }
 
-// Exclusive scan of pcount[sorted_val[r]] for r < n_vis -> offsets[r]; the
-// total goes to C_NPAIRS_RAW, min(total, cap) to C_NPAIRS.
+// Filtered pair count of the big Gaussians: one workgroup per Gaussian, its
+// rect's tiles spread over the threads.
+__global__ __launch_bounds__(256) void big_count(const uint32_t* __restrict__ big, const uint32_t* ctr,
+                                                 const float4* __restrict__ pg0, const float4* __restrict__ pg1,
+                                                 const uint32_t* __restrict__ prect,
+                                                 const uint32_t* __restrict__ prect2,
+                                                 const float* __restrict__ prelax, int W, int H,
+                                                 uint32_t* __restrict__ pcount, uint32_t n_g) {
+  __shared__ uint32_t s_red[4];
+  const uint32_t nb = ctr[C_NBIG];
+  for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    const uint32_t g = big[b];
+    if (g >= n_g) continue;
+    const uint32_t a = prect[g], e = prect2[g];
+    const int x0 = a & 0xFFFF, y0 = a >> 16, x1 = e & 0xFFFF, y1 = e >> 16;
+    const int w = x1 - x0 + 1, area = w * (y1 - y0 + 1);
+    const float4 p0 = pg0[g], p1 = pg1[g];
+    const float relax = prelax[g];
+    uint32_t cnt = 0;
+    for (int k = threadIdx.x; k < area; k += blockDim.x)
+      cnt += (relax >= 0.25f || tile_keep(p0, p1, relax, x0 + k % w, y0 + k / w, W, H)) ? 1u : 0u;
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+    if (lane() == 0) s_red[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) pcount[g] = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+    __syncthreads();
+  }
+}
+
+// Exclusive scan of the pair counts in depth order (r < n_vis), written per
+// cut position: offs[g] = first pair of Gaussian g. The total goes to
+// C_NPAIRS_RAW, min(total, cap) to C_NPAIRS.
 constexpr int kScanItems = 16, kScanTile = 256 * kScanItems;
 
 __global__ __launch_bounds__(256) void pair_scan(const uint32_t* __restrict__ sorted_val,
@@ -323,7 +359,10 @@ __global__ __launch_bounds__(256) void pair_scan(const uint32_t* __restrict__ so
     __syncthreads();
     for (int k = 0; k < kScanItems; ++k) {
       const uint32_t i = base + k * 256 + threadIdx.x;
-      if (i < n) offsets[i] = s_v[k * 256 + threadIdx.x];
+      if (i < n) {
+        const uint32_t g = sorted_val[i];
+        if (g < n_g) offsets[g] = s_v[k * 256 + threadIdx.x];
+      }
     }
     if (part == n_parts - 1 && threadIdx.x == 0) {
       const uint64_t total = ex + tot;
@@ -335,9 +374,11 @@ __global__ __launch_bounds__(256) void pair_scan(const uint32_t* __restrict__ so
   }
 }
 
+// Pair emission, Gaussians with rects of at most kBigArea tiles: one thread
+// each, tiles in row-major order from offs[g].
 template <bool FILTER>
 __global__ __launch_bounds__(256) void emit_pairs(const uint32_t* __restrict__ sorted_val,
-                                                  const uint32_t* __restrict__ offsets,
+                                                  const uint32_t* __restrict__ offs,
                                                   const float4* __restrict__ pg0, const float4* __restrict__ pg1,
                                                   const uint32_t* __restrict__ prect,
                                                   const uint32_t* __restrict__ prect2,
@@ -352,9 +393,10 @@ __global__ __launch_bounds__(256) void emit_pairs(const uint32_t* __restrict__ s
   for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
     const uint32_t g = sorted_val[r];
     if (g >= n_g) continue;
-    uint32_t o = offsets[r];
     const uint32_t a = prect[g], b = prect2[g];
     const int x0 = a & 0xFFFF, y0 = a >> 16, x1 = b & 0xFFFF, y1 = b >> 16;
+    if ((uint32_t)(x1 - x0 + 1) * (uint32_t)(y1 - y0 + 1) > kBigArea) continue;   // emit_big
+    uint32_t o = offs[g];
     const float relax = prelax[g];
     float4 p0, p1;
     if (FILTER) {
@@ -381,6 +423,56 @@ __global__ __launch_bounds__(256) void emit_pairs(const uint32_t* __restrict__ s
   }
 }
 
+// Pair emission of the big Gaussians: one workgroup per Gaussian; the kept
+// tiles of each 256-tile chunk are placed by a block scan (row-major order).
+template <bool FILTER>
+__global__ __launch_bounds__(256) void emit_big(const uint32_t* __restrict__ big, const uint32_t* __restrict__ offs,
+                                                const uint32_t* __restrict__ pcount,
+                                                const float4* __restrict__ pg0, const float4* __restrict__ pg1,
+                                                const uint32_t* __restrict__ prect,
+                                                const uint32_t* __restrict__ prect2,
+                                                const float* __restrict__ prelax, int W, int H, int tiles_x,
+                                                int bits0, uint32_t* __restrict__ tkey, uint32_t* __restrict__ tval,
+                                                uint32_t* ctr, uint32_t* hist, uint32_t cap, uint32_t n_g) {
+  __shared__ uint32_t s_hist[2][256];
+  __shared__ uint32_t s_scan[8];
+  for (int i = threadIdx.x; i < 512; i += blockDim.x) (&s_hist[0][0])[i] = 0;
+  __syncthreads();
+  const uint32_t nb = ctr[C_NBIG];
+  const uint32_t m0 = (1u << bits0) - 1u;
+  for (uint32_t bi = blockIdx.x; bi < nb; bi += gridDim.x) {
+    const uint32_t g = big[bi];
+    if (g >= n_g || pcount[g] == 0) continue;   // uniform over the block
+    const uint32_t a = prect[g], e = prect2[g];
+    const int x0 = a & 0xFFFF, y0 = a >> 16, x1 = e & 0xFFFF, y1 = e >> 16;
+    const int w = x1 - x0 + 1, area = w * (y1 - y0 + 1);
+    const float4 p0 = pg0[g], p1 = pg1[g];
+    const float relax = prelax[g];
+    uint32_t o = offs[g];
+    for (int base = 0; base < area; base += 256) {
+      const int k = base + (int)threadIdx.x;
+      const int tx = x0 + k % w, ty = y0 + k / w;
+      bool keep = k < area;
+      if (FILTER && keep && relax < 0.25f) keep = tile_keep(p0, p1, relax, tx, ty, W, H);
+      uint32_t tot;
+      const uint32_t pos = o + block_excl_scan256(keep ? 1u : 0u, s_scan, &tot);
+      if (keep && pos < cap) {
+        const uint32_t t = (uint32_t)(ty * tiles_x + tx);
+        tkey[pos] = t;
+        tval[pos] = g;
+        atomicAdd(&s_hist[0][t & m0], 1u);
+        atomicAdd(&s_hist[1][(t >> bits0) & 255u], 1u);
+      }
+      o += tot;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 512; i += blockDim.x) {
+    const uint32_t v = (&s_hist[0][0])[i];
+    if (v) atomicAdd(hist + 4 * 256 + i, v);
+  }
+}
+
 __global__ __launch_bounds__(256) void tile_ranges(const uint32_t* __restrict__ key, const uint32_t* ctr,
                                                    uint2* __restrict__ ranges, uint32_t ntiles) {
   const uint32_t n = ctr[C_NPAIRS];
@@ -392,21 +484,27 @@ __global__ __launch_bounds__(256) void tile_ranges(const uint32_t* __restrict__ 
   }
 }
 
-// One workgroup per tile; tiles are handed to XCDs in contiguous bands
-// (workgroup i runs on XCD i % 8) so that neighbouring tiles, which share
-// Gaussians, share an L2.
+// One workgroup per 16x16 tile; each wave owns one 8x8 quadrant. Tiles are
+// handed to XCDs in contiguous bands (workgroup i runs on XCD i % 8) so that
+// neighbouring tiles, which share Gaussians, share an L2. Each batch of 256
+// Gaussians (depth order) is staged in LDS together with, per quadrant, the
+// ordered list of those whose bounding square (radius pg2.w, beyond which no
+// pixel is blended) reaches it, so a wave only visits its own Gaussians.
 template <bool FILTER, bool SAVE>
 __global__ __launch_bounds__(256) void blend(const uint2* __restrict__ ranges, const uint32_t* __restrict__ tval,
                                              const float4* __restrict__ pg0, const float4* __restrict__ pg1,
                                              const float4* __restrict__ pg2, RCam cam, int ntiles, int per_xcd,
-                                             uint32_t n_g, uint32_t n_pairs_cap,
-                                             float* __restrict__ img, float* __restrict__ Tout,
-                                             int32_t* __restrict__ Nout) {
+                                             uint32_t n_g, uint32_t n_pairs_cap, float* __restrict__ img,
+                                             float* __restrict__ Tout, int32_t* __restrict__ Nout) {
   __shared__ float4 s0[256], s1[256], s2[256];
+  __shared__ uint8_t s_list[4][256];
+  __shared__ uint32_t s_wc[4][4];
   const int tile = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
   if (tile >= ntiles) return;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
-  const int px = tx * kTileSize + (threadIdx.x & 15), py = ty * kTileSize + (threadIdx.x >> 4);
+  const int qx0 = tx * kTileSize + (w & 1) * 8, qy0 = ty * kTileSize + (w >> 1) * 8;
+  const int px = qx0 + (l & 7), py = qy0 + (l >> 3);
   const bool inside = px < cam.W && py < cam.H;
   const float fxp = px + 0.5f, fyp = py + 0.5f;
   uint2 rg = ranges[tile];
@@ -418,37 +516,70 @@ __global__ __launch_bounds__(256) void blend(const uint2* __restrict__ ranges, c
   for (uint32_t b0 = rg.x; b0 < rg.y; b0 += 256) {
     if (__syncthreads_count(done) == 256) break;
     const uint32_t idx = b0 + threadIdx.x;
+    uint32_t qm = 0;
     if (idx < rg.y) {
       uint32_t g = tval[idx];
       if (g >= n_g) g = 0;
-      s0[threadIdx.x] = pg0[g];
-      s1[threadIdx.x] = pg1[g];
-      s2[threadIdx.x] = pg2[g];
+      const float4 a = pg0[g], b = pg1[g], c = pg2[g];
+      s0[threadIdx.x] = a;
+      s1[threadIdx.x] = b;
+      s2[threadIdx.x] = c;
+      const float R = c.w;
+      const int tx0 = tx * kTileSize, ty0 = ty * kTileSize;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float xa = tx0 + (q & 1) * 8 + 0.5f, ya = ty0 + (q >> 1) * 8 + 0.5f;
+        const bool hit = (a.x + R >= xa) && (a.x - R <= xa + 7.f) && (a.y + R >= ya) && (a.y - R <= ya + 7.f);
+        qm |= hit ? (1u << q) : 0u;
+      }
+    }
+    // ordered per-quadrant lists of the batch (ascending batch index = depth order)
+    uint64_t bal[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      bal[q] = __ballot((qm >> q) & 1u);
+      if (l == 0) s_wc[q][w] = (uint32_t)__popcll(bal[q]);
     }
     __syncthreads();
-    const int cnt = (int)min(256u, rg.y - b0);
-    if (!done) {
-      for (int j = 0; j < cnt; ++j) {
-        const float4 p0 = s0[j];
-        const float4 p1 = s1[j];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if ((qm >> q) & 1u) {
+        uint32_t base = 0;
+        for (int ww = 0; ww < w; ++ww) base += s_wc[q][ww];
+        s_list[q][base + (uint32_t)__popcll(bal[q] & lanemask_lt())] = (uint8_t)threadIdx.x;
+      }
+    }
+    __syncthreads();
+    const int cnt = (int)(s_wc[w][0] + s_wc[w][1] + s_wc[w][2] + s_wc[w][3]);
+    for (int jj = 0; jj < cnt; ++jj) {
+      if (__ballot(!done) == 0ull) break;   // the whole quadrant has terminated
+      const int j = s_list[w][jj];
+      const float4 p0 = s0[j];
+      const float4 p1 = s1[j];
+      if (!done) {
         const float dx = p0.x - fxp, dy = p0.y - fyp;
-        float power = -0.5f * (p0.z * dx * dx + p1.x * dy * dy) - p0.w * dx * dy;
+        // rho = A dx^2 + B dx dy + C dy^2, clamped to <= 0
+        float power = fmaf(dx, fmaf(p0.z, dx, p0.w * dy), (p1.x * dy) * dy);
         power = fminf(power, 0.f);
-        if (FILTER && power < p1.z) continue;   // Eq. 4: log(a*) - log(theta) >= rho, no exp needed
-        const float alpha = fminf(kAlphaMax, p1.y * __expf(power));
-        if (alpha < kAlphaMin) continue;
-        const float Tn = T * (1.f - alpha);
-        if (Tn < kTMin) {
-          done = true;
-          break;
+        // Eq. 4 (filter only): log(alpha*) - log(theta) > rho means alpha < alpha*, no exp needed
+        const bool pass = !FILTER || power >= p1.z;
+        if (pass) {
+          const float alpha = fminf(kAlphaMax, p1.y * __expf(power));
+          if (alpha >= kAlphaMin) {
+            const float Tn = T * (1.f - alpha);
+            if (Tn < kTMin) {
+              done = true;
+            } else {
+              const float4 p2 = s2[j];
+              const float wgt = alpha * T;
+              cr = fmaf(wgt, p2.x, cr);
+              cg = fmaf(wgt, p2.y, cg);
+              cb = fmaf(wgt, p2.z, cb);
+              T = Tn;
+              ++ncon;
+            }
+          }
         }
-        const float4 p2 = s2[j];
-        const float wgt = alpha * T;
-        cr = fmaf(wgt, p2.x, cr);
-        cg = fmaf(wgt, p2.y, cg);
-        cb = fmaf(wgt, p2.z, cb);
-        T = Tn;
-        ++ncon;
       }
     }
     __syncthreads();
@@ -507,7 +638,7 @@ size_t vy_render_workspace_bytes(int64_t max_g, int32_t max_w, int32_t max_h, in
   if (max_g < 1 || max_w < 1 || max_h < 1 || max_pairs < 1) return 0;
   const int64_t tiles = cdiv(max_w, kTileSize) * cdiv(max_h, kTileSize);
   size_t b = 0;
-  b += (size_t)max_g * (16 * 3 + 4 * 9);  // pg0..2, rect x2, count, relax, offsets, dkey x2, dval x2
+  b += (size_t)max_g * (16 * 3 + 4 * 10);  // pg0..2, rect x2, count, relax, big, offsets, dkey x2, dval x2
   b += (size_t)max_pairs * 4 * 4;                          // tkey x2, tval x2
   b += (size_t)tiles * 8;
   b += 64 * 4 + 6 * 256 * 4;
@@ -543,6 +674,7 @@ int vy_render_ctx_create(int64_t max_g, int32_t max_w, int32_t max_h, int64_t ma
   c->prect2 = cv.take<uint32_t>(max_g);
   c->pcount = cv.take<uint32_t>(max_g);
   c->prelax = cv.take<float>(max_g);
+  c->big = cv.take<uint32_t>(max_g);
   c->offsets = cv.take<uint32_t>(max_g);
   c->dkey[0] = cv.take<uint32_t>(max_g);
   c->dkey[1] = cv.take<uint32_t>(max_g);
@@ -630,18 +762,23 @@ int vy_render(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, co
     if (filter)
       project<true><<<blocks, 256, 0, st>>>(cut_ids, (const int32_t*)n_cut, s->gauss, s->sh, rc, c->pg0, c->pg1,
                                             c->pg2, c->prect, c->prect2, c->prelax, c->pcount, c->dkey[0], c->ctr,
-                                            c->hist, s->n);
+                                            c->hist, s->n, c->big);
     else
       project<false><<<blocks, 256, 0, st>>>(cut_ids, (const int32_t*)n_cut, s->gauss, s->sh, rc, c->pg0, c->pg1,
                                              c->pg2, c->prect, c->prect2, c->prelax, c->pcount, c->dkey[0], c->ctr,
-                                             c->hist, s->n);
+                                             c->hist, s->n, c->big);
     VY_LAUNCHED();
+    if (filter) {
+      big_count<<<512, 256, 0, st>>>(c->big, c->ctr, c->pg0, c->pg1, c->prect, c->prect2, c->prelax, rc.W, rc.H,
+                                     c->pcount, gcap);
+      VY_LAUNCHED();
+    }
   }
   {
     // depth sort of all cut entries (culled ones carry key 0xFFFFFFFF and sort last)
-    ProfScope ps(VY_STAGE_DEPTH_SORT, st);
     const int blocks = imin(cdiv(c->max_g, vysort::kTile), 1024);
     for (int p = 0; p < 4; ++p) {
+      ProfScope ps(VY_STAGE_DEPTH_SORT, st);
       uint32_t ep;
       if (int rcode = epoch_for(c, st, &ep)) return rcode;
       const uint32_t* kin = c->dkey[p & 1];
@@ -664,21 +801,30 @@ int vy_render(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, co
   {
     ProfScope ps(VY_STAGE_EMIT, st);
     const int blocks = imin(cdiv(c->max_g, 256), 2048);
-    if (filter)
+    if (filter) {
       emit_pairs<true><<<blocks, 256, 0, st>>>(c->dval[0], c->offsets, c->pg0, c->pg1, c->prect, c->prect2,
                                                c->prelax, rc.W, rc.H, rc.tiles_x, bits0, c->tkey[0], c->tval[0],
                                                c->ctr, c->hist, pcap, gcap);
-    else
+      VY_LAUNCHED();
+      emit_big<true><<<512, 256, 0, st>>>(c->big, c->offsets, c->pcount, c->pg0, c->pg1, c->prect, c->prect2,
+                                          c->prelax, rc.W, rc.H, rc.tiles_x, bits0, c->tkey[0], c->tval[0], c->ctr,
+                                          c->hist, pcap, gcap);
+    } else {
       emit_pairs<false><<<blocks, 256, 0, st>>>(c->dval[0], c->offsets, c->pg0, c->pg1, c->prect, c->prect2,
                                                 c->prelax, rc.W, rc.H, rc.tiles_x, bits0, c->tkey[0], c->tval[0],
                                                 c->ctr, c->hist, pcap, gcap);
+      VY_LAUNCHED();
+      emit_big<false><<<512, 256, 0, st>>>(c->big, c->offsets, c->pcount, c->pg0, c->pg1, c->prect, c->prect2,
+                                           c->prelax, rc.W, rc.H, rc.tiles_x, bits0, c->tkey[0], c->tval[0], c->ctr,
+                                           c->hist, pcap, gcap);
+    }
     VY_LAUNCHED();
   }
   {
-    ProfScope ps(VY_STAGE_TILE_SORT, st);
     const int blocks = imin(cdiv(c->max_pairs, vysort::kTile), 1024);
     const uint32_t* np = c->ctr + C_NPAIRS;
     for (int p = 0; p < 2; ++p) {
+      ProfScope ps(VY_STAGE_TILE_SORT, st);
       uint32_t ep;
       if (int rcode = epoch_for(c, st, &ep)) return rcode;
       const int shift = p == 0 ? 0 : bits0;

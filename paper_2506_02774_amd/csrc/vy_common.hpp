@@ -73,6 +73,7 @@ struct Scene {
   // Gaussian record: {mean.xyz, log theta}, {scale.xyz, theta}, {unit quaternion w,x,y,z}
   float4* gauss;
   const float* sh;   // borrowed [n][48]
+  int levels;        // tree depth + 1 (computed at upload)
   int32_t* scratch;  // small device scratch for validate
 };
 
@@ -87,9 +88,8 @@ struct Cut {
   uint32_t* fbits;      // frontier bitmap (kept zero between calls)
   uint32_t* cbits;      // cut bitmap
   int64_t n_words;
-  int32_t* items;       // worklist slots (kept at -1 between calls)
-  uint32_t* ctr;        // device counters: [0] head [1] tail [2] pending [3] error
-                        //   [4] compaction ticket
+  int32_t* q[2];        // level queues of the top-down traversal
+  uint32_t* ctr;        // device counters: [0..2] rotating queue counts [3] error [4] compaction ticket
   uint64_t* status;     // look-back status of the compaction scan (2 per partition)
   int64_t n_parts;      // compaction partitions
   uint32_t epoch;
@@ -108,10 +108,11 @@ struct RenderCtx {
   uint32_t* prect2;
   uint32_t* pcount;     // pairs per Gaussian
   float* prelax;        // per-Gaussian rounding allowance of the tile test
+  uint32_t* big;        // cut positions of Gaussians binned by a whole workgroup
   // depth sort
   uint32_t* dkey[2];
   uint32_t* dval[2];
-  uint32_t* offsets;    // exclusive scan of counts in depth order
+  uint32_t* offsets;    // first pair of each Gaussian (by cut position)
   // pairs
   uint32_t* tkey[2];
   uint32_t* tval[2];
