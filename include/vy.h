@@ -176,6 +176,10 @@ typedef struct vy_render_opts {
   float bg[3];          /* background colour (default black) */
   int32_t save_state;   /* 1: also write the per-pixel final transmittance and
                            contributor count (needed by the backward pass) */
+  int32_t split_min_pairs; /* > 0: tiles with more pairs are blended by several
+                              workgroups over depth bins, then composited (0: no
+                              splitting). The image is bitwise the same for any
+                              value; splitting forgoes early termination. */
 } vy_render_opts;
 
 typedef struct vy_render_ctx vy_render_ctx;
@@ -211,6 +215,18 @@ int vy_render_status(vy_render_ctx* ctx, int64_t* n_pairs, int64_t* n_visible, v
  * save_state = 1), and the projected Gaussians' 2D means [n][2] (cut order). */
 int vy_render_saved(const vy_render_ctx* ctx, const float** T_final, const int32_t** n_contrib,
                     const float** mean2d);
+
+/* Device pointers to the last frame's intermediates (inspection and tests):
+ * the pairs sorted by (tile, depth, node id) as tile ids and cut positions
+ * [n_pairs], the per-tile [start, end) ranges [tiles][2], and the projected
+ * Gaussians by cut position: rec0 {mean2d.x, mean2d.y, A, B} and rec1
+ * {C, theta, rho threshold of the filter, depth} with rho = A dx^2 + B dx dy +
+ * C dy^2, rec2 {r, g, b, pixel radius}, each [max_gaussians][4], and the tile
+ * rect corners packed x | y << 16 (inclusive). Any argument may be NULL. */
+int vy_render_pairs(const vy_render_ctx* ctx, const uint32_t** tile_keys, const uint32_t** cut_pos,
+                    const uint32_t** ranges);
+int vy_render_projected(const vy_render_ctx* ctx, const float** rec0, const float** rec1, const float** rec2,
+                        const uint32_t** rect_lo, const uint32_t** rect_hi);
 
 /* ------------------------------------------------------------------------ */
 /* Stage timing (HIP events recorded around every kernel launch)            */

@@ -45,7 +45,8 @@ class vy_scene_desc(ctypes.Structure):
 
 
 class vy_render_opts(ctypes.Structure):
-    _fields_ = [("alpha_filter", ctypes.c_int32), ("bg", ctypes.c_float * 3), ("save_state", ctypes.c_int32)]
+    _fields_ = [("alpha_filter", ctypes.c_int32), ("bg", ctypes.c_float * 3), ("save_state", ctypes.c_int32),
+                ("split_min_pairs", ctypes.c_int32)]
 
 
 _lib = None
@@ -82,6 +83,8 @@ def lib():
         "vy_render": ([P, P, ctypes.POINTER(vy_camera), ctypes.POINTER(vy_render_opts), P, P, P], ctypes.c_int),
         "vy_render_status": ([P, ctypes.POINTER(I64), ctypes.POINTER(I64), P], ctypes.c_int),
         "vy_render_saved": ([P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P)], ctypes.c_int),
+        "vy_render_pairs": ([P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P)], ctypes.c_int),
+        "vy_render_projected": ([P] + [ctypes.POINTER(P)] * 5, ctypes.c_int),
         "vy_profile_begin": ([I64], ctypes.c_int),
         "vy_profile_end": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)], ctypes.c_int),
         "vy_stage_name": ([ctypes.c_int], ctypes.c_char_p),
@@ -276,6 +279,40 @@ class RenderContext:
         _copy_d2h(N, pn.value)
         return T, N
 
+    def pairs(self, width, height):
+        """Last frame's sorted pairs (tile ids, cut positions) and tile ranges (synchronises)."""
+        rc, n_pairs, n_vis = self.status()
+        check(rc, "vy_render_status")
+        pk, pv, pr = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        check(lib().vy_render_pairs(self.handle, ctypes.byref(pk), ctypes.byref(pv), ctypes.byref(pr)),
+              "vy_render_pairs")
+        ntiles = ((width + 15) // 16) * ((height + 15) // 16)
+        keys = np.empty(n_pairs, np.uint32)
+        vals = np.empty(n_pairs, np.uint32)
+        ranges = np.empty((ntiles, 2), np.uint32)
+        if n_pairs:
+            _copy_d2h(keys, pk.value)
+            _copy_d2h(vals, pv.value)
+        _copy_d2h(ranges, pr.value)
+        return keys, vals, ranges
+
+    def projected(self, n):
+        """Projected records of the first n cut positions: (rec0, rec1, rec2) [n, 4] and rects (synchronises)."""
+        ptrs = [ctypes.c_void_p() for _ in range(5)]
+        check(lib().vy_render_projected(self.handle, *[ctypes.byref(p) for p in ptrs]), "vy_render_projected")
+        out = []
+        for p in ptrs[:3]:
+            a = np.empty((n, 4), np.float32)
+            if n:
+                _copy_d2h(a, p.value)
+            out.append(a)
+        for p in ptrs[3:]:
+            a = np.empty(n, np.uint32)
+            if n:
+                _copy_d2h(a, p.value)
+            out.append(a)
+        return out
+
     def __del__(self):
         try:
             if getattr(self, "handle", None):
@@ -305,7 +342,7 @@ def vy_lod_cut(scene: Scene, cam, tau: float, prev: Cut | None = None, out: Cut 
 
 
 def vy_render(scene: Scene, cut: Cut, cam, ctx: RenderContext, image=None, alpha_filter=False,
-              bg=(0.0, 0.0, 0.0), save_state=False, stream=None):
+              bg=(0.0, 0.0, 0.0), save_state=False, split_min_pairs=0, stream=None):
     """Enqueue rendering of `cut` into `image` (torch float32 [3, H, W] on the device)."""
     import torch
     if image is None:
@@ -317,6 +354,7 @@ def vy_render(scene: Scene, cut: Cut, cam, ctx: RenderContext, image=None, alpha
     for i in range(3):
         o.bg[i] = float(bg[i])
     o.save_state = 1 if save_state else 0
+    o.split_min_pairs = int(split_min_pairs)
     c = make_camera(cam)
     check(lib().vy_render(scene.handle, cut.handle, ctypes.byref(c), ctypes.byref(o),
                           ctypes.c_void_p(image.data_ptr()), ctx.handle, _stream(stream)), "vy_render")

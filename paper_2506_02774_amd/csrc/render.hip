@@ -55,6 +55,12 @@ enum {
   C_SCAN_TICKET = 10,
   C_OVERFLOW = 11,
   C_NBIG = 12,     // Gaussians whose rect exceeds kBigArea tiles
+  C_NHEAVY = 13,   // tiles split over several jobs
+  C_NJOBS = 14,    // blend jobs of split tiles
+  C_SLOTS = 15,    // per-bin result slots handed out
+  C_JOB_TICKET = 16,
+  C_NREDO = 17,    // (heavy tile, bin) units with pixels that stop in the bin
+  C_NTIER = 18,    // 18..20: tiles in the heavy-first tiers
   C_COUNT = 32
 };
 
@@ -214,7 +220,9 @@ __global__ __launch_bounds__(256) void project(const int32_t* __restrict__ cut, 
         const float mid = 0.5f * (a + c);
         const float lmax = mid + sqrtf(fmaxf(0.f, mid * mid - det));
         const float lmin = fmaxf(det / lmax, 1e-30f);
-        float r = ceilf(kRadiusK * sqrtf(lmax));
+        // per-axis extents: the ellipse d^T Sigma2^-1 d <= K^2 (outside it alpha < 1/255)
+        // lies within |dx| <= K sqrt(Sigma2_xx), |dy| <= K sqrt(Sigma2_yy)
+        float rx = fminf(ceilf(kRadiusK * sqrtf(a)), 65535.f), ry = fminf(ceilf(kRadiusK * sqrtf(c)), 65535.f);
         const float theta = g1.w, log_theta = g0.w;
         const float thr = cam.ln_amin - log_theta - kFilterDelta;
         // relative rounding bound of rho for this conic (condition number based)
@@ -222,27 +230,28 @@ __global__ __launch_bounds__(256) void project(const int32_t* __restrict__ cut, 
         if (FILTER) {
           if (thr > 0.f) valid = false;      // theta below alpha*: never blended
           if (valid && relax < 0.25f) {
-            // beyond r_f every pixel has rho < thr (with margin for rounding)
-            const float rf2 = 2.f * (-thr) * lmax * ((1.f + relax) / (1.f - relax)) * 1.001f + 2.f;
-            const float rf = ceilf(sqrtf(rf2));
-            r = fminf(r, rf);
+            // outside the box of the ellipse rho >= thr every pixel has rho < thr
+            // (margins for the rounding of the conic and of the per-pixel rho)
+            const float f = 2.f * (-thr) * ((1.f + relax) / (1.f - relax)) * 1.001f;
+            rx = fminf(rx, ceilf(sqrtf(f * a + 2.f)));
+            ry = fminf(ry, ceilf(sqrtf(f * c + 2.f)));
           }
         }
         if (valid) {
-          int x0 = (int)floorf((mx - r) / kTileSize), x1 = (int)floorf((mx + r) / kTileSize);
-          int y0 = (int)floorf((my - r) / kTileSize), y1 = (int)floorf((my + r) / kTileSize);
+          int x0 = (int)floorf((mx - rx) / kTileSize), x1 = (int)floorf((mx + rx) / kTileSize);
+          int y0 = (int)floorf((my - ry) / kTileSize), y1 = (int)floorf((my + ry) / kTileSize);
           x0 = max(x0, 0);
           y0 = max(y0, 0);
           x1 = min(x1, cam.tiles_x - 1);
           y1 = min(y1, cam.tiles_y - 1);
-          if (x0 > x1 || y0 > y1 || !(r > 0.f)) valid = false;
+          if (x0 > x1 || y0 > y1) valid = false;
           if (valid) {
             // rho = A dx^2 + B dx dy + C dy^2 with (A, B, C) = (-a/2, -b, -c/2) of the conic
             o0 = make_float4(mx, my, -0.5f * ca, -cb);
             o1 = make_float4(-0.5f * cc, theta, thr, z);
             const float dn = 1.f / sqrtf((dxw * dxw + dyw * dyw) + dzw * dzw);
             const float3 rgb = sh_colour(sh + 48 * (int64_t)node, dxw * dn, dyw * dn, dzw * dn);
-            o2 = make_float4(rgb.x, rgb.y, rgb.z, r);
+            o2 = make_float4(rgb.x, rgb.y, rgb.z, __uint_as_float((uint32_t)rx | ((uint32_t)ry << 16)));
             r0 = (uint32_t)x0 | ((uint32_t)y0 << 16);
             r1 = (uint32_t)x1 | ((uint32_t)y1 << 16);
             const uint32_t area = (uint32_t)(x1 - x0 + 1) * (uint32_t)(y1 - y0 + 1);
@@ -484,115 +493,633 @@ __global__ __launch_bounds__(256) void tile_ranges(const uint32_t* __restrict__ 
   }
 }
 
-// One workgroup per 16x16 tile; each wave owns one 8x8 quadrant. Tiles are
-// handed to XCDs in contiguous bands (workgroup i runs on XCD i % 8) so that
-// neighbouring tiles, which share Gaussians, share an L2. Each batch of 256
-// Gaussians (depth order) is staged in LDS together with, per quadrant, the
-// ordered list of those whose bounding square (radius pg2.w, beyond which no
-// pixel is blended) reaches it, so a wave only visits its own Gaussians.
-template <bool FILTER, bool SAVE>
-__global__ __launch_bounds__(256) void blend(const uint2* __restrict__ ranges, const uint32_t* __restrict__ tval,
-                                             const float4* __restrict__ pg0, const float4* __restrict__ pg1,
-                                             const float4* __restrict__ pg2, RCam cam, int ntiles, int per_xcd,
-                                             uint32_t n_g, uint32_t n_pairs_cap, float* __restrict__ img,
-                                             float* __restrict__ Tout, int32_t* __restrict__ Nout) {
-  __shared__ float4 s0[256], s1[256], s2[256];
-  __shared__ uint8_t s_list[4][256];
-  __shared__ uint32_t s_wc[4][4];
-  const int tile = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-  if (tile >= ntiles) return;
+// ---------------------------------------------------------------- blend ----
+//
+// Front-to-back blending (Eq. 3) per pixel, over the tile's pairs in depth
+// order. Canonical arithmetic: the depth axis is cut into fixed bins (the top
+// bits of the float32 depth: sixteen bins per octave); within a bin a pixel
+// accumulates C_b = sum alpha T_b c and T_b = prod (1 - alpha) starting from
+// (0, 1), and bins are combined in order, C = C + T C_b, T = T T_b. Blending
+// stops before the first Gaussian whose blend would take the global
+// transmittance T * T_b below 1e-4. Because the bins are a property of each
+// Gaussian, this arithmetic is the same whether a tile is blended by one
+// workgroup or split over several, and the same with and without the
+// preemptive filter (whose pair lists are subsequences of the plain ones).
+//
+// When asked for, tiles with more than split_min pairs are split into jobs of
+// whole bins; each job
+// writes per-bin (C_b, T_b) per pixel and a composite pass combines them,
+// re-blending exactly the one bin in which a pixel's transmittance crosses
+// 1e-4.
+//
+// Within a job, each wave owns one 16x4 band of the tile; every batch of 256
+// Gaussians is staged in LDS with, per band, the ordered list of those whose
+// pixel box (half-extents in pg2.w, beyond which no pixel is blended) reaches
+// it.
+constexpr uint32_t kTierMin[3] = {16384, 4096, 1024};   // tiles blended first, heaviest tier first
+constexpr int kMaxBins = 256;
+constexpr uint32_t kMaxHeavy = 2048;
+constexpr uint32_t kMaxJobsPerTile = 64;
+constexpr uint32_t kMaxBinSlots = 32768;
+constexpr int kHeavyRec = 4 + (kMaxBins + 1) + kMaxBins;   // tile, nb, slot base, -, pos[nb+1], key[nb]
+
+VY_DEV uint32_t depth_bin(float z) { return __float_as_uint(z) >> 19; }
+
+// Does the Gaussian's pixel box (half-extents packed in `ext` as rx | ry << 16)
+// reach the 16x4 band of pixel centres starting at (xa, ya)?
+VY_DEV bool band_hit(float mx, float my, float ext, float xa, float ya) {
+  const uint32_t e = __float_as_uint(ext);
+  const float rx = (float)(e & 0xFFFFu), ry = (float)(e >> 16);
+  return (mx + rx >= xa) && (mx - rx <= xa + 15.f) && (my + ry >= ya) && (my - ry <= ya + 3.f);
+}
+
+// alpha of Gaussian (p0, p1) at pixel centre (fx, fy); false if it is skipped
+// (alpha < alpha*, detected by Eq. 4 before the exponential when filtering).
+template <bool FILTER>
+VY_DEV bool eval_alpha(const float4 p0, const float4 p1, float fx, float fy, float& alpha) {
+  const float dx = p0.x - fx, dy = p0.y - fy;
+  float power = fmaf(dx, fmaf(p0.z, dx, p0.w * dy), (p1.x * dy) * dy);
+  power = fminf(power, 0.f);
+  if (FILTER && power < p1.z) return false;   // log(alpha*) - log(theta) > rho
+  alpha = fminf(kAlphaMax, p1.y * __expf(power));
+  return alpha >= kAlphaMin;
+}
+
+// LDS staging of pairs [b0, min(b0 + 256, pe)) of a tile: records in s0..s2,
+// depth-bin keys in s_key, and per band the ordered list of the batch entries
+// whose pixel box reaches it. Returns this wave's list length.
+struct Stage {
+  float4 s0[256], s1[256], s2[256];
+  uint32_t list[4][256];   // (depth bin << 8) | batch index, in depth order
+  uint32_t wc[4][4];
+};
+
+VY_DEV int stage_batch(Stage& S, uint32_t b0, uint32_t pe, const uint32_t* __restrict__ tval,
+                       const float4* __restrict__ pg0, const float4* __restrict__ pg1,
+                       const float4* __restrict__ pg2, uint32_t n_g, int tx, int ty) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
-  const int qx0 = tx * kTileSize + (w & 1) * 8, qy0 = ty * kTileSize + (w >> 1) * 8;
-  const int px = qx0 + (l & 7), py = qy0 + (l >> 3);
-  const bool inside = px < cam.W && py < cam.H;
-  const float fxp = px + 0.5f, fyp = py + 0.5f;
-  uint2 rg = ranges[tile];
-  if (rg.y > n_pairs_cap) rg.y = n_pairs_cap;
-  if (rg.x > rg.y) rg.x = rg.y;
-  float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f;
-  int32_t ncon = 0;
-  bool done = !inside;
-  for (uint32_t b0 = rg.x; b0 < rg.y; b0 += 256) {
-    if (__syncthreads_count(done) == 256) break;
-    const uint32_t idx = b0 + threadIdx.x;
-    uint32_t qm = 0;
-    if (idx < rg.y) {
-      uint32_t g = tval[idx];
-      if (g >= n_g) g = 0;
-      const float4 a = pg0[g], b = pg1[g], c = pg2[g];
-      s0[threadIdx.x] = a;
-      s1[threadIdx.x] = b;
-      s2[threadIdx.x] = c;
-      const float R = c.w;
-      const int tx0 = tx * kTileSize, ty0 = ty * kTileSize;
+  const uint32_t idx = b0 + threadIdx.x;
+  uint32_t qm = 0, key = 0;
+  if (idx < pe) {
+    uint32_t g = tval[idx];
+    if (g >= n_g) g = 0;
+    const float4 a = pg0[g], b = pg1[g], c = pg2[g];
+    S.s0[threadIdx.x] = a;
+    S.s1[threadIdx.x] = b;
+    S.s2[threadIdx.x] = c;
+    key = depth_bin(b.w);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float xa = tx0 + (q & 1) * 8 + 0.5f, ya = ty0 + (q >> 1) * 8 + 0.5f;
-        const bool hit = (a.x + R >= xa) && (a.x - R <= xa + 7.f) && (a.y + R >= ya) && (a.y - R <= ya + 7.f);
-        qm |= hit ? (1u << q) : 0u;
+    for (int q = 0; q < 4; ++q)
+      qm |= band_hit(a.x, a.y, c.w, tx * kTileSize + 0.5f, ty * kTileSize + q * 4 + 0.5f) ? (1u << q) : 0u;
+  }
+  uint64_t bal[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    bal[q] = __ballot((qm >> q) & 1u);
+    if (l == 0) S.wc[q][w] = (uint32_t)__popcll(bal[q]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if ((qm >> q) & 1u) {
+      uint32_t base = 0;
+      for (int ww = 0; ww < w; ++ww) base += S.wc[q][ww];
+      S.list[q][base + (uint32_t)__popcll(bal[q] & lanemask_lt())] = (key << 8) | threadIdx.x;
+    }
+  }
+  __syncthreads();
+  return (int)(S.wc[w][0] + S.wc[w][1] + S.wc[w][2] + S.wc[w][3]);
+}
+
+// Tile planning. Tiles with more than split_min pairs are split into jobs
+// (tile_flag = heavy index + 2); other tiles with many pairs are queued in
+// three tiers by size (tile_flag = 1) and blended first, heaviest tier first,
+// so that the longest tiles start at once; the rest (tile_flag = 0) follow in
+// tile order.
+__global__ __launch_bounds__(256) void plan_tiles(const uint2* __restrict__ ranges, int ntiles,
+                                                  uint32_t* __restrict__ tile_flag, uint32_t* __restrict__ heavy_list,
+                                                  uint32_t* __restrict__ tiers, uint32_t* ctr, uint32_t split_min) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += gridDim.x * blockDim.x) {
+    const uint2 r = ranges[t];
+    const uint32_t len = r.y > r.x ? r.y - r.x : 0u;
+    uint32_t f = 0;
+    if (len > split_min) {
+      const uint32_t h = fetch_add(ctr + C_NHEAVY, 1u);
+      if (h < kMaxHeavy) {
+        heavy_list[h] = (uint32_t)t;
+        f = h + 2;
       }
     }
-    // ordered per-quadrant lists of the batch (ascending batch index = depth order)
-    uint64_t bal[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      bal[q] = __ballot((qm >> q) & 1u);
-      if (l == 0) s_wc[q][w] = (uint32_t)__popcll(bal[q]);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if ((qm >> q) & 1u) {
-        uint32_t base = 0;
-        for (int ww = 0; ww < w; ++ww) base += s_wc[q][ww];
-        s_list[q][base + (uint32_t)__popcll(bal[q] & lanemask_lt())] = (uint8_t)threadIdx.x;
-      }
-    }
-    __syncthreads();
-    const int cnt = (int)(s_wc[w][0] + s_wc[w][1] + s_wc[w][2] + s_wc[w][3]);
-    for (int jj = 0; jj < cnt; ++jj) {
-      if (__ballot(!done) == 0ull) break;   // the whole quadrant has terminated
-      const int j = s_list[w][jj];
-      const float4 p0 = s0[j];
-      const float4 p1 = s1[j];
-      if (!done) {
-        const float dx = p0.x - fxp, dy = p0.y - fyp;
-        // rho = A dx^2 + B dx dy + C dy^2, clamped to <= 0
-        float power = fmaf(dx, fmaf(p0.z, dx, p0.w * dy), (p1.x * dy) * dy);
-        power = fminf(power, 0.f);
-        // Eq. 4 (filter only): log(alpha*) - log(theta) > rho means alpha < alpha*, no exp needed
-        const bool pass = !FILTER || power >= p1.z;
-        if (pass) {
-          const float alpha = fminf(kAlphaMax, p1.y * __expf(power));
-          if (alpha >= kAlphaMin) {
-            const float Tn = T * (1.f - alpha);
-            if (Tn < kTMin) {
-              done = true;
-            } else {
-              const float4 p2 = s2[j];
-              const float wgt = alpha * T;
-              cr = fmaf(wgt, p2.x, cr);
-              cg = fmaf(wgt, p2.y, cg);
-              cb = fmaf(wgt, p2.z, cb);
-              T = Tn;
-              ++ncon;
-            }
-          }
+    if (f == 0) {
+      for (int k = 0; k < 3; ++k)
+        if (len > kTierMin[k]) {
+          tiers[(size_t)k * ntiles + fetch_add(ctr + C_NTIER + k, 1u)] = (uint32_t)t;
+          f = 1;
+          break;
         }
+    }
+    tile_flag[t] = f;
+  }
+}
+
+// One workgroup per heavy tile: find its depth-bin boundaries (in order, by a
+// block scan over the tile's pairs) and cut it into jobs of whole bins of
+// about len/48 pairs (at least split_min/2) each.
+__global__ __launch_bounds__(256) void plan_heavy(const uint2* __restrict__ ranges,
+                                                  const uint32_t* __restrict__ tval,
+                                                  const float4* __restrict__ pg1,
+                                                  const uint32_t* __restrict__ heavy_list,
+                                                  uint32_t* __restrict__ tile_flag, uint32_t* __restrict__ heavy_rec,
+                                                  uint4* __restrict__ jobs, uint32_t* __restrict__ slot_owner,
+                                                  uint32_t* ctr, uint32_t n_g, uint32_t split_min) {
+  __shared__ uint32_t s_pos[kMaxBins + 1], s_key[kMaxBins], s_scan[8], s_base, s_ok;
+  uint32_t nh = ctr[C_NHEAVY];
+  if (nh > kMaxHeavy) nh = kMaxHeavy;
+  for (uint32_t h = blockIdx.x; h < nh; h += gridDim.x) {
+    const uint32_t tile = heavy_list[h];
+    const uint2 r = ranges[tile];
+    uint32_t nb = 0;   // uniform
+    for (uint32_t c0 = r.x; c0 < r.y; c0 += blockDim.x) {
+      const uint32_t i = c0 + threadIdx.x;
+      uint32_t k = 0, kp = 0;
+      bool bnd = false;
+      if (i < r.y) {
+        const uint32_t g = tval[i];
+        k = g < n_g ? depth_bin(pg1[g].w) : 0u;
+        if (i == r.x) {
+          bnd = true;
+        } else {
+          const uint32_t gp = tval[i - 1];
+          kp = gp < n_g ? depth_bin(pg1[gp].w) : 0u;
+          bnd = k != kp;
+        }
+      }
+      uint32_t tot;
+      const uint32_t o = nb + block_excl_scan256(bnd ? 1u : 0u, s_scan, &tot);
+      if (bnd && o < (uint32_t)kMaxBins) {
+        s_pos[o] = i;
+        s_key[o] = k;
+      }
+      nb += tot;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t ok = nb <= (uint32_t)kMaxBins ? 1u : 0u;
+      if (ok) {
+        s_pos[nb] = r.y;
+        const uint32_t base = fetch_add(ctr + C_SLOTS, nb);
+        if (base + nb > kMaxBinSlots) ok = 0;
+        s_base = base;
+      }
+      s_ok = ok;
+    }
+    __syncthreads();
+    uint32_t* rec = heavy_rec + (size_t)h * kHeavyRec;
+    if (s_ok) {
+      for (uint32_t a = threadIdx.x; a <= nb; a += blockDim.x) rec[4 + a] = s_pos[a];
+      for (uint32_t a = threadIdx.x; a < nb; a += blockDim.x) {
+        rec[4 + kMaxBins + 1 + a] = s_key[a];
+        slot_owner[s_base + a] = h;
+      }
+      if (threadIdx.x == 0) {
+        rec[0] = tile;
+        rec[1] = nb;
+        rec[2] = s_base;
+        const uint32_t len = r.y - r.x;
+        uint32_t ch = len / 48;
+        if (ch < split_min / 2) ch = split_min / 2;
+        uint32_t j0 = 0, nj = 0;
+        while (j0 < nb) {
+          uint32_t j1 = j0 + 1;
+          while (j1 < nb && (s_pos[j1] - s_pos[j0] < ch || nj + 1 >= kMaxJobsPerTile)) ++j1;
+          const uint32_t jid = fetch_add(ctr + C_NJOBS, 1u);
+          if (jid < kMaxHeavy * kMaxJobsPerTile) jobs[jid] = make_uint4(h, j0, j1, 0u);
+          ++nj;
+          j0 = j1;
+        }
+      }
+    } else if (threadIdx.x == 0) {
+      tile_flag[tile] = 0;   // blend it in one piece (with the other tiles)
+    }
+    __syncthreads();
+  }
+}
+
+// Per-pixel blending state of one job.
+struct PixAcc {
+  float Tt, C0, C1, C2;     // combined over finished bins (one-piece mode)
+  float Tb, Cb0, Cb1, Cb2;  // current bin
+  int32_t nt, nb;
+  bool done;
+  uint32_t cur_key;         // depth bin of the current bin (0xFFFFFFFF before the first)
+  uint32_t lb;              // local index of the current bin (split mode)
+};
+
+struct SplitOut {           // where split-mode jobs write their per-bin results
+  float4* bin_c;
+  int32_t* bin_n;
+  const uint32_t* bkey;     // keys of the job's bins (LDS), bkey[lb - lbin0]
+  uint32_t slot_base, lbin0, lbin1;
+  int pix;
+};
+
+VY_DEV void put_bin(const SplitOut& o, uint32_t lb, float4 v, int32_t n) {
+  const size_t k = ((size_t)(o.slot_base + lb)) * 256 + o.pix;
+  o.bin_c[k] = v;
+  o.bin_n[k] = n;
+}
+
+// Blend pairs [pb, pe) of tile (tx, ty) into A. SPLIT: per-bin results go to
+// `so` and a pixel stops only when its own bin's T falls below 1e-4 (marking
+// the bin with T = 0 for the composite); otherwise bins are combined in place
+// and a pixel stops before the Gaussian that would take Tt * T_b below 1e-4.
+// A pixel enters depth bin `key`: close its current bin (combine it in place,
+// or write it out in split mode, together with any bins it skipped).
+template <bool SPLIT>
+VY_DEV void bin_enter(PixAcc& A, uint32_t key, const SplitOut& so) {
+  if (SPLIT) {
+    if (A.cur_key != 0xFFFFFFFFu) {
+      put_bin(so, A.lb, make_float4(A.Cb0, A.Cb1, A.Cb2, A.Tb), A.nb);
+      ++A.lb;
+    }
+    while (A.lb < so.lbin1 && so.bkey[A.lb - so.lbin0] != key) {   // bins with nothing for this pixel
+      put_bin(so, A.lb, make_float4(0.f, 0.f, 0.f, 1.f), 0);
+      ++A.lb;
+    }
+  } else {
+    A.C0 = fmaf(A.Tt, A.Cb0, A.C0);
+    A.C1 = fmaf(A.Tt, A.Cb1, A.C1);
+    A.C2 = fmaf(A.Tt, A.Cb2, A.C2);
+    A.Tt = A.Tt * A.Tb;
+    A.nt += A.nb;
+  }
+  A.Tb = 1.f;
+  A.Cb0 = A.Cb1 = A.Cb2 = 0.f;
+  A.nb = 0;
+}
+
+// One Gaussian of the band list for every pixel of the wave (slow path of
+// blend_range, used around depth-bin boundaries): alpha = min(0.99, theta e^rho)
+// (Eq. 3), skipped below alpha* (with the filter, decided before the
+// exponential by Eq. 4); blending stops before a Gaussian that would take the
+// transmittance (Tt * T_b, or T_b alone in split mode) below 1e-4.
+template <bool FILTER, bool SPLIT>
+VY_DEV void blend_one(uint32_t key, const float4 p0, const float4 p1, const float4 p2, float fxp, float fyp,
+                      PixAcc& A, const SplitOut& so) {
+  if (key != A.cur_key) {                 // a new depth bin begins (wave-uniform)
+    if (!A.done) bin_enter<SPLIT>(A, key, so);   // a finished pixel keeps its state frozen
+    A.cur_key = key;
+  }
+  const float dx = p0.x - fxp, dy = p0.y - fyp;
+  // rho = A dx^2 + B dx dy + C dy^2, clamped to <= 0
+  float power = fmaf(dx, fmaf(p0.z, dx, p0.w * dy), (p1.x * dy) * dy);
+  power = fminf(power, 0.f);
+  bool live = !A.done;
+  if (FILTER) live = live && power >= p1.z;   // Eq. 4: rho < log(alpha*) - log(theta) => skip
+  if (__ballot(live) == 0ull) return;        // the exponential is needed by no pixel of the band
+  const float alpha = fminf(kAlphaMax, p1.y * __expf(power));
+  const bool ok = live && alpha >= kAlphaMin;
+  const float Tn = A.Tb * (1.f - alpha);
+  const bool stop = ok && (SPLIT ? (Tn < kTMin) : (A.Tt * Tn < kTMin));
+  const bool bl = ok && !stop;
+  const float wgt = bl ? alpha * A.Tb : 0.f;
+  A.Cb0 = fmaf(wgt, p2.x, A.Cb0);
+  A.Cb1 = fmaf(wgt, p2.y, A.Cb1);
+  A.Cb2 = fmaf(wgt, p2.z, A.Cb2);
+  A.Tb = bl ? Tn : ((SPLIT && stop) ? 0.f : A.Tb);
+  A.nb += bl ? 1 : 0;
+  A.done = A.done || stop;
+}
+
+// Blend pairs [pb, pe) of tile (tx, ty) into A. SPLIT: per-bin results go to
+// `so` and a pixel stops only when its own bin's T falls below 1e-4 (marking
+// the bin with T = 0 for the composite); otherwise bins are combined in place.
+// The band list is walked four entries at a time: all LDS loads are issued
+// first, and when the four share the current depth bin their alphas are
+// computed independently before the sequential transmittance chain, which
+// keeps the per-Gaussian latency low on the tiles with the longest lists.
+template <bool FILTER, bool SPLIT>
+VY_DEV void blend_range(Stage& S, uint32_t pb, uint32_t pe, const uint32_t* __restrict__ tval,
+                        const float4* __restrict__ pg0, const float4* __restrict__ pg1,
+                        const float4* __restrict__ pg2, uint32_t n_g, int tx, int ty, float fxp, float fyp,
+                        PixAcc& A, const SplitOut& so) {
+  const int w = threadIdx.x >> 6;
+  for (uint32_t b0 = pb; b0 < pe; b0 += 256) {
+    if (__syncthreads_count(A.done) == 256) break;
+    const int cnt = stage_batch(S, b0, pe, tval, pg0, pg1, pg2, n_g, tx, ty);
+    for (int jj = 0; jj < cnt; jj += 4) {
+      if (__ballot(!A.done) == 0ull) break;   // the whole band has terminated
+      const uint4 e4 = *reinterpret_cast<const uint4*>(&S.list[w][jj]);
+      const int m = cnt - jj < 4 ? cnt - jj : 4;
+      const uint32_t e[4] = {(uint32_t)__builtin_amdgcn_readfirstlane(e4.x),
+                             (uint32_t)__builtin_amdgcn_readfirstlane(e4.y),
+                             (uint32_t)__builtin_amdgcn_readfirstlane(e4.z),
+                             (uint32_t)__builtin_amdgcn_readfirstlane(e4.w)};
+      float4 q0[4], q1[4], q2[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t j = (k < m ? e[k] : e[0]) & 255u;
+        q0[k] = S.s0[j];
+        q1[k] = S.s1[j];
+        q2[k] = S.s2[j];
+      }
+      const uint32_t key = e[0] >> 8;
+      if (m == 4 && key == A.cur_key && (e[1] >> 8) == key && (e[2] >> 8) == key && (e[3] >> 8) == key) {
+        // fast path, one depth bin: rho and the alphas are independent of each
+        // other; only the transmittance chain below is sequential
+        float pw[4];
+        bool lv[4];
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const float dx = q0[k].x - fxp, dy = q0[k].y - fyp;
+          pw[k] = fminf(fmaf(dx, fmaf(q0[k].z, dx, q0[k].w * dy), (q1[k].x * dy) * dy), 0.f);
+          lv[k] = !A.done;
+          if (FILTER) lv[k] = lv[k] && pw[k] >= q1[k].z;   // Eq. 4 before the exponential
+          any = any || lv[k];
+        }
+        if (__ballot(any) == 0ull) continue;   // no pixel of the band needs these four
+        float al[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) al[k] = fminf(kAlphaMax, q1[k].y * __expf(pw[k]));
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const bool okk = lv[k] && al[k] >= kAlphaMin && !A.done;
+          const float Tn = A.Tb * (1.f - al[k]);
+          const bool stop = okk && (SPLIT ? (Tn < kTMin) : (A.Tt * Tn < kTMin));
+          const bool bl = okk && !stop;
+          const float wgt = bl ? al[k] * A.Tb : 0.f;
+          A.Cb0 = fmaf(wgt, q2[k].x, A.Cb0);
+          A.Cb1 = fmaf(wgt, q2[k].y, A.Cb1);
+          A.Cb2 = fmaf(wgt, q2[k].z, A.Cb2);
+          A.Tb = bl ? Tn : ((SPLIT && stop) ? 0.f : A.Tb);
+          A.nb += bl ? 1 : 0;
+          A.done = A.done || stop;
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (k < m) blend_one<FILTER, SPLIT>(e[k] >> 8, q0[k], q1[k], q2[k], fxp, fyp, A, so);
       }
     }
     __syncthreads();
   }
-  if (inside) {
-    const size_t hw = (size_t)cam.W * cam.H, o = (size_t)py * cam.W + px;
-    img[o] = fmaf(T, cam.bg[0], cr);
-    img[hw + o] = fmaf(T, cam.bg[1], cg);
-    img[2 * hw + o] = fmaf(T, cam.bg[2], cb);
-    if (SAVE) {
-      Tout[o] = T;
-      Nout[o] = ncon;
+}
+
+template <bool FILTER, bool SAVE>
+__global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ ranges, const uint32_t* __restrict__ tval,
+                                                  const float4* __restrict__ pg0, const float4* __restrict__ pg1,
+                                                  const float4* __restrict__ pg2, RCam cam, int ntiles,
+                                                  const uint32_t* __restrict__ tile_flag,
+                                                  const uint32_t* __restrict__ tiers,
+                                                  const uint32_t* __restrict__ heavy_rec,
+                                                  const uint4* __restrict__ jobs, float4* __restrict__ bin_c,
+                                                  int32_t* __restrict__ bin_n, uint32_t* ctr, uint32_t n_g,
+                                                  uint32_t n_pairs_cap, float* __restrict__ img,
+                                                  float* __restrict__ Tout, int32_t* __restrict__ Nout) {
+  __shared__ Stage S;
+  __shared__ uint32_t s_job;
+  __shared__ uint32_t s_bkey[kMaxBins];
+  uint32_t njobs = ctr[C_NJOBS];
+  if (njobs > kMaxHeavy * kMaxJobsPerTile) njobs = kMaxHeavy * kMaxJobsPerTile;
+  const uint32_t n0 = ctr[C_NTIER], n1 = ctr[C_NTIER + 1], n2 = ctr[C_NTIER + 2];
+  const uint32_t nfirst = njobs + n0 + n1 + n2;
+  const uint32_t total = nfirst + (uint32_t)ntiles;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  for (;;) {
+    if (threadIdx.x == 0) s_job = fetch_add(ctr + C_JOB_TICKET, 1u);
+    __syncthreads();
+    const uint32_t J = s_job;
+    if (J >= total) break;
+    const bool split = J < njobs;
+    uint32_t tile, pb, pe;
+    SplitOut so;
+    so.bin_c = bin_c;
+    so.bin_n = bin_n;
+    so.bkey = s_bkey;
+    so.slot_base = so.lbin0 = so.lbin1 = 0;
+    if (split) {
+      const uint4 jb = jobs[J];
+      const uint32_t* rec = heavy_rec + (size_t)jb.x * kHeavyRec;
+      tile = rec[0];
+      so.slot_base = rec[2];
+      so.lbin0 = jb.y;
+      so.lbin1 = jb.z;
+      pb = rec[4 + so.lbin0];
+      pe = rec[4 + so.lbin1];
+      for (uint32_t k = threadIdx.x; k < so.lbin1 - so.lbin0; k += blockDim.x)
+        s_bkey[k] = rec[4 + kMaxBins + 1 + so.lbin0 + k];
+    } else {
+      if (J < nfirst) {             // heavy-first tiers
+        uint32_t k = J - njobs;
+        const uint32_t* tl = tiers;
+        if (k >= n0) { k -= n0; tl += ntiles; if (k >= n1) { k -= n1; tl += ntiles; } }
+        tile = tl[k];
+      } else {
+        tile = J - nfirst;
+        if (tile_flag[tile] != 0) {   // split, or already blended as a heavy-first tile
+          __syncthreads();
+          continue;
+        }
+      }
+      const uint2 rg = ranges[tile];
+      pb = rg.x;
+      pe = rg.y;
     }
+    if (pe > n_pairs_cap) pe = n_pairs_cap;
+    if (pb > pe) pb = pe;
+    const int tx = (int)tile % cam.tiles_x, ty = (int)tile / cam.tiles_x;
+    const int px = tx * kTileSize + (l & 15), py = ty * kTileSize + w * 4 + (l >> 4);
+    const bool inside = px < cam.W && py < cam.H;
+    so.pix = (w * 4 + (l >> 4)) * kTileSize + (l & 15);   // row-major in the tile
+    PixAcc A;
+    A.Tt = 1.f;
+    A.C0 = A.C1 = A.C2 = 0.f;
+    A.Tb = 1.f;
+    A.Cb0 = A.Cb1 = A.Cb2 = 0.f;
+    A.nt = A.nb = 0;
+    A.done = !inside;
+    A.cur_key = 0xFFFFFFFFu;
+    A.lb = so.lbin0;
+    const float fxp = px + 0.5f, fyp = py + 0.5f;
+    // tiles on the critical path (split jobs and the heavy-first tiers) get the
+    // highest wave issue priority while they are blended
+    const bool urgent = J < nfirst;
+    if (urgent) __builtin_amdgcn_s_setprio(3);
+    if (split) {
+      blend_range<FILTER, true>(S, pb, pe, tval, pg0, pg1, pg2, n_g, tx, ty, fxp, fyp, A, so);
+      // the current bin, then bins without Gaussians for this band up to the job's end
+      if (A.cur_key != 0xFFFFFFFFu && A.lb < so.lbin1) {
+        put_bin(so, A.lb, make_float4(A.Cb0, A.Cb1, A.Cb2, A.Tb), A.nb);
+        ++A.lb;
+      }
+      for (; A.lb < so.lbin1; ++A.lb) put_bin(so, A.lb, make_float4(0.f, 0.f, 0.f, 1.f), 0);
+    } else {
+      blend_range<FILTER, false>(S, pb, pe, tval, pg0, pg1, pg2, n_g, tx, ty, fxp, fyp, A, so);
+      if (inside) {
+        A.C0 = fmaf(A.Tt, A.Cb0, A.C0);
+        A.C1 = fmaf(A.Tt, A.Cb1, A.C1);
+        A.C2 = fmaf(A.Tt, A.Cb2, A.C2);
+        A.Tt = A.Tt * A.Tb;
+        A.nt += A.nb;
+        const size_t hw = (size_t)cam.W * cam.H, o = (size_t)py * cam.W + px;
+        img[o] = fmaf(A.Tt, cam.bg[0], A.C0);
+        img[hw + o] = fmaf(A.Tt, cam.bg[1], A.C1);
+        img[2 * hw + o] = fmaf(A.Tt, cam.bg[2], A.C2);
+        if (SAVE) {
+          Tout[o] = A.Tt;
+          Nout[o] = A.nt;
+        }
+      }
+    }
+    if (urgent) __builtin_amdgcn_s_setprio(0);
+    __syncthreads();
+  }
+}
+
+// Composite of split tiles, step 1 (one workgroup per heavy tile, one thread
+// per pixel): combine the per-bin results in depth order up to the bin in
+// which the pixel's blending stops. Pixels that never stop are written here;
+// the others record (stop bin, C, T, n) for step 2, and every bin in which
+// some pixel stops becomes a redo unit.
+struct PixState {
+  float4 c;       // C.rgb and T before the stop bin
+  int32_t n;
+  uint32_t stop;  // stop bin, 0xFFFFFFFF when blending never stops
+};
+
+template <bool SAVE>
+__global__ __launch_bounds__(256) void composite_scan(RCam cam, const uint32_t* __restrict__ tile_flag,
+                                                      const uint32_t* __restrict__ heavy_rec,
+                                                      const float4* __restrict__ bin_c,
+                                                      const int32_t* __restrict__ bin_n, uint32_t* ctr,
+                                                      PixState* __restrict__ pstate, uint2* __restrict__ redo,
+                                                      float* __restrict__ img, float* __restrict__ Tout,
+                                                      int32_t* __restrict__ Nout) {
+  __shared__ uint32_t s_stop[kMaxBins / 32];
+  uint32_t nh = ctr[C_NHEAVY];
+  if (nh > kMaxHeavy) nh = kMaxHeavy;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  for (uint32_t h = blockIdx.x; h < nh; h += gridDim.x) {
+    const uint32_t* rec = heavy_rec + (size_t)h * kHeavyRec;
+    const uint32_t tile = rec[0];
+    if (tile_flag[tile] != h + 2) continue;   // blended in one piece (uniform)
+    const uint32_t nbins = rec[1], slot_base = rec[2];
+    if (threadIdx.x < kMaxBins / 32) s_stop[threadIdx.x] = 0;
+    __syncthreads();
+    const int tx = (int)tile % cam.tiles_x, ty = (int)tile / cam.tiles_x;
+    const int px = tx * kTileSize + (l & 15), py = ty * kTileSize + w * 4 + (l >> 4);
+    const bool inside = px < cam.W && py < cam.H;
+    const int pix = (w * 4 + (l >> 4)) * kTileSize + (l & 15);
+    float Tt = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+    int32_t nt = 0;
+    uint32_t stop = 0xFFFFFFFFu;
+    if (inside) {
+      for (uint32_t b = 0; b < nbins; ++b) {
+        const size_t o = ((size_t)(slot_base + b)) * 256 + pix;
+        const float4 r = bin_c[o];
+        const int32_t nn = bin_n[o];
+        if (Tt * r.w < kTMin) {
+          stop = b;
+          break;
+        }
+        C0 = fmaf(Tt, r.x, C0);
+        C1 = fmaf(Tt, r.y, C1);
+        C2 = fmaf(Tt, r.z, C2);
+        Tt = Tt * r.w;
+        nt += nn;
+      }
+      if (stop == 0xFFFFFFFFu) {
+        const size_t hw = (size_t)cam.W * cam.H, o = (size_t)py * cam.W + px;
+        img[o] = fmaf(Tt, cam.bg[0], C0);
+        img[hw + o] = fmaf(Tt, cam.bg[1], C1);
+        img[2 * hw + o] = fmaf(Tt, cam.bg[2], C2);
+        if (SAVE) {
+          Tout[o] = Tt;
+          Nout[o] = nt;
+        }
+      } else {
+        atomicOr(&s_stop[stop >> 5], 1u << (stop & 31));
+      }
+    }
+    PixState ps;
+    ps.c = make_float4(C0, C1, C2, Tt);
+    ps.n = nt;
+    ps.stop = stop;
+    pstate[(size_t)h * 256 + pix] = ps;
+    __syncthreads();
+    if (threadIdx.x < kMaxBins / 32) {
+      uint32_t m = s_stop[threadIdx.x];
+      while (m) {
+        const uint32_t bb = threadIdx.x * 32 + (uint32_t)(__ffs(m) - 1);
+        m &= m - 1;
+        const uint32_t u = fetch_add(ctr + C_NREDO, 1u);
+        if (u < kMaxBinSlots) redo[u] = make_uint2(h, bb);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Composite step 2, one workgroup per redo unit (heavy tile h, bin b): the
+// pixels whose blending stops in bin b re-blend it from LDS-staged batches
+// with their true transmittance and are written.
+template <bool FILTER, bool SAVE>
+__global__ __launch_bounds__(256) void composite_redo(const uint32_t* __restrict__ tval,
+                                                      const float4* __restrict__ pg0, const float4* __restrict__ pg1,
+                                                      const float4* __restrict__ pg2, RCam cam,
+                                                      const uint32_t* __restrict__ heavy_rec,
+                                                      const PixState* __restrict__ pstate,
+                                                      const uint2* __restrict__ redo, const uint32_t* ctr,
+                                                      uint32_t n_g, uint32_t n_pairs_cap, float* __restrict__ img,
+                                                      float* __restrict__ Tout, int32_t* __restrict__ Nout) {
+  __shared__ Stage S;
+  uint32_t nu = ctr[C_NREDO];
+  if (nu > kMaxBinSlots) nu = kMaxBinSlots;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  SplitOut so{};
+  for (uint32_t u = blockIdx.x; u < nu; u += gridDim.x) {
+    const uint2 unit = redo[u];
+    const uint32_t h = unit.x, b = unit.y;
+    const uint32_t* rec = heavy_rec + (size_t)h * kHeavyRec;
+    const uint32_t tile = rec[0];
+    const int tx = (int)tile % cam.tiles_x, ty = (int)tile / cam.tiles_x;
+    const int px = tx * kTileSize + (l & 15), py = ty * kTileSize + w * 4 + (l >> 4);
+    const int pix = (w * 4 + (l >> 4)) * kTileSize + (l & 15);
+    const PixState ps = pstate[(size_t)h * 256 + pix];
+    const bool mine = ps.stop == b && px < cam.W && py < cam.H;
+    PixAcc A;
+    A.Tt = ps.c.w;
+    A.C0 = ps.c.x;
+    A.C1 = ps.c.y;
+    A.C2 = ps.c.z;
+    A.nt = ps.n;
+    A.Tb = 1.f;
+    A.Cb0 = A.Cb1 = A.Cb2 = 0.f;
+    A.nb = 0;
+    A.done = !mine;
+    A.cur_key = rec[4 + kMaxBins + 1 + b];   // every pair of the bin has this key: no bin change
+    A.lb = 0;
+    uint32_t pb = rec[4 + b], pe = rec[4 + b + 1];
+    if (pe > n_pairs_cap) pe = n_pairs_cap;
+    if (pb > pe) pb = pe;
+    blend_range<FILTER, false>(S, pb, pe, tval, pg0, pg1, pg2, n_g, tx, ty, px + 0.5f, py + 0.5f, A, so);
+    if (mine) {
+      A.C0 = fmaf(A.Tt, A.Cb0, A.C0);
+      A.C1 = fmaf(A.Tt, A.Cb1, A.C1);
+      A.C2 = fmaf(A.Tt, A.Cb2, A.C2);
+      A.Tt = A.Tt * A.Tb;
+      A.nt += A.nb;
+      const size_t hw = (size_t)cam.W * cam.H, o = (size_t)py * cam.W + px;
+      img[o] = fmaf(A.Tt, cam.bg[0], A.C0);
+      img[hw + o] = fmaf(A.Tt, cam.bg[1], A.C1);
+      img[2 * hw + o] = fmaf(A.Tt, cam.bg[2], A.C2);
+      if (SAVE) {
+        Tout[o] = A.Tt;
+        Nout[o] = A.nt;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -644,6 +1171,9 @@ size_t vy_render_workspace_bytes(int64_t max_g, int32_t max_w, int32_t max_h, in
   b += 64 * 4 + 6 * 256 * 4;
   b += (size_t)status_words_for(max_g, max_pairs) * 8;
   b += (size_t)max_w * max_h * 8;                          // saved T, n_contrib
+  b += (size_t)tiles * 16 + kMaxHeavy * 4 + (size_t)kMaxHeavy * kHeavyRec * 4 + (size_t)kMaxHeavy * kMaxJobsPerTile * 16;
+  b += (size_t)kMaxBinSlots * (256 * 20 + 4 + 8);          // per-bin results of split tiles, slot owners, redo units
+  b += (size_t)kMaxHeavy * 256 * sizeof(PixState);
   b += 32 * 256;
   return b;
 }
@@ -690,6 +1220,16 @@ int vy_render_ctx_create(int64_t max_g, int32_t max_w, int32_t max_h, int64_t ma
   c->status_words = status_words_for(max_g, max_pairs);
   c->status = cv.take<uint64_t>(c->status_words);
   c->T_final = cv.take<float>((size_t)max_w * max_h);
+  c->tile_flag = cv.take<uint32_t>(c->max_tiles);
+  c->tiers = cv.take<uint32_t>(3 * c->max_tiles);
+  c->heavy_list = cv.take<uint32_t>(kMaxHeavy);
+  c->heavy_rec = cv.take<uint32_t>((size_t)kMaxHeavy * kHeavyRec);
+  c->jobs = cv.take<uint4>((size_t)kMaxHeavy * kMaxJobsPerTile);
+  c->slot_owner = cv.take<uint32_t>(kMaxBinSlots);
+  c->pstate_raw = cv.take<PixState>((size_t)kMaxHeavy * 256);
+  c->redo = cv.take<uint2>(kMaxBinSlots);
+  c->bin_c = cv.take<float4>((size_t)kMaxBinSlots * 256);
+  c->bin_n = cv.take<int32_t>((size_t)kMaxBinSlots * 256);
   c->n_contrib = cv.take<int32_t>((size_t)max_w * max_h);
   if (!cv.ok()) {
     free(c);
@@ -844,11 +1384,31 @@ int vy_render(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, co
   }
   {
     ProfScope ps(VY_STAGE_BLEND, st);
-    const int per_xcd = (int)cdiv(ntiles, 8);
-    const int blocks = per_xcd * 8;
-#define VY_BLEND(F, S)                                                                                      \
-  blend<F, S><<<blocks, 256, 0, st>>>(c->ranges, c->tval[0], c->pg0, c->pg1, c->pg2, rc, ntiles, per_xcd, gcap, pcap, image, \
-                                      c->T_final, c->n_contrib)
+    // splitting tiles by depth bins gives up early termination; it is off unless asked for
+    const bool split_on = opts && opts->split_min_pairs > 0;
+    const uint32_t split_min = split_on ? (uint32_t)opts->split_min_pairs : 0xFFFFFFFFu;
+    plan_tiles<<<imin(cdiv(ntiles, 256), 64), 256, 0, st>>>(c->ranges, ntiles, c->tile_flag, c->heavy_list,
+                                                            c->tiers, c->ctr, split_min);
+    VY_LAUNCHED();
+    if (split_on) {
+      plan_heavy<<<256, 256, 0, st>>>(c->ranges, c->tval[0], c->pg1, c->heavy_list, c->tile_flag, c->heavy_rec,
+                                      c->jobs, c->slot_owner, c->ctr, gcap, split_min);
+      VY_LAUNCHED();
+    }
+#define VY_BLEND(F, S)                                                                                          \
+  do {                                                                                                          \
+    blend_jobs<F, S><<<2048, 256, 0, st>>>(c->ranges, c->tval[0], c->pg0, c->pg1, c->pg2, rc, ntiles, c->tile_flag, \
+                                           c->tiers, c->heavy_rec, c->jobs, c->bin_c, c->bin_n, c->ctr, gcap, pcap,  \
+                                           image, c->T_final, c->n_contrib);                                   \
+    if (split_on) {                                                                                             \
+      composite_scan<S><<<256, 256, 0, st>>>(rc, c->tile_flag, c->heavy_rec, c->bin_c, c->bin_n, c->ctr,           \
+                                             reinterpret_cast<PixState*>(c->pstate_raw), c->redo, image,         \
+                                             c->T_final, c->n_contrib);                                         \
+      composite_redo<F, S><<<2048, 256, 0, st>>>(c->tval[0], c->pg0, c->pg1, c->pg2, rc, c->heavy_rec,             \
+                                                 reinterpret_cast<const PixState*>(c->pstate_raw), c->redo, c->ctr, \
+                                                 gcap, pcap, image, c->T_final, c->n_contrib);                  \
+    }                                                                                                           \
+  } while (0)
     if (filter) {
       if (save) VY_BLEND(true, true); else VY_BLEND(true, false);
     } else {
@@ -885,6 +1445,28 @@ int vy_render_saved(const vy_render_ctx* ctx, const float** T_final, const int32
   if (T_final) *T_final = c->T_final;
   if (n_contrib) *n_contrib = c->n_contrib;
   if (mean2d) *mean2d = (const float*)c->pg0;
+  return VY_OK;
+}
+
+int vy_render_pairs(const vy_render_ctx* ctx, const uint32_t** tile_keys, const uint32_t** cut_pos,
+                    const uint32_t** ranges) {
+  const RenderCtx* c = (const RenderCtx*)ctx;
+  if (!c || c->magic != kCtxMagic) return fail(VY_ERR_ARG, "vy_render_pairs: bad argument");
+  if (tile_keys) *tile_keys = c->tkey[0];
+  if (cut_pos) *cut_pos = c->tval[0];
+  if (ranges) *ranges = reinterpret_cast<const uint32_t*>(c->ranges);
+  return VY_OK;
+}
+
+int vy_render_projected(const vy_render_ctx* ctx, const float** rec0, const float** rec1, const float** rec2,
+                        const uint32_t** rect_lo, const uint32_t** rect_hi) {
+  const RenderCtx* c = (const RenderCtx*)ctx;
+  if (!c || c->magic != kCtxMagic) return fail(VY_ERR_ARG, "vy_render_projected: bad argument");
+  if (rec0) *rec0 = reinterpret_cast<const float*>(c->pg0);
+  if (rec1) *rec1 = reinterpret_cast<const float*>(c->pg1);
+  if (rec2) *rec2 = reinterpret_cast<const float*>(c->pg2);
+  if (rect_lo) *rect_lo = c->prect;
+  if (rect_hi) *rect_hi = c->prect2;
   return VY_OK;
 }
 

@@ -125,6 +125,17 @@ struct RenderCtx {
   uint32_t epoch;
   float* T_final;
   int32_t* n_contrib;
+  // blend planning: tiles split by depth bins
+  uint32_t* tile_flag;  // 0 = in tile order, 1 = heavy-first tier, h + 2 = split heavy tile h
+  uint32_t* tiers;      // 3 lists of heavy-first tiles
+  uint32_t* heavy_list;
+  uint32_t* heavy_rec;  // per heavy tile: tile, bins, slot base, bin boundaries and keys
+  uint4* jobs;          // (heavy tile, first bin, end bin)
+  uint32_t* slot_owner; // heavy tile of each per-bin result slot
+  void* pstate_raw;
+  uint2* redo;          // (heavy tile, bin) units of the composite's second step
+  float4* bin_c;        // per (bin slot, pixel): C_b.rgb, T_b
+  int32_t* bin_n;       // per (bin slot, pixel): contributors
 };
 
 uint32_t next_epoch(uint32_t& epoch);   // 24-bit epochs, never 0

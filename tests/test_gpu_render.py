@@ -103,3 +103,37 @@ def test_pair_overflow_reported(tiny, tiny_cams):
     assert rc == vy.VY_ERR_CAPACITY and need > 1000
     with pytest.raises(vy.VoyagerError):
         vy.vy_render(sc, cut, scenegen.identity_camera(512, 512), ctx)
+
+
+@pytest.mark.parametrize("split_min", [1, 24, 300])
+def test_split_blend_is_bitwise_identical(tiny, tiny_cams, split_min):
+    """Tiles blended over several workgroups (depth-bin jobs + composite) give
+    exactly the image, final transmittance and contributor counts of the
+    one-piece blend, with and without the alpha filter."""
+    vy, sc, host, ctx = tiny
+    for cam in tiny_cams[::3]:
+        cut = vy.vy_lod_cut(sc, cam, 2.0)
+        ref = vy.vy_render(sc, cut, cam, ctx, split_min_pairs=1 << 30, save_state=True).cpu().numpy()
+        T_ref, N_ref = ctx.saved(cam.width, cam.height)
+        for filt in (False, True):
+            img = vy.vy_render(sc, cut, cam, ctx, alpha_filter=filt, split_min_pairs=split_min,
+                               save_state=True).cpu().numpy()
+            rc, npairs, nvis = ctx.status()
+            vy.check(rc)
+            T, N = ctx.saved(cam.width, cam.height)
+            assert np.array_equal(img.view(np.uint32), ref.view(np.uint32)), (split_min, filt)
+            assert np.array_equal(T.view(np.uint32), T_ref.view(np.uint32))
+            assert np.array_equal(N, N_ref)
+
+
+def test_saved_state_matches_oracle(tiny, tiny_cams):
+    vy, sc, host, ctx = tiny
+    cam = tiny_cams[5]
+    cut = vy.vy_lod_cut(sc, cam, 2.0)
+    F, C = cut.ids()
+    vy.vy_render(sc, cut, cam, ctx, save_state=True, split_min_pairs=64)
+    T, N = ctx.saved(cam.width, cam.height)
+    ref = orender.render_image(oproj.project(host, C, cam), cam.width, cam.height)
+    ok = ~ref["ambiguous"]
+    assert np.max(np.abs(T[ok] - ref["T"][ok])) < 2e-3
+    assert np.mean(N[ok] == ref["n_contrib"][ok]) > 0.999
