@@ -28,7 +28,12 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector
+# algorithmic FLOPs of the blend: per pixel evaluation of a tile-list entry
+# (offset 2, rho 7, clamp 1, exp 1, theta 1, clamp 1 = 13) and per blended
+# Gaussian (1 - alpha, T update, alpha T, colour 3 FMA = 10)
+BLEND_FLOPS_EVAL, BLEND_FLOPS_CONTRIB = 13.0, 10.0
 T0 = time.time()
 
 
@@ -47,6 +52,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-tiles", type=int, default=16, help="tiles the oracle renders for the CPU baseline")
     ap.add_argument("--max-pairs", type=int, default=96 << 20)
+    ap.add_argument("--copy-mib", type=int, default=1024, help="size of the HBM copy used as the traffic reference")
     return ap.parse_args()
 
 
@@ -95,6 +101,7 @@ def stage_bytes(stage, c):
         "lod_classify": (4 + 32 + 16) * F + 4 * (F + C),
         "lod_compact": 2 * (N / 8) + 4 * (F + C),
         "lod_flat": 32 * N + 16 * N + N / 4,
+        "blend_plan": 8 * T + 4 * T,
         "project": (4 + 48 + 192 + 68) * C,
         "depth_sort": 60 * C,
         "pair_scan": 12 * V,
@@ -140,6 +147,22 @@ def main():
     img2 = torch.empty_like(img)
     ntiles = ((Wd + 15) // 16) * ((Hd + 15) // 16)
     log(f"GPU memory in use: {torch.cuda.memory_allocated() / 2**30:.1f} GiB")
+    # reference copy of known size (HBM-to-HBM): its achieved rate is the practical
+    # bandwidth ceiling, and under rocprofv3 --pmc its FETCH/WRITE_SIZE calibrate the counters
+    nb = args.copy_mib << 20
+    src = torch.empty(nb // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    ce0, ce1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ce0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    ce1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * nb * 5 / (ce0.elapsed_time(ce1) * 1e-3) / 1e9
+    del src, dst
+    log(f"reference copy {args.copy_mib} MiB: {copy_gbs:.0f} GB/s (read + write)")
 
     # ---------------------------------------------------------------- warmup
     for temporal, filt in ((True, True), (False, False)):
@@ -172,7 +195,7 @@ def main():
     # ------------------------------------------------ gates + per-frame counts
     log("verification pass (temporal cut == full cut, filtered == unfiltered, every frame)")
     gates = dict(frames=0, cut_mismatch=0, image_mismatch=0)
-    counts = dict(F=0.0, C=0.0, V=0.0, P=0.0, P_unf=0.0)
+    counts = dict(F=0.0, C=0.0, V=0.0, P=0.0, P_unf=0.0, evals=0.0, contribs=0.0)
     tst = vy.Cut(scene)
     for i, cam in enumerate(cams):
         if i == 0:
@@ -192,9 +215,12 @@ def main():
         vy.vy_render(scene, full_cut, cam, ctx, image=img, alpha_filter=False)
         rc, p_unf, _ = ctx.status()
         vy.check(rc)
-        vy.vy_render(scene, tst, cam, ctx, image=img2, alpha_filter=True)
+        vy.vy_render(scene, tst, cam, ctx, image=img2, alpha_filter=True, save_state=True)
         rc, p_f, v_f = ctx.status()
         vy.check(rc)
+        _, Nc, Ne = ctx.saved(Wd, Hd, evals=True)
+        counts["evals"] += float(Ne[Ne >= 0].sum())
+        counts["contribs"] += float(Nc.sum())
         if not torch.equal(img.view(torch.int32), img2.view(torch.int32)):
             gates["image_mismatch"] += 1
         gates["frames"] += 1
@@ -230,18 +256,33 @@ def main():
     dom = max(((k, ms) for k, (ms, n) in stages.items() if n), key=lambda t: t[1])[0]
     dom_ms, dom_n = stages[dom]
     launch_ms = dom_ms / dom_n
-    bytes_per_launch = stage_bytes(dom, cnt) * K / dom_n
-    achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
-    roofline = dict(kernel=dom, bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                    launch_ms=round(launch_ms, 5), bytes_per_launch=round(bytes_per_launch))
-    log(f"dominant kernel {dom}: {launch_ms:.4f} ms/launch, {achieved:.0f} GB/s algorithmic")
+    traffic = read_traffic(dom)
+    if dom == "blend":
+        # compute-type kernel: algorithmic FLOPs from the per-pixel evaluation counts
+        flops = BLEND_FLOPS_EVAL * avg["evals"] + BLEND_FLOPS_CONTRIB * avg["contribs"]
+        flops_per_launch = flops * K / dom_n
+        achieved = flops_per_launch / (launch_ms * 1e-3) / 1e12
+        roofline = dict(kernel="blend_jobs<true,false>", bound="alu", achieved=round(achieved, 3),
+                        peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s", frac=round(achieved / FP32_VECTOR_PEAK_TFLOPS, 5),
+                        traffic=traffic, launch_ms=round(launch_ms, 5), flops_per_launch=round(flops_per_launch),
+                        evals_per_launch=round(avg["evals"]), contribs_per_launch=round(avg["contribs"]),
+                        algorithmic_bytes_per_launch=round(stage_bytes("blend", cnt)))
+        log(f"dominant kernel blend: {launch_ms:.4f} ms/launch, {achieved:.2f} TFLOP/s algorithmic")
+    else:
+        bytes_per_launch = stage_bytes(dom, cnt) * K / dom_n
+        achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
+        roofline = dict(kernel=dom, bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                        launch_ms=round(launch_ms, 5), bytes_per_launch=round(bytes_per_launch))
+        log(f"dominant kernel {dom}: {launch_ms:.4f} ms/launch, {achieved:.0f} GB/s algorithmic")
 
     # ------------------------------------------------------ oracle on CPU
     cpu = None
     parity = dict(gates)
     if not args.no_cpu_baseline:
-        cpu, par = cpu_baseline(vy, torch, host, scene, cams, args.tau, ctx, img, args.cpu_tiles, state)
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):  # the oracle runs on one host thread; `cores` reports that
+            cpu, par = cpu_baseline(vy, torch, host, scene, cams, args.tau, ctx, img, args.cpu_tiles, state)
         parity.update(par)
 
     out = {
@@ -261,10 +302,29 @@ def main():
         "stages": per_stage,
         "stages_full_unfiltered_ms_per_frame": {k: round(ms / K, 5) for k, (ms, n) in prof["full"].items() if n},
         "roofline": roofline,
+        "reference_copy_GBps": round(copy_gbs, 1),
         "cpu_baseline": cpu,
         "parity": parity,
     }
     print(json.dumps(out), flush=True)
+
+
+def read_traffic(stage):
+    """HBM traffic per launch of the dominant kernel from the committed PMC
+    summary (profiles/*traffic*.md, a JSON line), or None when it is missing or
+    was taken on a different version of the kernel source."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_2506_02774_amd", "csrc", "render.hip")
+    sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*traffic*.md"))):
+        for line in open(f):
+            line = line.strip()
+            if line.startswith("{") and '"traffic_bytes_per_launch"' in line:
+                d = json.loads(line)
+                if d.get("stage") == stage and d.get("source_sha1") == sha:
+                    return d["traffic_bytes_per_launch"]
+    return None
 
 
 def ctypes_ptr(vy, cut, which):

@@ -210,11 +210,14 @@ int vy_render(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, co
  * device-side wait bound was hit. */
 int vy_render_status(vy_render_ctx* ctx, int64_t* n_pairs, int64_t* n_visible, void* stream);
 
-/* Device pointers into the context's saved state of the last frame: per-pixel
- * final transmittance [H][W] and contributor count [H][W] (written only with
- * save_state = 1), and the projected Gaussians' 2D means [n][2] (cut order). */
+/* Device pointers into the context's saved state of the last frame (written
+ * only with save_state = 1), each [H][W]: final transmittance, number of
+ * blended Gaussians, and the number of tile-list entries the pixel evaluated
+ * before blending stopped (its tile's whole list if it never stopped; -1 for
+ * pixels of tiles blended in split mode); and the projected Gaussians' 2D
+ * means [n][4] (cut order, first two floats). Any argument may be NULL. */
 int vy_render_saved(const vy_render_ctx* ctx, const float** T_final, const int32_t** n_contrib,
-                    const float** mean2d);
+                    const int32_t** n_eval, const float** mean2d);
 
 /* Device pointers to the last frame's intermediates (inspection and tests):
  * the pairs sorted by (tile, depth, node id) as tile ids and cut positions
@@ -245,6 +248,7 @@ enum {
   VY_STAGE_EMIT,
   VY_STAGE_TILE_SORT,
   VY_STAGE_RANGES,
+  VY_STAGE_BLEND_PLAN,
   VY_STAGE_BLEND,
   VY_NUM_STAGES
 };

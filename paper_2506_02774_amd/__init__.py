@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(HERE, "libvoyager.so")
 VY_OK, VY_ERR_ARG, VY_ERR_HIP, VY_ERR_CAPACITY, VY_ERR_STATE, VY_ERR_DEVICE = 0, -1, -2, -3, -4, -5
 VY_CUT_FRONTIER, VY_CUT_FLAT = 0, 1
 STAGES = ["lod_setup", "lod_flat", "lod_classify", "lod_traverse", "lod_compact", "render_setup", "project",
-          "depth_sort", "pair_scan", "emit", "tile_sort", "ranges", "blend"]
+          "depth_sort", "pair_scan", "emit", "tile_sort", "ranges", "blend_plan", "blend"]
 
 
 class VoyagerError(RuntimeError):
@@ -82,7 +82,8 @@ def lib():
         "vy_render_ctx_free": ([P], ctypes.c_int),
         "vy_render": ([P, P, ctypes.POINTER(vy_camera), ctypes.POINTER(vy_render_opts), P, P, P], ctypes.c_int),
         "vy_render_status": ([P, ctypes.POINTER(I64), ctypes.POINTER(I64), P], ctypes.c_int),
-        "vy_render_saved": ([P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P)], ctypes.c_int),
+        "vy_render_saved": ([P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P)],
+                            ctypes.c_int),
         "vy_render_pairs": ([P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P)], ctypes.c_int),
         "vy_render_projected": ([P] + [ctypes.POINTER(P)] * 5, ctypes.c_int),
         "vy_profile_begin": ([I64], ctypes.c_int),
@@ -268,16 +269,20 @@ class RenderContext:
         rc = lib().vy_render_status(self.handle, ctypes.byref(n_pairs), ctypes.byref(n_vis), _stream(stream))
         return rc, int(n_pairs.value), int(n_vis.value)
 
-    def saved(self, width, height):
-        """(T_final, n_contrib) of the last frame rendered with save_state (synchronises)."""
-        pt, pn, pm = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
-        check(lib().vy_render_saved(self.handle, ctypes.byref(pt), ctypes.byref(pn), ctypes.byref(pm)),
-              "vy_render_saved")
+    def saved(self, width, height, evals=False):
+        """(T_final, n_contrib[, n_eval]) of the last frame rendered with save_state (synchronises)."""
+        pt, pn, pe, pm = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        check(lib().vy_render_saved(self.handle, ctypes.byref(pt), ctypes.byref(pn), ctypes.byref(pe),
+                                    ctypes.byref(pm)), "vy_render_saved")
         T = np.empty((height, width), np.float32)
         N = np.empty((height, width), np.int32)
         _copy_d2h(T, pt.value)
         _copy_d2h(N, pn.value)
-        return T, N
+        if not evals:
+            return T, N
+        E = np.empty((height, width), np.int32)
+        _copy_d2h(E, pe.value)
+        return T, N, E
 
     def pairs(self, width, height):
         """Last frame's sorted pairs (tile ids, cut positions) and tile ranges (synchronises)."""

@@ -710,6 +710,7 @@ struct PixAcc {
   float Tt, C0, C1, C2;     // combined over finished bins (one-piece mode)
   float Tb, Cb0, Cb1, Cb2;  // current bin
   int32_t nt, nb;
+  uint32_t stop_pos;        // tile-list position of the Gaussian where blending stopped (save mode)
   bool done;
   uint32_t cur_key;         // depth bin of the current bin (0xFFFFFFFF before the first)
   uint32_t lb;              // local index of the current bin (split mode)
@@ -763,9 +764,9 @@ VY_DEV void bin_enter(PixAcc& A, uint32_t key, const SplitOut& so) {
 // (Eq. 3), skipped below alpha* (with the filter, decided before the
 // exponential by Eq. 4); blending stops before a Gaussian that would take the
 // transmittance (Tt * T_b, or T_b alone in split mode) below 1e-4.
-template <bool FILTER, bool SPLIT>
+template <bool FILTER, bool SPLIT, bool SAVE>
 VY_DEV void blend_one(uint32_t key, const float4 p0, const float4 p1, const float4 p2, float fxp, float fyp,
-                      PixAcc& A, const SplitOut& so) {
+                      PixAcc& A, const SplitOut& so, uint32_t pos) {
   if (key != A.cur_key) {                 // a new depth bin begins (wave-uniform)
     if (!A.done) bin_enter<SPLIT>(A, key, so);   // a finished pixel keeps its state frozen
     A.cur_key = key;
@@ -788,6 +789,7 @@ VY_DEV void blend_one(uint32_t key, const float4 p0, const float4 p1, const floa
   A.Cb2 = fmaf(wgt, p2.z, A.Cb2);
   A.Tb = bl ? Tn : ((SPLIT && stop) ? 0.f : A.Tb);
   A.nb += bl ? 1 : 0;
+  if (SAVE && stop) A.stop_pos = pos;
   A.done = A.done || stop;
 }
 
@@ -798,7 +800,7 @@ VY_DEV void blend_one(uint32_t key, const float4 p0, const float4 p1, const floa
 // first, and when the four share the current depth bin their alphas are
 // computed independently before the sequential transmittance chain, which
 // keeps the per-Gaussian latency low on the tiles with the longest lists.
-template <bool FILTER, bool SPLIT>
+template <bool FILTER, bool SPLIT, bool SAVE>
 VY_DEV void blend_range(Stage& S, uint32_t pb, uint32_t pe, const uint32_t* __restrict__ tval,
                         const float4* __restrict__ pg0, const float4* __restrict__ pg1,
                         const float4* __restrict__ pg2, uint32_t n_g, int tx, int ty, float fxp, float fyp,
@@ -854,12 +856,13 @@ VY_DEV void blend_range(Stage& S, uint32_t pb, uint32_t pe, const uint32_t* __re
           A.Cb2 = fmaf(wgt, q2[k].z, A.Cb2);
           A.Tb = bl ? Tn : ((SPLIT && stop) ? 0.f : A.Tb);
           A.nb += bl ? 1 : 0;
+          if (SAVE && stop) A.stop_pos = b0 + (e[k] & 255u);
           A.done = A.done || stop;
         }
       } else {
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-          if (k < m) blend_one<FILTER, SPLIT>(e[k] >> 8, q0[k], q1[k], q2[k], fxp, fyp, A, so);
+          if (k < m) blend_one<FILTER, SPLIT, SAVE>(e[k] >> 8, q0[k], q1[k], q2[k], fxp, fyp, A, so, b0 + (e[k] & 255u));
       }
     }
     __syncthreads();
@@ -876,7 +879,8 @@ __global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ rang
                                                   const uint4* __restrict__ jobs, float4* __restrict__ bin_c,
                                                   int32_t* __restrict__ bin_n, uint32_t* ctr, uint32_t n_g,
                                                   uint32_t n_pairs_cap, float* __restrict__ img,
-                                                  float* __restrict__ Tout, int32_t* __restrict__ Nout) {
+                                                  float* __restrict__ Tout, int32_t* __restrict__ Nout,
+                                                  int32_t* __restrict__ Eout) {
   __shared__ Stage S;
   __shared__ uint32_t s_job;
   __shared__ uint32_t s_bkey[kMaxBins];
@@ -938,6 +942,7 @@ __global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ rang
     A.Tb = 1.f;
     A.Cb0 = A.Cb1 = A.Cb2 = 0.f;
     A.nt = A.nb = 0;
+    A.stop_pos = 0xFFFFFFFFu;
     A.done = !inside;
     A.cur_key = 0xFFFFFFFFu;
     A.lb = so.lbin0;
@@ -947,7 +952,7 @@ __global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ rang
     const bool urgent = J < nfirst;
     if (urgent) __builtin_amdgcn_s_setprio(3);
     if (split) {
-      blend_range<FILTER, true>(S, pb, pe, tval, pg0, pg1, pg2, n_g, tx, ty, fxp, fyp, A, so);
+      blend_range<FILTER, true, false>(S, pb, pe, tval, pg0, pg1, pg2, n_g, tx, ty, fxp, fyp, A, so);
       // the current bin, then bins without Gaussians for this band up to the job's end
       if (A.cur_key != 0xFFFFFFFFu && A.lb < so.lbin1) {
         put_bin(so, A.lb, make_float4(A.Cb0, A.Cb1, A.Cb2, A.Tb), A.nb);
@@ -955,7 +960,7 @@ __global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ rang
       }
       for (; A.lb < so.lbin1; ++A.lb) put_bin(so, A.lb, make_float4(0.f, 0.f, 0.f, 1.f), 0);
     } else {
-      blend_range<FILTER, false>(S, pb, pe, tval, pg0, pg1, pg2, n_g, tx, ty, fxp, fyp, A, so);
+      blend_range<FILTER, false, SAVE>(S, pb, pe, tval, pg0, pg1, pg2, n_g, tx, ty, fxp, fyp, A, so);
       if (inside) {
         A.C0 = fmaf(A.Tt, A.Cb0, A.C0);
         A.C1 = fmaf(A.Tt, A.Cb1, A.C1);
@@ -969,6 +974,7 @@ __global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ rang
         if (SAVE) {
           Tout[o] = A.Tt;
           Nout[o] = A.nt;
+          Eout[o] = (int32_t)((A.stop_pos != 0xFFFFFFFFu ? A.stop_pos + 1u : pe) - pb);
         }
       }
     }
@@ -995,7 +1001,7 @@ __global__ __launch_bounds__(256) void composite_scan(RCam cam, const uint32_t* 
                                                       const int32_t* __restrict__ bin_n, uint32_t* ctr,
                                                       PixState* __restrict__ pstate, uint2* __restrict__ redo,
                                                       float* __restrict__ img, float* __restrict__ Tout,
-                                                      int32_t* __restrict__ Nout) {
+                                                      int32_t* __restrict__ Nout, int32_t* __restrict__ Eout) {
   __shared__ uint32_t s_stop[kMaxBins / 32];
   uint32_t nh = ctr[C_NHEAVY];
   if (nh > kMaxHeavy) nh = kMaxHeavy;
@@ -1037,6 +1043,7 @@ __global__ __launch_bounds__(256) void composite_scan(RCam cam, const uint32_t* 
         if (SAVE) {
           Tout[o] = Tt;
           Nout[o] = nt;
+          Eout[o] = -1;
         }
       } else {
         atomicOr(&s_stop[stop >> 5], 1u << (stop & 31));
@@ -1072,7 +1079,8 @@ __global__ __launch_bounds__(256) void composite_redo(const uint32_t* __restrict
                                                       const PixState* __restrict__ pstate,
                                                       const uint2* __restrict__ redo, const uint32_t* ctr,
                                                       uint32_t n_g, uint32_t n_pairs_cap, float* __restrict__ img,
-                                                      float* __restrict__ Tout, int32_t* __restrict__ Nout) {
+                                                      float* __restrict__ Tout, int32_t* __restrict__ Nout,
+                                                      int32_t* __restrict__ Eout) {
   __shared__ Stage S;
   uint32_t nu = ctr[C_NREDO];
   if (nu > kMaxBinSlots) nu = kMaxBinSlots;
@@ -1097,13 +1105,14 @@ __global__ __launch_bounds__(256) void composite_redo(const uint32_t* __restrict
     A.Tb = 1.f;
     A.Cb0 = A.Cb1 = A.Cb2 = 0.f;
     A.nb = 0;
+    A.stop_pos = 0xFFFFFFFFu;
     A.done = !mine;
     A.cur_key = rec[4 + kMaxBins + 1 + b];   // every pair of the bin has this key: no bin change
     A.lb = 0;
     uint32_t pb = rec[4 + b], pe = rec[4 + b + 1];
     if (pe > n_pairs_cap) pe = n_pairs_cap;
     if (pb > pe) pb = pe;
-    blend_range<FILTER, false>(S, pb, pe, tval, pg0, pg1, pg2, n_g, tx, ty, px + 0.5f, py + 0.5f, A, so);
+    blend_range<FILTER, false, false>(S, pb, pe, tval, pg0, pg1, pg2, n_g, tx, ty, px + 0.5f, py + 0.5f, A, so);
     if (mine) {
       A.C0 = fmaf(A.Tt, A.Cb0, A.C0);
       A.C1 = fmaf(A.Tt, A.Cb1, A.C1);
@@ -1117,6 +1126,7 @@ __global__ __launch_bounds__(256) void composite_redo(const uint32_t* __restrict
       if (SAVE) {
         Tout[o] = A.Tt;
         Nout[o] = A.nt;
+        Eout[o] = -1;
       }
     }
     __syncthreads();
@@ -1170,7 +1180,7 @@ size_t vy_render_workspace_bytes(int64_t max_g, int32_t max_w, int32_t max_h, in
   b += (size_t)tiles * 8;
   b += 64 * 4 + 6 * 256 * 4;
   b += (size_t)status_words_for(max_g, max_pairs) * 8;
-  b += (size_t)max_w * max_h * 8;                          // saved T, n_contrib
+  b += (size_t)max_w * max_h * 12;                         // saved T, n_contrib, n_eval
   b += (size_t)tiles * 16 + kMaxHeavy * 4 + (size_t)kMaxHeavy * kHeavyRec * 4 + (size_t)kMaxHeavy * kMaxJobsPerTile * 16;
   b += (size_t)kMaxBinSlots * (256 * 20 + 4 + 8);          // per-bin results of split tiles, slot owners, redo units
   b += (size_t)kMaxHeavy * 256 * sizeof(PixState);
@@ -1231,6 +1241,7 @@ int vy_render_ctx_create(int64_t max_g, int32_t max_w, int32_t max_h, int64_t ma
   c->bin_c = cv.take<float4>((size_t)kMaxBinSlots * 256);
   c->bin_n = cv.take<int32_t>((size_t)kMaxBinSlots * 256);
   c->n_contrib = cv.take<int32_t>((size_t)max_w * max_h);
+  c->n_eval = cv.take<int32_t>((size_t)max_w * max_h);
   if (!cv.ok()) {
     free(c);
     return fail(VY_ERR_ARG, "vy_render_ctx_create: workspace layout overflow");
@@ -1382,11 +1393,11 @@ int vy_render(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, co
     tile_ranges<<<blocks, 256, 0, st>>>(c->tkey[0], c->ctr, c->ranges, (uint32_t)ntiles);
     VY_LAUNCHED();
   }
+  // splitting tiles by depth bins gives up early termination; it is off unless asked for
+  const bool split_on = opts && opts->split_min_pairs > 0;
+  const uint32_t split_min = split_on ? (uint32_t)opts->split_min_pairs : 0xFFFFFFFFu;
   {
-    ProfScope ps(VY_STAGE_BLEND, st);
-    // splitting tiles by depth bins gives up early termination; it is off unless asked for
-    const bool split_on = opts && opts->split_min_pairs > 0;
-    const uint32_t split_min = split_on ? (uint32_t)opts->split_min_pairs : 0xFFFFFFFFu;
+    ProfScope ps(VY_STAGE_BLEND_PLAN, st);
     plan_tiles<<<imin(cdiv(ntiles, 256), 64), 256, 0, st>>>(c->ranges, ntiles, c->tile_flag, c->heavy_list,
                                                             c->tiers, c->ctr, split_min);
     VY_LAUNCHED();
@@ -1395,18 +1406,21 @@ int vy_render(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, co
                                       c->jobs, c->slot_owner, c->ctr, gcap, split_min);
       VY_LAUNCHED();
     }
+  }
+  {
+    ProfScope ps(VY_STAGE_BLEND, st);
 #define VY_BLEND(F, S)                                                                                          \
   do {                                                                                                          \
     blend_jobs<F, S><<<2048, 256, 0, st>>>(c->ranges, c->tval[0], c->pg0, c->pg1, c->pg2, rc, ntiles, c->tile_flag, \
                                            c->tiers, c->heavy_rec, c->jobs, c->bin_c, c->bin_n, c->ctr, gcap, pcap,  \
-                                           image, c->T_final, c->n_contrib);                                   \
+                                           image, c->T_final, c->n_contrib, c->n_eval);                       \
     if (split_on) {                                                                                             \
       composite_scan<S><<<256, 256, 0, st>>>(rc, c->tile_flag, c->heavy_rec, c->bin_c, c->bin_n, c->ctr,           \
                                              reinterpret_cast<PixState*>(c->pstate_raw), c->redo, image,         \
-                                             c->T_final, c->n_contrib);                                         \
+                                             c->T_final, c->n_contrib, c->n_eval);                              \
       composite_redo<F, S><<<2048, 256, 0, st>>>(c->tval[0], c->pg0, c->pg1, c->pg2, rc, c->heavy_rec,             \
                                                  reinterpret_cast<const PixState*>(c->pstate_raw), c->redo, c->ctr, \
-                                                 gcap, pcap, image, c->T_final, c->n_contrib);                  \
+                                                 gcap, pcap, image, c->T_final, c->n_contrib, c->n_eval);       \
     }                                                                                                           \
   } while (0)
     if (filter) {
@@ -1439,11 +1453,12 @@ int vy_render_status(vy_render_ctx* ctx, int64_t* n_pairs, int64_t* n_visible, v
 }
 
 int vy_render_saved(const vy_render_ctx* ctx, const float** T_final, const int32_t** n_contrib,
-                    const float** mean2d) {
+                    const int32_t** n_eval, const float** mean2d) {
   const RenderCtx* c = (const RenderCtx*)ctx;
   if (!c || c->magic != kCtxMagic) return fail(VY_ERR_ARG, "vy_render_saved: bad argument");
   if (T_final) *T_final = c->T_final;
   if (n_contrib) *n_contrib = c->n_contrib;
+  if (n_eval) *n_eval = c->n_eval;
   if (mean2d) *mean2d = (const float*)c->pg0;
   return VY_OK;
 }

@@ -125,6 +125,7 @@ struct RenderCtx {
   uint32_t epoch;
   float* T_final;
   int32_t* n_contrib;
+  int32_t* n_eval;
   // blend planning: tiles split by depth bins
   uint32_t* tile_flag;  // 0 = in tile order, 1 = heavy-first tier, h + 2 = split heavy tile h
   uint32_t* tiers;      // 3 lists of heavy-first tiles

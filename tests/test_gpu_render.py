@@ -137,3 +137,28 @@ def test_saved_state_matches_oracle(tiny, tiny_cams):
     ok = ~ref["ambiguous"]
     assert np.max(np.abs(T[ok] - ref["T"][ok])) < 2e-3
     assert np.mean(N[ok] == ref["n_contrib"][ok]) > 0.999
+
+
+@pytest.mark.parametrize("filt", [False, True])
+def test_saved_evaluation_counts(tiny, tiny_cams, filt):
+    """Per-pixel evaluation counts of the one-piece blend: every pixel walks its
+    tile's sorted list up to and including the entry that ends it (Section 3.1,
+    early termination), so n_contrib <= n_eval <= the tile's list length, and a
+    pixel whose list ran out evaluated all of it. Split jobs report -1."""
+    vy, sc, host, ctx = tiny
+    cam = tiny_cams[4]
+    cut = vy.vy_lod_cut(sc, cam, 2.0)
+    vy.vy_render(sc, cut, cam, ctx, alpha_filter=filt, save_state=True)
+    T, N, E = ctx.saved(cam.width, cam.height, evals=True)
+    keys, vals, ranges = ctx.pairs(cam.width, cam.height)
+    tx = (cam.width + 15) // 16
+    ys, xs = np.mgrid[0:cam.height, 0:cam.width]
+    t = (ys // 16) * tx + xs // 16
+    L = (ranges[:, 1].astype(np.int64) - ranges[:, 0].astype(np.int64))[t]
+    assert (E >= N).all() and (E <= L).all()
+    assert (E < L).any() and (E == L).any()
+    vy.vy_render(sc, cut, cam, ctx, alpha_filter=filt, save_state=True, split_min_pairs=1)
+    _, _, E2 = ctx.saved(cam.width, cam.height, evals=True)
+    assert (E2 == -1).any()
+    assert (E2[E2 >= 0] == E[E2 >= 0]).all()
+    assert ((E2 == -1) | (E2 >= 0)).all()
