@@ -104,8 +104,7 @@ def stage_bytes(stage, c):
         "blend_plan": 8 * T + 4 * T,
         "project": (4 + 48 + 192 + 68) * C,
         "depth_sort": 60 * C,
-        "pair_scan": 12 * V,
-        "emit": (16 + (36 if c["filter"] else 0)) * V + 8 * P,
+        "emit": (4 + 16 + 4) * V + 8 * P,
         "tile_sort": 32 * P,
         "ranges": 4 * P + 8 * T,
         "blend": (4 + 48) * P + 8 * T + 12 * px,

@@ -224,12 +224,15 @@ int vy_render_saved(const vy_render_ctx* ctx, const float** T_final, const int32
  * [n_pairs], the per-tile [start, end) ranges [tiles][2], and the projected
  * Gaussians by cut position: rec0 {mean2d.x, mean2d.y, A, B} and rec1
  * {C, theta, rho threshold of the filter, depth} with rho = A dx^2 + B dx dy +
- * C dy^2, rec2 {r, g, b, pixel radius}, each [max_gaussians][4], and the tile
- * rect corners packed x | y << 16 (inclusive). Any argument may be NULL. */
+ * C dy^2, rec2 {r, g, b, pixel half-extents rx | ry << 16 as float bits},
+ * each [max_gaussians][4] float, and the binning record [max_gaussians][4]
+ * uint32 {x0 | y0 << 16, x1 | y1 << 16 (inclusive tile rect), kept-tile mask
+ * (rects of at most 32 tiles: bit k = k-th tile in row-major order; 0 for
+ * bigger rects), pair count}. Any argument may be NULL. */
 int vy_render_pairs(const vy_render_ctx* ctx, const uint32_t** tile_keys, const uint32_t** cut_pos,
                     const uint32_t** ranges);
 int vy_render_projected(const vy_render_ctx* ctx, const float** rec0, const float** rec1, const float** rec2,
-                        const uint32_t** rect_lo, const uint32_t** rect_hi);
+                        const uint32_t** bin_rec);
 
 /* ------------------------------------------------------------------------ */
 /* Stage timing (HIP events recorded around every kernel launch)            */

@@ -85,7 +85,7 @@ def lib():
         "vy_render_saved": ([P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P)],
                             ctypes.c_int),
         "vy_render_pairs": ([P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P)], ctypes.c_int),
-        "vy_render_projected": ([P] + [ctypes.POINTER(P)] * 5, ctypes.c_int),
+        "vy_render_projected": ([P] + [ctypes.POINTER(P)] * 4, ctypes.c_int),
         "vy_profile_begin": ([I64], ctypes.c_int),
         "vy_profile_end": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)], ctypes.c_int),
         "vy_stage_name": ([ctypes.c_int], ctypes.c_char_p),
@@ -302,17 +302,14 @@ class RenderContext:
         return keys, vals, ranges
 
     def projected(self, n):
-        """Projected records of the first n cut positions: (rec0, rec1, rec2) [n, 4] and rects (synchronises)."""
-        ptrs = [ctypes.c_void_p() for _ in range(5)]
+        """Projected records of the first n cut positions (synchronises): rec0, rec1,
+        rec2 as float32 [n, 4] and the binning record as uint32 [n, 4] (tile rect
+        corners, kept-tile mask, pair count)."""
+        ptrs = [ctypes.c_void_p() for _ in range(4)]
         check(lib().vy_render_projected(self.handle, *[ctypes.byref(p) for p in ptrs]), "vy_render_projected")
         out = []
-        for p in ptrs[:3]:
-            a = np.empty((n, 4), np.float32)
-            if n:
-                _copy_d2h(a, p.value)
-            out.append(a)
-        for p in ptrs[3:]:
-            a = np.empty(n, np.uint32)
+        for p, dt in zip(ptrs, (np.float32, np.float32, np.float32, np.uint32)):
+            a = np.empty((n, 4), dt)
             if n:
                 _copy_d2h(a, p.value)
             out.append(a)

@@ -298,6 +298,8 @@ __global__ __launch_bounds__(256) void lod_level(const int32_t* __restrict__ in_
 
 // Compaction of the F and C bitmaps into ascending ids (decoupled look-back
 // scan over partitions of 1024 words), zeroing the bitmaps as they are read.
+// A partition is read as 4 rounds of 256 consecutive words (one per thread);
+// each round's ids are gathered in LDS and written out with coalesced stores.
 constexpr int kWordsPerThread = 4, kWordsPerPart = 256 * kWordsPerThread;
 
 __global__ __launch_bounds__(256) void lod_compact(int64_t n_words, uint32_t* __restrict__ fbits,
@@ -307,50 +309,58 @@ __global__ __launch_bounds__(256) void lod_compact(int64_t n_words, uint32_t* __
                                                    uint32_t n_parts) {
   __shared__ uint32_t s_scan[8], s_part;
   __shared__ uint64_t s_ex[2];
+  __shared__ int32_t s_ids[256 * 32];
   if (threadIdx.x == 0) s_part = fetch_add(ctr + kTicket, 1u);
   __syncthreads();
   const uint32_t part = s_part;
   if (part >= n_parts) return;
-  const int64_t w0 = (int64_t)part * kWordsPerPart + threadIdx.x * kWordsPerThread;
-  uint32_t fw[kWordsPerThread], cw[kWordsPerThread];
-  uint32_t fc = 0, cc = 0;
+  const int64_t base = (int64_t)part * kWordsPerPart;
+  uint32_t wd[2][kWordsPerThread], off[2][kWordsPerThread], rt[2][kWordsPerThread];
+  uint32_t tot[2] = {0, 0};
 #pragma unroll
   for (int k = 0; k < kWordsPerThread; ++k) {
-    const int64_t w = w0 + k;
-    fw[k] = w < n_words ? fbits[w] : 0u;
-    cw[k] = w < n_words ? cbits[w] : 0u;
-    fc += __popc(fw[k]);
-    cc += __popc(cw[k]);
+    const int64_t w = base + k * 256 + threadIdx.x;
+    wd[0][k] = w < n_words ? fbits[w] : 0u;
+    wd[1][k] = w < n_words ? cbits[w] : 0u;
   }
-  uint32_t ftot, ctot;
-  const uint32_t foff = block_excl_scan256(fc, s_scan, &ftot);
-  const uint32_t coff = block_excl_scan256(cc, s_scan, &ctot);
-  if (threadIdx.x == 0) s_ex[0] = lookback(status, part, 2, epoch, ftot, ctr + kErr);
-  if (threadIdx.x == 64) s_ex[1] = lookback(status + 1, part, 2, epoch, ctot, ctr + kErr);
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int k = 0; k < kWordsPerThread; ++k) {
+      off[q][k] = block_excl_scan256((uint32_t)__popc(wd[q][k]), s_scan, &rt[q][k]);
+      tot[q] += rt[q][k];
+    }
+  if (threadIdx.x < 64) {   // wave 0 walks the F chain, wave 1 the C chain
+    const uint64_t e = lookback_wave(status, part, 2, epoch, tot[0], ctr + kErr);
+    if (threadIdx.x == 0) s_ex[0] = e;
+  } else if (threadIdx.x < 128) {
+    const uint64_t e = lookback_wave(status + 1, part, 2, epoch, tot[1], ctr + kErr);
+    if (threadIdx.x == 64) s_ex[1] = e;
+  }
   __syncthreads();
-  int64_t fo = (int64_t)s_ex[0] + foff, co = (int64_t)s_ex[1] + coff;
 #pragma unroll
-  for (int k = 0; k < kWordsPerThread; ++k) {
-    const int64_t w = w0 + k;
-    uint32_t f = fw[k], c = cw[k];
-    while (f) {
-      const int b = __ffs(f) - 1;
-      f &= f - 1;
-      Fout[fo++] = (int32_t)(w * 32 + b);
-    }
-    while (c) {
-      const int b = __ffs(c) - 1;
-      c &= c - 1;
-      Cout[co++] = (int32_t)(w * 32 + b);
-    }
-    if (w < n_words) {
-      if (fw[k]) fbits[w] = 0u;
-      if (cw[k]) cbits[w] = 0u;
+  for (int q = 0; q < 2; ++q) {
+    int32_t* out = (q == 0 ? Fout : Cout) + s_ex[q];
+    uint32_t r0 = 0;   // ids of the partition before this round
+#pragma unroll
+    for (int k = 0; k < kWordsPerThread; ++k) {
+      const int64_t w = base + k * 256 + threadIdx.x;
+      uint32_t m = wd[q][k], o = off[q][k];
+      while (m) {
+        const int b = __ffs(m) - 1;
+        m &= m - 1;
+        s_ids[o++] = (int32_t)(w * 32 + b);
+      }
+      __syncthreads();
+      for (uint32_t i = threadIdx.x; i < rt[q][k]; i += 256) out[r0 + i] = s_ids[i];
+      r0 += rt[q][k];
+      if (wd[q][k]) (q == 0 ? fbits : cbits)[w] = 0u;
+      __syncthreads();
     }
   }
-  if (part == n_parts - 1 && threadIdx.x == 255) {
-    counts[f_slot] = (int32_t)fo;
-    counts[2] = (int32_t)co;
+  if (part == n_parts - 1 && threadIdx.x == 0) {
+    counts[f_slot] = (int32_t)(s_ex[0] + tot[0]);
+    counts[2] = (int32_t)(s_ex[1] + tot[1]);
   }
 }
 

@@ -7,9 +7,10 @@
 //                 depth key + its 4 digit histograms
 //   depth sort    4 stable onesweep passes over 8-bit digits of the depth bits
 //                 (values = cut positions, so equal depths keep node-id order)
-//   pair_scan     exclusive scan of the pair counts in depth order
-//   emit          Gaussian-tile pairs in depth order (tile key + cut position)
-//                 + the tile digit histograms
+//   emit          exclusive scan of the pair counts in depth order fused with
+//                 the emission of the Gaussian-tile pairs (tile key + cut
+//                 position) + the tile digit histograms; big Gaussians by
+//                 whole workgroups
 //   tile sort     2 stable onesweep passes on the tile id: afterwards pairs are
 //                 ordered by (tile, depth, node id) - an LSD radix sort by
 //                 (tile, depth) whose depth digits were sorted before the
@@ -162,9 +163,8 @@ template <bool FILTER>
 __global__ __launch_bounds__(256) void project(const int32_t* __restrict__ cut, const int32_t* n_cut_ptr,
                                                const float4* __restrict__ gauss, const float* __restrict__ sh,
                                                RCam cam, float4* __restrict__ pg0, float4* __restrict__ pg1,
-                                               float4* __restrict__ pg2, uint32_t* __restrict__ prect,
-                                               uint32_t* __restrict__ prect2, float* __restrict__ prelax,
-                                               uint32_t* __restrict__ pcount, uint32_t* __restrict__ dkey,
+                                               float4* __restrict__ pg2, uint4* __restrict__ prec,
+                                               float* __restrict__ prelax, uint32_t* __restrict__ dkey,
                                                uint32_t* ctr, uint32_t* hist, int64_t n_nodes,
                                                uint32_t* __restrict__ big) {
   __shared__ uint32_t s_hist[4][256];
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(256) void project(const int32_t* __restrict__ cut, 
     const float y = (cam.R[3] * dxw + cam.R[4] * dyw) + cam.R[5] * dzw;
     const float z = (cam.R[6] * dxw + cam.R[7] * dyw) + cam.R[8] * dzw;
     bool valid = z > cam.near;
-    uint32_t count = 0, key = 0xFFFFFFFFu;
+    uint32_t count = 0, mask = 0, key = 0xFFFFFFFFu;
     float4 o0 = make_float4(0, 0, 0, 0), o1 = make_float4(0, 0, 0, 0), o2 = make_float4(0, 0, 0, 0);
     uint32_t r0 = 0, r1 = 0;
     float relax = 0.f;
@@ -261,10 +261,14 @@ __global__ __launch_bounds__(256) void project(const int32_t* __restrict__ cut, 
               count = area;
               big[fetch_add(ctr + C_NBIG, 1u)] = (uint32_t)i;
             } else if (FILTER && relax < 0.25f) {
+              uint32_t bit = 1u;
               for (int ty = y0; ty <= y1; ++ty)
-                for (int tx = x0; tx <= x1; ++tx) count += tile_keep(o0, o1, relax, tx, ty, cam.W, cam.H) ? 1u : 0u;
+                for (int tx = x0; tx <= x1; ++tx, bit <<= 1)
+                  if (tile_keep(o0, o1, relax, tx, ty, cam.W, cam.H)) mask |= bit;
+              count = (uint32_t)__popc(mask);
             } else {
               count = area;
+              mask = area == 32u ? 0xFFFFFFFFu : (1u << area) - 1u;
             }
             if (count == 0) valid = false;
             else key = __float_as_uint(z);
@@ -272,14 +276,12 @@ __global__ __launch_bounds__(256) void project(const int32_t* __restrict__ cut, 
         }
       }
     }
-    if (!valid) count = 0;
+    if (!valid) count = mask = 0;
     pg0[i] = o0;
     pg1[i] = o1;
     pg2[i] = o2;
-    prect[i] = r0;
-    prect2[i] = r1;
+    prec[i] = make_uint4(r0, r1, mask, count);
     prelax[i] = relax;
-    pcount[i] = count;
     dkey[i] = key;
     nvis += count > 0 ? 1u : 0u;
 #pragma unroll
@@ -299,17 +301,15 @@ __global__ __launch_bounds__(256) void project(const int32_t* __restrict__ cut, 
 // rect's tiles spread over the threads.
 __global__ __launch_bounds__(256) void big_count(const uint32_t* __restrict__ big, const uint32_t* ctr,
                                                  const float4* __restrict__ pg0, const float4* __restrict__ pg1,
-                                                 const uint32_t* __restrict__ prect,
-                                                 const uint32_t* __restrict__ prect2,
-                                                 const float* __restrict__ prelax, int W, int H,
-                                                 uint32_t* __restrict__ pcount, uint32_t n_g) {
+                                                 uint4* __restrict__ prec, const float* __restrict__ prelax,
+                                                 int W, int H, uint32_t n_g) {
   __shared__ uint32_t s_red[4];
   const uint32_t nb = ctr[C_NBIG];
   for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
     const uint32_t g = big[b];
     if (g >= n_g) continue;
-    const uint32_t a = prect[g], e = prect2[g];
-    const int x0 = a & 0xFFFF, y0 = a >> 16, x1 = e & 0xFFFF, y1 = e >> 16;
+    const uint4 r = prec[g];
+    const int x0 = r.x & 0xFFFF, y0 = r.x >> 16, x1 = r.y & 0xFFFF, y1 = r.y >> 16;
     const int w = x1 - x0 + 1, area = w * (y1 - y0 + 1);
     const float4 p0 = pg0[g], p1 = pg1[g];
     const float relax = prelax[g];
@@ -319,25 +319,35 @@ __global__ __launch_bounds__(256) void big_count(const uint32_t* __restrict__ bi
     for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
     if (lane() == 0) s_red[threadIdx.x >> 6] = cnt;
     __syncthreads();
-    if (threadIdx.x == 0) pcount[g] = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+    if (threadIdx.x == 0) reinterpret_cast<uint32_t*>(prec + g)[3] = s_red[0] + s_red[1] + s_red[2] + s_red[3];
     __syncthreads();
   }
 }
 
-// Exclusive scan of the pair counts in depth order (r < n_vis), written per
-// cut position: offs[g] = first pair of Gaussian g. The total goes to
-// C_NPAIRS_RAW, min(total, cap) to C_NPAIRS.
+// Pair scan and emission (Section 3.1 "Sorting": one (tile, Gaussian) pair
+// per tile a Gaussian touches; with the filter, per the Eq. 4 tile test taken
+// in project). The visible Gaussians, in depth order (r < n_vis), get
+// consecutive ranges of the pair array by an exclusive scan of their pair
+// counts (decoupled look-back over partitions of kScanTile), and each writes
+// its pairs in row-major tile order from its kept-tile mask, so the array
+// comes out in (depth, node id) order for the stable tile sort. Big Gaussians
+// only get their offset here (offs[g]); emit_big writes their pairs. The total
+// goes to C_NPAIRS_RAW, min(total, cap) to C_NPAIRS.
 constexpr int kScanItems = 16, kScanTile = 256 * kScanItems;
 
-__global__ __launch_bounds__(256) void pair_scan(const uint32_t* __restrict__ sorted_val,
-                                                 const uint32_t* __restrict__ pcount,
-                                                 uint32_t* __restrict__ offsets, uint32_t* ctr, uint64_t* status,
-                                                 uint32_t epoch, uint32_t cap, uint32_t n_g) {
+__global__ __launch_bounds__(256) void pair_emit(const uint32_t* __restrict__ sorted_val,
+                                                 const uint4* __restrict__ prec, uint32_t* __restrict__ offsets,
+                                                 uint32_t* ctr, uint64_t* status, uint32_t epoch, int tiles_x,
+                                                 int bits0, uint32_t* __restrict__ tkey, uint32_t* __restrict__ tval,
+                                                 uint32_t* hist, uint32_t cap, uint32_t n_g) {
   __shared__ uint32_t s_v[kScanTile];
   __shared__ uint32_t s_scan[8], s_part;
   __shared__ uint64_t s_ex;
+  __shared__ uint32_t s_hist[2][256];
+  for (int i = threadIdx.x; i < 512; i += blockDim.x) (&s_hist[0][0])[i] = 0;
   const uint32_t n = ctr[C_NVIS];
   const uint32_t n_parts = (n + kScanTile - 1) / kScanTile;
+  const uint32_t m0 = (1u << bits0) - 1u;
   for (;;) {
     if (threadIdx.x == 0) s_part = fetch_add(ctr + C_SCAN_TICKET, 1u);
     __syncthreads();
@@ -349,7 +359,7 @@ __global__ __launch_bounds__(256) void pair_scan(const uint32_t* __restrict__ so
       uint32_t v = 0;
       if (i < n) {
         const uint32_t g = sorted_val[i];
-        v = g < n_g ? pcount[g] : 0u;
+        v = g < n_g ? prec[g].w : 0u;
       }
       s_v[k * 256 + threadIdx.x] = v;
     }
@@ -361,16 +371,43 @@ __global__ __launch_bounds__(256) void pair_scan(const uint32_t* __restrict__ so
     }
     uint32_t tot;
     const uint32_t off = block_excl_scan256(sum, s_scan, &tot);
-    if (threadIdx.x == 0) s_ex = lookback(status, part, 1, epoch, tot, ctr + C_ERR);
+    if (threadIdx.x < 64) {
+      const uint64_t e = lookback_wave(status, part, 1, epoch, tot, ctr + C_ERR);
+      if (threadIdx.x == 0) s_ex = e;
+    }
     __syncthreads();
     const uint64_t ex = s_ex;
     for (int k = 0; k < kScanItems; ++k) s_v[threadIdx.x * kScanItems + k] = (uint32_t)(ex + off + loc[k]);
     __syncthreads();
     for (int k = 0; k < kScanItems; ++k) {
       const uint32_t i = base + k * 256 + threadIdx.x;
-      if (i < n) {
-        const uint32_t g = sorted_val[i];
-        if (g < n_g) offsets[g] = s_v[k * 256 + threadIdx.x];
+      if (i >= n) continue;
+      const uint32_t g = sorted_val[i];
+      if (g >= n_g) continue;
+      const uint4 r = prec[g];
+      if (r.w == 0) continue;
+      uint32_t o = s_v[k * 256 + threadIdx.x];
+      if (r.z == 0) {   // big: emit_big writes its pairs
+        offsets[g] = o;
+        continue;
+      }
+      const int x0 = r.x & 0xFFFF, y0 = r.x >> 16, w = (int)(r.y & 0xFFFF) - x0 + 1;
+      const uint64_t wmask = (1ull << w) - 1ull;
+      uint64_t bits = r.z;
+      for (int ty = y0; bits; ++ty, bits >>= w) {
+        uint32_t rb = (uint32_t)(bits & wmask);
+        while (rb) {
+          const int b = __ffs(rb) - 1;
+          rb &= rb - 1;
+          const uint32_t t = (uint32_t)(ty * tiles_x + x0 + b);
+          if (o < cap) {
+            tkey[o] = t;
+            tval[o] = g;
+            atomicAdd(&s_hist[0][t & m0], 1u);
+            atomicAdd(&s_hist[1][(t >> bits0) & 255u], 1u);
+          }
+          ++o;
+        }
       }
     }
     if (part == n_parts - 1 && threadIdx.x == 0) {
@@ -380,50 +417,6 @@ __global__ __launch_bounds__(256) void pair_scan(const uint32_t* __restrict__ so
       if (total > cap) ctr[C_OVERFLOW] = 1;
     }
     __syncthreads();
-  }
-}
-
-// Pair emission, Gaussians with rects of at most kBigArea tiles: one thread
-// each, tiles in row-major order from offs[g].
-template <bool FILTER>
-__global__ __launch_bounds__(256) void emit_pairs(const uint32_t* __restrict__ sorted_val,
-                                                  const uint32_t* __restrict__ offs,
-                                                  const float4* __restrict__ pg0, const float4* __restrict__ pg1,
-                                                  const uint32_t* __restrict__ prect,
-                                                  const uint32_t* __restrict__ prect2,
-                                                  const float* __restrict__ prelax, int W, int H, int tiles_x,
-                                                  int bits0, uint32_t* __restrict__ tkey, uint32_t* __restrict__ tval,
-                                                  uint32_t* ctr, uint32_t* hist, uint32_t cap, uint32_t n_g) {
-  __shared__ uint32_t s_hist[2][256];
-  for (int i = threadIdx.x; i < 512; i += blockDim.x) (&s_hist[0][0])[i] = 0;
-  __syncthreads();
-  const uint32_t n = ctr[C_NVIS];
-  const uint32_t m0 = (1u << bits0) - 1u;
-  for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
-    const uint32_t g = sorted_val[r];
-    if (g >= n_g) continue;
-    const uint32_t a = prect[g], b = prect2[g];
-    const int x0 = a & 0xFFFF, y0 = a >> 16, x1 = b & 0xFFFF, y1 = b >> 16;
-    if ((uint32_t)(x1 - x0 + 1) * (uint32_t)(y1 - y0 + 1) > kBigArea) continue;   // emit_big
-    uint32_t o = offs[g];
-    const float relax = prelax[g];
-    float4 p0, p1;
-    if (FILTER) {
-      p0 = pg0[g];
-      p1 = pg1[g];
-    }
-    for (int ty = y0; ty <= y1; ++ty)
-      for (int tx = x0; tx <= x1; ++tx) {
-        if (FILTER && relax < 0.25f && !tile_keep(p0, p1, relax, tx, ty, W, H)) continue;
-        const uint32_t t = (uint32_t)(ty * tiles_x + tx);
-        if (o < cap) {
-          tkey[o] = t;
-          tval[o] = g;
-          atomicAdd(&s_hist[0][t & m0], 1u);
-          atomicAdd(&s_hist[1][(t >> bits0) & 255u], 1u);
-        }
-        ++o;
-      }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < 512; i += blockDim.x) {
@@ -436,10 +429,8 @@ __global__ __launch_bounds__(256) void emit_pairs(const uint32_t* __restrict__ s
 // tiles of each 256-tile chunk are placed by a block scan (row-major order).
 template <bool FILTER>
 __global__ __launch_bounds__(256) void emit_big(const uint32_t* __restrict__ big, const uint32_t* __restrict__ offs,
-                                                const uint32_t* __restrict__ pcount,
+                                                const uint4* __restrict__ prec,
                                                 const float4* __restrict__ pg0, const float4* __restrict__ pg1,
-                                                const uint32_t* __restrict__ prect,
-                                                const uint32_t* __restrict__ prect2,
                                                 const float* __restrict__ prelax, int W, int H, int tiles_x,
                                                 int bits0, uint32_t* __restrict__ tkey, uint32_t* __restrict__ tval,
                                                 uint32_t* ctr, uint32_t* hist, uint32_t cap, uint32_t n_g) {
@@ -451,9 +442,10 @@ __global__ __launch_bounds__(256) void emit_big(const uint32_t* __restrict__ big
   const uint32_t m0 = (1u << bits0) - 1u;
   for (uint32_t bi = blockIdx.x; bi < nb; bi += gridDim.x) {
     const uint32_t g = big[bi];
-    if (g >= n_g || pcount[g] == 0) continue;   // uniform over the block
-    const uint32_t a = prect[g], e = prect2[g];
-    const int x0 = a & 0xFFFF, y0 = a >> 16, x1 = e & 0xFFFF, y1 = e >> 16;
+    if (g >= n_g) continue;
+    const uint4 r = prec[g];
+    if (r.w == 0) continue;   // uniform over the block
+    const int x0 = r.x & 0xFFFF, y0 = r.x >> 16, x1 = r.y & 0xFFFF, y1 = r.y >> 16;
     const int w = x1 - x0 + 1, area = w * (y1 - y0 + 1);
     const float4 p0 = pg0[g], p1 = pg1[g];
     const float relax = prelax[g];
@@ -1175,7 +1167,7 @@ size_t vy_render_workspace_bytes(int64_t max_g, int32_t max_w, int32_t max_h, in
   if (max_g < 1 || max_w < 1 || max_h < 1 || max_pairs < 1) return 0;
   const int64_t tiles = cdiv(max_w, kTileSize) * cdiv(max_h, kTileSize);
   size_t b = 0;
-  b += (size_t)max_g * (16 * 3 + 4 * 10);  // pg0..2, rect x2, count, relax, big, offsets, dkey x2, dval x2
+  b += (size_t)max_g * (16 * 4 + 4 * 7);   // pg0..2, prec, relax, big, offsets, dkey x2, dval x2
   b += (size_t)max_pairs * 4 * 4;                          // tkey x2, tval x2
   b += (size_t)tiles * 8;
   b += 64 * 4 + 6 * 256 * 4;
@@ -1210,9 +1202,7 @@ int vy_render_ctx_create(int64_t max_g, int32_t max_w, int32_t max_h, int64_t ma
   c->pg0 = cv.take<float4>(max_g);
   c->pg1 = cv.take<float4>(max_g);
   c->pg2 = cv.take<float4>(max_g);
-  c->prect = cv.take<uint32_t>(max_g);
-  c->prect2 = cv.take<uint32_t>(max_g);
-  c->pcount = cv.take<uint32_t>(max_g);
+  c->prec = cv.take<uint4>(max_g);
   c->prelax = cv.take<float>(max_g);
   c->big = cv.take<uint32_t>(max_g);
   c->offsets = cv.take<uint32_t>(max_g);
@@ -1312,16 +1302,15 @@ int vy_render(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, co
     const int blocks = imin(cdiv(c->max_g, 256), 2048);
     if (filter)
       project<true><<<blocks, 256, 0, st>>>(cut_ids, (const int32_t*)n_cut, s->gauss, s->sh, rc, c->pg0, c->pg1,
-                                            c->pg2, c->prect, c->prect2, c->prelax, c->pcount, c->dkey[0], c->ctr,
+                                            c->pg2, c->prec, c->prelax, c->dkey[0], c->ctr,
                                             c->hist, s->n, c->big);
     else
       project<false><<<blocks, 256, 0, st>>>(cut_ids, (const int32_t*)n_cut, s->gauss, s->sh, rc, c->pg0, c->pg1,
-                                             c->pg2, c->prect, c->prect2, c->prelax, c->pcount, c->dkey[0], c->ctr,
+                                             c->pg2, c->prec, c->prelax, c->dkey[0], c->ctr,
                                              c->hist, s->n, c->big);
     VY_LAUNCHED();
     if (filter) {
-      big_count<<<512, 256, 0, st>>>(c->big, c->ctr, c->pg0, c->pg1, c->prect, c->prect2, c->prelax, rc.W, rc.H,
-                                     c->pcount, gcap);
+      big_count<<<512, 256, 0, st>>>(c->big, c->ctr, c->pg0, c->pg1, c->prec, c->prelax, rc.W, rc.H, gcap);
       VY_LAUNCHED();
     }
   }
@@ -1342,33 +1331,20 @@ int vy_render(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, co
   }
   // sorted order now in dkey[0] / dval[0]; the first C_NVIS entries are the visible Gaussians
   {
-    ProfScope ps(VY_STAGE_PAIR_SCAN, st);
+    // pair scan + emission in depth order, then the big Gaussians' pairs
+    ProfScope ps(VY_STAGE_EMIT, st);
     uint32_t ep;
     if (int rcode = epoch_for(c, st, &ep)) return rcode;
     const int blocks = imin(cdiv(c->max_g, kScanTile), 1024);
-    pair_scan<<<blocks, 256, 0, st>>>(c->dval[0], c->pcount, c->offsets, c->ctr, c->status, ep, pcap, gcap);
+    pair_emit<<<blocks, 256, 0, st>>>(c->dval[0], c->prec, c->offsets, c->ctr, c->status, ep, rc.tiles_x, bits0,
+                                      c->tkey[0], c->tval[0], c->hist, pcap, gcap);
     VY_LAUNCHED();
-  }
-  {
-    ProfScope ps(VY_STAGE_EMIT, st);
-    const int blocks = imin(cdiv(c->max_g, 256), 2048);
-    if (filter) {
-      emit_pairs<true><<<blocks, 256, 0, st>>>(c->dval[0], c->offsets, c->pg0, c->pg1, c->prect, c->prect2,
-                                               c->prelax, rc.W, rc.H, rc.tiles_x, bits0, c->tkey[0], c->tval[0],
-                                               c->ctr, c->hist, pcap, gcap);
-      VY_LAUNCHED();
-      emit_big<true><<<512, 256, 0, st>>>(c->big, c->offsets, c->pcount, c->pg0, c->pg1, c->prect, c->prect2,
-                                          c->prelax, rc.W, rc.H, rc.tiles_x, bits0, c->tkey[0], c->tval[0], c->ctr,
-                                          c->hist, pcap, gcap);
-    } else {
-      emit_pairs<false><<<blocks, 256, 0, st>>>(c->dval[0], c->offsets, c->pg0, c->pg1, c->prect, c->prect2,
-                                                c->prelax, rc.W, rc.H, rc.tiles_x, bits0, c->tkey[0], c->tval[0],
-                                                c->ctr, c->hist, pcap, gcap);
-      VY_LAUNCHED();
-      emit_big<false><<<512, 256, 0, st>>>(c->big, c->offsets, c->pcount, c->pg0, c->pg1, c->prect, c->prect2,
-                                           c->prelax, rc.W, rc.H, rc.tiles_x, bits0, c->tkey[0], c->tval[0], c->ctr,
-                                           c->hist, pcap, gcap);
-    }
+    if (filter)
+      emit_big<true><<<512, 256, 0, st>>>(c->big, c->offsets, c->prec, c->pg0, c->pg1, c->prelax, rc.W, rc.H,
+                                          rc.tiles_x, bits0, c->tkey[0], c->tval[0], c->ctr, c->hist, pcap, gcap);
+    else
+      emit_big<false><<<512, 256, 0, st>>>(c->big, c->offsets, c->prec, c->pg0, c->pg1, c->prelax, rc.W, rc.H,
+                                           rc.tiles_x, bits0, c->tkey[0], c->tval[0], c->ctr, c->hist, pcap, gcap);
     VY_LAUNCHED();
   }
   {
@@ -1474,14 +1450,13 @@ int vy_render_pairs(const vy_render_ctx* ctx, const uint32_t** tile_keys, const 
 }
 
 int vy_render_projected(const vy_render_ctx* ctx, const float** rec0, const float** rec1, const float** rec2,
-                        const uint32_t** rect_lo, const uint32_t** rect_hi) {
+                        const uint32_t** bin_rec) {
   const RenderCtx* c = (const RenderCtx*)ctx;
   if (!c || c->magic != kCtxMagic) return fail(VY_ERR_ARG, "vy_render_projected: bad argument");
   if (rec0) *rec0 = reinterpret_cast<const float*>(c->pg0);
   if (rec1) *rec1 = reinterpret_cast<const float*>(c->pg1);
   if (rec2) *rec2 = reinterpret_cast<const float*>(c->pg2);
-  if (rect_lo) *rect_lo = c->prect;
-  if (rect_hi) *rect_hi = c->prect2;
+  if (bin_rec) *bin_rec = reinterpret_cast<const uint32_t*>(c->prec);
   return VY_OK;
 }
 

@@ -101,7 +101,7 @@ __global__ __launch_bounds__(kThreads) void onesweep_pass(const uint32_t* __rest
     const uint32_t dstart = block_excl_scan256(dtot, s_scan, &btot);
     s_dstart[tid] = dstart;
     {
-      const uint64_t ex = lookback(status + tid, part, 256, epoch, dtot, err);
+      const uint64_t ex = lookback_k<8>(status + tid, part, 256, epoch, dtot, err);
       s_gofs[tid] = s_gstart[tid] + (uint32_t)ex - dstart;
     }
     __syncthreads();

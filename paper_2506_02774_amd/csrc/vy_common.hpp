@@ -104,9 +104,8 @@ struct RenderCtx {
   float4* pg0;          // {mean2d.x, mean2d.y, conic.a, conic.b}
   float4* pg1;          // {conic.c, theta, rho threshold (filter), depth}
   float4* pg2;          // {r, g, b, 0}
-  uint32_t* prect;      // packed tile rect x0 | y0 << 16, (x1, y1) in prect2
-  uint32_t* prect2;
-  uint32_t* pcount;     // pairs per Gaussian
+  uint4* prec;          // binning record {x0 | y0 << 16, x1 | y1 << 16 (inclusive tile rect),
+                        //   kept-tile mask (rect of <= 32 tiles, row-major bits; 0 = big), pair count}
   float* prelax;        // per-Gaussian rounding allowance of the tile test
   uint32_t* big;        // cut positions of Gaussians binned by a whole workgroup
   // depth sort
@@ -204,6 +203,105 @@ VY_DEV uint64_t lookback(uint64_t* status, uint32_t part, uint32_t stride, uint3
     excl += w & ((1ull << 38) - 1);
     if (flag == kFlagInc) break;
     --j;
+  }
+  st_rel(me, pack_status(epoch, kFlagInc, excl + aggregate));
+  return excl;
+}
+
+// Decoupled look-back by one whole wave (all 64 lanes call it): lane l polls
+// predecessor part-1-l, so each step covers 64 predecessors with independent
+// loads instead of one. The nearest inclusive prefix among them ends the walk
+// (virtual inclusive 0 before partition 0). Returns the exclusive prefix in
+// every lane; lane 0 publishes the aggregate first and the inclusive prefix
+// last.
+VY_DEV uint64_t lookback_wave(uint64_t* status, uint32_t part, uint32_t stride, uint32_t epoch,
+                              uint64_t aggregate, uint32_t* err) {
+  const uint32_t l = lane();
+  uint64_t* me = status + (uint64_t)part * stride;
+  if (part == 0) {
+    if (l == 0) st_rel(me, pack_status(epoch, kFlagInc, aggregate));
+    return 0;
+  }
+  if (l == 0) st_rel(me, pack_status(epoch, kFlagAgg, aggregate));
+  uint64_t excl = 0;
+  int64_t hi = (int64_t)part - 1;
+  uint32_t spins = 0;
+  for (;;) {
+    const int64_t j = hi - (int64_t)l;
+    uint64_t val = 0;
+    bool valid = true, inc = true;
+    if (j >= 0) {
+      const uint64_t w = ld_acq(status + (uint64_t)j * stride);
+      const uint64_t flag = (w >> 38) & 3ull;
+      valid = (uint32_t)(w >> 40) == epoch && flag != 0;
+      inc = valid && flag == kFlagInc;
+      val = w & ((1ull << 38) - 1);
+    }
+    const uint64_t inc_m = ballot(inc), bad_m = ballot(!valid);
+    const int k = inc_m ? __builtin_ctzll(inc_m) : 64;          // nearest inclusive
+    const uint64_t need = k >= 63 ? ~0ull : ((2ull << k) - 1ull);  // lanes 0..k
+    if (bad_m & need) {
+      if (++spins > kSpinLimit) {
+        if (l == 0) fetch_add(err, 1u);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    uint64_t v = (int)l <= k ? val : 0ull;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const uint32_t lo = __shfl_xor((uint32_t)v, o, 64), hi32 = __shfl_xor((uint32_t)(v >> 32), o, 64);
+      v += ((uint64_t)hi32 << 32) | lo;
+    }
+    excl += v;
+    if (k < 64) break;
+    hi -= 64;
+  }
+  if (l == 0) st_rel(me, pack_status(epoch, kFlagInc, excl + aggregate));
+  return excl;
+}
+
+// Decoupled look-back by one thread that polls K predecessors per step with
+// independent loads (for the per-digit chains of the radix sort, where every
+// thread walks its own chain).
+template <int K>
+VY_DEV uint64_t lookback_k(uint64_t* status, uint32_t part, uint32_t stride, uint32_t epoch, uint64_t aggregate,
+                           uint32_t* err) {
+  uint64_t* me = status + (uint64_t)part * stride;
+  if (part == 0) {
+    st_rel(me, pack_status(epoch, kFlagInc, aggregate));
+    return 0;
+  }
+  st_rel(me, pack_status(epoch, kFlagAgg, aggregate));
+  uint64_t excl = 0;
+  int64_t j = (int64_t)part - 1;
+  uint32_t spins = 0;
+  while (j >= 0) {
+    uint64_t w[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) w[i] = j - i >= 0 ? ld_acq(status + (uint64_t)(j - i) * stride) : 0ull;
+    bool done = false, stall = false;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      if (done || stall || j < 0) continue;
+      const uint64_t flag = (w[i] >> 38) & 3ull;
+      if ((uint32_t)(w[i] >> 40) != epoch || flag == 0) {
+        stall = true;   // poll again from predecessor j
+        continue;
+      }
+      excl += w[i] & ((1ull << 38) - 1);
+      if (flag == kFlagInc) done = true;
+      else --j;
+    }
+    if (done) break;
+    if (stall) {
+      if (++spins > kSpinLimit) {
+        fetch_add(err, 1u);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
   }
   st_rel(me, pack_status(epoch, kFlagInc, excl + aggregate));
   return excl;

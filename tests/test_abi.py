@@ -61,3 +61,25 @@ def test_argument_errors_without_gpu():
     assert L.vy_render_ctx_create(10, 64, 64, 100, None, 0, ctypes.byref(h)) == vy.VY_ERR_ARG
     assert L.vy_profile_begin(0) == vy.VY_ERR_ARG
     assert L.vy_stage_name(13) == b"blend" and L.vy_stage_name(12) == b"blend_plan" and L.vy_stage_name(99) == b"?"
+
+
+def declared_arity():
+    """Parameter count of every function declared in include/vy.h."""
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    out = {}
+    for name, params in re.findall(r"\b(vy_[a-z0-9_]+)\s*\(([^()]*)\)\s*;", src):
+        p = params.strip()
+        out[name] = 0 if p in ("", "void") else p.count(",") + 1
+    return out
+
+
+def test_binding_matches_header_arity():
+    """The ctypes signatures of the binding take exactly the parameters that the
+    header declares (a mismatch would only show up as a failed call on a GPU)."""
+    vy, L = _lib()
+    decl = declared_arity()
+    assert len(decl) >= 20
+    for name, n in decl.items():
+        f = getattr(L, name)
+        assert f.argtypes is not None, name
+        assert len(f.argtypes) == n, (name, len(f.argtypes), n)

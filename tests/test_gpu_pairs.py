@@ -27,7 +27,8 @@ def frame(tiny_scene, tiny_cams):
 def test_projection_matches_oracle(frame):
     vy, sc, host, ctx, cam, cut, C = frame
     vy.vy_render(sc, cut, cam, ctx)
-    r0, r1, r2, lo, hi = ctx.projected(len(C))
+    r0, r1, r2, br = ctx.projected(len(C))
+    lo, hi = br[:, 0], br[:, 1]
     p = oproj.project(host, C, cam)
     gv = (lo != 0) | (hi != 0) | (r1[:, 3] > 0)
     both = gv & p["valid"]
@@ -58,7 +59,8 @@ def test_sorted_pairs(frame, filt):
     vy, sc, host, ctx, cam, cut, C = frame
     vy.vy_render(sc, cut, cam, ctx, alpha_filter=filt)
     keys, vals, ranges = ctx.pairs(cam.width, cam.height)
-    r0, r1, r2, lo, hi = ctx.projected(len(C))
+    r0, r1, r2, br = ctx.projected(len(C))
+    lo, hi, mask, count = br[:, 0], br[:, 1], br[:, 2], br[:, 3]
     tx_n = (cam.width + 15) // 16
     # ranges partition the pair list by tile, in tile order
     nz = ranges[:, 1] > ranges[:, 0]
@@ -85,3 +87,18 @@ def test_sorted_pairs(frame, filt):
         assert got <= exp
     else:
         assert got == exp
+    # pair counts: per Gaussian, as many pairs as its record says; for rects of
+    # at most 32 tiles exactly the tiles of its kept-tile mask (row-major bits)
+    per_g = np.bincount(vals, minlength=len(C))
+    assert np.array_equal(per_g, count.astype(np.int64))
+    w = (hi & 0xFFFF).astype(np.int64) - (lo & 0xFFFF) + 1
+    h = (hi >> 16).astype(np.int64) - (lo >> 16) + 1
+    small = (count > 0) & (w * h <= 32)
+    assert small.sum() > 0 and np.all(mask[(count > 0) & ~small] == 0)
+    bits = {}
+    for t, g in got:
+        if small[g]:
+            x0, y0 = lo[g] & 0xFFFF, lo[g] >> 16
+            k = (t // tx_n - y0) * w[g] + (t % tx_n - x0)
+            bits[g] = bits.get(g, 0) | (1 << int(k))
+    assert all(bits.get(int(g), 0) == int(mask[g]) for g in np.nonzero(small)[0])
