@@ -180,6 +180,11 @@ typedef struct vy_render_opts {
                               workgroups over depth bins, then composited (0: no
                               splitting). The image is bitwise the same for any
                               value; splitting forgoes early termination. */
+  int32_t walk;         /* how a band of 16x4 pixels walks its tile list: 0 (auto)
+                           per chunk of 64 entries, all pixels together when
+                           most entries cover most pixels, else each pixel over
+                           its own entries; 1: always together; 2: always per
+                           pixel. The image is bitwise the same for any value. */
 } vy_render_opts;
 
 typedef struct vy_render_ctx vy_render_ctx;

@@ -517,29 +517,28 @@ constexpr int kHeavyRec = 4 + (kMaxBins + 1) + kMaxBins;   // tile, nb, slot bas
 
 VY_DEV uint32_t depth_bin(float z) { return __float_as_uint(z) >> 19; }
 
-// Does the Gaussian's pixel box (half-extents packed in `ext` as rx | ry << 16)
-// reach the 16x4 band of pixel centres starting at (xa, ya)?
+// Pixel rule of the blend: Gaussian i is evaluated at pixel centre f only when
+// |mean2d - f| <= (rx, ry) per axis, the half-extents of its pixel box, with
+// the differences computed exactly as for rho. Outside the box alpha < alpha*
+// (and with the filter, Eq. 4 fails), so the rule removes only evaluations
+// that cannot blend; stating it explicitly makes every walk of a tile list
+// (per band, per pixel, split by depth) evaluate the same (Gaussian, pixel)
+// pairs bit for bit.
+//
+// Can the pixel box (half-extents packed in `ext` as rx | ry << 16) hold a
+// pixel centre of the 16x4 band starting at (xa, ya)? A half-pixel slack makes
+// this a superset of the pixel rule under rounding.
 VY_DEV bool band_hit(float mx, float my, float ext, float xa, float ya) {
   const uint32_t e = __float_as_uint(ext);
-  const float rx = (float)(e & 0xFFFFu), ry = (float)(e >> 16);
+  const float rx = (float)(e & 0xFFFFu) + 0.5f, ry = (float)(e >> 16) + 0.5f;
   return (mx + rx >= xa) && (mx - rx <= xa + 15.f) && (my + ry >= ya) && (my - ry <= ya + 3.f);
 }
 
-// alpha of Gaussian (p0, p1) at pixel centre (fx, fy); false if it is skipped
-// (alpha < alpha*, detected by Eq. 4 before the exponential when filtering).
-template <bool FILTER>
-VY_DEV bool eval_alpha(const float4 p0, const float4 p1, float fx, float fy, float& alpha) {
-  const float dx = p0.x - fx, dy = p0.y - fy;
-  float power = fmaf(dx, fmaf(p0.z, dx, p0.w * dy), (p1.x * dy) * dy);
-  power = fminf(power, 0.f);
-  if (FILTER && power < p1.z) return false;   // log(alpha*) - log(theta) > rho
-  alpha = fminf(kAlphaMax, p1.y * __expf(power));
-  return alpha >= kAlphaMin;
-}
-
-// LDS staging of pairs [b0, min(b0 + 256, pe)) of a tile: records in s0..s2,
-// depth-bin keys in s_key, and per band the ordered list of the batch entries
-// whose pixel box reaches it. Returns this wave's list length.
+// LDS staging of pairs [b0, min(b0 + 256, pe)) of a tile: records in s0..s2
+// (with the pixel box half-extents as floats, ry in s1.w and rx in s2.w, in
+// place of the depth and the packed extents), and per band the ordered list of
+// (depth bin << 8 | batch index) of the entries whose pixel box may reach it.
+// Returns this wave's list length.
 struct Stage {
   float4 s0[256], s1[256], s2[256];
   uint32_t list[4][256];   // (depth bin << 8) | batch index, in depth order
@@ -556,9 +555,10 @@ VY_DEV int stage_batch(Stage& S, uint32_t b0, uint32_t pe, const uint32_t* __res
     uint32_t g = tval[idx];
     if (g >= n_g) g = 0;
     const float4 a = pg0[g], b = pg1[g], c = pg2[g];
+    const uint32_t ex = __float_as_uint(c.w);
     S.s0[threadIdx.x] = a;
-    S.s1[threadIdx.x] = b;
-    S.s2[threadIdx.x] = c;
+    S.s1[threadIdx.x] = make_float4(b.x, b.y, b.z, (float)(ex >> 16));      // .w = ry
+    S.s2[threadIdx.x] = make_float4(c.x, c.y, c.z, (float)(ex & 0xFFFFu));  // .w = rx
     key = depth_bin(b.w);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
@@ -767,7 +767,7 @@ VY_DEV void blend_one(uint32_t key, const float4 p0, const float4 p1, const floa
   // rho = A dx^2 + B dx dy + C dy^2, clamped to <= 0
   float power = fmaf(dx, fmaf(p0.z, dx, p0.w * dy), (p1.x * dy) * dy);
   power = fminf(power, 0.f);
-  bool live = !A.done;
+  bool live = !A.done && fabsf(dx) <= p2.w && fabsf(dy) <= p1.w;   // pixel rule
   if (FILTER) live = live && power >= p1.z;   // Eq. 4: rho < log(alpha*) - log(theta) => skip
   if (__ballot(live) == 0ull) return;        // the exponential is needed by no pixel of the band
   const float alpha = fminf(kAlphaMax, p1.y * __expf(power));
@@ -785,6 +785,82 @@ VY_DEV void blend_one(uint32_t key, const float4 p0, const float4 p1, const floa
   A.done = A.done || stop;
 }
 
+// Per-pixel walk of up to 64 band-list entries [jj, jj + m) (one-piece mode):
+// each lane visits, in list order, only the entries that pass the pixel rule
+// at its own pixel centre (bits of `mk`). The depth bins that the skipped
+// entries would have opened and left empty fold as exact no-ops (C + T 0 = C,
+// T 1 = T), so the result is bitwise that of the band walk.
+template <bool FILTER, bool SAVE>
+VY_DEV void blend_sparse(const Stage& S, int w, int jj, uint64_t mk, uint32_t b0, float fxp, float fyp, PixAcc& A) {
+  while (__ballot(mk != 0ull) != 0ull) {
+    if (mk == 0ull) continue;
+    const int k = __builtin_ctzll(mk);
+    mk &= mk - 1ull;
+    const uint32_t e = S.list[w][jj + k];
+    const uint32_t j = e & 255u, key = e >> 8;
+    const float4 p0 = S.s0[j], p1 = S.s1[j], p2 = S.s2[j];
+    if (key != A.cur_key) {
+      A.C0 = fmaf(A.Tt, A.Cb0, A.C0);
+      A.C1 = fmaf(A.Tt, A.Cb1, A.C1);
+      A.C2 = fmaf(A.Tt, A.Cb2, A.C2);
+      A.Tt = A.Tt * A.Tb;
+      A.nt += A.nb;
+      A.Tb = 1.f;
+      A.Cb0 = A.Cb1 = A.Cb2 = 0.f;
+      A.nb = 0;
+      A.cur_key = key;
+    }
+    const float dx = p0.x - fxp, dy = p0.y - fyp;
+    const float power = fminf(fmaf(dx, fmaf(p0.z, dx, p0.w * dy), (p1.x * dy) * dy), 0.f);
+    if (FILTER && power < p1.z) continue;   // Eq. 4 before the exponential
+    const float alpha = fminf(kAlphaMax, p1.y * __expf(power));
+    if (alpha < kAlphaMin) continue;
+    const float Tn = A.Tb * (1.f - alpha);
+    if (A.Tt * Tn < kTMin) {
+      if (SAVE) A.stop_pos = b0 + j;
+      A.done = true;
+      mk = 0ull;
+      continue;
+    }
+    const float wgt = alpha * A.Tb;
+    A.Cb0 = fmaf(wgt, p2.x, A.Cb0);
+    A.Cb1 = fmaf(wgt, p2.y, A.Cb1);
+    A.Cb2 = fmaf(wgt, p2.z, A.Cb2);
+    A.Tb = Tn;
+    A.nb += 1;
+  }
+}
+
+// Coverage masks of band-list entries [jj, jj + m) for the wave's pixels: bit
+// k of lane (c, r) is set when entry jj + k passes the pixel rule at the pixel
+// centre (xa + c, ya + r).
+VY_DEV uint64_t cover_masks(const Stage& S, int w, int jj, int m, float xa, float ya, int l) {
+  float mx = 0.f, my = 0.f, rx = -1.f, ry = -1.f;   // empty box for lanes past the chunk
+  if (l < m) {
+    const uint32_t j = S.list[w][jj + l] & 255u;
+    const float4 a = S.s0[j];
+    mx = a.x;
+    my = a.y;
+    rx = S.s2[j].w;
+    ry = S.s1[j].w;
+  }
+  const int c = l & 15, r = l >> 4;
+  uint64_t mc = 0ull, mr = 0ull;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const float f = xa + (float)i;   // the pixel centre, exactly as the blend forms it
+    const uint64_t b = __ballot(fabsf(mx - f) <= rx);
+    mc = c == i ? b : mc;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float f = ya + (float)i;
+    const uint64_t b = __ballot(fabsf(my - f) <= ry);
+    mr = r == i ? b : mr;
+  }
+  return mc & mr;
+}
+
 // Blend pairs [pb, pe) of tile (tx, ty) into A. SPLIT: per-bin results go to
 // `so` and a pixel stops only when its own bin's T falls below 1e-4 (marking
 // the bin with T = 0 for the composite); otherwise bins are combined in place.
@@ -796,15 +872,32 @@ template <bool FILTER, bool SPLIT, bool SAVE>
 VY_DEV void blend_range(Stage& S, uint32_t pb, uint32_t pe, const uint32_t* __restrict__ tval,
                         const float4* __restrict__ pg0, const float4* __restrict__ pg1,
                         const float4* __restrict__ pg2, uint32_t n_g, int tx, int ty, float fxp, float fyp,
-                        PixAcc& A, const SplitOut& so) {
+                        PixAcc& A, const SplitOut& so, int walk) {
   const int w = threadIdx.x >> 6;
   for (uint32_t b0 = pb; b0 < pe; b0 += 256) {
     if (__syncthreads_count(A.done) == 256) break;
     const int cnt = stage_batch(S, b0, pe, tval, pg0, pg1, pg2, n_g, tx, ty);
-    for (int jj = 0; jj < cnt; jj += 4) {
+    for (int jc = 0; jc < cnt; jc += 64) {
+     const int mc = cnt - jc < 64 ? cnt - jc : 64;
+     if (!SPLIT && walk != 1) {
+       // small pixel boxes (far Gaussians) cover few pixels of the band: then
+       // every pixel walks only its own entries of this chunk
+       if (__ballot(!A.done) == 0ull) break;
+       uint64_t mk = cover_masks(S, w, jc, mc, tx * kTileSize + 0.5f, ty * kTileSize + w * 4 + 0.5f,
+                                 (int)(threadIdx.x & 63));
+       if (A.done) mk = 0ull;
+       int mx = __popcll(mk);
+#pragma unroll
+       for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+       if (walk == 2 || mx * 5 < mc * 3) {
+         blend_sparse<FILTER, SAVE>(S, w, jc, mk, b0, fxp, fyp, A);
+         continue;
+       }
+     }
+     for (int jj = jc; jj < jc + mc; jj += 4) {
       if (__ballot(!A.done) == 0ull) break;   // the whole band has terminated
       const uint4 e4 = *reinterpret_cast<const uint4*>(&S.list[w][jj]);
-      const int m = cnt - jj < 4 ? cnt - jj : 4;
+      const int m = jc + mc - jj < 4 ? jc + mc - jj : 4;
       const uint32_t e[4] = {(uint32_t)__builtin_amdgcn_readfirstlane(e4.x),
                              (uint32_t)__builtin_amdgcn_readfirstlane(e4.y),
                              (uint32_t)__builtin_amdgcn_readfirstlane(e4.z),
@@ -828,7 +921,7 @@ VY_DEV void blend_range(Stage& S, uint32_t pb, uint32_t pe, const uint32_t* __re
         for (int k = 0; k < 4; ++k) {
           const float dx = q0[k].x - fxp, dy = q0[k].y - fyp;
           pw[k] = fminf(fmaf(dx, fmaf(q0[k].z, dx, q0[k].w * dy), (q1[k].x * dy) * dy), 0.f);
-          lv[k] = !A.done;
+          lv[k] = !A.done && fabsf(dx) <= q2[k].w && fabsf(dy) <= q1[k].w;   // pixel rule
           if (FILTER) lv[k] = lv[k] && pw[k] >= q1[k].z;   // Eq. 4 before the exponential
           any = any || lv[k];
         }
@@ -856,6 +949,7 @@ VY_DEV void blend_range(Stage& S, uint32_t pb, uint32_t pe, const uint32_t* __re
         for (int k = 0; k < 4; ++k)
           if (k < m) blend_one<FILTER, SPLIT, SAVE>(e[k] >> 8, q0[k], q1[k], q2[k], fxp, fyp, A, so, b0 + (e[k] & 255u));
       }
+     }
     }
     __syncthreads();
   }
@@ -872,7 +966,7 @@ __global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ rang
                                                   int32_t* __restrict__ bin_n, uint32_t* ctr, uint32_t n_g,
                                                   uint32_t n_pairs_cap, float* __restrict__ img,
                                                   float* __restrict__ Tout, int32_t* __restrict__ Nout,
-                                                  int32_t* __restrict__ Eout) {
+                                                  int32_t* __restrict__ Eout, int walk) {
   __shared__ Stage S;
   __shared__ uint32_t s_job;
   __shared__ uint32_t s_bkey[kMaxBins];
@@ -944,7 +1038,7 @@ __global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ rang
     const bool urgent = J < nfirst;
     if (urgent) __builtin_amdgcn_s_setprio(3);
     if (split) {
-      blend_range<FILTER, true, false>(S, pb, pe, tval, pg0, pg1, pg2, n_g, tx, ty, fxp, fyp, A, so);
+      blend_range<FILTER, true, false>(S, pb, pe, tval, pg0, pg1, pg2, n_g, tx, ty, fxp, fyp, A, so, 1);
       // the current bin, then bins without Gaussians for this band up to the job's end
       if (A.cur_key != 0xFFFFFFFFu && A.lb < so.lbin1) {
         put_bin(so, A.lb, make_float4(A.Cb0, A.Cb1, A.Cb2, A.Tb), A.nb);
@@ -952,7 +1046,7 @@ __global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ rang
       }
       for (; A.lb < so.lbin1; ++A.lb) put_bin(so, A.lb, make_float4(0.f, 0.f, 0.f, 1.f), 0);
     } else {
-      blend_range<FILTER, false, SAVE>(S, pb, pe, tval, pg0, pg1, pg2, n_g, tx, ty, fxp, fyp, A, so);
+      blend_range<FILTER, false, SAVE>(S, pb, pe, tval, pg0, pg1, pg2, n_g, tx, ty, fxp, fyp, A, so, walk);
       if (inside) {
         A.C0 = fmaf(A.Tt, A.Cb0, A.C0);
         A.C1 = fmaf(A.Tt, A.Cb1, A.C1);
@@ -1072,7 +1166,7 @@ __global__ __launch_bounds__(256) void composite_redo(const uint32_t* __restrict
                                                       const uint2* __restrict__ redo, const uint32_t* ctr,
                                                       uint32_t n_g, uint32_t n_pairs_cap, float* __restrict__ img,
                                                       float* __restrict__ Tout, int32_t* __restrict__ Nout,
-                                                      int32_t* __restrict__ Eout) {
+                                                      int32_t* __restrict__ Eout, int walk) {
   __shared__ Stage S;
   uint32_t nu = ctr[C_NREDO];
   if (nu > kMaxBinSlots) nu = kMaxBinSlots;
@@ -1104,7 +1198,8 @@ __global__ __launch_bounds__(256) void composite_redo(const uint32_t* __restrict
     uint32_t pb = rec[4 + b], pe = rec[4 + b + 1];
     if (pe > n_pairs_cap) pe = n_pairs_cap;
     if (pb > pe) pb = pe;
-    blend_range<FILTER, false, false>(S, pb, pe, tval, pg0, pg1, pg2, n_g, tx, ty, px + 0.5f, py + 0.5f, A, so);
+    blend_range<FILTER, false, false>(S, pb, pe, tval, pg0, pg1, pg2, n_g, tx, ty, px + 0.5f, py + 0.5f, A, so,
+                                      walk);
     if (mine) {
       A.C0 = fmaf(A.Tt, A.Cb0, A.C0);
       A.C1 = fmaf(A.Tt, A.Cb1, A.C1);
@@ -1283,6 +1378,8 @@ int vy_render(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, co
                 (long long)s->n);
   const bool filter = opts && opts->alpha_filter;
   const bool save = opts && opts->save_state;
+  const int walk = opts ? opts->walk : 0;
+  if (walk < 0 || walk > 2) return fail(VY_ERR_ARG, "vy_render: walk must be 0, 1 or 2");
   hipStream_t st = (hipStream_t)stream;
   const RCam rc = make_rcam(cam, opts);
   const int ntiles = rc.tiles_x * rc.tiles_y;
@@ -1389,14 +1486,14 @@ int vy_render(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, co
   do {                                                                                                          \
     blend_jobs<F, S><<<2048, 256, 0, st>>>(c->ranges, c->tval[0], c->pg0, c->pg1, c->pg2, rc, ntiles, c->tile_flag, \
                                            c->tiers, c->heavy_rec, c->jobs, c->bin_c, c->bin_n, c->ctr, gcap, pcap,  \
-                                           image, c->T_final, c->n_contrib, c->n_eval);                       \
+                                           image, c->T_final, c->n_contrib, c->n_eval, walk);                 \
     if (split_on) {                                                                                             \
       composite_scan<S><<<256, 256, 0, st>>>(rc, c->tile_flag, c->heavy_rec, c->bin_c, c->bin_n, c->ctr,           \
                                              reinterpret_cast<PixState*>(c->pstate_raw), c->redo, image,         \
                                              c->T_final, c->n_contrib, c->n_eval);                              \
       composite_redo<F, S><<<2048, 256, 0, st>>>(c->tval[0], c->pg0, c->pg1, c->pg2, rc, c->heavy_rec,             \
                                                  reinterpret_cast<const PixState*>(c->pstate_raw), c->redo, c->ctr, \
-                                                 gcap, pcap, image, c->T_final, c->n_contrib, c->n_eval);       \
+                                                 gcap, pcap, image, c->T_final, c->n_contrib, c->n_eval, walk); \
     }                                                                                                           \
   } while (0)
     if (filter) {

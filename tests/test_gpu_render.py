@@ -66,6 +66,12 @@ def test_random_gaussians_ragged_image():
         res = image_parity(a, ref)
         print(bg, res, pa, pb, flush=True)
         assert res["ok"], res
+        # both blend walks on wide anisotropic Gaussians, with and without the filter
+        for filt in (False, True):
+            imgs = [vy.vy_render(sc, cut, cam, ctx, alpha_filter=filt, bg=bg, walk=w).cpu().numpy()
+                    for w in (1, 2)]
+            assert np.array_equal(imgs[0].view(np.uint32), imgs[1].view(np.uint32))
+            assert np.array_equal(imgs[0].view(np.uint32), a.view(np.uint32))
 
 
 def test_empty_cut_gives_background(tiny):
@@ -162,3 +168,24 @@ def test_saved_evaluation_counts(tiny, tiny_cams, filt):
     assert (E2 == -1).any()
     assert (E2[E2 >= 0] == E[E2 >= 0]).all()
     assert ((E2 == -1) | (E2 >= 0)).all()
+
+
+@pytest.mark.parametrize("filt", [False, True])
+def test_walks_are_bitwise_identical(tiny, tiny_cams, filt):
+    """The band walk, the per-pixel walk and the automatic choice between them
+    evaluate the same (Gaussian, pixel) pairs with the same arithmetic: images,
+    final transmittance, contributor and evaluation counts agree bit for bit."""
+    vy, sc, host, ctx = tiny
+    for cam in tiny_cams[::2]:
+        cut = vy.vy_lod_cut(sc, cam, 2.0)
+        out = []
+        for walk in (0, 1, 2):
+            img = vy.vy_render(sc, cut, cam, ctx, alpha_filter=filt, save_state=True, walk=walk).cpu().numpy()
+            vy.check(ctx.status()[0])
+            T, N, E = ctx.saved(cam.width, cam.height, evals=True)
+            out.append((img.view(np.uint32), T.view(np.uint32), N, E))
+        for o in out[1:]:
+            for a, b in zip(out[0], o):
+                assert np.array_equal(a, b)
+    with pytest.raises(vy.VoyagerError):
+        vy.vy_render(sc, cut, tiny_cams[0], ctx, walk=3)
