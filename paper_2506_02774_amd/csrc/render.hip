@@ -534,13 +534,14 @@ VY_DEV bool band_hit(float mx, float my, float ext, float xa, float ya) {
   return (mx + rx >= xa) && (mx - rx <= xa + 15.f) && (my + ry >= ya) && (my - ry <= ya + 3.f);
 }
 
-// LDS staging of pairs [b0, min(b0 + 256, pe)) of a tile: records in s0..s2
-// (with the pixel box half-extents as floats, ry in s1.w and rx in s2.w, in
-// place of the depth and the packed extents), and per band the ordered list of
-// (depth bin << 8 | batch index) of the entries whose pixel box may reach it.
-// Returns this wave's list length.
+// LDS staging of pairs [b0, min(b0 + 256, pe)) of a tile: per band, the
+// ordered list of (depth bin << 8 | batch index) of the entries whose pixel box
+// may reach it, and their records in the same order (r0 = pg0, r1 = pg1 with
+// ry in .w, r2 = pg2 with rx in .w: the pixel box half-extents as floats in
+// place of the depth and the packed extents), so that a band reads an entry's
+// key and record with independent LDS loads. Returns this wave's list length.
 struct Stage {
-  float4 s0[256], s1[256], s2[256];
+  float4 r0[4][256], r1[4][256], r2[4][256];   // records per band, in band-list order
   uint32_t list[4][256];   // (depth bin << 8) | batch index, in depth order
   uint32_t wc[4][4];
 };
@@ -551,14 +552,15 @@ VY_DEV int stage_batch(Stage& S, uint32_t b0, uint32_t pe, const uint32_t* __res
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const uint32_t idx = b0 + threadIdx.x;
   uint32_t qm = 0, key = 0;
+  float4 a, b1, c1;
   if (idx < pe) {
     uint32_t g = tval[idx];
     if (g >= n_g) g = 0;
-    const float4 a = pg0[g], b = pg1[g], c = pg2[g];
+    a = pg0[g];
+    const float4 b = pg1[g], c = pg2[g];
     const uint32_t ex = __float_as_uint(c.w);
-    S.s0[threadIdx.x] = a;
-    S.s1[threadIdx.x] = make_float4(b.x, b.y, b.z, (float)(ex >> 16));      // .w = ry
-    S.s2[threadIdx.x] = make_float4(c.x, c.y, c.z, (float)(ex & 0xFFFFu));  // .w = rx
+    b1 = make_float4(b.x, b.y, b.z, (float)(ex >> 16));      // .w = ry
+    c1 = make_float4(c.x, c.y, c.z, (float)(ex & 0xFFFFu));  // .w = rx
     key = depth_bin(b.w);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
@@ -576,7 +578,11 @@ VY_DEV int stage_batch(Stage& S, uint32_t b0, uint32_t pe, const uint32_t* __res
     if ((qm >> q) & 1u) {
       uint32_t base = 0;
       for (int ww = 0; ww < w; ++ww) base += S.wc[q][ww];
-      S.list[q][base + (uint32_t)__popcll(bal[q] & lanemask_lt())] = (key << 8) | threadIdx.x;
+      const uint32_t pos = base + (uint32_t)__popcll(bal[q] & lanemask_lt());
+      S.list[q][pos] = (key << 8) | threadIdx.x;
+      S.r0[q][pos] = a;
+      S.r1[q][pos] = b1;
+      S.r2[q][pos] = c1;
     }
   }
   __syncthreads();
@@ -711,7 +717,7 @@ struct PixAcc {
 struct SplitOut {           // where split-mode jobs write their per-bin results
   float4* bin_c;
   int32_t* bin_n;
-  const uint32_t* bkey;     // keys of the job's bins (LDS), bkey[lb - lbin0]
+  const uint32_t* bkey;     // keys of the job's bins (heavy record), bkey[lb - lbin0]
   uint32_t slot_base, lbin0, lbin1;
   int pix;
 };
@@ -792,42 +798,69 @@ VY_DEV void blend_one(uint32_t key, const float4 p0, const float4 p1, const floa
 // T 1 = T), so the result is bitwise that of the band walk.
 template <bool FILTER, bool SAVE>
 VY_DEV void blend_sparse(const Stage& S, int w, int jj, uint64_t mk, uint32_t b0, float fxp, float fyp, PixAcc& A) {
+  // Up to four of the lane's entries per step: their records are loaded and
+  // their alphas computed independently; only the transmittance chain is
+  // sequential. A depth bin is opened lazily, at the first entry that blends
+  // in it: nothing changes the pixel's state in between, so the fold is the
+  // same as at the bin's first entry.
   while (__ballot(mk != 0ull) != 0ull) {
-    if (mk == 0ull) continue;
-    const int k = __builtin_ctzll(mk);
-    mk &= mk - 1ull;
-    const uint32_t e = S.list[w][jj + k];
-    const uint32_t j = e & 255u, key = e >> 8;
-    const float4 p0 = S.s0[j], p1 = S.s1[j], p2 = S.s2[j];
-    if (key != A.cur_key) {
-      A.C0 = fmaf(A.Tt, A.Cb0, A.C0);
-      A.C1 = fmaf(A.Tt, A.Cb1, A.C1);
-      A.C2 = fmaf(A.Tt, A.Cb2, A.C2);
-      A.Tt = A.Tt * A.Tb;
-      A.nt += A.nb;
-      A.Tb = 1.f;
-      A.Cb0 = A.Cb1 = A.Cb2 = 0.f;
-      A.nb = 0;
-      A.cur_key = key;
+    int pos[4];
+    bool vk[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      vk[u] = mk != 0ull;
+      pos[u] = jj + (vk[u] ? __builtin_ctzll(mk) : 0);
+      mk &= mk - 1ull;
     }
-    const float dx = p0.x - fxp, dy = p0.y - fyp;
-    const float power = fminf(fmaf(dx, fmaf(p0.z, dx, p0.w * dy), (p1.x * dy) * dy), 0.f);
-    if (FILTER && power < p1.z) continue;   // Eq. 4 before the exponential
-    const float alpha = fminf(kAlphaMax, p1.y * __expf(power));
-    if (alpha < kAlphaMin) continue;
-    const float Tn = A.Tb * (1.f - alpha);
-    if (A.Tt * Tn < kTMin) {
-      if (SAVE) A.stop_pos = b0 + j;
-      A.done = true;
-      mk = 0ull;
-      continue;
+    uint32_t e[4];
+    float4 p0[4], p1[4], p2[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      e[u] = S.list[w][pos[u]];
+      p0[u] = S.r0[w][pos[u]];
+      p1[u] = S.r1[w][pos[u]];
+      p2[u] = S.r2[w][pos[u]];
     }
-    const float wgt = alpha * A.Tb;
-    A.Cb0 = fmaf(wgt, p2.x, A.Cb0);
-    A.Cb1 = fmaf(wgt, p2.y, A.Cb1);
-    A.Cb2 = fmaf(wgt, p2.z, A.Cb2);
-    A.Tb = Tn;
-    A.nb += 1;
+    float al[4];
+    bool ok[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const float dx = p0[u].x - fxp, dy = p0[u].y - fyp;
+      const float power = fminf(fmaf(dx, fmaf(p0[u].z, dx, p0[u].w * dy), (p1[u].x * dy) * dy), 0.f);
+      ok[u] = vk[u];
+      if (FILTER) ok[u] = ok[u] && power >= p1[u].z;   // Eq. 4 before the exponential
+      al[u] = fminf(kAlphaMax, p1[u].y * __expf(power));
+      ok[u] = ok[u] && al[u] >= kAlphaMin;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (!ok[u] || A.done) continue;
+      const uint32_t key = e[u] >> 8;
+      if (key != A.cur_key) {
+        A.C0 = fmaf(A.Tt, A.Cb0, A.C0);
+        A.C1 = fmaf(A.Tt, A.Cb1, A.C1);
+        A.C2 = fmaf(A.Tt, A.Cb2, A.C2);
+        A.Tt = A.Tt * A.Tb;
+        A.nt += A.nb;
+        A.Tb = 1.f;
+        A.Cb0 = A.Cb1 = A.Cb2 = 0.f;
+        A.nb = 0;
+        A.cur_key = key;
+      }
+      const float Tn = A.Tb * (1.f - al[u]);
+      if (A.Tt * Tn < kTMin) {
+        if (SAVE) A.stop_pos = b0 + (e[u] & 255u);
+        A.done = true;
+        continue;
+      }
+      const float wgt = al[u] * A.Tb;
+      A.Cb0 = fmaf(wgt, p2[u].x, A.Cb0);
+      A.Cb1 = fmaf(wgt, p2[u].y, A.Cb1);
+      A.Cb2 = fmaf(wgt, p2[u].z, A.Cb2);
+      A.Tb = Tn;
+      A.nb += 1;
+    }
+    if (A.done) mk = 0ull;
   }
 }
 
@@ -837,12 +870,11 @@ VY_DEV void blend_sparse(const Stage& S, int w, int jj, uint64_t mk, uint32_t b0
 VY_DEV uint64_t cover_masks(const Stage& S, int w, int jj, int m, float xa, float ya, int l) {
   float mx = 0.f, my = 0.f, rx = -1.f, ry = -1.f;   // empty box for lanes past the chunk
   if (l < m) {
-    const uint32_t j = S.list[w][jj + l] & 255u;
-    const float4 a = S.s0[j];
+    const float4 a = S.r0[w][jj + l];
     mx = a.x;
     my = a.y;
-    rx = S.s2[j].w;
-    ry = S.s1[j].w;
+    rx = S.r2[w][jj + l].w;
+    ry = S.r1[w][jj + l].w;
   }
   const int c = l & 15, r = l >> 4;
   uint64_t mc = 0ull, mr = 0ull;
@@ -905,10 +937,10 @@ VY_DEV void blend_range(Stage& S, uint32_t pb, uint32_t pe, const uint32_t* __re
       float4 q0[4], q1[4], q2[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const uint32_t j = (k < m ? e[k] : e[0]) & 255u;
-        q0[k] = S.s0[j];
-        q1[k] = S.s1[j];
-        q2[k] = S.s2[j];
+        const int pos = k < m ? jj + k : jj;
+        q0[k] = S.r0[w][pos];
+        q1[k] = S.r1[w][pos];
+        q2[k] = S.r2[w][pos];
       }
       const uint32_t key = e[0] >> 8;
       if (m == 4 && key == A.cur_key && (e[1] >> 8) == key && (e[2] >> 8) == key && (e[3] >> 8) == key) {
@@ -969,7 +1001,6 @@ __global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ rang
                                                   int32_t* __restrict__ Eout, int walk) {
   __shared__ Stage S;
   __shared__ uint32_t s_job;
-  __shared__ uint32_t s_bkey[kMaxBins];
   uint32_t njobs = ctr[C_NJOBS];
   if (njobs > kMaxHeavy * kMaxJobsPerTile) njobs = kMaxHeavy * kMaxJobsPerTile;
   const uint32_t n0 = ctr[C_NTIER], n1 = ctr[C_NTIER + 1], n2 = ctr[C_NTIER + 2];
@@ -986,7 +1017,7 @@ __global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ rang
     SplitOut so;
     so.bin_c = bin_c;
     so.bin_n = bin_n;
-    so.bkey = s_bkey;
+    so.bkey = nullptr;
     so.slot_base = so.lbin0 = so.lbin1 = 0;
     if (split) {
       const uint4 jb = jobs[J];
@@ -997,8 +1028,7 @@ __global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ rang
       so.lbin1 = jb.z;
       pb = rec[4 + so.lbin0];
       pe = rec[4 + so.lbin1];
-      for (uint32_t k = threadIdx.x; k < so.lbin1 - so.lbin0; k += blockDim.x)
-        s_bkey[k] = rec[4 + kMaxBins + 1 + so.lbin0 + k];
+      so.bkey = rec + 4 + kMaxBins + 1 + so.lbin0;
     } else {
       if (J < nfirst) {             // heavy-first tiers
         uint32_t k = J - njobs;
