@@ -183,8 +183,11 @@ typedef struct vy_render_opts {
   int32_t walk;         /* how a band of 16x4 pixels walks its tile list: 0 (auto)
                            per chunk of 64 entries, all pixels together when
                            most entries cover most pixels, else each pixel over
-                           its own entries; 1: always together; 2: always per
-                           pixel. The image is bitwise the same for any value. */
+                           its own entries, and tiles with more than 4096 pairs
+                           are blended band by band by waves of their own;
+                           1: always together; 2: always per pixel (1 and 2
+                           blend every tile with one workgroup). The image is
+                           bitwise the same for any value. */
 } vy_render_opts;
 
 typedef struct vy_render_ctx vy_render_ctx;

@@ -62,6 +62,7 @@ enum {
   C_JOB_TICKET = 16,
   C_NREDO = 17,    // (heavy tile, bin) units with pixels that stop in the bin
   C_NTIER = 18,    // 18..20: tiles in the heavy-first tiers
+  C_BAND_TICKET = 21,   // wave-level band jobs of the two heaviest tiers
   C_COUNT = 32
 };
 
@@ -509,6 +510,7 @@ __global__ __launch_bounds__(256) void tile_ranges(const uint32_t* __restrict__ 
 // pixel box (half-extents in pg2.w, beyond which no pixel is blended) reaches
 // it.
 constexpr uint32_t kTierMin[3] = {16384, 4096, 1024};   // tiles blended first, heaviest tier first
+constexpr int kBandWGs = 256;   // workgroups whose waves blend the two heaviest tiers band by band
 constexpr int kMaxBins = 256;
 constexpr uint32_t kMaxHeavy = 2048;
 constexpr uint32_t kMaxJobsPerTile = 64;
@@ -893,6 +895,86 @@ VY_DEV uint64_t cover_masks(const Stage& S, int w, int jj, int m, float xa, floa
   return mc & mr;
 }
 
+// Blend band-list entries [jc, jc + mc) (mc <= 64) of the wave's LDS region
+// w, tile-list positions counted from b0, for the band whose first pixel
+// centre is (xa, ya): per pixel (each lane over its own entries) when most
+// entries cover few pixels of the band, else all pixels together.
+template <bool FILTER, bool SPLIT, bool SAVE>
+VY_DEV void walk_chunk(const Stage& S, int w, int jc, int mc, uint32_t b0, float xa, float ya, float fxp, float fyp,
+                       PixAcc& A, const SplitOut& so, int walk) {
+  if (!SPLIT && walk != 1) {
+    // small pixel boxes (far Gaussians) cover few pixels of the band: then
+    // every pixel walks only its own entries of this chunk
+    if (__ballot(!A.done) == 0ull) return;
+    uint64_t mk = cover_masks(S, w, jc, mc, xa, ya, (int)(threadIdx.x & 63));
+    if (A.done) mk = 0ull;
+    int mx = __popcll(mk);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+    if (walk == 2 || mx * 5 < mc * 3) {
+      blend_sparse<FILTER, SAVE>(S, w, jc, mk, b0, fxp, fyp, A);
+      return;
+    }
+  }
+  for (int jj = jc; jj < jc + mc; jj += 4) {
+    if (__ballot(!A.done) == 0ull) return;   // the whole band has terminated
+    const uint4 e4 = *reinterpret_cast<const uint4*>(&S.list[w][jj]);
+    const int m = jc + mc - jj < 4 ? jc + mc - jj : 4;
+    const uint32_t e[4] = {(uint32_t)__builtin_amdgcn_readfirstlane(e4.x),
+                           (uint32_t)__builtin_amdgcn_readfirstlane(e4.y),
+                           (uint32_t)__builtin_amdgcn_readfirstlane(e4.z),
+                           (uint32_t)__builtin_amdgcn_readfirstlane(e4.w)};
+    float4 q0[4], q1[4], q2[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int pos = k < m ? jj + k : jj;
+      q0[k] = S.r0[w][pos];
+      q1[k] = S.r1[w][pos];
+      q2[k] = S.r2[w][pos];
+    }
+    const uint32_t key = e[0] >> 8;
+    if (m == 4 && key == A.cur_key && (e[1] >> 8) == key && (e[2] >> 8) == key && (e[3] >> 8) == key) {
+      // fast path, one depth bin: rho and the alphas are independent of each
+      // other; only the transmittance chain below is sequential
+      float pw[4];
+      bool lv[4];
+      bool any = false;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float dx = q0[k].x - fxp, dy = q0[k].y - fyp;
+        pw[k] = fminf(fmaf(dx, fmaf(q0[k].z, dx, q0[k].w * dy), (q1[k].x * dy) * dy), 0.f);
+        lv[k] = !A.done && fabsf(dx) <= q2[k].w && fabsf(dy) <= q1[k].w;   // pixel rule
+        if (FILTER) lv[k] = lv[k] && pw[k] >= q1[k].z;   // Eq. 4 before the exponential
+        any = any || lv[k];
+      }
+      if (__ballot(any) == 0ull) continue;   // no pixel of the band needs these four
+      float al[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) al[k] = fminf(kAlphaMax, q1[k].y * __expf(pw[k]));
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const bool okk = lv[k] && al[k] >= kAlphaMin && !A.done;
+        const float Tn = A.Tb * (1.f - al[k]);
+        const bool stop = okk && (SPLIT ? (Tn < kTMin) : (A.Tt * Tn < kTMin));
+        const bool bl = okk && !stop;
+        const float wgt = bl ? al[k] * A.Tb : 0.f;
+        A.Cb0 = fmaf(wgt, q2[k].x, A.Cb0);
+        A.Cb1 = fmaf(wgt, q2[k].y, A.Cb1);
+        A.Cb2 = fmaf(wgt, q2[k].z, A.Cb2);
+        A.Tb = bl ? Tn : ((SPLIT && stop) ? 0.f : A.Tb);
+        A.nb += bl ? 1 : 0;
+        if (SAVE && stop) A.stop_pos = b0 + (e[k] & 255u);
+        A.done = A.done || stop;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (k < m)
+          blend_one<FILTER, SPLIT, SAVE>(e[k] >> 8, q0[k], q1[k], q2[k], fxp, fyp, A, so, b0 + (e[k] & 255u));
+    }
+  }
+}
+
 // Blend pairs [pb, pe) of tile (tx, ty) into A. SPLIT: per-bin results go to
 // `so` and a pixel stops only when its own bin's T falls below 1e-4 (marking
 // the bin with T = 0 for the composite); otherwise bins are combined in place.
@@ -910,81 +992,113 @@ VY_DEV void blend_range(Stage& S, uint32_t pb, uint32_t pe, const uint32_t* __re
     if (__syncthreads_count(A.done) == 256) break;
     const int cnt = stage_batch(S, b0, pe, tval, pg0, pg1, pg2, n_g, tx, ty);
     for (int jc = 0; jc < cnt; jc += 64) {
-     const int mc = cnt - jc < 64 ? cnt - jc : 64;
-     if (!SPLIT && walk != 1) {
-       // small pixel boxes (far Gaussians) cover few pixels of the band: then
-       // every pixel walks only its own entries of this chunk
-       if (__ballot(!A.done) == 0ull) break;
-       uint64_t mk = cover_masks(S, w, jc, mc, tx * kTileSize + 0.5f, ty * kTileSize + w * 4 + 0.5f,
-                                 (int)(threadIdx.x & 63));
-       if (A.done) mk = 0ull;
-       int mx = __popcll(mk);
-#pragma unroll
-       for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
-       if (walk == 2 || mx * 5 < mc * 3) {
-         blend_sparse<FILTER, SAVE>(S, w, jc, mk, b0, fxp, fyp, A);
-         continue;
-       }
-     }
-     for (int jj = jc; jj < jc + mc; jj += 4) {
-      if (__ballot(!A.done) == 0ull) break;   // the whole band has terminated
-      const uint4 e4 = *reinterpret_cast<const uint4*>(&S.list[w][jj]);
-      const int m = jc + mc - jj < 4 ? jc + mc - jj : 4;
-      const uint32_t e[4] = {(uint32_t)__builtin_amdgcn_readfirstlane(e4.x),
-                             (uint32_t)__builtin_amdgcn_readfirstlane(e4.y),
-                             (uint32_t)__builtin_amdgcn_readfirstlane(e4.z),
-                             (uint32_t)__builtin_amdgcn_readfirstlane(e4.w)};
-      float4 q0[4], q1[4], q2[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int pos = k < m ? jj + k : jj;
-        q0[k] = S.r0[w][pos];
-        q1[k] = S.r1[w][pos];
-        q2[k] = S.r2[w][pos];
-      }
-      const uint32_t key = e[0] >> 8;
-      if (m == 4 && key == A.cur_key && (e[1] >> 8) == key && (e[2] >> 8) == key && (e[3] >> 8) == key) {
-        // fast path, one depth bin: rho and the alphas are independent of each
-        // other; only the transmittance chain below is sequential
-        float pw[4];
-        bool lv[4];
-        bool any = false;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const float dx = q0[k].x - fxp, dy = q0[k].y - fyp;
-          pw[k] = fminf(fmaf(dx, fmaf(q0[k].z, dx, q0[k].w * dy), (q1[k].x * dy) * dy), 0.f);
-          lv[k] = !A.done && fabsf(dx) <= q2[k].w && fabsf(dy) <= q1[k].w;   // pixel rule
-          if (FILTER) lv[k] = lv[k] && pw[k] >= q1[k].z;   // Eq. 4 before the exponential
-          any = any || lv[k];
-        }
-        if (__ballot(any) == 0ull) continue;   // no pixel of the band needs these four
-        float al[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) al[k] = fminf(kAlphaMax, q1[k].y * __expf(pw[k]));
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const bool okk = lv[k] && al[k] >= kAlphaMin && !A.done;
-          const float Tn = A.Tb * (1.f - al[k]);
-          const bool stop = okk && (SPLIT ? (Tn < kTMin) : (A.Tt * Tn < kTMin));
-          const bool bl = okk && !stop;
-          const float wgt = bl ? al[k] * A.Tb : 0.f;
-          A.Cb0 = fmaf(wgt, q2[k].x, A.Cb0);
-          A.Cb1 = fmaf(wgt, q2[k].y, A.Cb1);
-          A.Cb2 = fmaf(wgt, q2[k].z, A.Cb2);
-          A.Tb = bl ? Tn : ((SPLIT && stop) ? 0.f : A.Tb);
-          A.nb += bl ? 1 : 0;
-          if (SAVE && stop) A.stop_pos = b0 + (e[k] & 255u);
-          A.done = A.done || stop;
-        }
-      } else {
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-          if (k < m) blend_one<FILTER, SPLIT, SAVE>(e[k] >> 8, q0[k], q1[k], q2[k], fxp, fyp, A, so, b0 + (e[k] & 255u));
-      }
-     }
+      if (__ballot(!A.done) == 0ull) break;
+      walk_chunk<FILTER, SPLIT, SAVE>(S, w, jc, cnt - jc < 64 ? cnt - jc : 64, b0, tx * kTileSize + 0.5f,
+                                      ty * kTileSize + w * 4 + 0.5f, fxp, fyp, A, so, walk);
     }
     __syncthreads();
   }
+}
+
+// Final fold of the open depth bin and the pixel's outputs (image with the
+// background behind the remaining transmittance; in save mode T, the number of
+// blended Gaussians and the number of tile-list entries walked).
+template <bool SAVE>
+VY_DEV void pixel_out(PixAcc& A, const RCam& cam, int px, int py, uint32_t pb, uint32_t pe, float* __restrict__ img,
+                      float* __restrict__ Tout, int32_t* __restrict__ Nout, int32_t* __restrict__ Eout) {
+  A.C0 = fmaf(A.Tt, A.Cb0, A.C0);
+  A.C1 = fmaf(A.Tt, A.Cb1, A.C1);
+  A.C2 = fmaf(A.Tt, A.Cb2, A.C2);
+  A.Tt = A.Tt * A.Tb;
+  A.nt += A.nb;
+  const size_t hw = (size_t)cam.W * cam.H, o = (size_t)py * cam.W + px;
+  img[o] = fmaf(A.Tt, cam.bg[0], A.C0);
+  img[hw + o] = fmaf(A.Tt, cam.bg[1], A.C1);
+  img[2 * hw + o] = fmaf(A.Tt, cam.bg[2], A.C2);
+  if (SAVE) {
+    Tout[o] = A.Tt;
+    Nout[o] = A.nt;
+    Eout[o] = (int32_t)((A.stop_pos != 0xFFFFFFFFu ? A.stop_pos + 1u : pe) - pb);
+  }
+}
+
+VY_DEV void pix_init(PixAcc& A, bool inside) {
+  A.Tt = 1.f;
+  A.C0 = A.C1 = A.C2 = 0.f;
+  A.Tb = 1.f;
+  A.Cb0 = A.Cb1 = A.Cb2 = 0.f;
+  A.nt = A.nb = 0;
+  A.stop_pos = 0xFFFFFFFFu;
+  A.done = !inside;
+  A.cur_key = 0xFFFFFFFFu;
+  A.lb = 0;
+}
+
+// Wave-level blend of one 16x4 band of a heavy tile, with no workgroup
+// barriers, so that the bands of a tile finish independently: the wave walks
+// the tile's pairs in chunks of 64 (one per lane) with the records of the next
+// chunk and the cut positions of the one after in flight, compacts the entries
+// whose pixel box may reach the band into its LDS region, and blends them as
+// the workgroup walk does (same rules, bitwise the same pixels).
+template <bool FILTER, bool SAVE>
+VY_DEV void blend_band(Stage& S, int w, int tx, int ty, int band, uint32_t pb, uint32_t pe,
+                       const uint32_t* __restrict__ tval, const float4* __restrict__ pg0,
+                       const float4* __restrict__ pg1, const float4* __restrict__ pg2, uint32_t n_g, const RCam& cam,
+                       float* __restrict__ img, float* __restrict__ Tout, int32_t* __restrict__ Nout,
+                       int32_t* __restrict__ Eout, int walk) {
+  const int l = (int)(threadIdx.x & 63);
+  const int px = tx * kTileSize + (l & 15), py = ty * kTileSize + band * 4 + (l >> 4);
+  const bool inside = px < cam.W && py < cam.H;
+  PixAcc A;
+  pix_init(A, inside);
+  const SplitOut so{};
+  const float fxp = px + 0.5f, fyp = py + 0.5f;
+  const float xa = tx * kTileSize + 0.5f, ya = ty * kTileSize + band * 4 + 0.5f;
+  float4 na = make_float4(0.f, 0.f, 0.f, 0.f), nb = na, nc = na;
+  uint32_t g1 = 0;
+  if (pb + l < pe) {
+    uint32_t g = tval[pb + l];
+    if (g >= n_g) g = 0;
+    na = pg0[g];
+    nb = pg1[g];
+    nc = pg2[g];
+  }
+  if (pb + 64 + l < pe) {
+    g1 = tval[pb + 64 + l];
+    if (g1 >= n_g) g1 = 0;
+  }
+  for (uint32_t b0 = pb; b0 < pe; b0 += 64) {
+    if (__ballot(!A.done) == 0ull) break;
+    const float4 a = na, b = nb, c = nc;
+    const bool hit = b0 + l < pe && band_hit(a.x, a.y, c.w, xa, ya);
+    if (b0 + 64 + l < pe) {
+      na = pg0[g1];
+      nb = pg1[g1];
+      nc = pg2[g1];
+    }
+    if (b0 + 128 + l < pe) {
+      g1 = tval[b0 + 128 + l];
+      if (g1 >= n_g) g1 = 0;
+    }
+    const uint64_t bal = __ballot(hit);
+    if (hit) {
+      const uint32_t pos = (uint32_t)__popcll(bal & lanemask_lt());
+      const uint32_t ex = __float_as_uint(c.w);
+      S.list[w][pos] = (depth_bin(b.w) << 8) | (uint32_t)l;
+      S.r0[w][pos] = a;
+      S.r1[w][pos] = make_float4(b.x, b.y, b.z, (float)(ex >> 16));
+      S.r2[w][pos] = make_float4(c.x, c.y, c.z, (float)(ex & 0xFFFFu));
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int cnt = __popcll(bal);
+    if (cnt) walk_chunk<FILTER, false, SAVE>(S, w, 0, cnt, b0, xa, ya, fxp, fyp, A, so, walk);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  if (inside) pixel_out<SAVE>(A, cam, px, py, pb, pe, img, Tout, Nout, Eout);
 }
 
 template <bool FILTER, bool SAVE>
@@ -998,15 +1112,40 @@ __global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ rang
                                                   int32_t* __restrict__ bin_n, uint32_t* ctr, uint32_t n_g,
                                                   uint32_t n_pairs_cap, float* __restrict__ img,
                                                   float* __restrict__ Tout, int32_t* __restrict__ Nout,
-                                                  int32_t* __restrict__ Eout, int walk) {
+                                                  int32_t* __restrict__ Eout, int walk, int band_wgs) {
   __shared__ Stage S;
   __shared__ uint32_t s_job;
   uint32_t njobs = ctr[C_NJOBS];
   if (njobs > kMaxHeavy * kMaxJobsPerTile) njobs = kMaxHeavy * kMaxJobsPerTile;
   const uint32_t n0 = ctr[C_NTIER], n1 = ctr[C_NTIER + 1], n2 = ctr[C_NTIER + 2];
-  const uint32_t nfirst = njobs + n0 + n1 + n2;
-  const uint32_t total = nfirst + (uint32_t)ntiles;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if ((int)blockIdx.x < band_wgs) {
+    // the first band_wgs workgroups: every wave takes (tile, band) jobs of the
+    // two heaviest tiers on its own, at the highest issue priority
+    const uint32_t nband = 4u * (n0 + n1);
+    __builtin_amdgcn_s_setprio(3);
+    for (;;) {
+      uint32_t jb = 0;
+      if (l == 0) jb = fetch_add(ctr + C_BAND_TICKET, 1u);
+      jb = (uint32_t)__builtin_amdgcn_readfirstlane(jb);
+      if (jb >= nband) break;
+      const uint32_t k = jb >> 2;
+      const uint32_t tile = k < n0 ? tiers[k] : tiers[(size_t)ntiles + (k - n0)];
+      const uint2 rg = ranges[tile];
+      uint32_t pb = rg.x, pe = rg.y;
+      if (pe > n_pairs_cap) pe = n_pairs_cap;
+      if (pb > pe) pb = pe;
+      blend_band<FILTER, SAVE>(S, w, (int)tile % cam.tiles_x, (int)tile / cam.tiles_x, (int)(jb & 3u), pb, pe, tval,
+                               pg0, pg1, pg2, n_g, cam, img, Tout, Nout, Eout, walk);
+    }
+    __builtin_amdgcn_s_setprio(0);
+    return;
+  }
+  // tile jobs: split jobs, the heavy-first tiers not taken by band jobs, then
+  // every other tile in order
+  const uint32_t nt0 = band_wgs > 0 ? 0u : n0 + n1;
+  const uint32_t nfirst = njobs + nt0 + n2;
+  const uint32_t total = nfirst + (uint32_t)ntiles;
   for (;;) {
     if (threadIdx.x == 0) s_job = fetch_add(ctr + C_JOB_TICKET, 1u);
     __syncthreads();
@@ -1033,7 +1172,16 @@ __global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ rang
       if (J < nfirst) {             // heavy-first tiers
         uint32_t k = J - njobs;
         const uint32_t* tl = tiers;
-        if (k >= n0) { k -= n0; tl += ntiles; if (k >= n1) { k -= n1; tl += ntiles; } }
+        if (band_wgs > 0) {
+          tl += 2 * (size_t)ntiles;
+        } else if (k >= n0) {
+          k -= n0;
+          tl += ntiles;
+          if (k >= n1) {
+            k -= n1;
+            tl += ntiles;
+          }
+        }
         tile = tl[k];
       } else {
         tile = J - nfirst;
@@ -1053,14 +1201,7 @@ __global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ rang
     const bool inside = px < cam.W && py < cam.H;
     so.pix = (w * 4 + (l >> 4)) * kTileSize + (l & 15);   // row-major in the tile
     PixAcc A;
-    A.Tt = 1.f;
-    A.C0 = A.C1 = A.C2 = 0.f;
-    A.Tb = 1.f;
-    A.Cb0 = A.Cb1 = A.Cb2 = 0.f;
-    A.nt = A.nb = 0;
-    A.stop_pos = 0xFFFFFFFFu;
-    A.done = !inside;
-    A.cur_key = 0xFFFFFFFFu;
+    pix_init(A, inside);
     A.lb = so.lbin0;
     const float fxp = px + 0.5f, fyp = py + 0.5f;
     // tiles on the critical path (split jobs and the heavy-first tiers) get the
@@ -1077,22 +1218,7 @@ __global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ rang
       for (; A.lb < so.lbin1; ++A.lb) put_bin(so, A.lb, make_float4(0.f, 0.f, 0.f, 1.f), 0);
     } else {
       blend_range<FILTER, false, SAVE>(S, pb, pe, tval, pg0, pg1, pg2, n_g, tx, ty, fxp, fyp, A, so, walk);
-      if (inside) {
-        A.C0 = fmaf(A.Tt, A.Cb0, A.C0);
-        A.C1 = fmaf(A.Tt, A.Cb1, A.C1);
-        A.C2 = fmaf(A.Tt, A.Cb2, A.C2);
-        A.Tt = A.Tt * A.Tb;
-        A.nt += A.nb;
-        const size_t hw = (size_t)cam.W * cam.H, o = (size_t)py * cam.W + px;
-        img[o] = fmaf(A.Tt, cam.bg[0], A.C0);
-        img[hw + o] = fmaf(A.Tt, cam.bg[1], A.C1);
-        img[2 * hw + o] = fmaf(A.Tt, cam.bg[2], A.C2);
-        if (SAVE) {
-          Tout[o] = A.Tt;
-          Nout[o] = A.nt;
-          Eout[o] = (int32_t)((A.stop_pos != 0xFFFFFFFFu ? A.stop_pos + 1u : pe) - pb);
-        }
-      }
+      if (inside) pixel_out<SAVE>(A, cam, px, py, pb, pe, img, Tout, Nout, Eout);
     }
     if (urgent) __builtin_amdgcn_s_setprio(0);
     __syncthreads();
@@ -1497,6 +1623,8 @@ int vy_render(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, co
     VY_LAUNCHED();
   }
   // splitting tiles by depth bins gives up early termination; it is off unless asked for
+  // automatic walk: the two heaviest tiers are blended band by band by waves of their own
+  const int band_wgs = walk == 0 ? kBandWGs : 0;
   const bool split_on = opts && opts->split_min_pairs > 0;
   const uint32_t split_min = split_on ? (uint32_t)opts->split_min_pairs : 0xFFFFFFFFu;
   {
@@ -1514,9 +1642,10 @@ int vy_render(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, co
     ProfScope ps(VY_STAGE_BLEND, st);
 #define VY_BLEND(F, S)                                                                                          \
   do {                                                                                                          \
-    blend_jobs<F, S><<<2048, 256, 0, st>>>(c->ranges, c->tval[0], c->pg0, c->pg1, c->pg2, rc, ntiles, c->tile_flag, \
-                                           c->tiers, c->heavy_rec, c->jobs, c->bin_c, c->bin_n, c->ctr, gcap, pcap,  \
-                                           image, c->T_final, c->n_contrib, c->n_eval, walk);                 \
+    blend_jobs<F, S><<<band_wgs + 2048, 256, 0, st>>>(c->ranges, c->tval[0], c->pg0, c->pg1, c->pg2, rc, ntiles,    \
+                                                      c->tile_flag, c->tiers, c->heavy_rec, c->jobs, c->bin_c,      \
+                                                      c->bin_n, c->ctr, gcap, pcap, image, c->T_final, c->n_contrib, \
+                                                      c->n_eval, walk, band_wgs);                                   \
     if (split_on) {                                                                                             \
       composite_scan<S><<<256, 256, 0, st>>>(rc, c->tile_flag, c->heavy_rec, c->bin_c, c->bin_n, c->ctr,           \
                                              reinterpret_cast<PixState*>(c->pstate_raw), c->redo, image,         \
