@@ -1036,7 +1036,7 @@ VY_DEV void pix_init(PixAcc& A, bool inside) {
 
 // Wave-level blend of one 16x4 band of a heavy tile, with no workgroup
 // barriers, so that the bands of a tile finish independently: the wave walks
-// the tile's pairs in chunks of 64 (one per lane) with the records of the next
+// the tile's pairs in chunks of 128 (two per lane) with the records of the next
 // chunk and the cut positions of the one after in flight, compacts the entries
 // whose pixel box may reach the band into its LDS region, and blends them as
 // the workgroup walk does (same rules, bitwise the same pixels).
@@ -1054,46 +1054,70 @@ VY_DEV void blend_band(Stage& S, int w, int tx, int ty, int band, uint32_t pb, u
   const SplitOut so{};
   const float fxp = px + 0.5f, fyp = py + 0.5f;
   const float xa = tx * kTileSize + 0.5f, ya = ty * kTileSize + band * 4 + 0.5f;
-  float4 na = make_float4(0.f, 0.f, 0.f, 0.f), nb = na, nc = na;
-  uint32_t g1 = 0;
-  if (pb + l < pe) {
-    uint32_t g = tval[pb + l];
-    if (g >= n_g) g = 0;
-    na = pg0[g];
-    nb = pg1[g];
-    nc = pg2[g];
+  // chunks of 2 x 64 pairs: lane l holds pairs b0 + l and b0 + 64 + l
+  float4 na[2], nb[2], nc[2];
+  uint32_t g1[2] = {0u, 0u};
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    na[h] = nb[h] = nc[h] = make_float4(0.f, 0.f, 0.f, 0.f);
+    const uint32_t p0 = pb + h * 64 + l;
+    if (p0 < pe) {
+      uint32_t g = tval[p0];
+      if (g >= n_g) g = 0;
+      na[h] = pg0[g];
+      nb[h] = pg1[g];
+      nc[h] = pg2[g];
+    }
+    const uint32_t p1 = pb + 128 + h * 64 + l;
+    if (p1 < pe) {
+      g1[h] = tval[p1];
+      if (g1[h] >= n_g) g1[h] = 0;
+    }
   }
-  if (pb + 64 + l < pe) {
-    g1 = tval[pb + 64 + l];
-    if (g1 >= n_g) g1 = 0;
-  }
-  for (uint32_t b0 = pb; b0 < pe; b0 += 64) {
+  for (uint32_t b0 = pb; b0 < pe; b0 += 128) {
     if (__ballot(!A.done) == 0ull) break;
-    const float4 a = na, b = nb, c = nc;
-    const bool hit = b0 + l < pe && band_hit(a.x, a.y, c.w, xa, ya);
-    if (b0 + 64 + l < pe) {
-      na = pg0[g1];
-      nb = pg1[g1];
-      nc = pg2[g1];
+    bool hit[2];
+    float4 a[2], b[2], c[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      a[h] = na[h];
+      b[h] = nb[h];
+      c[h] = nc[h];
+      hit[h] = b0 + h * 64 + l < pe && band_hit(a[h].x, a[h].y, c[h].w, xa, ya);
     }
-    if (b0 + 128 + l < pe) {
-      g1 = tval[b0 + 128 + l];
-      if (g1 >= n_g) g1 = 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {   // records of the next chunk, cut positions of the one after
+      if (b0 + 128 + h * 64 + l < pe) {
+        na[h] = pg0[g1[h]];
+        nb[h] = pg1[g1[h]];
+        nc[h] = pg2[g1[h]];
+      }
+      if (b0 + 256 + h * 64 + l < pe) {
+        g1[h] = tval[b0 + 256 + h * 64 + l];
+        if (g1[h] >= n_g) g1[h] = 0;
+      }
     }
-    const uint64_t bal = __ballot(hit);
-    if (hit) {
-      const uint32_t pos = (uint32_t)__popcll(bal & lanemask_lt());
-      const uint32_t ex = __float_as_uint(c.w);
-      S.list[w][pos] = (depth_bin(b.w) << 8) | (uint32_t)l;
-      S.r0[w][pos] = a;
-      S.r1[w][pos] = make_float4(b.x, b.y, b.z, (float)(ex >> 16));
-      S.r2[w][pos] = make_float4(c.x, c.y, c.z, (float)(ex & 0xFFFFu));
+    const uint64_t bal0 = __ballot(hit[0]), bal1 = __ballot(hit[1]);
+    const uint32_t c0 = (uint32_t)__popcll(bal0);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (hit[h]) {
+        const uint32_t pos = (h ? c0 : 0u) + (uint32_t)__popcll((h ? bal1 : bal0) & lanemask_lt());
+        const uint32_t ex = __float_as_uint(c[h].w);
+        S.list[w][pos] = (depth_bin(b[h].w) << 8) | (uint32_t)(h * 64 + l);
+        S.r0[w][pos] = a[h];
+        S.r1[w][pos] = make_float4(b[h].x, b[h].y, b[h].z, (float)(ex >> 16));
+        S.r2[w][pos] = make_float4(c[h].x, c[h].y, c[h].z, (float)(ex & 0xFFFFu));
+      }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int cnt = __popcll(bal);
-    if (cnt) walk_chunk<FILTER, false, SAVE>(S, w, 0, cnt, b0, xa, ya, fxp, fyp, A, so, walk);
+    const int cnt = (int)(c0 + (uint32_t)__popcll(bal1));
+    for (int jc = 0; jc < cnt; jc += 64) {
+      if (__ballot(!A.done) == 0ull) break;
+      walk_chunk<FILTER, false, SAVE>(S, w, jc, cnt - jc < 64 ? cnt - jc : 64, b0, xa, ya, fxp, fyp, A, so, walk);
+    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
