@@ -1593,7 +1593,7 @@ int vy_render(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, co
   }
   {
     // depth sort of all cut entries (culled ones carry key 0xFFFFFFFF and sort last)
-    const int blocks = imin(cdiv(c->max_g, vysort::kTile), 1024);
+    const int blocks = imin(cdiv(c->max_g, vysort::kTile), 256);
     for (int p = 0; p < 4; ++p) {
       ProfScope ps(VY_STAGE_DEPTH_SORT, st);
       uint32_t ep;
@@ -1612,7 +1612,7 @@ int vy_render(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, co
     ProfScope ps(VY_STAGE_EMIT, st);
     uint32_t ep;
     if (int rcode = epoch_for(c, st, &ep)) return rcode;
-    const int blocks = imin(cdiv(c->max_g, kScanTile), 1024);
+    const int blocks = imin(cdiv(c->max_g, kScanTile), 512);
     pair_emit<<<blocks, 256, 0, st>>>(c->dval[0], c->prec, c->offsets, c->ctr, c->status, ep, rc.tiles_x, bits0,
                                       c->tkey[0], c->tval[0], c->hist, pcap, gcap);
     VY_LAUNCHED();
@@ -1625,7 +1625,7 @@ int vy_render(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, co
     VY_LAUNCHED();
   }
   {
-    const int blocks = imin(cdiv(c->max_pairs, vysort::kTile), 1024);
+    const int blocks = imin(cdiv(c->max_pairs, vysort::kTile), 256);
     const uint32_t* np = c->ctr + C_NPAIRS;
     for (int p = 0; p < 2; ++p) {
       ProfScope ps(VY_STAGE_TILE_SORT, st);

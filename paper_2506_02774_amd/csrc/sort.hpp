@@ -1,6 +1,6 @@
 // Stable LSD radix sort passes (onesweep: one scatter launch per digit with
-// decoupled look-back across partitions) and a single-pass exclusive scan,
-// for uint32 keys and uint32 values on gfx950 (wave64, LDS staging).
+// decoupled look-back across partitions) for uint32 keys and uint32 values on
+// gfx950 (wave64, LDS staging).
 //
 // Included by render.hip only.
 #pragma once
@@ -11,14 +11,43 @@ namespace vysort {
 
 using namespace vyd;
 
-constexpr int kThreads = 256;
-constexpr int kItems = 16;                    // keys per thread per partition
-constexpr int kTile = kThreads * kItems;      // 4096 keys per partition
+// 1024-thread workgroups of 16 waves, 8 keys per thread: 8192 keys per
+// partition, so that a pass over a few million keys needs a few hundred
+// partitions (a short look-back chain) that all run at once.
+constexpr int kThreads = 1024;
+constexpr int kItems = 8;                     // keys per thread per partition
+constexpr int kTile = kThreads * kItems;      // keys per partition
 constexpr int kWaves = kThreads / 64;
+
+// Exclusive scan of one value per thread of the first 256 threads of the
+// block (all threads call it; the others pass 0 and get 0). `sh` needs 5 words.
+VY_DEV uint32_t scan_first256(uint32_t v, uint32_t* sh, uint32_t* total) {
+  const uint32_t l = lane(), w = threadIdx.x >> 6;
+  uint32_t x = w < 4 ? v : 0u;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (l >= (uint32_t)o) x += y;
+  }
+  if (w < 4 && l == 63) sh[w] = x;
+  __syncthreads();
+  uint32_t wbase = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t s = sh[i];
+    if (i < (int)w) wbase += s;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return w < 4 ? wbase + x - v : 0u;
+}
 
 // One stable scatter pass on digit (key >> shift) & mask (mask <= 255).
 // `ghist` holds this digit's global histogram (256 counts of the n keys).
 // vals_in == nullptr means value = input index. n = min(*n_ptr, n_cap).
+// Partitions are taken in ticket order; each publishes its 256 digit counts
+// and looks back for its predecessors' (`status`, 256 words per partition).
 __global__ __launch_bounds__(kThreads) void onesweep_pass(const uint32_t* __restrict__ keys_in,
                                                           const uint32_t* __restrict__ vals_in,
                                                           uint32_t* __restrict__ keys_out,
@@ -41,8 +70,9 @@ __global__ __launch_bounds__(kThreads) void onesweep_pass(const uint32_t* __rest
   const uint32_t n_parts = (n + kTile - 1) / kTile;
   {
     uint32_t tot;
-    const uint32_t g = ghist[tid];
-    s_gstart[tid] = block_excl_scan256(g, s_scan, &tot);
+    const uint32_t g = tid < 256 ? ghist[tid] : 0u;
+    const uint32_t x = scan_first256(g, s_scan, &tot);
+    if (tid < 256) s_gstart[tid] = x;
   }
   for (;;) {
     if (tid == 0) s_part = fetch_add(ticket, 1u);
@@ -56,7 +86,7 @@ __global__ __launch_bounds__(kThreads) void onesweep_pass(const uint32_t* __rest
     const uint32_t base = part * kTile;
     const uint32_t cnt = (n - base) < (uint32_t)kTile ? (n - base) : (uint32_t)kTile;
     uint32_t key[kItems], val[kItems], rnk[kItems];
-    // load: wave w round r covers partition items w*1024 + r*64 + lane (ranking order)
+    // load: wave w round r covers partition items w*64*kItems + r*64 + lane (ranking order)
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
       const uint32_t li = w * (64 * kItems) + r * 64 + l;
@@ -64,6 +94,8 @@ __global__ __launch_bounds__(kThreads) void onesweep_pass(const uint32_t* __rest
       key[r] = ok ? keys_in[base + li] : 0xFFFFFFFFu;
       val[r] = ok ? (vals_in ? vals_in[base + li] : base + li) : 0u;
     }
+    // rank within the wave: lanes with the same digit found by ballots over
+    // its bits, counted in order against the wave's running digit counts
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
       const uint32_t li = w * (64 * kItems) + r * 64 + l;
@@ -84,23 +116,22 @@ __global__ __launch_bounds__(kThreads) void onesweep_pass(const uint32_t* __rest
       __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    // per digit: wave exclusive offsets and the block total
+    // per digit: wave exclusive offsets and the partition total
     uint32_t dtot = 0;
-    {
-      const uint32_t d = tid;
+    if (tid < 256) {
       uint32_t run = 0;
 #pragma unroll
       for (int ww = 0; ww < kWaves; ++ww) {
-        const uint32_t c = s_whist[ww][d];
-        s_whist[ww][d] = run;
+        const uint32_t c = s_whist[ww][tid];
+        s_whist[ww][tid] = run;
         run += c;
       }
       dtot = run;
     }
     uint32_t btot;
-    const uint32_t dstart = block_excl_scan256(dtot, s_scan, &btot);
-    s_dstart[tid] = dstart;
-    {
+    const uint32_t dstart = scan_first256(dtot, s_scan, &btot);
+    if (tid < 256) {
+      s_dstart[tid] = dstart;
       const uint64_t ex = lookback_k<8>(status + tid, part, 256, epoch, dtot, err);
       s_gofs[tid] = s_gstart[tid] + (uint32_t)ex - dstart;
     }
