@@ -216,21 +216,25 @@ __global__ __launch_bounds__(256) void lod_classify(const int32_t* __restrict__ 
 
 // Level launches of the top-down traversal (Section 4.1 "Fully-Streaming LoD
 // Tree Traversal": only expanded nodes and their children are visited). Each
-// thread takes one queued node and descends up to kLocalLevels levels on its
-// own (a small DFS stack), emitting frontier nodes to the bitmaps; nodes one
-// level deeper are handed to the next launch through an LDS buffer that the
-// block appends to the output queue with a single atomic. ceil(levels /
-// kLocalLevels) launches cover any tree depth; launches with an empty input
-// queue return at once. Queue counters rotate over three slots: launch j
-// reads cnt[j % 3], appends to cnt[(j + 1) % 3] and clears cnt[(j + 2) % 3].
+// thread takes one queued node and descends up to LEVELS levels on its own (a
+// small DFS stack; deeper per-thread descents serialise dependent node loads),
+// emitting frontier nodes to the bitmaps; nodes one level deeper are handed to
+// the next launch through an LDS buffer that the block appends to the output
+// queue with a single atomic. ceil(tree depth / LEVELS) launches cover any
+// descent; the last one flags a node it would have to hand on (possible only
+// when a fanout above the stack's capacity defers a node early). Launches with
+// an empty input queue return at once. Queue counters rotate over three slots:
+// launch j reads cnt[j % 3], appends to cnt[(j + 1) % 3] and clears
+// cnt[(j + 2) % 3].
 constexpr int kLocalLevels = 4;
 constexpr int kStack = 16;
 constexpr int kOutPerBlock = 256 * 16;
 
+template <int LEVELS>
 __global__ __launch_bounds__(256) void lod_level(const int32_t* __restrict__ in_q, uint32_t* cnt3, int j,
                                                  int32_t* __restrict__ out_q, const float4* __restrict__ lod,
                                                  const int32_t* __restrict__ ccount, LodCam cam, uint32_t cap,
-                                                 uint32_t* fbits, uint32_t* cbits, uint32_t* err) {
+                                                 uint32_t* fbits, uint32_t* cbits, uint32_t* err, int last) {
   __shared__ int32_t s_out[kOutPerBlock];
   __shared__ uint32_t s_n, s_base;
   const uint32_t n_in = ld_acq(cnt3 + (j % 3));
@@ -267,10 +271,12 @@ __global__ __launch_bounds__(256) void lod_level(const int32_t* __restrict__ in_
       const int32_t fc = __float_as_int(a.w), cc = ccount[n];
       for (int k = cc - 1; k >= 0; --k) {
         const int32_t ch = fc + k;
-        if (d + 1 < kLocalLevels && sp < kStack) {
+        if (d + 1 < LEVELS && sp < kStack) {
           stk[sp] = ch;
           dep[sp] = d + 1;
           ++sp;
+        } else if (last) {
+          fetch_add(err, 1u);   // deeper than the launches cover: the cut would be incomplete
         } else {
           const uint32_t slot = atomicAdd(&s_n, 1u);
           if (slot < (uint32_t)kOutPerBlock) {
@@ -300,14 +306,53 @@ __global__ __launch_bounds__(256) void lod_level(const int32_t* __restrict__ in_
 // scan over partitions of 1024 words), zeroing the bitmaps as they are read.
 // A partition is read as 4 rounds of 256 consecutive words (one per thread);
 // each round's ids are gathered in LDS and written out with coalesced stores.
+// The 8 per-thread counts (2 bitmaps x 4 rounds, each <= 32) are scanned in
+// one pass as 16-bit fields of 4 words (a partition's totals stay below 2^16).
 constexpr int kWordsPerThread = 4, kWordsPerPart = 256 * kWordsPerThread;
+
+VY_DEV uint4 block_excl_scan256_x4(uint4 v, uint4* sh, uint4* total) {
+  const uint32_t l = lane(), w = threadIdx.x >> 6;
+  uint4 x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint4 y = make_uint4(__shfl_up(x.x, o, 64), __shfl_up(x.y, o, 64), __shfl_up(x.z, o, 64),
+                               __shfl_up(x.w, o, 64));
+    if (l >= (uint32_t)o) {
+      x.x += y.x;
+      x.y += y.y;
+      x.z += y.z;
+      x.w += y.w;
+    }
+  }
+  if (l == 63) sh[w] = x;
+  __syncthreads();
+  uint4 wb = make_uint4(0, 0, 0, 0), tot = make_uint4(0, 0, 0, 0);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint4 t = sh[i];
+    if (i < (int)w) {
+      wb.x += t.x;
+      wb.y += t.y;
+      wb.z += t.z;
+      wb.w += t.w;
+    }
+    tot.x += t.x;
+    tot.y += t.y;
+    tot.z += t.z;
+    tot.w += t.w;
+  }
+  __syncthreads();
+  *total = tot;
+  return make_uint4(wb.x + x.x - v.x, wb.y + x.y - v.y, wb.z + x.z - v.z, wb.w + x.w - v.w);
+}
 
 __global__ __launch_bounds__(256) void lod_compact(int64_t n_words, uint32_t* __restrict__ fbits,
                                                    uint32_t* __restrict__ cbits, int32_t* __restrict__ Fout,
                                                    int32_t* __restrict__ Cout, int32_t* counts, int f_slot,
                                                    uint32_t* ctr, uint64_t* status, uint32_t epoch,
                                                    uint32_t n_parts) {
-  __shared__ uint32_t s_scan[8], s_part;
+  __shared__ uint4 s_scan4[4];
+  __shared__ uint32_t s_part;
   __shared__ uint64_t s_ex[2];
   __shared__ int32_t s_ids[256 * 32];
   if (threadIdx.x == 0) s_part = fetch_add(ctr + kTicket, 1u);
@@ -315,21 +360,33 @@ __global__ __launch_bounds__(256) void lod_compact(int64_t n_words, uint32_t* __
   const uint32_t part = s_part;
   if (part >= n_parts) return;
   const int64_t base = (int64_t)part * kWordsPerPart;
-  uint32_t wd[2][kWordsPerThread], off[2][kWordsPerThread], rt[2][kWordsPerThread];
-  uint32_t tot[2] = {0, 0};
+  uint32_t wd[2][kWordsPerThread];
 #pragma unroll
   for (int k = 0; k < kWordsPerThread; ++k) {
     const int64_t w = base + k * 256 + threadIdx.x;
     wd[0][k] = w < n_words ? fbits[w] : 0u;
     wd[1][k] = w < n_words ? cbits[w] : 0u;
   }
+  // fields: .x = F rounds 0 | 1 << 16, .y = F rounds 2 | 3, .z/.w the same for C
+  const uint4 cnt4 = make_uint4((uint32_t)__popc(wd[0][0]) | ((uint32_t)__popc(wd[0][1]) << 16),
+                                (uint32_t)__popc(wd[0][2]) | ((uint32_t)__popc(wd[0][3]) << 16),
+                                (uint32_t)__popc(wd[1][0]) | ((uint32_t)__popc(wd[1][1]) << 16),
+                                (uint32_t)__popc(wd[1][2]) | ((uint32_t)__popc(wd[1][3]) << 16));
+  uint4 tot4;
+  const uint4 off4 = block_excl_scan256_x4(cnt4, s_scan4, &tot4);
+  uint32_t off[2][kWordsPerThread], rt[2][kWordsPerThread], tot[2];
+  {
+    const uint32_t o[4] = {off4.x, off4.y, off4.z, off4.w}, t[4] = {tot4.x, tot4.y, tot4.z, tot4.w};
 #pragma unroll
-  for (int q = 0; q < 2; ++q)
+    for (int q = 0; q < 2; ++q) {
 #pragma unroll
-    for (int k = 0; k < kWordsPerThread; ++k) {
-      off[q][k] = block_excl_scan256((uint32_t)__popc(wd[q][k]), s_scan, &rt[q][k]);
-      tot[q] += rt[q][k];
+      for (int k = 0; k < kWordsPerThread; ++k) {
+        off[q][k] = (o[2 * q + (k >> 1)] >> (16 * (k & 1))) & 0xFFFFu;
+        rt[q][k] = (t[2 * q + (k >> 1)] >> (16 * (k & 1))) & 0xFFFFu;
+      }
+      tot[q] = rt[q][0] + rt[q][1] + rt[q][2] + rt[q][3];
     }
+  }
   if (threadIdx.x < 64) {   // wave 0 walks the F chain, wave 1 the C chain
     const uint64_t e = lookback_wave(status, part, 2, epoch, tot[0], ctr + kErr);
     if (threadIdx.x == 0) s_ex[0] = e;
@@ -510,8 +567,9 @@ int vy_lod_cut(const vy_scene* scene, const vy_camera* cam, float tau, vy_cut* p
     const int blocks = (int)((s->n + 255) / 256 < 1024 ? (s->n + 255) / 256 : 1024);
     for (int j = 0; j < launches; ++j) {
       ProfScope ps(VY_STAGE_LOD_TRAVERSE, st);
-      lod_level<<<blocks, 256, 0, st>>>(o->q[j & 1], o->ctr + kQ0, j, o->q[(j + 1) & 1], s->lod, s->ccount, L,
-                                        cap, o->fbits, o->cbits, o->ctr + kErr);
+      lod_level<kLocalLevels><<<blocks, 256, 0, st>>>(o->q[j & 1], o->ctr + kQ0, j, o->q[(j + 1) & 1], s->lod,
+                                                      s->ccount, L, cap, o->fbits, o->cbits, o->ctr + kErr,
+                                                      j + 1 == launches);
       VY_LAUNCHED();
     }
   }
