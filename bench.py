@@ -12,7 +12,10 @@ p50/p99 frame times, the plain full-search + unfiltered renderer on the same
 frames, the 2x2 ablation for tau in {1, 2, 4}, bitwise gates (temporal cut ==
 full cut, filtered image == unfiltered image, every frame), per-stage times,
 the roofline of the dominant kernel, and the FP64 oracle timed on the host.
-Progress goes to stderr.
+Then, in a child process once the walkthrough's buffers are freed, the
+multi-viewer serving benchmark (paper_2506_02774_amd.serving: 64 viewers on 4
+resident scenes at mixed resolutions, one frame at a time against several
+streams); its JSON is embedded under "serving". Progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -50,6 +53,7 @@ def parse():
     ap.add_argument("--tau", type=float, default=2.0, help="tau of the headline number")
     ap.add_argument("--no-ablation", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="skip the multi-viewer serving benchmark")
     ap.add_argument("--cpu-tiles", type=int, default=16, help="tiles the oracle renders for the CPU baseline")
     ap.add_argument("--max-pairs", type=int, default=96 << 20)
     ap.add_argument("--copy-mib", type=int, default=1024, help="size of the HBM copy used as the traffic reference")
@@ -306,7 +310,28 @@ def main():
         "cpu_baseline": cpu,
         "parity": parity,
     }
+    if not args.no_serving and args.config == "full":
+        del ctx, state, full_cut, img, scene
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        out["serving"] = serving_child()
     print(json.dumps(out), flush=True)
+
+
+def serving_child(timeout_s=480):
+    """Runs the serving benchmark in a child process (its progress goes to our
+    stderr) and returns its JSON, or an error record."""
+    import subprocess
+    log("serving benchmark (child process)")
+    try:
+        r = subprocess.run([sys.executable, "-m", "paper_2506_02774_amd.serving"], cwd=ROOT, stdout=subprocess.PIPE,
+                           timeout=timeout_s)
+        lines = r.stdout.decode().strip().splitlines()
+        if r.returncode != 0 or not lines:
+            return {"error": f"exit status {r.returncode}"}
+        return json.loads(lines[-1])
+    except Exception as e:   # the walkthrough results above stand on their own
+        return {"error": repr(e)}
 
 
 def read_traffic(stage):

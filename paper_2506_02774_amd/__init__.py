@@ -49,6 +49,35 @@ class vy_render_opts(ctypes.Structure):
                 ("split_min_pairs", ctypes.c_int32), ("walk", ctypes.c_int32)]
 
 
+class vy_session(ctypes.Structure):
+    _fields_ = [("scene", ctypes.c_void_p), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("tau", ctypes.c_float), ("alpha_filter", ctypes.c_int32), ("max_gaussians", ctypes.c_int64),
+                ("max_pairs", ctypes.c_int64)]
+
+
+class vy_frame_req(ctypes.Structure):
+    _fields_ = [("session", ctypes.c_int32), ("reserved", ctypes.c_int32), ("t_arrival", ctypes.c_double),
+                ("cam", vy_camera), ("image", ctypes.c_void_p)]
+
+
+class vy_frame_stats(ctypes.Structure):
+    _fields_ = [("image_hash", ctypes.c_uint64), ("n_cut", ctypes.c_uint32), ("n_pairs", ctypes.c_uint32),
+                ("n_visible", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("n_frontier", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class vy_frame_result(ctypes.Structure):
+    _fields_ = [("t_admit", ctypes.c_double), ("t_dispatch", ctypes.c_double), ("t_start", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("status", ctypes.c_int32), ("stream", ctypes.c_int32)]
+
+
+class vy_server_config(ctypes.Structure):
+    _fields_ = [("arena", ctypes.c_void_p), ("n_streams", ctypes.c_int32), ("streams", ctypes.POINTER(ctypes.c_void_p)),
+                ("max_inflight", ctypes.c_int32), ("max_viewers", ctypes.c_int32)]
+
+
+VY_RUN_REALTIME = 1
+
 _lib = None
 
 
@@ -89,6 +118,24 @@ def lib():
         "vy_profile_begin": ([I64], ctypes.c_int),
         "vy_profile_end": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)], ctypes.c_int),
         "vy_stage_name": ([ctypes.c_int], ctypes.c_char_p),
+        # vy_serve.h
+        "vy_arena_create": ([P, SZ, ctypes.POINTER(P)], ctypes.c_int),
+        "vy_arena_free": ([P], ctypes.c_int),
+        "vy_arena_alloc": ([P, SZ, ctypes.POINTER(P)], ctypes.c_int),
+        "vy_arena_release": ([P, P], ctypes.c_int),
+        "vy_arena_stats": ([P, ctypes.POINTER(SZ), ctypes.POINTER(SZ), ctypes.POINTER(I64), ctypes.POINTER(I64)],
+                           ctypes.c_int),
+        "vy_session_bytes": ([ctypes.POINTER(vy_session)], SZ),
+        "vy_server_create": ([ctypes.POINTER(vy_server_config), ctypes.POINTER(P)], ctypes.c_int),
+        "vy_server_free": ([P], ctypes.c_int),
+        "vy_server_run": ([P, ctypes.POINTER(vy_session), I32, ctypes.POINTER(vy_frame_req), I64, I32, P,
+                           ctypes.POINTER(vy_frame_result)], ctypes.c_int),
+        "vy_server_last_run": ([P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(SZ),
+                                ctypes.POINTER(I64), ctypes.POINTER(I64)], ctypes.c_int),
+        "vy_server_simulate": ([ctypes.POINTER(vy_server_config), ctypes.POINTER(I64), ctypes.POINTER(I64), I32,
+                                ctypes.POINTER(vy_frame_req), I64, ctypes.POINTER(ctypes.c_double),
+                                ctypes.POINTER(ctypes.c_uint32), I32, ctypes.POINTER(vy_frame_result),
+                                ctypes.POINTER(I64)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvoyager.so")
-SOURCES = ["api.hip", "scene.hip", "lod.hip", "render.hip"]
+SOURCES = ["api.hip", "scene.hip", "lod.hip", "render.hip", "serve.hip"]
 HEADERS = ["vy_common.hpp", "sort.hpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=off",
@@ -27,8 +27,8 @@ def build(force: bool = True, verbose: bool = False) -> str:
     """Compile every source (all of them when `force`) and link the library."""
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    inc = os.path.join(os.path.dirname(HERE), "include", "vy.h")
-    hdrs = [os.path.join(CSRC, h) for h in HEADERS] + [inc]
+    inc = [os.path.join(os.path.dirname(HERE), "include", h) for h in ("vy.h", "vy_serve.h")]
+    hdrs = [os.path.join(CSRC, h) for h in HEADERS] + inc
     objs = []
     for src in SOURCES:
         sp = os.path.join(CSRC, src)

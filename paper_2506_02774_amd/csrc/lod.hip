@@ -467,6 +467,15 @@ size_t vy_cut_workspace_bytes(int64_t n) {
 }
 
 int vy_cut_create(const vy_scene* scene, void* ws, size_t ws_bytes, vy_cut** out) {
+  return vy::cut_create_on(scene, ws, ws_bytes, nullptr, true, out);
+}
+
+}  // extern "C"
+
+namespace vy {
+
+// vy_cut_create with the initialisation enqueued on `st`; `sync` waits for it.
+int cut_create_on(const vy_scene* scene, void* ws, size_t ws_bytes, hipStream_t st, bool sync, vy_cut** out) {
   const Scene* s = (const Scene*)scene;
   if (!s || s->magic != kSceneMagic || !ws || !out) return fail(VY_ERR_ARG, "vy_cut_create: bad argument");
   if (ws_bytes < vy_cut_workspace_bytes(s->n))
@@ -495,13 +504,13 @@ int vy_cut_create(const vy_scene* scene, void* ws, size_t ws_bytes, vy_cut** out
     free(c);
     return fail(VY_ERR_ARG, "vy_cut_create: workspace layout overflow");
   }
-  // one-time initialisation (synchronous): bitmaps zero, worklist slots -1
-  hipError_t e = hipMemset(c->fbits, 0, sizeof(uint32_t) * c->n_words);
-  if (e == hipSuccess) e = hipMemset(c->cbits, 0, sizeof(uint32_t) * c->n_words);
-  if (e == hipSuccess) e = hipMemset(c->counts, 0, 64 * 4);
-  if (e == hipSuccess) e = hipMemset(c->ctr, 0, 64 * 4);
-  if (e == hipSuccess) e = hipMemset(c->status, 0, 16 * c->n_parts);
-  if (e == hipSuccess) e = hipDeviceSynchronize();
+  // one-time initialisation: bitmaps, counters and look-back status zero
+  hipError_t e = hipMemsetAsync(c->fbits, 0, sizeof(uint32_t) * c->n_words, st);
+  if (e == hipSuccess) e = hipMemsetAsync(c->cbits, 0, sizeof(uint32_t) * c->n_words, st);
+  if (e == hipSuccess) e = hipMemsetAsync(c->counts, 0, 64 * 4, st);
+  if (e == hipSuccess) e = hipMemsetAsync(c->ctr, 0, 64 * 4, st);
+  if (e == hipSuccess) e = hipMemsetAsync(c->status, 0, 16 * c->n_parts, st);
+  if (e == hipSuccess && sync) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     free(c);
     return fail(VY_ERR_HIP, "vy_cut_create: %s", hipGetErrorString(e));
@@ -509,6 +518,10 @@ int vy_cut_create(const vy_scene* scene, void* ws, size_t ws_bytes, vy_cut** out
   *out = (vy_cut*)c;
   return VY_OK;
 }
+
+}  // namespace vy
+
+extern "C" {
 
 int vy_cut_free(vy_cut* cut) {
   Cut* c = (Cut*)cut;
@@ -630,4 +643,6 @@ int vy_cut_set_frontier(vy_cut* cut, const int32_t* ids, int64_t n, void* stream
 namespace vy {
 const int32_t* cut_ids_dev(const Cut* c) { return c->C; }
 const int32_t* cut_count_dev(const Cut* c) { return c->counts + 2; }
+const int32_t* cut_frontier_count_dev(const Cut* c) { return c->counts + (c->cur < 0 ? 0 : c->cur); }
+const uint32_t* cut_err_dev(const Cut* c) { return c->ctr + kErr; }
 }  // namespace vy

@@ -27,10 +27,6 @@
 
 #pragma clang fp contract(off)
 
-namespace vy {
-const int32_t* cut_ids_dev(const Cut* c);
-const int32_t* cut_count_dev(const Cut* c);
-}  // namespace vy
 
 namespace {
 
@@ -63,6 +59,7 @@ enum {
   C_NREDO = 17,    // (heavy tile, bin) units with pixels that stop in the bin
   C_NTIER = 18,    // 18..20: tiles in the heavy-first tiers
   C_BAND_TICKET = 21,   // wave-level band jobs of the two heaviest tiers
+  C_GOVER = 22,    // cut size when it exceeds the context's max_gaussians (else 0)
   C_COUNT = 32
 };
 
@@ -167,11 +164,14 @@ __global__ __launch_bounds__(256) void project(const int32_t* __restrict__ cut, 
                                                float4* __restrict__ pg2, uint4* __restrict__ prec,
                                                float* __restrict__ prelax, uint32_t* __restrict__ dkey,
                                                uint32_t* ctr, uint32_t* hist, int64_t n_nodes,
-                                               uint32_t* __restrict__ big) {
+                                               uint32_t* __restrict__ big, uint32_t gcap) {
   __shared__ uint32_t s_hist[4][256];
   for (int i = threadIdx.x; i < 4 * 256; i += blockDim.x) (&s_hist[0][0])[i] = 0;
   __syncthreads();
-  const int64_t n = *n_cut_ptr;
+  const uint32_t n_all = (uint32_t)*n_cut_ptr;
+  // a cut larger than the context renders its first gcap entries and is reported
+  if (n_all > gcap && blockIdx.x == 0 && threadIdx.x == 0) ctr[C_GOVER] = n_all;
+  const int64_t n = n_all < gcap ? n_all : gcap;
   uint32_t nvis = 0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     int32_t node = cut[i];
@@ -1427,6 +1427,49 @@ RCam make_rcam(const vy_camera* c, const vy_render_opts* opt) {
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int imin(int64_t a, int64_t b) { return (int)(a < b ? a : b); }
 
+// ------------------------------------------------------------------------
+// Frame summary for the serving runtime: an order-independent 64-bit hash of
+// the image's bits, the sum over flat index i of mix64(i << 32 | bits(image[i]))
+// modulo 2^64 (mix64 is the finaliser of Steele, Lea and Flood's SplitMix64),
+// so that any changed value changes the hash, plus the frame's counts and
+// error flags. The record must be zero before the launch (the hash is summed
+// with one atomic add per workgroup).
+struct FrameStats {
+  unsigned long long hash;
+  uint32_t n_cut, n_pairs, n_visible, flags, n_frontier, pad;
+};
+static_assert(sizeof(FrameStats) == 32, "frame record layout");
+
+VY_DEV uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(256) void frame_finish(const uint32_t* __restrict__ img, uint32_t n,
+                                                    const int32_t* n_front, const int32_t* n_cut,
+                                                    const uint32_t* cut_err, const uint32_t* ctr,
+                                                    FrameStats* out) {
+  __shared__ unsigned long long s_part[4];
+  unsigned long long acc = 0;
+  for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u)
+    acc += mix64(((uint64_t)i << 32) | img[i]);
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (lane() == 0) s_part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicAdd(&out->hash, s_part[0] + s_part[1] + s_part[2] + s_part[3]);
+    if (blockIdx.x == 0) {
+      out->n_cut = (uint32_t)*n_cut;
+      out->n_frontier = (uint32_t)*n_front;
+      out->n_pairs = ctr[C_NPAIRS_RAW];
+      out->n_visible = ctr[C_NVIS];
+      out->flags = (ctr[C_OVERFLOW] ? 1u : 0u) | (ctr[C_GOVER] ? 2u : 0u) | (ctr[C_ERR] ? 4u : 0u) |
+                   (*cut_err ? 8u : 0u);
+    }
+  }
+}
+
 }  // namespace
 
 using namespace vy;
@@ -1439,6 +1482,14 @@ static int64_t status_words_for(int64_t max_g, int64_t max_pairs) {
 }
 
 size_t vy_render_workspace_bytes(int64_t max_g, int32_t max_w, int32_t max_h, int64_t max_pairs) {
+  return render_workspace_bytes(max_g, max_w, max_h, max_pairs, true);
+}
+
+}  // extern "C"
+
+namespace vy {
+
+size_t render_workspace_bytes(int64_t max_g, int32_t max_w, int32_t max_h, int64_t max_pairs, bool split) {
   if (max_g < 1 || max_w < 1 || max_h < 1 || max_pairs < 1) return 0;
   const int64_t tiles = cdiv(max_w, kTileSize) * cdiv(max_h, kTileSize);
   size_t b = 0;
@@ -1448,23 +1499,38 @@ size_t vy_render_workspace_bytes(int64_t max_g, int32_t max_w, int32_t max_h, in
   b += 64 * 4 + 6 * 256 * 4;
   b += (size_t)status_words_for(max_g, max_pairs) * 8;
   b += (size_t)max_w * max_h * 12;                         // saved T, n_contrib, n_eval
-  b += (size_t)tiles * 16 + kMaxHeavy * 4 + (size_t)kMaxHeavy * kHeavyRec * 4 + (size_t)kMaxHeavy * kMaxJobsPerTile * 16;
-  b += (size_t)kMaxBinSlots * (256 * 20 + 4 + 8);          // per-bin results of split tiles, slot owners, redo units
-  b += (size_t)kMaxHeavy * 256 * sizeof(PixState);
+  b += (size_t)tiles * 16;                                 // tile flags, tiers
+  if (split) {                                             // tiles split by depth bins
+    b += kMaxHeavy * 4 + (size_t)kMaxHeavy * kHeavyRec * 4 + (size_t)kMaxHeavy * kMaxJobsPerTile * 16;
+    b += (size_t)kMaxBinSlots * (256 * 20 + 4 + 8);        // per-bin results, slot owners, redo units
+    b += (size_t)kMaxHeavy * 256 * sizeof(PixState);
+  }
   b += 32 * 256;
   return b;
 }
 
+}  // namespace vy
+
+extern "C" {
+
 int vy_render_ctx_create(int64_t max_g, int32_t max_w, int32_t max_h, int64_t max_pairs, void* ws, size_t bytes,
                          vy_render_ctx** out) {
+  return render_ctx_create_on(max_g, max_w, max_h, max_pairs, true, ws, bytes, nullptr, true, out);
+}
+
+}  // extern "C"
+
+namespace vy {
+
+int render_ctx_create_on(int64_t max_g, int32_t max_w, int32_t max_h, int64_t max_pairs, bool split, void* ws,
+                         size_t bytes, hipStream_t st, bool sync, vy_render_ctx** out) {
   if (!ws || !out || max_g < 1 || max_w < 1 || max_h < 1 || max_pairs < 1 || max_pairs > 0x7FFFFFFF ||
       max_g > 0x7FFFFFFF || max_w > 32768 || max_h > 32768)
     return fail(VY_ERR_ARG, "vy_render_ctx_create: bad argument");
   if (cdiv(max_w, kTileSize) * cdiv(max_h, kTileSize) > 65536)
     return fail(VY_ERR_ARG, "vy_render_ctx_create: more than 65536 tiles (16-bit tile keys)");
-  if (bytes < vy_render_workspace_bytes(max_g, max_w, max_h, max_pairs))
-    return fail(VY_ERR_ARG, "vy_render_ctx_create: workspace %zu < %zu bytes", bytes,
-                vy_render_workspace_bytes(max_g, max_w, max_h, max_pairs));
+  const size_t need = render_workspace_bytes(max_g, max_w, max_h, max_pairs, split);
+  if (bytes < need) return fail(VY_ERR_ARG, "vy_render_ctx_create: workspace %zu < %zu bytes", bytes, need);
   RenderCtx* c = (RenderCtx*)calloc(1, sizeof(RenderCtx));
   if (!c) return fail(VY_ERR_ARG, "vy_render_ctx_create: out of host memory");
   Carver cv(ws, bytes);
@@ -1497,23 +1563,26 @@ int vy_render_ctx_create(int64_t max_g, int32_t max_w, int32_t max_h, int64_t ma
   c->T_final = cv.take<float>((size_t)max_w * max_h);
   c->tile_flag = cv.take<uint32_t>(c->max_tiles);
   c->tiers = cv.take<uint32_t>(3 * c->max_tiles);
-  c->heavy_list = cv.take<uint32_t>(kMaxHeavy);
-  c->heavy_rec = cv.take<uint32_t>((size_t)kMaxHeavy * kHeavyRec);
-  c->jobs = cv.take<uint4>((size_t)kMaxHeavy * kMaxJobsPerTile);
-  c->slot_owner = cv.take<uint32_t>(kMaxBinSlots);
-  c->pstate_raw = cv.take<PixState>((size_t)kMaxHeavy * 256);
-  c->redo = cv.take<uint2>(kMaxBinSlots);
-  c->bin_c = cv.take<float4>((size_t)kMaxBinSlots * 256);
-  c->bin_n = cv.take<int32_t>((size_t)kMaxBinSlots * 256);
+  c->split = split;
+  if (split) {
+    c->heavy_list = cv.take<uint32_t>(kMaxHeavy);
+    c->heavy_rec = cv.take<uint32_t>((size_t)kMaxHeavy * kHeavyRec);
+    c->jobs = cv.take<uint4>((size_t)kMaxHeavy * kMaxJobsPerTile);
+    c->slot_owner = cv.take<uint32_t>(kMaxBinSlots);
+    c->pstate_raw = cv.take<PixState>((size_t)kMaxHeavy * 256);
+    c->redo = cv.take<uint2>(kMaxBinSlots);
+    c->bin_c = cv.take<float4>((size_t)kMaxBinSlots * 256);
+    c->bin_n = cv.take<int32_t>((size_t)kMaxBinSlots * 256);
+  }
   c->n_contrib = cv.take<int32_t>((size_t)max_w * max_h);
   c->n_eval = cv.take<int32_t>((size_t)max_w * max_h);
   if (!cv.ok()) {
     free(c);
     return fail(VY_ERR_ARG, "vy_render_ctx_create: workspace layout overflow");
   }
-  hipError_t e = hipMemset(c->status, 0, sizeof(uint64_t) * c->status_words);
-  if (e == hipSuccess) e = hipMemset(c->ctr, 0, 64 * 4);
-  if (e == hipSuccess) e = hipDeviceSynchronize();
+  hipError_t e = hipMemsetAsync(c->status, 0, sizeof(uint64_t) * c->status_words, st);
+  if (e == hipSuccess) e = hipMemsetAsync(c->ctr, 0, 64 * 4, st);
+  if (e == hipSuccess && sync) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     free(c);
     return fail(VY_ERR_HIP, "vy_render_ctx_create: %s", hipGetErrorString(e));
@@ -1522,6 +1591,10 @@ int vy_render_ctx_create(int64_t max_g, int32_t max_w, int32_t max_h, int64_t ma
   *out = (vy_render_ctx*)c;
   return VY_OK;
 }
+
+}  // namespace vy
+
+extern "C" {
 
 int vy_render_ctx_free(vy_render_ctx* ctx) {
   RenderCtx* c = (RenderCtx*)ctx;
@@ -1553,9 +1626,6 @@ int vy_render(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, co
                 c->max_w, c->max_h);
   if (!(cam->fx > 0.f) || !(cam->fy > 0.f) || !(cam->znear > 0.f))
     return fail(VY_ERR_ARG, "vy_render: invalid camera intrinsics");
-  if (c->max_g < s->n)
-    return fail(VY_ERR_ARG, "vy_render: context max_gaussians %lld < scene nodes %lld", (long long)c->max_g,
-                (long long)s->n);
   const bool filter = opts && opts->alpha_filter;
   const bool save = opts && opts->save_state;
   const int walk = opts ? opts->walk : 0;
@@ -1580,11 +1650,11 @@ int vy_render(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, co
     if (filter)
       project<true><<<blocks, 256, 0, st>>>(cut_ids, (const int32_t*)n_cut, s->gauss, s->sh, rc, c->pg0, c->pg1,
                                             c->pg2, c->prec, c->prelax, c->dkey[0], c->ctr,
-                                            c->hist, s->n, c->big);
+                                            c->hist, s->n, c->big, gcap);
     else
       project<false><<<blocks, 256, 0, st>>>(cut_ids, (const int32_t*)n_cut, s->gauss, s->sh, rc, c->pg0, c->pg1,
                                              c->pg2, c->prec, c->prelax, c->dkey[0], c->ctr,
-                                             c->hist, s->n, c->big);
+                                             c->hist, s->n, c->big, gcap);
     VY_LAUNCHED();
     if (filter) {
       big_count<<<512, 256, 0, st>>>(c->big, c->ctr, c->pg0, c->pg1, c->prec, c->prelax, rc.W, rc.H, gcap);
@@ -1650,6 +1720,7 @@ int vy_render(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, co
   // automatic walk: the two heaviest tiers are blended band by band by waves of their own
   const int band_wgs = walk == 0 ? kBandWGs : 0;
   const bool split_on = opts && opts->split_min_pairs > 0;
+  if (split_on && !c->split) return fail(VY_ERR_ARG, "vy_render: this context has no room for split tiles");
   const uint32_t split_min = split_on ? (uint32_t)opts->split_min_pairs : 0xFFFFFFFFu;
   {
     ProfScope ps(VY_STAGE_BLEND_PLAN, st);
@@ -1693,11 +1764,16 @@ int vy_render(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, co
 int vy_render_status(vy_render_ctx* ctx, int64_t* n_pairs, int64_t* n_visible, void* stream) {
   RenderCtx* c = (RenderCtx*)ctx;
   if (!c || c->magic != kCtxMagic) return fail(VY_ERR_ARG, "vy_render_status: bad argument");
-  uint32_t h[16];
+  uint32_t h[C_COUNT];
   hipStream_t st = (hipStream_t)stream;
   VY_HIP(hipMemcpyAsync(h, c->ctr, sizeof(h), hipMemcpyDeviceToHost, st));
   VY_HIP(hipStreamSynchronize(st));
   if (n_visible) *n_visible = h[C_NVIS];
+  if (h[C_GOVER]) {
+    if (n_pairs) *n_pairs = h[C_NPAIRS];
+    return fail(VY_ERR_CAPACITY, "vy_render: cut of %u Gaussians exceeds max_gaussians %lld", h[C_GOVER],
+                (long long)c->max_g);
+  }
   if (h[C_OVERFLOW]) {
     if (n_pairs) *n_pairs = h[C_NPAIRS_RAW];
     return fail(VY_ERR_CAPACITY, "vy_render: %u pairs exceed max_pairs %lld", h[C_NPAIRS_RAW],
@@ -1741,3 +1817,22 @@ int vy_render_projected(const vy_render_ctx* ctx, const float** rec0, const floa
 }
 
 }  // extern "C"
+
+namespace vy {
+
+int render_frame_finish(const vy_cut* cut, const vy_render_ctx* ctx, const float* image, int32_t width,
+                        int32_t height, void* stats, hipStream_t st) {
+  const Cut* ct = (const Cut*)cut;
+  const RenderCtx* c = (const RenderCtx*)ctx;
+  if (!ct || ct->magic != kCutMagic || !c || c->magic != kCtxMagic || !image || !stats || width < 1 ||
+      height < 1 || (int64_t)width * height > (int64_t)c->max_w * c->max_h)
+    return fail(VY_ERR_ARG, "frame summary: bad argument");
+  const uint32_t n = 3u * (uint32_t)width * (uint32_t)height;
+  frame_finish<<<imin(cdiv(n, 256 * 16), 1024), 256, 0, st>>>((const uint32_t*)image, n,
+                                                             cut_frontier_count_dev(ct), cut_count_dev(ct),
+                                                             cut_err_dev(ct), c->ctr, (FrameStats*)stats);
+  VY_LAUNCHED();
+  return VY_OK;
+}
+
+}  // namespace vy

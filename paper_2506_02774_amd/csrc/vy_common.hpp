@@ -136,9 +136,27 @@ struct RenderCtx {
   uint2* redo;          // (heavy tile, bin) units of the composite's second step
   float4* bin_c;        // per (bin slot, pixel): C_b.rgb, T_b
   int32_t* bin_n;       // per (bin slot, pixel): contributors
+  bool split;           // the buffers of split tiles exist
 };
 
 uint32_t next_epoch(uint32_t& epoch);   // 24-bit epochs, never 0
+
+// Entry points shared between the library's sources.
+// vy_cut_create / vy_render_ctx_create with their one-time initialisation
+// enqueued on `st` (`sync`: wait for it, as the public functions do).
+int cut_create_on(const vy_scene* scene, void* ws, size_t ws_bytes, hipStream_t st, bool sync, vy_cut** out);
+// `split`: with the buffers of tiles split by depth bins (split_min_pairs > 0).
+int render_ctx_create_on(int64_t max_g, int32_t max_w, int32_t max_h, int64_t max_pairs, bool split, void* ws,
+                         size_t bytes, hipStream_t st, bool sync, vy_render_ctx** out);
+size_t render_workspace_bytes(int64_t max_g, int32_t max_w, int32_t max_h, int64_t max_pairs, bool split);
+const int32_t* cut_ids_dev(const Cut* c);
+const int32_t* cut_count_dev(const Cut* c);            // |C|
+const int32_t* cut_frontier_count_dev(const Cut* c);   // |F| of the latest frontier
+const uint32_t* cut_err_dev(const Cut* c);             // device-side bound hits of the last cut
+// Enqueues the kernel that writes a frame's summary record (32 bytes, see
+// vy_frame_stats in vy_serve.h): image hash, cut and pair counts, flags.
+int render_frame_finish(const vy_cut* cut, const vy_render_ctx* ctx, const float* image, int32_t width,
+                        int32_t height, void* stats, hipStream_t st);
 
 }  // namespace vy
 

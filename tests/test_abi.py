@@ -1,5 +1,5 @@
 """CPU-only checks of the C-ABI library: it loads, exports every entry point
-declared in include/vy.h, sizes workspaces, and rejects bad arguments before
+declared in include/*.h, sizes workspaces, and rejects bad arguments before
 touching the GPU."""
 import ctypes
 import os
@@ -8,7 +8,12 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "vy.h")
+HEADERS = sorted(os.path.join(ROOT, "include", h) for h in os.listdir(os.path.join(ROOT, "include"))
+                 if h.endswith(".h"))
+
+
+def _header_text():
+    return "\n".join(open(h).read() for h in HEADERS)
 
 
 def _lib():
@@ -20,8 +25,7 @@ def _lib():
 
 
 def declared_functions():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"/\*.*?\*/", "", _header_text(), flags=re.S)
     return sorted(set(re.findall(r"\b(vy_[a-z0-9_]+)\s*\(", src)))
 
 
@@ -64,8 +68,8 @@ def test_argument_errors_without_gpu():
 
 
 def declared_arity():
-    """Parameter count of every function declared in include/vy.h."""
-    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    """Parameter count of every function declared in include/*.h."""
+    src = re.sub(r"/\*.*?\*/", "", _header_text(), flags=re.S)
     out = {}
     for name, params in re.findall(r"\b(vy_[a-z0-9_]+)\s*\(([^()]*)\)\s*;", src):
         p = params.strip()

@@ -1,0 +1,218 @@
+"""GPU checks of the serving runtime (vy_serve.h, through the C ABI): every
+viewer's image is bitwise the same when served in a mix of viewers, on one
+or several streams and under admission pressure, as when the viewer is
+rendered alone with vy_lod_cut + vy_render; the per-frame record (image hash,
+counts) matches the image and the cut; one served frame against the oracle."""
+import numpy as np
+import pytest
+
+import scenegen
+from oracle import project as oproj, render as orender
+
+from gpu_util import image_parity, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def host_hash(img):
+    """Sum over i of SplitMix64's finaliser of (i << 32 | bits(img[i])), mod 2^64."""
+    bits = np.ascontiguousarray(img, np.float32).view(np.uint32).ravel().astype(np.uint64)
+    z = (np.arange(bits.size, dtype=np.uint64) << np.uint64(32)) | bits
+    z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+    z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    z = z ^ (z >> np.uint64(31))
+    return int(z.sum(dtype=np.uint64))
+
+
+@pytest.fixture(scope="module")
+def world(tiny_scene):
+    vy = require_gpu()
+    from paper_2506_02774_amd import serving
+    cfg_a = scenegen.CONFIGS["tiny"]
+    cfg_b = scenegen.scaled_config("tiny", 60_000)
+    host_b = scenegen.make_city(cfg_b)
+    scenes = [vy.Scene(tiny_scene), vy.Scene(host_b)]
+    return vy, serving, scenes, [tiny_scene, host_b], [cfg_a, cfg_b]
+
+
+def _trace(world, seed=7):
+    """8 sessions on 2 scenes, 3 sizes (one not a multiple of 16), filter on and
+    off, 4-6 frames each, arrivals interleaved."""
+    vy, serving, scenes, hosts, cfgs = world
+    rng = np.random.default_rng(seed)
+    sizes = [(128, 96), (200, 120), (256, 144)]
+    sessions, frames = [], []
+    for s in range(8):
+        si = s % 2
+        W, H = sizes[s % 3]
+        filt = s % 4 != 3
+        n = int(rng.integers(4, 7))
+        pos, yaw = scenegen.walkthrough_path(cfgs[si], frames=40)
+        off = int(rng.integers(0, 40 - n))
+        cams = [scenegen.look_camera(pos[off + j], yaw[off + j] + 0.3 * s, 0.05 * (s % 3), W, H)
+                for j in range(n)]
+        sessions.append(dict(scene=si, W=W, H=H, filt=filt, cams=cams))
+    t, items, nxt = 0.0, [], [0] * 8
+    while any(nxt[s] < len(sessions[s]["cams"]) for s in range(8)):
+        s = int(rng.choice([q for q in range(8) if nxt[q] < len(sessions[q]["cams"])]))
+        items.append((s, nxt[s], t))
+        nxt[s] += 1
+        t += float(rng.exponential(0.002))
+    return sessions, items
+
+
+def _alone(world, sessions):
+    """Each session rendered alone, frame after frame, with the plain entry points."""
+    vy, serving, scenes, hosts, cfgs = world
+    out = {}
+    for s, d in enumerate(sessions):
+        sc = scenes[d["scene"]]
+        ctx = vy.RenderContext(sc.n, d["W"], d["H"], 64 * d["W"] * d["H"] + (1 << 20))
+        cut = None
+        tau = d.get("tau", 2.0)
+        for j, cam in enumerate(d["cams"]):
+            cut = vy.vy_lod_cut(sc, cam, tau, prev=cut, out=cut) if cut is not None else vy.vy_lod_cut(sc, cam, tau)
+            img = vy.vy_render(sc, cut, cam, ctx, alpha_filter=d["filt"]).cpu().numpy()
+            vy.check(ctx.status()[0])
+            nf, nc = cut.counts()
+            out[(s, j)] = (img, nc, nf)
+    return out
+
+
+def _serve(world, sessions, items, n_streams, inflight, budget, max_viewers, realtime):
+    import torch
+    vy, serving, scenes, hosts, cfgs = world
+    sess = [serving.session_struct(scenes[d["scene"]], d["W"], d["H"], 2.0, d["filt"]) for d in sessions]
+    need = [serving.session_bytes(x) for x in sess]
+    assert all(b > 0 for b in need)
+    arena = serving.Arena(budget if budget else sum(need) + (1 << 20))
+    images = [torch.full((3, sessions[s]["H"], sessions[s]["W"]), float("nan"), device="cuda") for s, _, _ in items]
+    reqs, n = serving.build_requests((s, t, sessions[s]["cams"][j], images[i].data_ptr())
+                                     for i, (s, j, t) in enumerate(items))
+    srv = serving.Server(arena, n_streams, inflight, max_viewers)
+    torch.cuda.synchronize()
+    res, st = srv.run(sess, reqs, n, realtime=realtime, stats=True)
+    info = srv.last_run()
+    assert arena.stats()["n_live"] == 0
+    return res, st, [im.cpu().numpy() for im in images], info, need
+
+
+@pytest.mark.parametrize("n_streams,inflight,squeeze,realtime", [(1, 1, False, False), (4, 2, False, True),
+                                                                 (4, 2, True, False), (3, 1, True, True)])
+def test_served_images_equal_alone(world, n_streams, inflight, squeeze, realtime):
+    vy, serving, scenes, hosts, cfgs = world
+    sessions, items = _trace(world)
+    alone = _alone(world, sessions)
+    if squeeze:   # room for the two largest sessions: later ones wait for admission
+        sess = [serving.session_struct(scenes[d["scene"]], d["W"], d["H"], 2.0, d["filt"]) for d in sessions]
+        need = sorted(serving.session_bytes(x) for x in sess)
+        budget, max_viewers = need[-1] + need[-2] + 4096, 8
+    else:
+        budget, max_viewers = 0, 8
+    res, st, images, info, need = _serve(world, sessions, items, n_streams, inflight, budget, max_viewers, realtime)
+    print(f"streams {n_streams} inflight {inflight} squeeze {squeeze}: {info}", flush=True)
+    assert not res["status"].any() and not st["flags"].any()
+    assert info["admitted"] == len(sessions)
+    if squeeze:
+        assert info["waited"] > 0 and info["peak_resident"] < len(sessions) and info["peak_bytes"] <= budget
+    assert set(res["stream"].tolist()) <= set(range(n_streams))
+    assert np.all(res["t_done"] >= res["t_start"]) and np.all(res["t_dispatch"] >= res["t_admit"])
+    for i, (s, j, t) in enumerate(items):
+        ref, nc, nf = alone[(s, j)]
+        assert np.array_equal(images[i].view(np.uint32), ref.view(np.uint32)), (s, j)
+        assert st["image_hash"][i] == host_hash(images[i]), (s, j)
+        assert st["n_cut"][i] == nc and st["n_frontier"][i] == nf, (s, j)
+        if realtime:
+            assert res["t_dispatch"][i] >= t - 1e-3
+
+
+def test_capacity_growth_keeps_images(world):
+    """Sessions whose runtime-chosen capacities (2 * pixels Gaussians, 4 *
+    pixels pairs) are below what their frames need: the runtime grows their
+    render workspaces, renders the overflowed frames again, and every image
+    equals the one rendered alone."""
+    import torch
+    vy, serving, scenes, hosts, cfgs = world
+    W, H, tau = 48, 36, 0.15          # the detail of a 640-pixel-wide view at tau = 2 on a tiny image
+    sessions = []
+    for s in range(3):
+        pos, yaw = scenegen.walkthrough_path(cfgs[1], frames=20)
+        cams = [scenegen.look_camera(pos[4 * s + j], yaw[4 * s + j] + 0.7 * s, 0.0, W, H) for j in range(5)]
+        sessions.append(dict(scene=1, W=W, H=H, filt=s != 1, cams=cams, tau=tau))
+    alone = _alone(world, sessions)
+    assert max(nc for (_, nc, _) in alone.values()) > 2 * W * H     # the default cut capacity overflows
+    items = [(s, j, 0.001 * (3 * j + s)) for j in range(5) for s in range(3)]
+    sess = [serving.session_struct(scenes[1], W, H, tau, d["filt"]) for d in sessions]
+    arena = serving.Arena(256 << 20)
+    images = [torch.full((3, H, W), float("nan"), device="cuda") for _ in items]
+    reqs, n = serving.build_requests((s, t, sessions[s]["cams"][j], images[i].data_ptr())
+                                     for i, (s, j, t) in enumerate(items))
+    srv = serving.Server(arena, 2, 2, 3)
+    res, st = srv.run(sess, reqs, n, realtime=False, stats=False)
+    info = srv.last_run()
+    print(info, flush=True)
+    assert info["regrown"] >= 1 and info["redone"] >= 1
+    assert not res["status"].any() and arena.stats()["n_live"] == 0
+    for i, (s, j, t) in enumerate(items):
+        assert np.array_equal(images[i].cpu().numpy().view(np.uint32), alone[(s, j)][0].view(np.uint32)), (s, j)
+
+
+def test_own_buffers_and_hash_only(world):
+    """Requests without an output image render into the session's buffer; the
+    hash in the frame record still equals that of the image rendered alone."""
+    import torch
+    vy, serving, scenes, hosts, cfgs = world
+    sessions, items = _trace(world, seed=9)
+    alone = _alone(world, sessions)
+    sess = [serving.session_struct(scenes[d["scene"]], d["W"], d["H"], 2.0, d["filt"]) for d in sessions]
+    arena = serving.Arena(sum(serving.session_bytes(x) for x in sess) + (1 << 20))
+    reqs, n = serving.build_requests((s, t, sessions[s]["cams"][j], 0) for (s, j, t) in items)
+    srv = serving.Server(arena, 2, 2, 8)
+    torch.cuda.synchronize()
+    res, st = srv.run(sess, reqs, n, realtime=False, stats=True)
+    assert not res["status"].any() and not st["flags"].any()
+    for i, (s, j, t) in enumerate(items):
+        assert st["image_hash"][i] == host_hash(alone[(s, j)][0]), (s, j)
+
+
+def test_served_frame_matches_oracle(world):
+    import torch
+    vy, serving, scenes, hosts, cfgs = world
+    cam = scenegen.walkthrough(cfgs[0], frames=3, width=160, height=112)[2]
+    sess = [serving.session_struct(scenes[0], 160, 112, 2.0, True)]
+    arena = serving.Arena(serving.session_bytes(sess[0]) + 4096)
+    img = torch.empty((3, 112, 160), device="cuda")
+    reqs, n = serving.build_requests([(0, 0.0, cam, img.data_ptr())])
+    srv = serving.Server(arena, 1, 1, 1)
+    torch.cuda.synchronize()
+    res, st = srv.run(sess, reqs, n, realtime=False)
+    assert not res["status"].any() and not st["flags"].any()
+    cut = vy.vy_lod_cut(scenes[0], cam, 2.0)
+    F, C = cut.ids()
+    assert st["n_cut"][0] == len(C)
+    ref = orender.render_image(oproj.project(hosts[0], C, cam), 160, 112)
+    r = image_parity(img.cpu().numpy(), ref)
+    assert r["ok"], r
+
+
+def test_capacity_flags_and_bad_requests(world):
+    import torch
+    vy, serving, scenes, hosts, cfgs = world
+    cam = scenegen.walkthrough(cfgs[0], frames=1, width=128, height=96)[0]
+    # too small a cut capacity and too few pairs: flagged, the run still completes
+    sess = [serving.session_struct(scenes[0], 128, 96, 2.0, True, max_gaussians=64),
+            serving.session_struct(scenes[0], 128, 96, 2.0, True, max_pairs=100)]
+    arena = serving.Arena(sum(serving.session_bytes(x) for x in sess) + 4096)
+    reqs, n = serving.build_requests([(0, 0.0, cam, 0), (1, 0.0, cam, 0)])
+    srv = serving.Server(arena, 2, 1, 2)
+    torch.cuda.synchronize()
+    res, st = srv.run(sess, reqs, n, realtime=False)
+    assert not res["status"].any()
+    assert st["flags"][0] & 2 and st["n_cut"][0] > 64
+    assert st["flags"][1] & 1 and st["n_pairs"][1] > 100
+    # a camera whose size differs from its session's is rejected before anything runs
+    bad = scenegen.walkthrough(cfgs[0], frames=1, width=64, height=64)[0]
+    reqs, n = serving.build_requests([(0, 0.0, bad, 0)])
+    with pytest.raises(vy.VoyagerError) as e:
+        srv.run(sess[:1], reqs, n, realtime=False)
+    assert e.value.code == vy.VY_ERR_ARG
