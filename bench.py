@@ -11,8 +11,9 @@ Prints ONE JSON line: FPS of temporal LoD + alpha filter (the method), with
 p50/p99 frame times, the plain full-search + unfiltered renderer on the same
 frames, the 2x2 ablation for tau in {1, 2, 4}, bitwise gates (temporal cut ==
 full cut, filtered image == unfiltered image, every frame), per-stage times,
-the roofline of the dominant kernel, and the FP64 oracle timed on the host.
-Then, in a child process once the walkthrough's buffers are freed, the
+the roofline of the dominant kernel, the FP64 oracle timed on the host, and
+the LUT exponential of Section 4.2 (FPS and PSNR / SSIM against the exact
+image for table sizes 8..128). Then, in a child process once the walkthrough's buffers are freed, the
 multi-viewer serving benchmark (paper_2506_02774_amd.serving: 64 viewers on 4
 resident scenes at mixed resolutions, one frame at a time against several
 streams); its JSON is embedded under "serving". Progress goes to stderr.
@@ -54,13 +55,14 @@ def parse():
     ap.add_argument("--no-ablation", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the multi-viewer serving benchmark")
+    ap.add_argument("--no-lut", action="store_true", help="skip the LUT-exponential study")
     ap.add_argument("--cpu-tiles", type=int, default=16, help="tiles the oracle renders for the CPU baseline")
     ap.add_argument("--max-pairs", type=int, default=96 << 20)
     ap.add_argument("--copy-mib", type=int, default=1024, help="size of the HBM copy used as the traffic reference")
     return ap.parse_args()
 
 
-def frame_loop(vy, torch, scene, cams, tau, temporal, filt, state, full_cut, ctx, img, per_frame=True):
+def frame_loop(vy, torch, scene, cams, tau, temporal, filt, state, full_cut, ctx, img, per_frame=True, lut=0):
     """Run the frames; returns per-frame ms (events on torch's current stream)."""
     ev = []
     for i, cam in enumerate(cams):
@@ -77,17 +79,17 @@ def frame_loop(vy, torch, scene, cams, tau, temporal, filt, state, full_cut, ctx
         else:
             vy.vy_lod_cut(scene, cam, tau, out=full_cut)
             cut = full_cut
-        vy.vy_render(scene, cut, cam, ctx, image=img, alpha_filter=filt)
+        vy.vy_render(scene, cut, cam, ctx, image=img, alpha_filter=filt, lut_entries=lut)
         if per_frame:
             e1.record()
             ev.append((e0, e1))
     return ev
 
 
-def timed(vy, torch, scene, cams, tau, temporal, filt, state, full_cut, ctx, img):
+def timed(vy, torch, scene, cams, tau, temporal, filt, state, full_cut, ctx, img, lut=0):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev = frame_loop(vy, torch, scene, cams, tau, temporal, filt, state, full_cut, ctx, img)
+    ev = frame_loop(vy, torch, scene, cams, tau, temporal, filt, state, full_cut, ctx, img, lut=lut)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = np.array([a.elapsed_time(b) for a, b in ev])
@@ -196,6 +198,9 @@ def main():
             ablation[f"tau={tau:g}"] = row
             log(f"ablation tau={tau:g}: " + ", ".join(f"{k} {v['fps']:.0f}" for k, v in row.items()))
 
+    # ------------------------------------------------- LUT exponential (Eq. 5)
+    lut = {} if args.no_lut else lut_study(vy, torch, scene, cams, args.tau, state, full_cut, ctx, img, img2)
+
     # ------------------------------------------------ gates + per-frame counts
     log("verification pass (temporal cut == full cut, filtered == unfiltered, every frame)")
     gates = dict(frames=0, cut_mismatch=0, image_mismatch=0)
@@ -266,7 +271,7 @@ def main():
         flops = BLEND_FLOPS_EVAL * avg["evals"] + BLEND_FLOPS_CONTRIB * avg["contribs"]
         flops_per_launch = flops * K / dom_n
         achieved = flops_per_launch / (launch_ms * 1e-3) / 1e12
-        roofline = dict(kernel="blend_jobs<true,false>", bound="alu", achieved=round(achieved, 3),
+        roofline = dict(kernel="blend_jobs<true,false,false>", bound="alu", achieved=round(achieved, 3),
                         peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s", frac=round(achieved / FP32_VECTOR_PEAK_TFLOPS, 5),
                         traffic=traffic, launch_ms=round(launch_ms, 5), flops_per_launch=round(flops_per_launch),
                         evals_per_launch=round(avg["evals"]), contribs_per_launch=round(avg["contribs"]),
@@ -302,6 +307,7 @@ def main():
         "full_unfiltered": {k: round(v, 4) for k, v in base.items()},
         "speedup_vs_full_unfiltered": round(head["fps"] / base["fps"], 3),
         "ablation": ablation,
+        "lut": lut,
         "mean_counts": {k: round(v) for k, v in avg.items()},
         "stages": per_stage,
         "stages_full_unfiltered_ms_per_frame": {k: round(ms / K, 5) for k, (ms, n) in prof["full"].items() if n},
@@ -316,6 +322,38 @@ def main():
         torch.cuda.empty_cache()
         out["serving"] = serving_child()
     print(json.dumps(out), flush=True)
+
+
+def lut_study(vy, torch, scene, cams, tau, state, full_cut, ctx, img, img2, ms=(8, 16, 32, 64, 128),
+              frames=(0, 60, 120, 180, 240, 299)):
+    """The LUT exponential of Section 4.2 on the walkthrough (temporal cut + alpha
+    filter): FPS per table size m, and PSNR / SSIM of its images against the
+    exact exponential's on sampled frames (filtered == unfiltered checked there)."""
+    from paper_2506_02774_amd import quality
+    exact = timed(vy, torch, scene, cams, tau, True, True, state, full_cut, ctx, img)
+    out = {"exact": {"fps": round(exact["fps"], 2), "p50_ms": round(exact["p50_ms"], 4)}}
+    frames = [f for f in frames if f < len(cams)]
+    refs = {}
+    for f in frames:
+        vy.vy_lod_cut(scene, cams[f], tau, out=full_cut)
+        vy.vy_render(scene, full_cut, cams[f], ctx, image=img, alpha_filter=True)
+        refs[f] = img.cpu().numpy()
+    for m in ms:
+        r = timed(vy, torch, scene, cams, tau, True, True, state, full_cut, ctx, img, lut=m)
+        ps, ss, mismatch = [], [], 0
+        for f in frames:
+            vy.vy_lod_cut(scene, cams[f], tau, out=full_cut)
+            vy.vy_render(scene, full_cut, cams[f], ctx, image=img, alpha_filter=True, lut_entries=m)
+            vy.vy_render(scene, full_cut, cams[f], ctx, image=img2, alpha_filter=False, lut_entries=m)
+            mismatch += 0 if torch.equal(img.view(torch.int32), img2.view(torch.int32)) else 1
+            a = img.cpu().numpy()
+            ps.append(quality.psnr(a, refs[f]))
+            ss.append(quality.ssim(a, refs[f]))
+        out[f"m={m}"] = {"fps": round(r["fps"], 2), "p50_ms": round(r["p50_ms"], 4),
+                         "psnr_db_vs_exact": round(float(np.mean(ps)), 2), "ssim_vs_exact": round(float(np.mean(ss)), 5),
+                         "filtered_ne_unfiltered_frames": mismatch}
+        log(f"LUT m={m}: {out[f'm={m}']}")
+    return out
 
 
 def serving_child(timeout_s=480):

@@ -188,6 +188,14 @@ typedef struct vy_render_opts {
                            1: always together; 2: always per pixel (1 and 2
                            blend every tile with one workgroup). The image is
                            bitwise the same for any value. */
+  int32_t lut_entries;  /* 0: alpha uses the exponential. m in 1..128: the
+                           lookup table of Section 4.2 (Eq. 5): e^rho is read
+                           from m + 1 values e^(-5.55 k / m), k = 0..m, at
+                           k = round(rho / -5.55 * m) (clamped to m), held in
+                           LDS. An approximation: the image differs from the
+                           exact one (filtered and unfiltered still agree bit
+                           for bit: the preemptive check keeps a margin of half
+                           an interval more). Not with split_min_pairs > 0. */
 } vy_render_opts;
 
 typedef struct vy_render_ctx vy_render_ctx;

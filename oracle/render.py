@@ -16,12 +16,22 @@ filter and no LUT: every valid Gaussian is a candidate, pruned only by the
 exact radius bound of oracle.project (plus 2 px slack, which cannot change the
 result because the pruned alphas are below alpha* there).
 
+LUT variant (Section 4.2, Eq. 5; used only when lut_m > 0): e^rho is replaced
+by a table of the effective range [-5.55, 0] split into m intervals, read at
+index round(rho / -5.55 * m). Readings: the table holds the m + 1 node values
+e^(-5.55 k / m), k = 0..m (rounding to the nearest index can give 0..m, one
+more than m entries), each rounded once to float32 as a device table stores
+them; an index above m (rho below -5.55) reads node m, where theta e^rho is
+below alpha* for theta <= 1.
+
 Ambiguity accounting (for comparison with a float32 renderer): a pixel is
 flagged when a decision that float32 rounding could flip is within a margin:
 |ln alpha - ln alpha*| <= amb_alpha for a Gaussian visited up to termination,
 |T(1 - alpha) - 1e-4| <= amb_t * 1e-4 at a blend, two consecutive contributors
 with depths within amb_depth (relative), or a contributor within 1e-6
-(relative) of the near plane.
+(relative) of the near plane; with the LUT also a Gaussian whose table
+position -rho m / 5.55 lies within float32 reach of a rounding midpoint
+(k + 1/2), the reach growing with the condition number of its conic.
 """
 from __future__ import annotations
 
@@ -35,6 +45,34 @@ T_MIN = 1e-4
 SLACK = 2.0
 
 
+LUT_RANGE = 5.55
+
+
+def lut_table(m):
+    """The m + 1 node values e^(-5.55 k / m), k = 0..m (Section 4.2), as float32
+    values (returned as float64)."""
+    k = np.arange(m + 1, dtype=np.float64)
+    return np.exp(-LUT_RANGE * k / m).astype(np.float32).astype(np.float64)
+
+
+def lut_index(rho, m):
+    """Eq. 5: round(rho / -5.55 * m), to the nearest integer (ties to even), at most m."""
+    return np.minimum(np.rint(np.asarray(rho, np.float64) / -LUT_RANGE * m), m).astype(np.int64)
+
+
+def lut_exp(rho, m):
+    """e^rho read from the table (Section 4.2)."""
+    return lut_table(m)[lut_index(rho, m)]
+
+
+def conic_condition(conic):
+    """lambda_max / lambda_min of the symmetric 2x2 conics [a, b, c] (n, 3)."""
+    a, b, c = conic[:, 0], conic[:, 1], conic[:, 2]
+    mid = 0.5 * (a + c)
+    rad = np.sqrt(np.maximum(0.0, 0.25 * (a - c) ** 2 + b * b))
+    return (mid + rad) / np.maximum(mid - rad, 1e-300)
+
+
 def depth_order(proj):
     """Indices of valid Gaussians sorted by (depth, node id)."""
     v = np.nonzero(proj["valid"])[0]
@@ -43,8 +81,9 @@ def depth_order(proj):
 
 
 def render_pixels(proj, px, py, bg=(0.0, 0.0, 0.0), order=None, amb_alpha=2e-4, amb_t=2e-4, amb_depth=1e-6,
-                  chunk=2048):
-    """Blend pixels with integer coordinates (px, py) (1-D arrays).
+                  chunk=2048, lut_m=0, amb_lut=4e-6):
+    """Blend pixels with integer coordinates (px, py) (1-D arrays); lut_m > 0
+    reads e^rho from the table of Section 4.2 with m = lut_m.
 
     Returns dict(rgb (P, 3), T (P,), n_contrib (P,), ambiguous (P,) bool)."""
     if order is None:
@@ -69,6 +108,9 @@ def render_pixels(proj, px, py, bg=(0.0, 0.0, 0.0), order=None, amb_alpha=2e-4, 
     rgb_g = proj["rgb"][cand]
     dep = proj["depth"][cand]
     nearm = proj["near_margin"][cand]
+    if lut_m:
+        table = lut_table(lut_m)
+        lut_reach = amb_lut * (1.0 + conic_condition(con))   # float32 reach of -rho m / 5.55, relative
     T = np.ones(P)
     C = np.zeros((P, 3))
     done = np.zeros(P, bool)
@@ -83,7 +125,12 @@ def render_pixels(proj, px, py, bg=(0.0, 0.0, 0.0), order=None, amb_alpha=2e-4, 
         inside = (np.abs(dx) <= rc[None, s:e]) & (np.abs(dy) <= rc[None, s:e])
         Q = con[None, s:e, 0] * dx * dx + 2.0 * con[None, s:e, 1] * dx * dy + con[None, s:e, 2] * dy * dy
         rho = np.minimum(0.0, -0.5 * Q)
-        alpha = np.minimum(ALPHA_MAX, th[None, s:e] * np.exp(rho))
+        if lut_m:
+            tpos = rho / -LUT_RANGE * lut_m
+            ex = table[np.minimum(np.rint(tpos), lut_m).astype(np.int64)]
+        else:
+            ex = np.exp(rho)
+        alpha = np.minimum(ALPHA_MAX, th[None, s:e] * ex)
         alpha = np.where(inside, alpha, 0.0)
         use = inside & (alpha >= ALPHA_MIN) & ~done[:, None]
         a = np.where(use, alpha, 0.0)
@@ -101,6 +148,9 @@ def render_pixels(proj, px, py, bg=(0.0, 0.0, 0.0), order=None, amb_alpha=2e-4, 
         amb |= np.any(relevant & (np.abs(la - ln_amin) <= amb_alpha), axis=1)
         amb |= np.any(use & relevant & (np.abs(Tafter - T_MIN) <= amb_t * T_MIN), axis=1)
         amb |= np.any(active & (nearm[None, s:e] <= 1e-6), axis=1)
+        if lut_m:
+            mid = np.abs(tpos - np.floor(tpos) - 0.5)
+            amb |= np.any(relevant & (tpos < lut_m + 0.5) & (mid <= lut_reach[None, s:e] * (1.0 + tpos)), axis=1)
         # depth ties between consecutive contributors
         idx = np.where(active, np.arange(e - s)[None, :], -1)
         last = np.maximum.accumulate(idx, axis=1)
@@ -143,10 +193,11 @@ def render_image(proj, width, height, bg=(0.0, 0.0, 0.0), tiles=None, tile=16, *
     return dict(image=img, T=Tf, n_contrib=nc, ambiguous=amb)
 
 
-def render_pixel_loop(proj, px: int, py: int, bg=(0.0, 0.0, 0.0)):
+def render_pixel_loop(proj, px: int, py: int, bg=(0.0, 0.0, 0.0), lut_m=0):
     """The definition as a plain loop over every valid Gaussian (one pixel,
     no pruning). Slow; used to pin render_pixels on tiny inputs."""
     order = depth_order(proj)
+    table = lut_table(lut_m) if lut_m else None
     T = 1.0
     C = np.zeros(3)
     n = 0
@@ -155,7 +206,12 @@ def render_pixel_loop(proj, px: int, py: int, bg=(0.0, 0.0, 0.0)):
         dy = py + 0.5 - proj["mean2d"][i, 1]
         A, B, Cc = proj["conic"][i]
         rho = min(0.0, -0.5 * (A * dx * dx + 2 * B * dx * dy + Cc * dy * dy))
-        alpha = min(ALPHA_MAX, proj["theta"][i] * math.exp(rho))
+        if lut_m:
+            k = min(int(round(rho / -LUT_RANGE * lut_m)), lut_m)   # Python's round: ties to even
+            ex = table[k]
+        else:
+            ex = math.exp(rho)
+        alpha = min(ALPHA_MAX, proj["theta"][i] * ex)
         if alpha < ALPHA_MIN:
             continue
         t_next = T * (1.0 - alpha)

@@ -46,7 +46,7 @@ class vy_scene_desc(ctypes.Structure):
 
 class vy_render_opts(ctypes.Structure):
     _fields_ = [("alpha_filter", ctypes.c_int32), ("bg", ctypes.c_float * 3), ("save_state", ctypes.c_int32),
-                ("split_min_pairs", ctypes.c_int32), ("walk", ctypes.c_int32)]
+                ("split_min_pairs", ctypes.c_int32), ("walk", ctypes.c_int32), ("lut_entries", ctypes.c_int32)]
 
 
 class vy_session(ctypes.Structure):
@@ -391,7 +391,7 @@ def vy_lod_cut(scene: Scene, cam, tau: float, prev: Cut | None = None, out: Cut 
 
 
 def vy_render(scene: Scene, cut: Cut, cam, ctx: RenderContext, image=None, alpha_filter=False,
-              bg=(0.0, 0.0, 0.0), save_state=False, split_min_pairs=0, walk=0, stream=None):
+              bg=(0.0, 0.0, 0.0), save_state=False, split_min_pairs=0, walk=0, lut_entries=0, stream=None):
     """Enqueue rendering of `cut` into `image` (torch float32 [3, H, W] on the device)."""
     import torch
     if image is None:
@@ -405,6 +405,7 @@ def vy_render(scene: Scene, cut: Cut, cam, ctx: RenderContext, image=None, alpha
     o.save_state = 1 if save_state else 0
     o.split_min_pairs = int(split_min_pairs)
     o.walk = int(walk)
+    o.lut_entries = int(lut_entries)
     c = make_camera(cam)
     check(lib().vy_render(scene.handle, cut.handle, ctypes.byref(c), ctypes.byref(o),
                           ctypes.c_void_p(image.data_ptr()), ctx.handle, _stream(stream)), "vy_render")

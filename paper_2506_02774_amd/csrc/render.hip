@@ -72,6 +72,7 @@ struct RCam {
   int W, H, tiles_x, tiles_y;
   float bg[3];
   float ln_amin;             // log(1/255)
+  float fdelta;              // margin of the preemptive check (wider with the LUT)
 };
 
 __global__ void render_setup(uint32_t* ctr, uint32_t* hist, uint2* ranges, int ntiles) {
@@ -225,7 +226,7 @@ __global__ __launch_bounds__(256) void project(const int32_t* __restrict__ cut, 
         // lies within |dx| <= K sqrt(Sigma2_xx), |dy| <= K sqrt(Sigma2_yy)
         float rx = fminf(ceilf(kRadiusK * sqrtf(a)), 65535.f), ry = fminf(ceilf(kRadiusK * sqrtf(c)), 65535.f);
         const float theta = g1.w, log_theta = g0.w;
-        const float thr = cam.ln_amin - log_theta - kFilterDelta;
+        const float thr = cam.ln_amin - log_theta - cam.fdelta;
         // relative rounding bound of rho for this conic (condition number based)
         relax = 1e-6f * (lmax / lmin);
         if (FILTER) {
@@ -705,6 +706,26 @@ __global__ __launch_bounds__(256) void plan_heavy(const uint2* __restrict__ rang
   }
 }
 
+// The exponential of alpha = min(0.99, theta e^rho) (Eq. 3): the hardware
+// exponential, or (LUT) the lookup table of Section 4.2: m + 1 values
+// e^(-5.55 k / m), k = 0..m, over the effective range [-5.55, 0] of rho, read
+// at the nearest node, index round(rho / -5.55 * m) (clamped to m; alpha is
+// below alpha* there for theta <= 1). The table lives in LDS.
+constexpr int kLutMax = 128;
+constexpr double kLutRange = 5.55;
+struct ExpLut {
+  const float* tab;
+  float scale;   // m / 5.55
+  int m;
+};
+
+template <bool LUT>
+VY_DEV float exp_rho(float power, const ExpLut& L) {
+  if (!LUT) return __expf(power);
+  const int k = (int)rintf(-power * L.scale);
+  return L.tab[k < L.m ? k : L.m];
+}
+
 // Per-pixel blending state of one job.
 struct PixAcc {
   float Tt, C0, C1, C2;     // combined over finished bins (one-piece mode)
@@ -764,9 +785,9 @@ VY_DEV void bin_enter(PixAcc& A, uint32_t key, const SplitOut& so) {
 // (Eq. 3), skipped below alpha* (with the filter, decided before the
 // exponential by Eq. 4); blending stops before a Gaussian that would take the
 // transmittance (Tt * T_b, or T_b alone in split mode) below 1e-4.
-template <bool FILTER, bool SPLIT, bool SAVE>
+template <bool FILTER, bool SPLIT, bool SAVE, bool LUT>
 VY_DEV void blend_one(uint32_t key, const float4 p0, const float4 p1, const float4 p2, float fxp, float fyp,
-                      PixAcc& A, const SplitOut& so, uint32_t pos) {
+                      PixAcc& A, const SplitOut& so, uint32_t pos, const ExpLut& L) {
   if (key != A.cur_key) {                 // a new depth bin begins (wave-uniform)
     if (!A.done) bin_enter<SPLIT>(A, key, so);   // a finished pixel keeps its state frozen
     A.cur_key = key;
@@ -778,7 +799,7 @@ VY_DEV void blend_one(uint32_t key, const float4 p0, const float4 p1, const floa
   bool live = !A.done && fabsf(dx) <= p2.w && fabsf(dy) <= p1.w;   // pixel rule
   if (FILTER) live = live && power >= p1.z;   // Eq. 4: rho < log(alpha*) - log(theta) => skip
   if (__ballot(live) == 0ull) return;        // the exponential is needed by no pixel of the band
-  const float alpha = fminf(kAlphaMax, p1.y * __expf(power));
+  const float alpha = fminf(kAlphaMax, p1.y * exp_rho<LUT>(power, L));
   const bool ok = live && alpha >= kAlphaMin;
   const float Tn = A.Tb * (1.f - alpha);
   const bool stop = ok && (SPLIT ? (Tn < kTMin) : (A.Tt * Tn < kTMin));
@@ -798,8 +819,9 @@ VY_DEV void blend_one(uint32_t key, const float4 p0, const float4 p1, const floa
 // at its own pixel centre (bits of `mk`). The depth bins that the skipped
 // entries would have opened and left empty fold as exact no-ops (C + T 0 = C,
 // T 1 = T), so the result is bitwise that of the band walk.
-template <bool FILTER, bool SAVE>
-VY_DEV void blend_sparse(const Stage& S, int w, int jj, uint64_t mk, uint32_t b0, float fxp, float fyp, PixAcc& A) {
+template <bool FILTER, bool SAVE, bool LUT>
+VY_DEV void blend_sparse(const Stage& S, int w, int jj, uint64_t mk, uint32_t b0, float fxp, float fyp, PixAcc& A,
+                         const ExpLut& L) {
   // Up to four of the lane's entries per step: their records are loaded and
   // their alphas computed independently; only the transmittance chain is
   // sequential. A depth bin is opened lazily, at the first entry that blends
@@ -831,7 +853,7 @@ VY_DEV void blend_sparse(const Stage& S, int w, int jj, uint64_t mk, uint32_t b0
       const float power = fminf(fmaf(dx, fmaf(p0[u].z, dx, p0[u].w * dy), (p1[u].x * dy) * dy), 0.f);
       ok[u] = vk[u];
       if (FILTER) ok[u] = ok[u] && power >= p1[u].z;   // Eq. 4 before the exponential
-      al[u] = fminf(kAlphaMax, p1[u].y * __expf(power));
+      al[u] = fminf(kAlphaMax, p1[u].y * exp_rho<LUT>(power, L));
       ok[u] = ok[u] && al[u] >= kAlphaMin;
     }
 #pragma unroll
@@ -899,9 +921,9 @@ VY_DEV uint64_t cover_masks(const Stage& S, int w, int jj, int m, float xa, floa
 // w, tile-list positions counted from b0, for the band whose first pixel
 // centre is (xa, ya): per pixel (each lane over its own entries) when most
 // entries cover few pixels of the band, else all pixels together.
-template <bool FILTER, bool SPLIT, bool SAVE>
+template <bool FILTER, bool SPLIT, bool SAVE, bool LUT>
 VY_DEV void walk_chunk(const Stage& S, int w, int jc, int mc, uint32_t b0, float xa, float ya, float fxp, float fyp,
-                       PixAcc& A, const SplitOut& so, int walk) {
+                       PixAcc& A, const SplitOut& so, int walk, const ExpLut& L) {
   if (!SPLIT && walk != 1) {
     // small pixel boxes (far Gaussians) cover few pixels of the band: then
     // every pixel walks only its own entries of this chunk
@@ -912,7 +934,7 @@ VY_DEV void walk_chunk(const Stage& S, int w, int jc, int mc, uint32_t b0, float
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
     if (walk == 2 || mx * 5 < mc * 3) {
-      blend_sparse<FILTER, SAVE>(S, w, jc, mk, b0, fxp, fyp, A);
+      blend_sparse<FILTER, SAVE, LUT>(S, w, jc, mk, b0, fxp, fyp, A, L);
       return;
     }
   }
@@ -950,7 +972,7 @@ VY_DEV void walk_chunk(const Stage& S, int w, int jc, int mc, uint32_t b0, float
       if (__ballot(any) == 0ull) continue;   // no pixel of the band needs these four
       float al[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) al[k] = fminf(kAlphaMax, q1[k].y * __expf(pw[k]));
+      for (int k = 0; k < 4; ++k) al[k] = fminf(kAlphaMax, q1[k].y * exp_rho<LUT>(pw[k], L));
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const bool okk = lv[k] && al[k] >= kAlphaMin && !A.done;
@@ -970,7 +992,8 @@ VY_DEV void walk_chunk(const Stage& S, int w, int jc, int mc, uint32_t b0, float
 #pragma unroll
       for (int k = 0; k < 4; ++k)
         if (k < m)
-          blend_one<FILTER, SPLIT, SAVE>(e[k] >> 8, q0[k], q1[k], q2[k], fxp, fyp, A, so, b0 + (e[k] & 255u));
+          blend_one<FILTER, SPLIT, SAVE, LUT>(e[k] >> 8, q0[k], q1[k], q2[k], fxp, fyp, A, so, b0 + (e[k] & 255u),
+                                              L);
     }
   }
 }
@@ -982,19 +1005,19 @@ VY_DEV void walk_chunk(const Stage& S, int w, int jc, int mc, uint32_t b0, float
 // first, and when the four share the current depth bin their alphas are
 // computed independently before the sequential transmittance chain, which
 // keeps the per-Gaussian latency low on the tiles with the longest lists.
-template <bool FILTER, bool SPLIT, bool SAVE>
+template <bool FILTER, bool SPLIT, bool SAVE, bool LUT>
 VY_DEV void blend_range(Stage& S, uint32_t pb, uint32_t pe, const uint32_t* __restrict__ tval,
                         const float4* __restrict__ pg0, const float4* __restrict__ pg1,
                         const float4* __restrict__ pg2, uint32_t n_g, int tx, int ty, float fxp, float fyp,
-                        PixAcc& A, const SplitOut& so, int walk) {
+                        PixAcc& A, const SplitOut& so, int walk, const ExpLut& L) {
   const int w = threadIdx.x >> 6;
   for (uint32_t b0 = pb; b0 < pe; b0 += 256) {
     if (__syncthreads_count(A.done) == 256) break;
     const int cnt = stage_batch(S, b0, pe, tval, pg0, pg1, pg2, n_g, tx, ty);
     for (int jc = 0; jc < cnt; jc += 64) {
       if (__ballot(!A.done) == 0ull) break;
-      walk_chunk<FILTER, SPLIT, SAVE>(S, w, jc, cnt - jc < 64 ? cnt - jc : 64, b0, tx * kTileSize + 0.5f,
-                                      ty * kTileSize + w * 4 + 0.5f, fxp, fyp, A, so, walk);
+      walk_chunk<FILTER, SPLIT, SAVE, LUT>(S, w, jc, cnt - jc < 64 ? cnt - jc : 64, b0, tx * kTileSize + 0.5f,
+                                           ty * kTileSize + w * 4 + 0.5f, fxp, fyp, A, so, walk, L);
     }
     __syncthreads();
   }
@@ -1040,12 +1063,12 @@ VY_DEV void pix_init(PixAcc& A, bool inside) {
 // chunk and the cut positions of the one after in flight, compacts the entries
 // whose pixel box may reach the band into its LDS region, and blends them as
 // the workgroup walk does (same rules, bitwise the same pixels).
-template <bool FILTER, bool SAVE>
+template <bool FILTER, bool SAVE, bool LUT>
 VY_DEV void blend_band(Stage& S, int w, int tx, int ty, int band, uint32_t pb, uint32_t pe,
                        const uint32_t* __restrict__ tval, const float4* __restrict__ pg0,
                        const float4* __restrict__ pg1, const float4* __restrict__ pg2, uint32_t n_g, const RCam& cam,
                        float* __restrict__ img, float* __restrict__ Tout, int32_t* __restrict__ Nout,
-                       int32_t* __restrict__ Eout, int walk) {
+                       int32_t* __restrict__ Eout, int walk, const ExpLut& L) {
   const int l = (int)(threadIdx.x & 63);
   const int px = tx * kTileSize + (l & 15), py = ty * kTileSize + band * 4 + (l >> 4);
   const bool inside = px < cam.W && py < cam.H;
@@ -1116,7 +1139,8 @@ VY_DEV void blend_band(Stage& S, int w, int tx, int ty, int band, uint32_t pb, u
     const int cnt = (int)(c0 + (uint32_t)__popcll(bal1));
     for (int jc = 0; jc < cnt; jc += 64) {
       if (__ballot(!A.done) == 0ull) break;
-      walk_chunk<FILTER, false, SAVE>(S, w, jc, cnt - jc < 64 ? cnt - jc : 64, b0, xa, ya, fxp, fyp, A, so, walk);
+      walk_chunk<FILTER, false, SAVE, LUT>(S, w, jc, cnt - jc < 64 ? cnt - jc : 64, b0, xa, ya, fxp, fyp, A, so, walk,
+                                           L);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -1125,7 +1149,7 @@ VY_DEV void blend_band(Stage& S, int w, int tx, int ty, int band, uint32_t pb, u
   if (inside) pixel_out<SAVE>(A, cam, px, py, pb, pe, img, Tout, Nout, Eout);
 }
 
-template <bool FILTER, bool SAVE>
+template <bool FILTER, bool SAVE, bool LUT>
 __global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ ranges, const uint32_t* __restrict__ tval,
                                                   const float4* __restrict__ pg0, const float4* __restrict__ pg1,
                                                   const float4* __restrict__ pg2, RCam cam, int ntiles,
@@ -1136,9 +1160,18 @@ __global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ rang
                                                   int32_t* __restrict__ bin_n, uint32_t* ctr, uint32_t n_g,
                                                   uint32_t n_pairs_cap, float* __restrict__ img,
                                                   float* __restrict__ Tout, int32_t* __restrict__ Nout,
-                                                  int32_t* __restrict__ Eout, int walk, int band_wgs) {
+                                                  int32_t* __restrict__ Eout, int walk, int band_wgs, int lut_m) {
   __shared__ Stage S;
   __shared__ uint32_t s_job;
+  __shared__ float s_lut[LUT ? kLutMax + 1 : 1];
+  ExpLut L{s_lut, 0.f, 0};
+  if (LUT) {
+    // table values in double, rounded once to float
+    for (int k = threadIdx.x; k <= lut_m; k += blockDim.x) s_lut[k] = (float)exp(-kLutRange * k / lut_m);
+    L.scale = (float)(lut_m / kLutRange);
+    L.m = lut_m;
+    __syncthreads();
+  }
   uint32_t njobs = ctr[C_NJOBS];
   if (njobs > kMaxHeavy * kMaxJobsPerTile) njobs = kMaxHeavy * kMaxJobsPerTile;
   const uint32_t n0 = ctr[C_NTIER], n1 = ctr[C_NTIER + 1], n2 = ctr[C_NTIER + 2];
@@ -1159,8 +1192,8 @@ __global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ rang
       uint32_t pb = rg.x, pe = rg.y;
       if (pe > n_pairs_cap) pe = n_pairs_cap;
       if (pb > pe) pb = pe;
-      blend_band<FILTER, SAVE>(S, w, (int)tile % cam.tiles_x, (int)tile / cam.tiles_x, (int)(jb & 3u), pb, pe, tval,
-                               pg0, pg1, pg2, n_g, cam, img, Tout, Nout, Eout, walk);
+      blend_band<FILTER, SAVE, LUT>(S, w, (int)tile % cam.tiles_x, (int)tile / cam.tiles_x, (int)(jb & 3u), pb, pe,
+                                    tval, pg0, pg1, pg2, n_g, cam, img, Tout, Nout, Eout, walk, L);
     }
     __builtin_amdgcn_s_setprio(0);
     return;
@@ -1233,7 +1266,7 @@ __global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ rang
     const bool urgent = J < nfirst;
     if (urgent) __builtin_amdgcn_s_setprio(3);
     if (split) {
-      blend_range<FILTER, true, false>(S, pb, pe, tval, pg0, pg1, pg2, n_g, tx, ty, fxp, fyp, A, so, 1);
+      blend_range<FILTER, true, false, LUT>(S, pb, pe, tval, pg0, pg1, pg2, n_g, tx, ty, fxp, fyp, A, so, 1, L);
       // the current bin, then bins without Gaussians for this band up to the job's end
       if (A.cur_key != 0xFFFFFFFFu && A.lb < so.lbin1) {
         put_bin(so, A.lb, make_float4(A.Cb0, A.Cb1, A.Cb2, A.Tb), A.nb);
@@ -1241,7 +1274,7 @@ __global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ rang
       }
       for (; A.lb < so.lbin1; ++A.lb) put_bin(so, A.lb, make_float4(0.f, 0.f, 0.f, 1.f), 0);
     } else {
-      blend_range<FILTER, false, SAVE>(S, pb, pe, tval, pg0, pg1, pg2, n_g, tx, ty, fxp, fyp, A, so, walk);
+      blend_range<FILTER, false, SAVE, LUT>(S, pb, pe, tval, pg0, pg1, pg2, n_g, tx, ty, fxp, fyp, A, so, walk, L);
       if (inside) pixel_out<SAVE>(A, cam, px, py, pb, pe, img, Tout, Nout, Eout);
     }
     if (urgent) __builtin_amdgcn_s_setprio(0);
@@ -1378,8 +1411,8 @@ __global__ __launch_bounds__(256) void composite_redo(const uint32_t* __restrict
     uint32_t pb = rec[4 + b], pe = rec[4 + b + 1];
     if (pe > n_pairs_cap) pe = n_pairs_cap;
     if (pb > pe) pb = pe;
-    blend_range<FILTER, false, false>(S, pb, pe, tval, pg0, pg1, pg2, n_g, tx, ty, px + 0.5f, py + 0.5f, A, so,
-                                      walk);
+    blend_range<FILTER, false, false, false>(S, pb, pe, tval, pg0, pg1, pg2, n_g, tx, ty, px + 0.5f, py + 0.5f, A,
+                                             so, walk, ExpLut{});
     if (mine) {
       A.C0 = fmaf(A.Tt, A.Cb0, A.C0);
       A.C1 = fmaf(A.Tt, A.Cb1, A.C1);
@@ -1421,6 +1454,11 @@ RCam make_rcam(const vy_camera* c, const vy_render_opts* opt) {
   r.tiles_y = (c->height + kTileSize - 1) / kTileSize;
   for (int k = 0; k < 3; ++k) r.bg[k] = opt ? opt->bg[k] : 0.f;
   r.ln_amin = logf(kAlphaMin);
+  // With the LUT the exponential is read at the nearest table node, up to half
+  // an interval (5.55 / 2m) above rho: the check keeps that much more margin so
+  // that the filtered image stays identical to the unfiltered one.
+  const int m = opt ? opt->lut_entries : 0;
+  r.fdelta = kFilterDelta + (m > 0 ? (float)(kLutRange / (2.0 * m)) * 1.001f : 0.f);
   return r;
 }
 
@@ -1630,6 +1668,10 @@ int vy_render(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, co
   const bool save = opts && opts->save_state;
   const int walk = opts ? opts->walk : 0;
   if (walk < 0 || walk > 2) return fail(VY_ERR_ARG, "vy_render: walk must be 0, 1 or 2");
+  if (opts && (opts->lut_entries < 0 || opts->lut_entries > kLutMax))
+    return fail(VY_ERR_ARG, "vy_render: lut_entries must be 0..%d", kLutMax);
+  if (opts && opts->lut_entries > 0 && opts->split_min_pairs > 0)
+    return fail(VY_ERR_ARG, "vy_render: split tiles are blended with the exact exponential only");
   hipStream_t st = (hipStream_t)stream;
   const RCam rc = make_rcam(cam, opts);
   const int ntiles = rc.tiles_x * rc.tiles_y;
@@ -1721,6 +1763,7 @@ int vy_render(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, co
   const int band_wgs = walk == 0 ? kBandWGs : 0;
   const bool split_on = opts && opts->split_min_pairs > 0;
   if (split_on && !c->split) return fail(VY_ERR_ARG, "vy_render: this context has no room for split tiles");
+  const int lut_m = opts ? opts->lut_entries : 0;
   const uint32_t split_min = split_on ? (uint32_t)opts->split_min_pairs : 0xFFFFFFFFu;
   {
     ProfScope ps(VY_STAGE_BLEND_PLAN, st);
@@ -1735,12 +1778,14 @@ int vy_render(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, co
   }
   {
     ProfScope ps(VY_STAGE_BLEND, st);
+#define VY_BLEND_JOBS(F, S, LT)                                                                                 \
+  blend_jobs<F, S, LT><<<band_wgs + 2048, 256, 0, st>>>(c->ranges, c->tval[0], c->pg0, c->pg1, c->pg2, rc, ntiles,   \
+                                                        c->tile_flag, c->tiers, c->heavy_rec, c->jobs, c->bin_c,    \
+                                                        c->bin_n, c->ctr, gcap, pcap, image, c->T_final,           \
+                                                        c->n_contrib, c->n_eval, walk, band_wgs, lut_m)
 #define VY_BLEND(F, S)                                                                                          \
   do {                                                                                                          \
-    blend_jobs<F, S><<<band_wgs + 2048, 256, 0, st>>>(c->ranges, c->tval[0], c->pg0, c->pg1, c->pg2, rc, ntiles,    \
-                                                      c->tile_flag, c->tiers, c->heavy_rec, c->jobs, c->bin_c,      \
-                                                      c->bin_n, c->ctr, gcap, pcap, image, c->T_final, c->n_contrib, \
-                                                      c->n_eval, walk, band_wgs);                                   \
+    if (lut_m > 0) VY_BLEND_JOBS(F, S, true); else VY_BLEND_JOBS(F, S, false);                                  \
     if (split_on) {                                                                                             \
       composite_scan<S><<<256, 256, 0, st>>>(rc, c->tile_flag, c->heavy_rec, c->bin_c, c->bin_n, c->ctr,           \
                                              reinterpret_cast<PixState*>(c->pstate_raw), c->redo, image,         \
@@ -1756,6 +1801,7 @@ int vy_render(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, co
       if (save) VY_BLEND(false, true); else VY_BLEND(false, false);
     }
 #undef VY_BLEND
+#undef VY_BLEND_JOBS
     VY_LAUNCHED();
   }
   return VY_OK;

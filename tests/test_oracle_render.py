@@ -79,3 +79,95 @@ def test_vectorised_equals_loop():
         np.testing.assert_allclose(out["image"][:, y, x], c, atol=1e-12)
         assert out["n_contrib"][y, x] == n
         np.testing.assert_allclose(out["T"][y, x], T, rtol=1e-12)
+
+
+# ------------------------------------------------------------- LUT (Eq. 5) ----
+
+def test_lut_table_is_the_node_values():
+    """m + 1 nodes over [-5.55, 0]: e^0 = 1 first, e^-5.55 last, a geometric
+    sequence of ratio e^(-5.55/m) (float32 values)."""
+    for m in (8, 32, 128):
+        t = render.lut_table(m)
+        assert len(t) == m + 1
+        assert t[0] == 1.0 and t[-1] == float(np.float32(math.exp(-5.55)))
+        np.testing.assert_allclose(t[1:] / t[:-1], math.exp(-5.55 / m), rtol=3e-7)
+        assert np.all(t.astype(np.float32).astype(np.float64) == t)
+
+
+def test_lut_index_rounds_to_the_nearest_node():
+    m = 32
+    h = 5.55 / m
+    for k in (0, 1, 7, 31, 32):
+        assert render.lut_index(-k * h, m) == k
+        if k < m:
+            assert render.lut_index(-(k + 0.5) * h + 1e-9, m) == k        # just before the midpoint
+            assert render.lut_index(-(k + 0.5) * h - 1e-9, m) == k + 1    # just after it
+    assert render.lut_index(0.0, m) == 0
+    assert render.lut_index(-5.55 * 1.2, m) == m                      # below the range: the last node
+    assert render.lut_index(-1e6, m) == m
+
+
+def test_lut_error_bound_is_half_an_interval():
+    """|table/e^rho - 1| <= e^(5.55 / 2m) - 1 over [-5.55, 0], and the bound is
+    reached near the midpoints (a table of interval centres, or truncation
+    instead of rounding, would err by up to a whole interval)."""
+    rho = np.linspace(-5.55, 0.0, 200001)
+    for m in (8, 32, 128):
+        bound = math.exp(5.55 / (2 * m)) - 1
+        err = np.abs(render.lut_exp(rho, m) / np.exp(rho) - 1)
+        assert err.max() <= bound * (1 + 1e-5) + 2e-7
+        assert err.max() >= 0.95 * bound
+
+
+def test_lut_single_gaussian_at_node_offsets():
+    """A pixel whose rho lies a tenth of an interval off node k (either side)
+    reads the node value e^(-5.55 k / m): alpha = theta e^(-5.55 k / m)."""
+    m, q, theta = 16, 0.02, 0.9                       # isotropic conic: rho = -q d^2 / 2
+    h = 5.55 / m
+    for k in (0, 3, 9, 15):
+        for off in (0.1, -0.1):
+            rho = min(0.0, -k * h + off * h)
+            dx = math.sqrt(-2 * rho / q)
+            p = _proj([0.5 - dx], [0.5], [[q, 0.0, q]], [theta], [[0.3, 0.6, 1.0]], [2.0])
+            r = render.render_pixels(p, [0], [0], lut_m=m)
+            a = theta * float(np.float32(math.exp(-5.55 * k / m)))
+            want = np.array([0.3, 0.6, 1.0]) * a if a >= 1 / 255 else np.zeros(3)
+            np.testing.assert_allclose(r["rgb"][0], want, rtol=1e-12, atol=1e-15)
+
+
+def test_lut_vectorised_equals_loop():
+    sc = scenegen.random_gaussians(60, 2, 32, 24, depth_range=(2, 10), scale_range=(-3.0, -1.0))
+    cam = scenegen.identity_camera(32, 24)
+    p = project.project(sc, np.arange(60), cam)
+    out = render.render_image(p, 32, 24, bg=(0.2, 0.3, 0.4), chunk=5, lut_m=16)
+    rng = np.random.default_rng(1)
+    for _ in range(40):
+        x, y = int(rng.integers(32)), int(rng.integers(24))
+        c, T, n = render.render_pixel_loop(p, x, y, bg=(0.2, 0.3, 0.4), lut_m=16)
+        np.testing.assert_allclose(out["image"][:, y, x], c, atol=1e-12)
+        assert out["n_contrib"][y, x] == n
+
+
+def test_lut_converges_to_the_exponential():
+    sc = scenegen.random_gaussians(80, 3, 32, 24, depth_range=(2, 10), scale_range=(-3.0, -1.0))
+    cam = scenegen.identity_camera(32, 24)
+    p = project.project(sc, np.arange(80), cam)
+    exact = render.render_image(p, 32, 24)["image"]
+    errs = []
+    for m in (8, 64, 20000):
+        e = np.abs(render.render_image(p, 32, 24, lut_m=m)["image"] - exact)
+        errs.append(e.mean())
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 1e-4
+
+
+def test_lut_midpoint_is_ambiguous():
+    m = 32
+    h = 5.55 / m
+    q = 0.02
+    d = math.sqrt(2 * 3.5 * h / q)                    # rho = -3.5 h: a rounding midpoint
+    p = _proj([0.5 - d + 0.5], [0.5], [[q, 0.0, q]], [0.9], [[1, 1, 1]], [2.0])
+    p["mean2d"][0, 0] = 0.5 - d                       # pixel (0, 0) centre at distance d
+    r = render.render_pixels(p, [0, 0], [0, 0], lut_m=m)
+    assert r["ambiguous"][0]
+    r2 = render.render_pixels(p, [0], [0], lut_m=0)
+    assert not r2["ambiguous"][0]
