@@ -56,6 +56,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the multi-viewer serving benchmark")
     ap.add_argument("--no-lut", action="store_true", help="skip the LUT-exponential study")
+    ap.add_argument("--no-backward", action="store_true", help="skip timing the backward pass")
     ap.add_argument("--cpu-tiles", type=int, default=16, help="tiles the oracle renders for the CPU baseline")
     ap.add_argument("--max-pairs", type=int, default=96 << 20)
     ap.add_argument("--copy-mib", type=int, default=1024, help="size of the HBM copy used as the traffic reference")
@@ -263,6 +264,7 @@ def main():
         per_stage[k] = dict(ms_per_frame=round(ms / K, 5), launches_per_frame=n / K,
                             algorithmic_GBps=round(b / (ms / K * 1e-3) / 1e9, 1) if ms > 0 else None)
     dom = max(((k, ms) for k, (ms, n) in stages.items() if n), key=lambda t: t[1])[0]
+    bwd = None if args.no_backward else backward_study(vy, torch, scene, cams, args.tau, state, ctx, img)
     dom_ms, dom_n = stages[dom]
     launch_ms = dom_ms / dom_n
     traffic = read_traffic(dom)
@@ -308,6 +310,7 @@ def main():
         "speedup_vs_full_unfiltered": round(head["fps"] / base["fps"], 3),
         "ablation": ablation,
         "lut": lut,
+        "backward": bwd,
         "mean_counts": {k: round(v) for k, v in avg.items()},
         "stages": per_stage,
         "stages_full_unfiltered_ms_per_frame": {k: round(ms / K, 5) for k, (ms, n) in prof["full"].items() if n},
@@ -353,6 +356,56 @@ def lut_study(vy, torch, scene, cams, tau, state, full_cut, ctx, img, img2, ms=(
                          "psnr_db_vs_exact": round(float(np.mean(ps)), 2), "ssim_vs_exact": round(float(np.mean(ss)), 5),
                          "filtered_ne_unfiltered_frames": mismatch}
         log(f"LUT m={m}: {out[f'm={m}']}")
+    return out
+
+
+def backward_study(vy, torch, scene, cams, tau, state, ctx, img, n_frames=60):
+    """Forward with saved state, then the backward of sum(w * image) (w fixed,
+    seeded), frame after frame on the walkthrough: per-stage milliseconds and
+    the rate of forward + backward steps. Gradient buffers for every node are
+    allocated once; each backward overwrites the rows of the cut's Gaussians."""
+    import ctypes
+    L = vy.lib()
+    n = scene.n
+    shapes = dict(mean=(n, 3), log_scale=(n, 3), quat=(n, 4), opacity_logit=(n,), sh=(n, 48))
+    gt = {k: torch.zeros(sh, device="cuda") for k, sh in shapes.items()}
+    g = vy.vy_grads()
+    for k, t in gt.items():
+        setattr(g, k, t.data_ptr())
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    w = torch.randn(img.shape, device="cuda", generator=gen)
+    frames = cams[:n_frames]
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def step(i, cam):
+        if i == 0:
+            vy.vy_lod_cut(scene, cam, tau, out=state)
+        else:
+            vy.vy_lod_cut(scene, cam, tau, prev=state, out=state)
+        vy.vy_render(scene, state, cam, ctx, image=img, alpha_filter=True, save_state=True)
+        c = vy.make_camera(cam)
+        vy.check(L.vy_render_backward(scene.handle, state.handle, ctypes.byref(c), ctypes.c_void_p(w.data_ptr()),
+                                      ctypes.byref(g), ctx.handle, stream), "vy_render_backward")
+
+    step(0, frames[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, cam in enumerate(frames):
+        step(i, cam)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    vy.profile_begin(64 * len(frames) + 64)
+    for i, cam in enumerate(frames):
+        step(i, cam)
+    torch.cuda.synchronize()
+    prof = vy.profile_end()
+    K = len(frames)
+    fwd_ms = sum(ms for k, (ms, nl) in prof.items() if nl and not k.startswith("bwd_")) / K
+    out = {"frames": K, "steps_per_s": round(K / wall, 2), "ms_per_step": round(1e3 * wall / K, 4),
+           "forward_saved_ms": round(fwd_ms, 4),
+           "bwd_blend_ms": round(prof["bwd_blend"][0] / K, 4), "bwd_project_ms": round(prof["bwd_project"][0] / K, 4),
+           "grad_norms_last_frame": {k: float(t.norm()) for k, t in gt.items()}}
+    log(f"backward: {out}")
     return out
 
 

@@ -228,27 +228,61 @@ int vy_render_status(vy_render_ctx* ctx, int64_t* n_pairs, int64_t* n_visible, v
 
 /* Device pointers into the context's saved state of the last frame (written
  * only with save_state = 1), each [H][W]: final transmittance, number of
- * blended Gaussians, and the number of tile-list entries the pixel evaluated
+ * blended Gaussians, the number of tile-list entries the pixel evaluated
  * before blending stopped (its tile's whole list if it never stopped; -1 for
- * pixels of tiles blended in split mode); and the projected Gaussians' 2D
- * means [n][4] (cut order, first two floats). Any argument may be NULL. */
+ * pixels of tiles blended in split mode), and the position in the sorted pair
+ * list of the last Gaussian the pixel blended (-1 if none; not written in
+ * split mode); and the projected Gaussians' 2D means [n][4] (cut order, first
+ * two floats). Any argument may be NULL. */
 int vy_render_saved(const vy_render_ctx* ctx, const float** T_final, const int32_t** n_contrib,
-                    const int32_t** n_eval, const float** mean2d);
+                    const int32_t** n_eval, const int32_t** last_contrib, const float** mean2d);
 
-/* Device pointers to the last frame's intermediates (inspection and tests):
- * the pairs sorted by (tile, depth, node id) as tile ids and cut positions
- * [n_pairs], the per-tile [start, end) ranges [tiles][2], and the projected
- * Gaussians by cut position: rec0 {mean2d.x, mean2d.y, A, B} and rec1
- * {C, theta, rho threshold of the filter, depth} with rho = A dx^2 + B dx dy +
- * C dy^2, rec2 {r, g, b, pixel half-extents rx | ry << 16 as float bits},
- * each [max_gaussians][4] float, and the binning record [max_gaussians][4]
- * uint32 {x0 | y0 << 16, x1 | y1 << 16 (inclusive tile rect), kept-tile mask
- * (rects of at most 32 tiles: bit k = k-th tile in row-major order; 0 for
- * bigger rects), pair count}. Any argument may be NULL. */
 int vy_render_pairs(const vy_render_ctx* ctx, const uint32_t** tile_keys, const uint32_t** cut_pos,
                     const uint32_t** ranges);
 int vy_render_projected(const vy_render_ctx* ctx, const float** rec0, const float** rec1, const float** rec2,
                         const uint32_t** bin_rec);
+
+/* ------------------------------------------------------------------------ */
+/* Backward pass: gradients of a rendered image                             */
+/* ------------------------------------------------------------------------ */
+
+/* Gradient outputs: DEVICE float32 arrays indexed by node id, laid out like the
+ * arrays given to vy_scene_upload. Every Gaussian of the cut writes its own
+ * rows (zeros where it did not reach the image); rows of other nodes are not
+ * touched. Any output pointer may be NULL (not written). */
+typedef struct vy_grads {
+  float* mean;            /* [n][3] world-space means */
+  float* log_scale;       /* [n][3] */
+  float* quat;            /* [n][4] (w, x, y, z) */
+  float* opacity_logit;   /* [n] */
+  float* sh;              /* [n][48] (16 coefficients x 3 channels) */
+  float* mean2d;          /* [n][2] screen-space means (a by-product) */
+  const float* quat_raw;  /* [n][4] DEVICE: the quaternions as given to
+                             vy_scene_upload, which normalises them; `quat` is
+                             then the gradient for these raw values. NULL: for
+                             the unit quaternion. */
+} vy_grads;
+
+/* dL/d(parameters) of the image of the last vy_render on `ctx`, given
+ * dL/dimage (DEVICE float32, planar [3][H][W]). That render must have used
+ * save_state = 1, no split tiles and the exact exponential, with this scene,
+ * this cut (not recomputed since) and this camera (VY_ERR_STATE otherwise).
+ * The depth order, the pixel boxes and the alpha* / transmittance decisions of
+ * that frame are held fixed (piecewise differentiation).
+ * Steps:
+ *   1. The blend (Section 3.1 "Rasterization", Eq. 3) is replayed back to
+ *      front from each pixel's last blended Gaussian, recovering the
+ *      transmittance from the saved final value.
+ *   2. Per Gaussian, the gradients of its 2D mean, conic, opacity and colour
+ *      are summed over each wave and added with atomics.
+ *   3. The projection (Section 3.1 "Culling & Projection": EWA with the
+ *      Jacobian clamps and the low-pass), the SH colour with its clamp, the
+ *      scale exponential, the quaternion rotation and the opacity sigmoid are
+ *      differentiated per Gaussian.
+ * Overwrites the depth-sort and binning intermediates of the context (see
+ * vy_render_projected). Enqueued on `stream`. */
+int vy_render_backward(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, const float* dL_dimage,
+                       const vy_grads* grads, vy_render_ctx* ctx, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Stage timing (HIP events recorded around every kernel launch)            */
@@ -269,6 +303,8 @@ enum {
   VY_STAGE_RANGES,
   VY_STAGE_BLEND_PLAN,
   VY_STAGE_BLEND,
+  VY_STAGE_BWD_BLEND,    /* vy_render_backward: blend replay */
+  VY_STAGE_BWD_PROJECT,  /* vy_render_backward: projection, SH, sigmoid */
   VY_NUM_STAGES
 };
 

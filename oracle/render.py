@@ -81,11 +81,13 @@ def depth_order(proj):
 
 
 def render_pixels(proj, px, py, bg=(0.0, 0.0, 0.0), order=None, amb_alpha=2e-4, amb_t=2e-4, amb_depth=1e-6,
-                  chunk=2048, lut_m=0, amb_lut=4e-6):
+                  chunk=2048, lut_m=0, amb_lut=4e-6, signature=False):
     """Blend pixels with integer coordinates (px, py) (1-D arrays); lut_m > 0
     reads e^rho from the table of Section 4.2 with m = lut_m.
 
-    Returns dict(rgb (P, 3), T (P,), n_contrib (P,), ambiguous (P,) bool)."""
+    Returns dict(rgb (P, 3), T (P,), n_contrib (P,), ambiguous (P,) bool), and
+    with `signature` a per-pixel uint64 digest of which Gaussians it blended
+    (equal digests: the same blend decisions)."""
     if order is None:
         order = depth_order(proj)
     px = np.asarray(px, np.int64)
@@ -116,6 +118,11 @@ def render_pixels(proj, px, py, bg=(0.0, 0.0, 0.0), order=None, amb_alpha=2e-4, 
     done = np.zeros(P, bool)
     ncon = np.zeros(P, np.int64)
     amb = np.zeros(P, bool)
+    sig = np.zeros(P, np.uint64)
+    if signature:
+        z = proj["ids"][cand].astype(np.uint64) * np.uint64(0x9E3779B97F4A7C15) + np.uint64(1)
+        z = (z ^ (z >> np.uint64(31))) * np.uint64(0xBF58476D1CE4E5B9)
+        hv = z ^ (z >> np.uint64(29))
     prev_depth = np.full(P, np.nan)
     ln_amin = math.log(ALPHA_MIN)
     for s in range(0, len(cand), chunk):
@@ -142,6 +149,8 @@ def render_pixels(proj, px, py, bg=(0.0, 0.0, 0.0), order=None, amb_alpha=2e-4, 
         w = np.where(active, a * Tbefore, 0.0)
         C += w @ rgb_g[s:e]
         ncon += active.sum(axis=1)
+        if signature:
+            sig += np.where(active, hv[None, s:e], np.uint64(0)).sum(axis=1, dtype=np.uint64)
         relevant = (~stop | first_stop) & inside & ~done[:, None]
         with np.errstate(divide="ignore"):
             la = np.log(np.where(alpha > 0, alpha, 1e-300))
@@ -166,7 +175,10 @@ def render_pixels(proj, px, py, bg=(0.0, 0.0, 0.0), order=None, amb_alpha=2e-4, 
         T = np.where(any_stop, np.where(first_stop, Tbefore, 0.0).sum(axis=1), Tafter[:, -1])
         done |= any_stop
     bgv = np.asarray(bg, np.float64)
-    return dict(rgb=C + T[:, None] * bgv[None, :], T=T, n_contrib=ncon, ambiguous=amb)
+    out = dict(rgb=C + T[:, None] * bgv[None, :], T=T, n_contrib=ncon, ambiguous=amb)
+    if signature:
+        out["signature"] = sig
+    return out
 
 
 def render_image(proj, width, height, bg=(0.0, 0.0, 0.0), tiles=None, tile=16, **kw):
@@ -177,6 +189,7 @@ def render_image(proj, width, height, bg=(0.0, 0.0, 0.0), tiles=None, tile=16, *
     Tf = np.full((height, width), np.nan)
     nc = np.full((height, width), -1, np.int64)
     amb = np.zeros((height, width), bool)
+    sig = np.zeros((height, width), np.uint64) if kw.get("signature") else None
     tx_n = (width + tile - 1) // tile
     ty_n = (height + tile - 1) // tile
     all_tiles = range(tx_n * ty_n) if tiles is None else tiles
@@ -190,7 +203,12 @@ def render_image(proj, width, height, bg=(0.0, 0.0, 0.0), tiles=None, tile=16, *
         Tf[PY.ravel(), PX.ravel()] = r["T"]
         nc[PY.ravel(), PX.ravel()] = r["n_contrib"]
         amb[PY.ravel(), PX.ravel()] = r["ambiguous"]
-    return dict(image=img, T=Tf, n_contrib=nc, ambiguous=amb)
+        if sig is not None:
+            sig[PY.ravel(), PX.ravel()] = r["signature"]
+    out = dict(image=img, T=Tf, n_contrib=nc, ambiguous=amb)
+    if sig is not None:
+        out["signature"] = sig
+    return out
 
 
 def render_pixel_loop(proj, px: int, py: int, bg=(0.0, 0.0, 0.0), lut_m=0):

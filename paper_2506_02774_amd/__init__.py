@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(HERE, "libvoyager.so")
 VY_OK, VY_ERR_ARG, VY_ERR_HIP, VY_ERR_CAPACITY, VY_ERR_STATE, VY_ERR_DEVICE = 0, -1, -2, -3, -4, -5
 VY_CUT_FRONTIER, VY_CUT_FLAT = 0, 1
 STAGES = ["lod_setup", "lod_flat", "lod_classify", "lod_traverse", "lod_compact", "render_setup", "project",
-          "depth_sort", "pair_scan", "emit", "tile_sort", "ranges", "blend_plan", "blend"]
+          "depth_sort", "pair_scan", "emit", "tile_sort", "ranges", "blend_plan", "blend", "bwd_blend", "bwd_project"]
 
 
 class VoyagerError(RuntimeError):
@@ -47,6 +47,11 @@ class vy_scene_desc(ctypes.Structure):
 class vy_render_opts(ctypes.Structure):
     _fields_ = [("alpha_filter", ctypes.c_int32), ("bg", ctypes.c_float * 3), ("save_state", ctypes.c_int32),
                 ("split_min_pairs", ctypes.c_int32), ("walk", ctypes.c_int32), ("lut_entries", ctypes.c_int32)]
+
+
+class vy_grads(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("mean", "log_scale", "quat", "opacity_logit", "sh", "mean2d",
+                                               "quat_raw")]
 
 
 class vy_session(ctypes.Structure):
@@ -111,7 +116,9 @@ def lib():
         "vy_render_ctx_free": ([P], ctypes.c_int),
         "vy_render": ([P, P, ctypes.POINTER(vy_camera), ctypes.POINTER(vy_render_opts), P, P, P], ctypes.c_int),
         "vy_render_status": ([P, ctypes.POINTER(I64), ctypes.POINTER(I64), P], ctypes.c_int),
-        "vy_render_saved": ([P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P)],
+        "vy_render_backward": ([P, P, ctypes.POINTER(vy_camera), P, ctypes.POINTER(vy_grads), P, P], ctypes.c_int),
+        "vy_render_saved": ([P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P),
+                             ctypes.POINTER(P)],
                             ctypes.c_int),
         "vy_render_pairs": ([P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P)], ctypes.c_int),
         "vy_render_projected": ([P] + [ctypes.POINTER(P)] * 4, ctypes.c_int),
@@ -316,20 +323,26 @@ class RenderContext:
         rc = lib().vy_render_status(self.handle, ctypes.byref(n_pairs), ctypes.byref(n_vis), _stream(stream))
         return rc, int(n_pairs.value), int(n_vis.value)
 
-    def saved(self, width, height, evals=False):
-        """(T_final, n_contrib[, n_eval]) of the last frame rendered with save_state (synchronises)."""
-        pt, pn, pe, pm = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+    def saved(self, width, height, evals=False, last=False):
+        """(T_final, n_contrib[, n_eval][, last contributor]) of the last frame
+        rendered with save_state (synchronises)."""
+        pt, pn, pe, pl, pm = (ctypes.c_void_p() for _ in range(5))
         check(lib().vy_render_saved(self.handle, ctypes.byref(pt), ctypes.byref(pn), ctypes.byref(pe),
-                                    ctypes.byref(pm)), "vy_render_saved")
+                                    ctypes.byref(pl), ctypes.byref(pm)), "vy_render_saved")
         T = np.empty((height, width), np.float32)
         N = np.empty((height, width), np.int32)
         _copy_d2h(T, pt.value)
         _copy_d2h(N, pn.value)
-        if not evals:
-            return T, N
-        E = np.empty((height, width), np.int32)
-        _copy_d2h(E, pe.value)
-        return T, N, E
+        out = [T, N]
+        if evals:
+            E = np.empty((height, width), np.int32)
+            _copy_d2h(E, pe.value)
+            out.append(E)
+        if last:
+            Lc = np.empty((height, width), np.int32)
+            _copy_d2h(Lc, pl.value)
+            out.append(Lc)
+        return tuple(out)
 
     def pairs(self, width, height):
         """Last frame's sorted pairs (tile ids, cut positions) and tile ranges (synchronises)."""
@@ -410,6 +423,34 @@ def vy_render(scene: Scene, cut: Cut, cam, ctx: RenderContext, image=None, alpha
     check(lib().vy_render(scene.handle, cut.handle, ctypes.byref(c), ctypes.byref(o),
                           ctypes.c_void_p(image.data_ptr()), ctx.handle, _stream(stream)), "vy_render")
     return image
+
+
+def vy_render_backward(scene: Scene, cut: Cut, cam, ctx: RenderContext, dL_dimage, quat_raw=None,
+                       mean2d=False, stream=None):
+    """Gradients of the last vy_render(..., save_state=True) on `ctx` for
+    dL/dimage (torch float32 [3, H, W] on the device). Returns a dict of
+    node-indexed torch tensors: mean [n, 3], log_scale [n, 3], quat [n, 4]
+    (for `quat_raw`, the quaternions as uploaded, when given; else for the unit
+    quaternion), opacity_logit [n], sh [n, 16, 3] (and mean2d [n, 2])."""
+    import torch
+    n = scene.n
+    if dL_dimage.dtype != torch.float32 or not dL_dimage.is_contiguous() or \
+            tuple(dL_dimage.shape) != (3, cam.height, cam.width):
+        raise VoyagerError(VY_ERR_ARG, "dL_dimage must be a contiguous float32 tensor of shape (3, H, W)")
+    dev = dL_dimage.device
+    out = dict(mean=torch.zeros((n, 3), device=dev), log_scale=torch.zeros((n, 3), device=dev),
+               quat=torch.zeros((n, 4), device=dev), opacity_logit=torch.zeros(n, device=dev),
+               sh=torch.zeros((n, 16, 3), device=dev))
+    if mean2d:
+        out["mean2d"] = torch.zeros((n, 2), device=dev)
+    g = vy_grads()
+    for k, t in out.items():
+        setattr(g, k, t.data_ptr())
+    g.quat_raw = quat_raw.data_ptr() if quat_raw is not None else None
+    c = make_camera(cam)
+    check(lib().vy_render_backward(scene.handle, cut.handle, ctypes.byref(c), ctypes.c_void_p(dL_dimage.data_ptr()),
+                                   ctypes.byref(g), ctx.handle, _stream(stream)), "vy_render_backward")
+    return out
 
 
 def profile_begin(capacity=1 << 16):

@@ -80,7 +80,7 @@ const char* vy_version(void) { return "voyager-mi355x 0.1 (gfx950)"; }
 
 static const char* kStageNames[VY_NUM_STAGES] = {
     "lod_setup", "lod_flat", "lod_classify", "lod_traverse", "lod_compact", "render_setup", "project",
-    "depth_sort", "pair_scan", "emit", "tile_sort", "ranges", "blend_plan", "blend"};
+    "depth_sort", "pair_scan", "emit", "tile_sort", "ranges", "blend_plan", "blend", "bwd_blend", "bwd_project"};
 
 const char* vy_stage_name(int stage) {
   if (stage < 0 || stage >= VY_NUM_STAGES) return "?";

@@ -595,6 +595,7 @@ int vy_lod_cut(const vy_scene* scene, const vy_camera* cam, float tau, vy_cut* p
     VY_LAUNCHED();
   }
   o->cur = dst;
+  ++o->version;
   return VY_OK;
 }
 
@@ -634,6 +635,7 @@ int vy_cut_set_frontier(vy_cut* cut, const int32_t* ids, int64_t n, void* stream
   set_count<<<1, 64, 0, st>>>(c->counts + dst, (int32_t)n);
   VY_LAUNCHED();
   c->cur = dst;
+  ++c->version;
   return VY_OK;
 }
 

@@ -732,6 +732,7 @@ struct PixAcc {
   float Tb, Cb0, Cb1, Cb2;  // current bin
   int32_t nt, nb;
   uint32_t stop_pos;        // tile-list position of the Gaussian where blending stopped (save mode)
+  uint32_t last;            // tile-list position of the last blended Gaussian (save mode)
   bool done;
   uint32_t cur_key;         // depth bin of the current bin (0xFFFFFFFF before the first)
   uint32_t lb;              // local index of the current bin (split mode)
@@ -810,6 +811,7 @@ VY_DEV void blend_one(uint32_t key, const float4 p0, const float4 p1, const floa
   A.Cb2 = fmaf(wgt, p2.z, A.Cb2);
   A.Tb = bl ? Tn : ((SPLIT && stop) ? 0.f : A.Tb);
   A.nb += bl ? 1 : 0;
+  if (SAVE && bl) A.last = pos;
   if (SAVE && stop) A.stop_pos = pos;
   A.done = A.done || stop;
 }
@@ -883,6 +885,7 @@ VY_DEV void blend_sparse(const Stage& S, int w, int jj, uint64_t mk, uint32_t b0
       A.Cb2 = fmaf(wgt, p2[u].z, A.Cb2);
       A.Tb = Tn;
       A.nb += 1;
+      if (SAVE) A.last = b0 + (e[u] & 255u);
     }
     if (A.done) mk = 0ull;
   }
@@ -985,6 +988,7 @@ VY_DEV void walk_chunk(const Stage& S, int w, int jc, int mc, uint32_t b0, float
         A.Cb2 = fmaf(wgt, q2[k].z, A.Cb2);
         A.Tb = bl ? Tn : ((SPLIT && stop) ? 0.f : A.Tb);
         A.nb += bl ? 1 : 0;
+        if (SAVE && bl) A.last = b0 + (e[k] & 255u);
         if (SAVE && stop) A.stop_pos = b0 + (e[k] & 255u);
         A.done = A.done || stop;
       }
@@ -1025,10 +1029,12 @@ VY_DEV void blend_range(Stage& S, uint32_t pb, uint32_t pe, const uint32_t* __re
 
 // Final fold of the open depth bin and the pixel's outputs (image with the
 // background behind the remaining transmittance; in save mode T, the number of
-// blended Gaussians and the number of tile-list entries walked).
+// blended Gaussians, the number of tile-list entries walked and the tile-list
+// position of the last blended Gaussian, -1 if none).
 template <bool SAVE>
 VY_DEV void pixel_out(PixAcc& A, const RCam& cam, int px, int py, uint32_t pb, uint32_t pe, float* __restrict__ img,
-                      float* __restrict__ Tout, int32_t* __restrict__ Nout, int32_t* __restrict__ Eout) {
+                      float* __restrict__ Tout, int32_t* __restrict__ Nout, int32_t* __restrict__ Eout,
+                      int32_t* __restrict__ Lout) {
   A.C0 = fmaf(A.Tt, A.Cb0, A.C0);
   A.C1 = fmaf(A.Tt, A.Cb1, A.C1);
   A.C2 = fmaf(A.Tt, A.Cb2, A.C2);
@@ -1042,6 +1048,7 @@ VY_DEV void pixel_out(PixAcc& A, const RCam& cam, int px, int py, uint32_t pb, u
     Tout[o] = A.Tt;
     Nout[o] = A.nt;
     Eout[o] = (int32_t)((A.stop_pos != 0xFFFFFFFFu ? A.stop_pos + 1u : pe) - pb);
+    Lout[o] = A.last == 0xFFFFFFFFu ? -1 : (int32_t)A.last;
   }
 }
 
@@ -1052,6 +1059,7 @@ VY_DEV void pix_init(PixAcc& A, bool inside) {
   A.Cb0 = A.Cb1 = A.Cb2 = 0.f;
   A.nt = A.nb = 0;
   A.stop_pos = 0xFFFFFFFFu;
+  A.last = 0xFFFFFFFFu;
   A.done = !inside;
   A.cur_key = 0xFFFFFFFFu;
   A.lb = 0;
@@ -1068,7 +1076,7 @@ VY_DEV void blend_band(Stage& S, int w, int tx, int ty, int band, uint32_t pb, u
                        const uint32_t* __restrict__ tval, const float4* __restrict__ pg0,
                        const float4* __restrict__ pg1, const float4* __restrict__ pg2, uint32_t n_g, const RCam& cam,
                        float* __restrict__ img, float* __restrict__ Tout, int32_t* __restrict__ Nout,
-                       int32_t* __restrict__ Eout, int walk, const ExpLut& L) {
+                       int32_t* __restrict__ Eout, int32_t* __restrict__ Lout, int walk, const ExpLut& L) {
   const int l = (int)(threadIdx.x & 63);
   const int px = tx * kTileSize + (l & 15), py = ty * kTileSize + band * 4 + (l >> 4);
   const bool inside = px < cam.W && py < cam.H;
@@ -1146,7 +1154,7 @@ VY_DEV void blend_band(Stage& S, int w, int tx, int ty, int band, uint32_t pb, u
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  if (inside) pixel_out<SAVE>(A, cam, px, py, pb, pe, img, Tout, Nout, Eout);
+  if (inside) pixel_out<SAVE>(A, cam, px, py, pb, pe, img, Tout, Nout, Eout, Lout);
 }
 
 template <bool FILTER, bool SAVE, bool LUT>
@@ -1160,7 +1168,8 @@ __global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ rang
                                                   int32_t* __restrict__ bin_n, uint32_t* ctr, uint32_t n_g,
                                                   uint32_t n_pairs_cap, float* __restrict__ img,
                                                   float* __restrict__ Tout, int32_t* __restrict__ Nout,
-                                                  int32_t* __restrict__ Eout, int walk, int band_wgs, int lut_m) {
+                                                  int32_t* __restrict__ Eout, int32_t* __restrict__ Lout, int walk,
+                                                  int band_wgs, int lut_m) {
   __shared__ Stage S;
   __shared__ uint32_t s_job;
   __shared__ float s_lut[LUT ? kLutMax + 1 : 1];
@@ -1193,7 +1202,7 @@ __global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ rang
       if (pe > n_pairs_cap) pe = n_pairs_cap;
       if (pb > pe) pb = pe;
       blend_band<FILTER, SAVE, LUT>(S, w, (int)tile % cam.tiles_x, (int)tile / cam.tiles_x, (int)(jb & 3u), pb, pe,
-                                    tval, pg0, pg1, pg2, n_g, cam, img, Tout, Nout, Eout, walk, L);
+                                    tval, pg0, pg1, pg2, n_g, cam, img, Tout, Nout, Eout, Lout, walk, L);
     }
     __builtin_amdgcn_s_setprio(0);
     return;
@@ -1275,7 +1284,7 @@ __global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ rang
       for (; A.lb < so.lbin1; ++A.lb) put_bin(so, A.lb, make_float4(0.f, 0.f, 0.f, 1.f), 0);
     } else {
       blend_range<FILTER, false, SAVE, LUT>(S, pb, pe, tval, pg0, pg1, pg2, n_g, tx, ty, fxp, fyp, A, so, walk, L);
-      if (inside) pixel_out<SAVE>(A, cam, px, py, pb, pe, img, Tout, Nout, Eout);
+      if (inside) pixel_out<SAVE>(A, cam, px, py, pb, pe, img, Tout, Nout, Eout, Lout);
     }
     if (urgent) __builtin_amdgcn_s_setprio(0);
     __syncthreads();
@@ -1433,6 +1442,346 @@ __global__ __launch_bounds__(256) void composite_redo(const uint32_t* __restrict
   }
 }
 
+// ------------------------------------------------------------------------
+// Backward pass. The image is C = sum_i c_i alpha_i T_i + T_final bg with
+// T_i = prod_{j<i} (1 - alpha_j) over the Gaussians a pixel blended (Eq. 3).
+// Walking them back to front from the last one, T_i = T_{i+1} / (1 - alpha_i)
+// and with S_i = sum_{j>i} c_j alpha_j T_j + T_final bg (what lies behind i):
+//   dC/dc_i = alpha_i T_i,   dC/dalpha_i = c_i T_i - S_i / (1 - alpha_i).
+// alpha = min(0.99, theta e^rho) and rho = min(0, A dx^2 + B dx dy + C dy^2)
+// (dx = mean - pixel centre) carry it to theta, the 2D mean and (A, B, C);
+// the clamps pass no gradient. Per Gaussian, the nine sums are reduced over
+// each wave and added into per-cut-position accumulators.
+struct GradAcc {
+  float* v[9];   // d/d mean2d.x, mean2d.y, A, B, C, theta, r, g, b
+};
+
+__global__ __launch_bounds__(256) void bwd_zero(GradAcc acc, const int32_t* n_cut_ptr, uint32_t gcap) {
+  uint32_t n = (uint32_t)*n_cut_ptr;
+  if (n > gcap) n = gcap;
+  for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u)
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc.v[k][i] = 0.f;
+}
+
+__global__ __launch_bounds__(256) void blend_backward(const uint2* __restrict__ ranges,
+                                                      const uint32_t* __restrict__ tval,
+                                                      const float4* __restrict__ pg0, const float4* __restrict__ pg1,
+                                                      const float4* __restrict__ pg2, RCam cam, int ntiles,
+                                                      const float* __restrict__ dimg, const float* __restrict__ Tfin,
+                                                      const int32_t* __restrict__ last, uint32_t n_g,
+                                                      uint32_t n_pairs_cap, GradAcc acc) {
+  __shared__ float4 s0[256], s1[256], s2[256];
+  __shared__ uint32_t s_g[256];
+  __shared__ float s_acc[9][256];
+  __shared__ int s_max;
+  const int l = (int)(threadIdx.x & 63);
+  const size_t hw = (size_t)cam.W * cam.H;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
+    const int px = tx * kTileSize + (int)(threadIdx.x & 15), py = ty * kTileSize + (int)(threadIdx.x >> 4);
+    const bool inside = px < cam.W && py < cam.H;
+    const size_t o = (size_t)py * cam.W + px;
+    const uint2 rg = ranges[tile];
+    uint32_t pb = rg.x, pe = rg.y;
+    if (pe > n_pairs_cap) pe = n_pairs_cap;
+    if (pb > pe) pb = pe;
+    float d0 = 0.f, d1 = 0.f, d2 = 0.f, T = 1.f;
+    int lst = -1;
+    if (inside) {
+      d0 = dimg[o];
+      d1 = dimg[hw + o];
+      d2 = dimg[2 * hw + o];
+      T = Tfin[o];
+      lst = last[o];
+    }
+    float S0 = T * cam.bg[0], S1 = T * cam.bg[1], S2 = T * cam.bg[2];
+    if (threadIdx.x == 0) s_max = -1;
+    __syncthreads();
+    if (lst >= 0) atomicMax(&s_max, lst);
+    __syncthreads();
+    const int pend = s_max + 1;
+    const float fxp = px + 0.5f, fyp = py + 0.5f;
+    for (int bend = pend; bend > (int)pb; bend -= 256) {
+      const int b0 = bend - 256 > (int)pb ? bend - 256 : (int)pb;
+      const int cnt = bend - b0;
+      if ((int)threadIdx.x < cnt) {
+        uint32_t g = tval[b0 + threadIdx.x];
+        if (g >= n_g) g = 0;
+        s_g[threadIdx.x] = g;
+        s0[threadIdx.x] = pg0[g];
+        s1[threadIdx.x] = pg1[g];
+        s2[threadIdx.x] = pg2[g];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) s_acc[k][threadIdx.x] = 0.f;
+      }
+      __syncthreads();
+      for (int j = cnt - 1; j >= 0; --j) {
+        const float4 p0 = s0[j], p1 = s1[j], p2 = s2[j];
+        const float dx = p0.x - fxp, dy = p0.y - fyp;
+        const float raw = fmaf(dx, fmaf(p0.z, dx, p0.w * dy), (p1.x * dy) * dy);
+        const float power = fminf(raw, 0.f);
+        const uint32_t ext = __float_as_uint(p2.w);
+        bool on = inside && b0 + j <= lst && fabsf(dx) <= (float)(ext & 0xFFFFu) && fabsf(dy) <= (float)(ext >> 16);
+        const float e = __expf(power);
+        const float araw = p1.y * e;
+        const float alpha = fminf(kAlphaMax, araw);
+        on = on && alpha >= kAlphaMin;   // the forward's decision, recomputed the same way
+        float v[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (on) {
+          const float om = 1.f - alpha;
+          T = T / om;                                          // transmittance in front of this Gaussian
+          const float w = alpha * T;
+          v[6] = w * d0;
+          v[7] = w * d1;
+          v[8] = w * d2;
+          const float io = 1.f / om;
+          const float dla = (p2.x * T - S0 * io) * d0 + (p2.y * T - S1 * io) * d1 + (p2.z * T - S2 * io) * d2;
+          S0 = fmaf(p2.x, w, S0);
+          S1 = fmaf(p2.y, w, S1);
+          S2 = fmaf(p2.z, w, S2);
+          if (araw < kAlphaMax) {
+            v[5] = dla * e;                                    // d alpha / d theta = e^rho
+            if (raw < 0.f) {
+              const float gr = dla * alpha;                    // d alpha / d rho = alpha
+              v[0] = gr * fmaf(2.f * p0.z, dx, p0.w * dy);
+              v[1] = gr * fmaf(p0.w, dx, 2.f * p1.x * dy);
+              v[2] = gr * dx * dx;
+              v[3] = gr * dx * dy;
+              v[4] = gr * dy * dy;
+            }
+          }
+        }
+        if (__ballot(on) != 0ull) {
+#pragma unroll
+          for (int k = 0; k < 9; ++k) {
+            float x = v[k];
+#pragma unroll
+            for (int s = 32; s > 0; s >>= 1) x += __shfl_xor(x, s, 64);
+            v[k] = x;
+          }
+          if (l == 0) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) atomicAdd(&s_acc[k][j], v[k]);
+          }
+        }
+      }
+      __syncthreads();
+      if ((int)threadIdx.x < cnt) {
+        const uint32_t g = s_g[threadIdx.x];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+          const float x = s_acc[k][threadIdx.x];
+          if (x != 0.f) atomicAdd(acc.v[k] + g, x);
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Gradients of the SH colour's basis (the forward's polynomial forms) at the
+// unit direction (x, y, z): rows are d Y_k / d(x, y, z).
+VY_DEV void sh_basis_grad(float x, float y, float z, float Y[16], float G[16][3]) {
+  const float C0 = 0.28209479177387814f, C1 = 0.4886025119029199f, C2a = 1.0925484305920792f;
+  const float C20 = 0.31539156525252005f, C22 = 0.5462742152960396f, C33 = 0.5900435899266435f;
+  const float C32 = 2.890611442640554f, C31 = 0.4570457994644658f, C30 = 0.3731763325901154f;
+  const float C32p = 1.445305721320277f;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  Y[0] = C0;            G[0][0] = 0.f;                G[0][1] = 0.f;                 G[0][2] = 0.f;
+  Y[1] = C1 * y;        G[1][0] = 0.f;                G[1][1] = C1;                  G[1][2] = 0.f;
+  Y[2] = C1 * z;        G[2][0] = 0.f;                G[2][1] = 0.f;                 G[2][2] = C1;
+  Y[3] = C1 * x;        G[3][0] = C1;                 G[3][1] = 0.f;                 G[3][2] = 0.f;
+  Y[4] = C2a * x * y;   G[4][0] = C2a * y;            G[4][1] = C2a * x;             G[4][2] = 0.f;
+  Y[5] = C2a * y * z;   G[5][0] = 0.f;                G[5][1] = C2a * z;             G[5][2] = C2a * y;
+  Y[6] = C20 * (3.f * zz - 1.f);
+  G[6][0] = 0.f;        G[6][1] = 0.f;                G[6][2] = 6.f * C20 * z;
+  Y[7] = C2a * x * z;   G[7][0] = C2a * z;            G[7][1] = 0.f;                 G[7][2] = C2a * x;
+  Y[8] = C22 * (xx - yy);
+  G[8][0] = 2.f * C22 * x;  G[8][1] = -2.f * C22 * y;  G[8][2] = 0.f;
+  Y[9] = C33 * y * (3.f * xx - yy);
+  G[9][0] = 6.f * C33 * x * y;  G[9][1] = 3.f * C33 * (xx - yy);  G[9][2] = 0.f;
+  Y[10] = C32 * x * y * z;
+  G[10][0] = C32 * y * z;  G[10][1] = C32 * x * z;  G[10][2] = C32 * x * y;
+  Y[11] = C31 * y * (5.f * zz - 1.f);
+  G[11][0] = 0.f;  G[11][1] = C31 * (5.f * zz - 1.f);  G[11][2] = 10.f * C31 * y * z;
+  Y[12] = C30 * z * (5.f * zz - 3.f);
+  G[12][0] = 0.f;  G[12][1] = 0.f;  G[12][2] = C30 * (15.f * zz - 3.f);
+  Y[13] = C31 * x * (5.f * zz - 1.f);
+  G[13][0] = C31 * (5.f * zz - 1.f);  G[13][1] = 0.f;  G[13][2] = 10.f * C31 * x * z;
+  Y[14] = C32p * z * (xx - yy);
+  G[14][0] = 2.f * C32p * x * z;  G[14][1] = -2.f * C32p * y * z;  G[14][2] = C32p * (xx - yy);
+  Y[15] = C33 * x * (xx - 3.f * yy);
+  G[15][0] = 3.f * C33 * (xx - yy);  G[15][1] = -6.f * C33 * x * y;  G[15][2] = 0.f;
+}
+
+struct NodeGrads {
+  float* mean;           // [n][3]
+  float* log_scale;      // [n][3]
+  float* quat;           // [n][4]
+  float* logit;          // [n]
+  float* sh;             // [n][48]
+  float* mean2d;         // [n][2]
+  const float* quat_raw; // [n][4] or null
+};
+
+// Per cut Gaussian: the projection (Section 3.1 "Culling & Projection", as in
+// `project`) differentiated from the accumulated 2D-mean, conic, opacity and
+// colour gradients down to the node's parameters.
+__global__ __launch_bounds__(256) void project_backward(const int32_t* __restrict__ cut, const int32_t* n_cut_ptr,
+                                                        const float4* __restrict__ gauss,
+                                                        const float* __restrict__ sh, RCam cam, GradAcc acc,
+                                                        NodeGrads out, int64_t n_nodes, uint32_t gcap) {
+  uint32_t n = (uint32_t)*n_cut_ptr;
+  if (n > gcap) n = gcap;
+  for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u) {
+    const int32_t node = cut[i];
+    if (node < 0 || node >= n_nodes) continue;
+    float gm[3] = {0.f, 0.f, 0.f}, gls[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f}, glogit = 0.f;
+    float gsh[48];
+#pragma unroll
+    for (int k = 0; k < 48; ++k) gsh[k] = 0.f;
+    const float g_mx = acc.v[0][i], g_my = acc.v[1][i];
+    const float4 g0 = gauss[3 * (int64_t)node], g1 = gauss[3 * (int64_t)node + 1], g2 = gauss[3 * (int64_t)node + 2];
+    const float dxw = g0.x - cam.px, dyw = g0.y - cam.py, dzw = g0.z - cam.pz;
+    const float x = (cam.R[0] * dxw + cam.R[1] * dyw) + cam.R[2] * dzw;
+    const float y = (cam.R[3] * dxw + cam.R[4] * dyw) + cam.R[5] * dzw;
+    const float z = (cam.R[6] * dxw + cam.R[7] * dyw) + cam.R[8] * dzw;
+    if (z > cam.near) {
+      const float qw = g2.x, qx = g2.y, qy = g2.z, qz = g2.w;
+      const float Rq[9] = {1.f - 2.f * (qy * qy + qz * qz), 2.f * (qx * qy - qw * qz), 2.f * (qx * qz + qw * qy),
+                           2.f * (qx * qy + qw * qz), 1.f - 2.f * (qx * qx + qz * qz), 2.f * (qy * qz - qw * qx),
+                           2.f * (qx * qz - qw * qy), 2.f * (qy * qz + qw * qx), 1.f - 2.f * (qx * qx + qy * qy)};
+      const float s[3] = {g1.x, g1.y, g1.z};
+      const float iz = 1.f / z;
+      const float ur = x * iz, vr = y * iz;
+      const float u = fminf(fmaxf(ur, cam.ulo), cam.uhi), v = fminf(fmaxf(vr, cam.vlo), cam.vhi);
+      float T0[3], T1[3], M[9], V0[3], V1[3];
+      for (int k = 0; k < 3; ++k) {
+        T0[k] = (cam.fx * iz) * (cam.R[k] - u * cam.R[6 + k]);
+        T1[k] = (cam.fy * iz) * (cam.R[3 + k] - v * cam.R[6 + k]);
+      }
+      for (int r = 0; r < 3; ++r)
+        for (int j = 0; j < 3; ++j) M[3 * r + j] = Rq[3 * r + j] * s[j];
+      for (int j = 0; j < 3; ++j) {
+        V0[j] = (T0[0] * M[j] + T0[1] * M[3 + j]) + T0[2] * M[6 + j];
+        V1[j] = (T1[0] * M[j] + T1[1] * M[3 + j]) + T1[2] * M[6 + j];
+      }
+      const float a = ((V0[0] * V0[0] + V0[1] * V0[1]) + V0[2] * V0[2]) + kLowpass;
+      const float b = (V0[0] * V1[0] + V0[1] * V1[1]) + V0[2] * V1[2];
+      const float c = ((V1[0] * V1[0] + V1[1] * V1[1]) + V1[2] * V1[2]) + kLowpass;
+      const float det = fmaf(a, c, -b * b);
+      if (det > 0.f) {
+        // conic (ca, cb, cc) = (c, -b, a) / det; rho uses (A, B, C) = (-ca/2, -cb, -cc/2)
+        const float dca = -0.5f * acc.v[2][i], dcb = -acc.v[3][i], dcc = -0.5f * acc.v[4][i];
+        const float id2 = 1.f / (det * det);
+        const float ga = (-c * c * dca + b * c * dcb - b * b * dcc) * id2;
+        const float gb = (2.f * b * c * dca - (a * c + b * b) * dcb + 2.f * a * b * dcc) * id2;
+        const float gc = (-b * b * dca + a * b * dcb - a * a * dcc) * id2;
+        // Sigma2 = V V^T (+ low-pass): a = |V0|^2, b = V0.V1, c = |V1|^2
+        float gV0[3], gV1[3];
+        for (int j = 0; j < 3; ++j) {
+          gV0[j] = 2.f * ga * V0[j] + gb * V1[j];
+          gV1[j] = gb * V0[j] + 2.f * gc * V1[j];
+        }
+        // V = T M
+        float gT0[3], gT1[3], gM[9];
+        for (int k = 0; k < 3; ++k) {
+          gT0[k] = (gV0[0] * M[3 * k] + gV0[1] * M[3 * k + 1]) + gV0[2] * M[3 * k + 2];
+          gT1[k] = (gV1[0] * M[3 * k] + gV1[1] * M[3 * k + 1]) + gV1[2] * M[3 * k + 2];
+          for (int j = 0; j < 3; ++j) gM[3 * k + j] = T0[k] * gV0[j] + T1[k] * gV1[j];
+        }
+        // M = Rq diag(s): scales (as log-scales) and the rotation
+        float gR[9];
+        for (int j = 0; j < 3; ++j) {
+          const float gs = (gM[j] * Rq[j] + gM[3 + j] * Rq[3 + j]) + gM[6 + j] * Rq[6 + j];
+          gls[j] = gs * s[j];
+          for (int r = 0; r < 3; ++r) gR[3 * r + j] = gM[3 * r + j] * s[j];
+        }
+        gq[0] = 2.f * (-qz * gR[1] + qy * gR[2] + qz * gR[3] - qx * gR[5] - qy * gR[6] + qx * gR[7]);
+        gq[1] = 2.f * (qy * gR[1] + qz * gR[2] + qy * gR[3] - 2.f * qx * gR[4] - qw * gR[5] + qz * gR[6] +
+                       qw * gR[7] - 2.f * qx * gR[8]);
+        gq[2] = 2.f * (-2.f * qy * gR[0] + qx * gR[1] + qw * gR[2] + qx * gR[3] + qz * gR[5] - qw * gR[6] +
+                       qz * gR[7] - 2.f * qy * gR[8]);
+        gq[3] = 2.f * (-2.f * qz * gR[0] - qw * gR[1] + qx * gR[2] + qw * gR[3] - 2.f * qz * gR[4] + qy * gR[5] +
+                       qx * gR[6] + qy * gR[7]);
+        // T rows: fx/z (R0 - u R2), fy/z (R1 - v R2); mean2d = (fx x/z + cx, fy y/z + cy)
+        float g_iz = g_mx * cam.fx * x + g_my * cam.fy * y, g_u = 0.f, g_v = 0.f;
+        for (int k = 0; k < 3; ++k) {
+          g_iz += gT0[k] * cam.fx * (cam.R[k] - u * cam.R[6 + k]) + gT1[k] * cam.fy * (cam.R[3 + k] - v * cam.R[6 + k]);
+          g_u -= gT0[k] * cam.fx * iz * cam.R[6 + k];
+          g_v -= gT1[k] * cam.fy * iz * cam.R[6 + k];
+        }
+        const bool fu = ur > cam.ulo && ur < cam.uhi, fv = vr > cam.vlo && vr < cam.vhi;   // clamps pass nothing
+        float gx = g_mx * cam.fx * iz, gy = g_my * cam.fy * iz;
+        if (fu) {
+          gx += g_u * iz;
+          g_iz += g_u * x;
+        }
+        if (fv) {
+          gy += g_v * iz;
+          g_iz += g_v * y;
+        }
+        const float gz = -g_iz * iz * iz;
+        // x_cam = R (mean - pos)
+        for (int k = 0; k < 3; ++k) gm[k] = (cam.R[k] * gx + cam.R[3 + k] * gy) + cam.R[6 + k] * gz;
+        // opacity: theta = sigmoid(logit)
+        const float th = g1.w;
+        glogit = acc.v[5][i] * th * (1.f - th);
+        // colour: clamp(sum_k Y_k(d) sh_k + 0.5, 0, 1), d = (mean - camera centre) / |.|
+        const float dn = 1.f / sqrtf((dxw * dxw + dyw * dyw) + dzw * dzw);
+        const float ux = dxw * dn, uy = dyw * dn, uz = dzw * dn;
+        float Y[16], G[16][3];
+        sh_basis_grad(ux, uy, uz, Y, G);
+        const float* cf = sh + 48 * (int64_t)node;
+        float raw[3] = {0.f, 0.f, 0.f};
+        for (int k = 0; k < 16; ++k)
+          for (int ch = 0; ch < 3; ++ch) raw[ch] = fmaf(Y[k], cf[3 * k + ch], raw[ch]);
+        float gcol[3];
+        for (int ch = 0; ch < 3; ++ch) {
+          const float cr = raw[ch] + 0.5f;
+          gcol[ch] = (cr > 0.f && cr < 1.f) ? acc.v[6 + ch][i] : 0.f;
+        }
+        float gd[3] = {0.f, 0.f, 0.f};
+        for (int k = 0; k < 16; ++k) {
+          float w = 0.f;
+          for (int ch = 0; ch < 3; ++ch) {
+            gsh[3 * k + ch] = Y[k] * gcol[ch];
+            w = fmaf(cf[3 * k + ch], gcol[ch], w);
+          }
+          for (int e = 0; e < 3; ++e) gd[e] = fmaf(w, G[k][e], gd[e]);
+        }
+        const float rad = (ux * gd[0] + uy * gd[1]) + uz * gd[2];
+        gm[0] += (gd[0] - ux * rad) * dn;
+        gm[1] += (gd[1] - uy * rad) * dn;
+        gm[2] += (gd[2] - uz * rad) * dn;
+      }
+    }
+    // the unit quaternion came from the caller's q / |q|
+    if (out.quat_raw) {
+      const float* qr = out.quat_raw + 4 * (int64_t)node;
+      const float nq = sqrtf((qr[0] * qr[0] + qr[1] * qr[1]) + (qr[2] * qr[2] + qr[3] * qr[3]));
+      const float in = 1.f / nq;
+      const float qh[4] = {qr[0] * in, qr[1] * in, qr[2] * in, qr[3] * in};
+      const float dot = (qh[0] * gq[0] + qh[1] * gq[1]) + (qh[2] * gq[2] + qh[3] * gq[3]);
+      for (int k = 0; k < 4; ++k) gq[k] = (gq[k] - qh[k] * dot) * in;
+    }
+    if (out.mean)
+      for (int k = 0; k < 3; ++k) out.mean[3 * (int64_t)node + k] = gm[k];
+    if (out.log_scale)
+      for (int k = 0; k < 3; ++k) out.log_scale[3 * (int64_t)node + k] = gls[k];
+    if (out.quat)
+      for (int k = 0; k < 4; ++k) out.quat[4 * (int64_t)node + k] = gq[k];
+    if (out.logit) out.logit[node] = glogit;
+    if (out.sh)
+      for (int k = 0; k < 48; ++k) out.sh[48 * (int64_t)node + k] = gsh[k];
+    if (out.mean2d) {
+      out.mean2d[2 * (int64_t)node] = g_mx;
+      out.mean2d[2 * (int64_t)node + 1] = g_my;
+    }
+  }
+}
+
 RCam make_rcam(const vy_camera* c, const vy_render_opts* opt) {
   RCam r;
   for (int i = 0; i < 9; ++i) r.R[i] = c->R[i];
@@ -1536,7 +1885,7 @@ size_t render_workspace_bytes(int64_t max_g, int32_t max_w, int32_t max_h, int64
   b += (size_t)tiles * 8;
   b += 64 * 4 + 6 * 256 * 4;
   b += (size_t)status_words_for(max_g, max_pairs) * 8;
-  b += (size_t)max_w * max_h * 12;                         // saved T, n_contrib, n_eval
+  b += (size_t)max_w * max_h * 16;                         // saved T, n_contrib, n_eval, last contributor
   b += (size_t)tiles * 16;                                 // tile flags, tiers
   if (split) {                                             // tiles split by depth bins
     b += kMaxHeavy * 4 + (size_t)kMaxHeavy * kHeavyRec * 4 + (size_t)kMaxHeavy * kMaxJobsPerTile * 16;
@@ -1614,6 +1963,7 @@ int render_ctx_create_on(int64_t max_g, int32_t max_w, int32_t max_h, int64_t ma
   }
   c->n_contrib = cv.take<int32_t>((size_t)max_w * max_h);
   c->n_eval = cv.take<int32_t>((size_t)max_w * max_h);
+  c->last_contrib = cv.take<int32_t>((size_t)max_w * max_h);
   if (!cv.ok()) {
     free(c);
     return fail(VY_ERR_ARG, "vy_render_ctx_create: workspace layout overflow");
@@ -1764,6 +2114,13 @@ int vy_render(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, co
   const bool split_on = opts && opts->split_min_pairs > 0;
   if (split_on && !c->split) return fail(VY_ERR_ARG, "vy_render: this context has no room for split tiles");
   const int lut_m = opts ? opts->lut_entries : 0;
+  // what the backward pass will find saved
+  c->saved = save && !split_on && lut_m == 0;
+  c->saved_scene = s;
+  c->saved_cut = ct;
+  c->saved_version = ct->version;
+  c->saved_cam = *cam;
+  for (int k = 0; k < 3; ++k) c->saved_bg[k] = opts ? opts->bg[k] : 0.f;
   const uint32_t split_min = split_on ? (uint32_t)opts->split_min_pairs : 0xFFFFFFFFu;
   {
     ProfScope ps(VY_STAGE_BLEND_PLAN, st);
@@ -1782,7 +2139,8 @@ int vy_render(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, co
   blend_jobs<F, S, LT><<<band_wgs + 2048, 256, 0, st>>>(c->ranges, c->tval[0], c->pg0, c->pg1, c->pg2, rc, ntiles,   \
                                                         c->tile_flag, c->tiers, c->heavy_rec, c->jobs, c->bin_c,    \
                                                         c->bin_n, c->ctr, gcap, pcap, image, c->T_final,           \
-                                                        c->n_contrib, c->n_eval, walk, band_wgs, lut_m)
+                                                        c->n_contrib, c->n_eval, c->last_contrib, walk, band_wgs,  \
+                                                        lut_m)
 #define VY_BLEND(F, S)                                                                                          \
   do {                                                                                                          \
     if (lut_m > 0) VY_BLEND_JOBS(F, S, true); else VY_BLEND_JOBS(F, S, false);                                  \
@@ -1802,6 +2160,55 @@ int vy_render(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, co
     }
 #undef VY_BLEND
 #undef VY_BLEND_JOBS
+    VY_LAUNCHED();
+  }
+  return VY_OK;
+}
+
+int vy_render_backward(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, const float* dL_dimage,
+                       const vy_grads* grads, vy_render_ctx* ctx, void* stream) {
+  const Scene* s = (const Scene*)scene;
+  const Cut* ct = (const Cut*)cut;
+  RenderCtx* c = (RenderCtx*)ctx;
+  if (!s || s->magic != kSceneMagic || !ct || ct->magic != kCutMagic || !c || c->magic != kCtxMagic || !cam ||
+      !dL_dimage || !grads)
+    return fail(VY_ERR_ARG, "vy_render_backward: bad argument");
+  if (!c->saved)
+    return fail(VY_ERR_STATE, "vy_render_backward: the last vy_render on this context did not save its state "
+                              "(save_state = 1, no split tiles, exact exponential)");
+  if (c->saved_scene != s || c->saved_cut != ct || c->saved_version != ct->version ||
+      memcmp(&c->saved_cam, cam, sizeof(vy_camera)) != 0)
+    return fail(VY_ERR_STATE, "vy_render_backward: the saved frame is of another scene, cut or camera");
+  hipStream_t st = (hipStream_t)stream;
+  const RCam rc = make_rcam(cam, nullptr);
+  RCam rcb = rc;
+  for (int k = 0; k < 3; ++k) rcb.bg[k] = c->saved_bg[k];
+  const int ntiles = rc.tiles_x * rc.tiles_y;
+  const uint32_t gcap = (uint32_t)c->max_g, pcap = (uint32_t)c->max_pairs;
+  const int32_t* cut_ids = cut_ids_dev(ct);
+  const int32_t* n_cut = cut_count_dev(ct);
+  // per-cut-position accumulators in buffers the forward no longer needs
+  // (depth-sort keys and values, Gaussian offsets, big list, rounding
+  // allowances, binning records)
+  float* pr = reinterpret_cast<float*>(c->prec);
+  GradAcc acc{{reinterpret_cast<float*>(c->dkey[0]), reinterpret_cast<float*>(c->dkey[1]),
+               reinterpret_cast<float*>(c->dval[0]), reinterpret_cast<float*>(c->dval[1]),
+               reinterpret_cast<float*>(c->offsets), reinterpret_cast<float*>(c->big), c->prelax, pr,
+               pr + c->max_g}};
+  const int gblocks = imin(cdiv(c->max_g, 256), 2048);
+  {
+    ProfScope ps(VY_STAGE_BWD_BLEND, st);
+    bwd_zero<<<gblocks, 256, 0, st>>>(acc, n_cut, gcap);
+    VY_LAUNCHED();
+    blend_backward<<<imin(ntiles, 16384), 256, 0, st>>>(c->ranges, c->tval[0], c->pg0, c->pg1, c->pg2, rcb, ntiles,
+                                                        dL_dimage, c->T_final, c->last_contrib, gcap, pcap, acc);
+    VY_LAUNCHED();
+  }
+  {
+    ProfScope ps(VY_STAGE_BWD_PROJECT, st);
+    NodeGrads out{grads->mean, grads->log_scale, grads->quat, grads->opacity_logit, grads->sh, grads->mean2d,
+                  grads->quat_raw};
+    project_backward<<<gblocks, 256, 0, st>>>(cut_ids, n_cut, s->gauss, s->sh, rc, acc, out, s->n, gcap);
     VY_LAUNCHED();
   }
   return VY_OK;
@@ -1831,12 +2238,13 @@ int vy_render_status(vy_render_ctx* ctx, int64_t* n_pairs, int64_t* n_visible, v
 }
 
 int vy_render_saved(const vy_render_ctx* ctx, const float** T_final, const int32_t** n_contrib,
-                    const int32_t** n_eval, const float** mean2d) {
+                    const int32_t** n_eval, const int32_t** last_contrib, const float** mean2d) {
   const RenderCtx* c = (const RenderCtx*)ctx;
   if (!c || c->magic != kCtxMagic) return fail(VY_ERR_ARG, "vy_render_saved: bad argument");
   if (T_final) *T_final = c->T_final;
   if (n_contrib) *n_contrib = c->n_contrib;
   if (n_eval) *n_eval = c->n_eval;
+  if (last_contrib) *last_contrib = c->last_contrib;
   if (mean2d) *mean2d = (const float*)c->pg0;
   return VY_OK;
 }

@@ -93,6 +93,7 @@ struct Cut {
   uint64_t* status;     // look-back status of the compaction scan (2 per partition)
   int64_t n_parts;      // compaction partitions
   uint32_t epoch;
+  uint64_t version;     // counts the cuts written into this handle
 };
 
 struct RenderCtx {
@@ -125,6 +126,14 @@ struct RenderCtx {
   float* T_final;
   int32_t* n_contrib;
   int32_t* n_eval;
+  int32_t* last_contrib;  // tile-list position of the last blended Gaussian, -1 if none
+  // what the last frame saved for the backward pass (vy_render with save_state)
+  bool saved;             // saved state complete: save_state, no split tiles, exact exponential
+  const void* saved_scene;
+  const void* saved_cut;
+  uint64_t saved_version; // version of that cut
+  vy_camera saved_cam;
+  float saved_bg[3];
   // blend planning: tiles split by depth bins
   uint32_t* tile_flag;  // 0 = in tile order, 1 = heavy-first tier, h + 2 = split heavy tile h
   uint32_t* tiers;      // 3 lists of heavy-first tiles

@@ -262,6 +262,7 @@ def test_struct_layouts_match_the_header(tmp_path):
         "vy_server_config": ["arena", "n_streams", "streams", "max_inflight", "max_viewers"],
         "vy_camera": ["R", "pos", "fx", "fy", "cx", "cy", "width", "height", "znear"],
         "vy_render_opts": ["alpha_filter", "bg", "save_state", "split_min_pairs", "walk", "lut_entries"],
+        "vy_grads": ["mean", "log_scale", "quat", "opacity_logit", "sh", "mean2d", "quat_raw"],
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "vy_serve.h"', "int main(void) {"]
     for s, fs in fields.items():
