@@ -217,6 +217,36 @@ class Scene:
         keep = self.arrays["sh"]
         self.arrays = {"sh": keep}
 
+    @classmethod
+    def from_tensors(cls, tree: dict, params: dict, stream=None):
+        """Upload from device tensors: `tree` holds parent, first_child,
+        child_count (int32) and aabb_lo, aabb_hi (float32 [n, 3]); `params`
+        holds mean [n, 3], log_scale [n, 3], quat [n, 4], opacity_logit [n] and
+        sh [n, 16, 3] (float32, contiguous). The sh tensor is borrowed."""
+        import torch
+        self = cls.__new__(cls)
+        L = lib()
+        self.n = int(tree["parent"].shape[0])
+        self.host = None
+        arrays = dict(tree)
+        arrays.update(params)
+        d = vy_scene_desc()
+        d.n_nodes = self.n
+        for k in ("parent", "first_child", "child_count", "aabb_lo", "aabb_hi", "mean", "log_scale", "quat",
+                  "opacity_logit", "sh"):
+            t = arrays[k]
+            if not (t.is_cuda and t.is_contiguous()):
+                raise VoyagerError(VY_ERR_ARG, f"{k} must be a contiguous device tensor")
+            setattr(d, k, t.data_ptr())
+        nb = L.vy_scene_workspace_bytes(self.n)
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=arrays["mean"].device)
+        h = ctypes.c_void_p()
+        check(L.vy_scene_upload(ctypes.byref(d), ctypes.c_void_p(self.ws.data_ptr()), nb, _stream(stream),
+                                ctypes.byref(h)), "vy_scene_upload")
+        self.handle = h
+        self.arrays = {"sh": arrays["sh"]}
+        return self
+
     def validate(self, stream=None) -> int:
         nb = ctypes.c_int64()
         check(lib().vy_scene_validate(self.handle, ctypes.byref(nb), _stream(stream)), "vy_scene_validate")
