@@ -63,7 +63,8 @@ def parse():
     return ap.parse_args()
 
 
-def frame_loop(vy, torch, scene, cams, tau, temporal, filt, state, full_cut, ctx, img, per_frame=True, lut=0):
+def frame_loop(vy, torch, scene, cams, tau, temporal, filt, state, full_cut, ctx, img, per_frame=True, lut=0,
+               mode=0):
     """Run the frames; returns per-frame ms (events on torch's current stream)."""
     ev = []
     for i, cam in enumerate(cams):
@@ -73,12 +74,12 @@ def frame_loop(vy, torch, scene, cams, tau, temporal, filt, state, full_cut, ctx
             e0.record()
         if temporal:
             if i == 0:
-                vy.vy_lod_cut(scene, cam, tau, out=state)
+                vy.vy_lod_cut(scene, cam, tau, out=state, mode=mode)
             else:
-                vy.vy_lod_cut(scene, cam, tau, prev=state, out=state)
+                vy.vy_lod_cut(scene, cam, tau, prev=state, out=state, mode=mode)
             cut = state
         else:
-            vy.vy_lod_cut(scene, cam, tau, out=full_cut)
+            vy.vy_lod_cut(scene, cam, tau, out=full_cut, mode=mode)
             cut = full_cut
         vy.vy_render(scene, cut, cam, ctx, image=img, alpha_filter=filt, lut_entries=lut)
         if per_frame:
@@ -87,10 +88,10 @@ def frame_loop(vy, torch, scene, cams, tau, temporal, filt, state, full_cut, ctx
     return ev
 
 
-def timed(vy, torch, scene, cams, tau, temporal, filt, state, full_cut, ctx, img, lut=0):
+def timed(vy, torch, scene, cams, tau, temporal, filt, state, full_cut, ctx, img, lut=0, mode=0):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev = frame_loop(vy, torch, scene, cams, tau, temporal, filt, state, full_cut, ctx, img, lut=lut)
+    ev = frame_loop(vy, torch, scene, cams, tau, temporal, filt, state, full_cut, ctx, img, lut=lut, mode=mode)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = np.array([a.elapsed_time(b) for a, b in ev])
@@ -198,6 +199,24 @@ def main():
                         k: round(v, 4) for k, v in r.items() if k in ("fps", "p50_ms", "p99_ms")}
             ablation[f"tau={tau:g}"] = row
             log(f"ablation tau={tau:g}: " + ", ".join(f"{k} {v['fps']:.0f}" for k, v in row.items()))
+
+    # --------- LoD traversal: workgroup breadth-first (default) vs per-thread depth-first
+    traversal = {}
+    for name, temporal, filt in (("temporal+filter", True, True), ("full+unfiltered", False, False)):
+        row = {}
+        for tname, mode in (("bfs", 0), ("dfs", vy.VY_CUT_DFS)):
+            r = timed(vy, torch, scene, cams, args.tau, temporal, filt, state, full_cut, ctx, img, mode=mode)
+            vy.profile_begin(64 * K + 64)
+            frame_loop(vy, torch, scene, cams, args.tau, temporal, filt, state, full_cut, ctx, img, per_frame=False,
+                       mode=mode)
+            torch.cuda.synchronize()
+            pr = vy.profile_end()
+            row[tname] = {"fps": round(r["fps"], 2), "p99_ms": round(r["p99_ms"], 4),
+                          "lod_ms_per_frame": round(sum(ms for k, (ms, n) in pr.items() if k.startswith("lod_")) / K,
+                                                    5),
+                          "lod_traverse_ms_per_frame": round(pr["lod_traverse"][0] / K, 5)}
+        traversal[name] = row
+        log(f"traversal {name}: {row}")
 
     # ------------------------------------------------- LUT exponential (Eq. 5)
     lut = {} if args.no_lut else lut_study(vy, torch, scene, cams, args.tau, state, full_cut, ctx, img, img2)
@@ -310,6 +329,7 @@ def main():
         "speedup_vs_full_unfiltered": round(head["fps"] / base["fps"], 3),
         "ablation": ablation,
         "lut": lut,
+        "lod_traversal": traversal,
         "backward": bwd,
         "mean_counts": {k: round(v) for k, v in avg.items()},
         "stages": per_stage,

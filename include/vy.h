@@ -129,8 +129,14 @@ enum {
   VY_CUT_FRONTIER = 0, /* full search: top-down traversal from the root that visits
                           only expanded nodes and their children (Section 4.1,
                           "Fully-Streaming LoD Tree Traversal") */
-  VY_CUT_FLAT = 1      /* full search: exhaustive test of every node (the baseline
+  VY_CUT_FLAT = 1,     /* full search: exhaustive test of every node (the baseline
                           exhaustive search of Section 3.2 "Cut Finding") */
+  VY_CUT_DFS = 2       /* flag, for the top-down traversal of a full or temporal
+                          search: each thread walks its queued node's subtree
+                          depth first, 4 levels per launch, instead of the
+                          default workgroup-wide breadth-first walk of 7 levels
+                          per launch (frontier in LDS). The cut is the same
+                          either way. */
 };
 
 /* Computes the cut for `cam` at LoD granularity `tau` (pixels).
@@ -138,12 +144,14 @@ enum {
  * outside the view frustum (4 side planes through the camera centre and the
  * near plane), and fx * ext(n) > tau * dist(n), where ext is the longest AABB
  * side and dist the distance from the camera centre to the AABB.
- *   prev == NULL : full search, method `full_mode` (VY_CUT_FRONTIER/FLAT).
+ *   prev == NULL : full search, method `full_mode` (VY_CUT_FRONTIER or
+ *                  VY_CUT_FLAT, optionally | VY_CUT_DFS).
  *   prev != NULL : temporal search (Algorithm 1) seeded with prev's frontier;
  *                  prev must hold a cut of the same scene (VY_ERR_STATE if it
  *                  has never been computed, VY_ERR_ARG for another scene).
  *                  prev == out is allowed. The result is identical, bit for
- *                  bit, to the full search.
+ *                  bit, to the full search. `full_mode` may carry
+ *                  VY_CUT_DFS here too.
  * Enqueued on `stream`. */
 int vy_lod_cut(const vy_scene* scene, const vy_camera* cam, float tau, vy_cut* prev, vy_cut* out,
                int full_mode, void* stream);

@@ -302,6 +302,99 @@ __global__ __launch_bounds__(256) void lod_level(const int32_t* __restrict__ in_
   }
 }
 
+// Level launches with a workgroup-local breadth-first walk (Section 4.1,
+// "Fully-Streaming LoD Tree Traversal"). A workgroup takes SEEDS queued nodes
+// at a time and walks their subtrees level by level for LEVELS levels, with
+// each level's frontier in LDS and one node per thread: a level costs one
+// dependent record load per thread instead of one per node of a per-thread
+// descent. SEEDS << (LEVELS - 1) frontier slots hold every node of a binary
+// tree's LEVELS levels (wider fanouts that overflow them queue the extra
+// nodes for the next launch). The children of the last level are queued for
+// the next launch with one atomic per 256 nodes. ceil(tree depth / LEVELS)
+// launches cover any descent, and the last one flags a node it would have to
+// queue. Queue counters rotate over three slots as in lod_level.
+constexpr int kBfsLevels = 13, kBfsSeeds = 1, kBfsSlots = kBfsSeeds << (kBfsLevels - 1);
+
+__global__ __launch_bounds__(256) void lod_bfs(const int32_t* __restrict__ in_q, uint32_t* cnt3, int j,
+                                               int32_t* __restrict__ out_q, const float4* __restrict__ lod,
+                                               const int32_t* __restrict__ ccount, LodCam cam, uint32_t cap,
+                                               uint32_t* fbits, uint32_t* cbits, uint32_t* err, int last) {
+  __shared__ int32_t s_f[2][kBfsSlots];
+  __shared__ uint32_t s_n[2], s_scan[8], s_tail[1];
+  const uint32_t n_in = ld_acq(cnt3 + (j % 3));
+  if (blockIdx.x == 0 && threadIdx.x == 0) cnt3[(j + 2) % 3] = 0;
+  uint32_t* out_cnt = cnt3 + ((j + 1) % 3);
+  const uint32_t tid = threadIdx.x;
+  const uint32_t nchunks = (n_in + kBfsSeeds - 1) / kBfsSeeds;
+  for (uint32_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
+    const uint32_t c0 = chunk * kBfsSeeds;
+    const uint32_t ns = n_in - c0 < (uint32_t)kBfsSeeds ? n_in - c0 : (uint32_t)kBfsSeeds;
+    if (tid < ns) {
+      int32_t nd = in_q[c0 + tid];
+      if (nd < 0 || (uint32_t)nd >= cap) {
+        fetch_add(err, 1u);
+        nd = -1;
+      }
+      s_f[0][tid] = nd;
+    }
+    if (tid == 0) {
+      s_n[0] = ns;
+      s_n[1] = 0;
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int d = 0; d < kBfsLevels; ++d) {
+      const uint32_t nc = s_n[cur] < (uint32_t)kBfsSlots ? s_n[cur] : (uint32_t)kBfsSlots;
+      if (nc == 0) break;   // uniform: read after the barrier
+      const bool deepest = d + 1 == kBfsLevels;
+      // rounds of 256 nodes (a uniform trip count: the last level's queueing uses block barriers)
+      for (uint32_t r0 = 0; r0 < nc; r0 += blockDim.x) {
+        const uint32_t t = r0 + tid;
+        const int32_t n = t < nc ? s_f[cur][t] : -1;
+        uint32_t push = 0;
+        int32_t fc = 0;
+        if (n >= 0) {
+          const float4 a = lod[2 * (int64_t)n], b = lod[2 * (int64_t)n + 1];
+          bool vis;
+          if (!lod_expand(a, b, cam, vis)) {
+            emit_node(n, vis, fbits, cbits);
+          } else {
+            fc = __float_as_int(a.w);
+            const int32_t cc = ccount[n];
+            if (deepest) {
+              push = (uint32_t)cc;
+            } else {
+              for (int k = 0; k < cc; ++k) {
+                const uint32_t slot = atomicAdd(&s_n[cur ^ 1], 1u);
+                if (slot < (uint32_t)kBfsSlots) {
+                  s_f[cur ^ 1][slot] = fc + k;
+                } else if (last) {
+                  fetch_add(err, 1u);
+                } else {
+                  const uint32_t g = fetch_add(out_cnt, 1u);   // past the slots (fanout above 2): next launch
+                  if (g < cap) out_q[g] = fc + k;
+                  else fetch_add(err, 1u);
+                }
+              }
+            }
+          }
+        }
+        if (deepest) {
+          if (last) {
+            if (push) fetch_add(err, 1u);   // deeper than the launches cover: the cut would be incomplete
+          } else {
+            push_children(push, fc, out_q, out_cnt, cap, err, s_scan, s_tail);
+          }
+        }
+      }
+      __syncthreads();
+      if (tid == 0) s_n[cur] = 0;
+      cur ^= 1;
+      __syncthreads();
+    }
+  }
+}
+
 // Compaction of the F and C bitmaps into ascending ids (decoupled look-back
 // scan over partitions of 1024 words), zeroing the bitmaps as they are read.
 // A partition is read as 4 rounds of 256 consecutive words (one per thread);
@@ -546,16 +639,17 @@ int vy_lod_cut(const vy_scene* scene, const vy_camera* cam, float tau, vy_cut* p
     if (p->magic != kCutMagic) return fail(VY_ERR_ARG, "vy_lod_cut: prev is not a cut");
     if (p->scene != s) return fail(VY_ERR_ARG, "vy_lod_cut: prev cut belongs to another scene");
     if (p->cur < 0) return fail(VY_ERR_STATE, "vy_lod_cut: prev cut has no frontier yet");
-  } else if (full_mode != VY_CUT_FRONTIER && full_mode != VY_CUT_FLAT) {
-    return fail(VY_ERR_ARG, "vy_lod_cut: unknown full_mode %d", full_mode);
   }
+  if ((full_mode & ~(VY_CUT_FLAT | VY_CUT_DFS)) != 0)
+    return fail(VY_ERR_ARG, "vy_lod_cut: unknown mode %d", full_mode);
   hipStream_t st = (hipStream_t)stream;
   const LodCam L = make_cam(cam, tau);
   const uint32_t cap = (uint32_t)s->n;
   // destination frontier buffer: never the one we read from
   const int src = p ? p->cur : -1;
   const int dst = (p == o) ? 1 - src : (o->cur < 0 ? 0 : 1 - o->cur);
-  const bool flat = !p && full_mode == VY_CUT_FLAT;
+  const bool flat = !p && (full_mode & VY_CUT_FLAT) != 0;
+  const bool dfs = (full_mode & VY_CUT_DFS) != 0;
   {
     ProfScope ps(VY_STAGE_LOD_SETUP, st);
     lod_setup<<<1, 64, 0, st>>>(o->ctr, o->q[0], (!p && !flat) ? 1 : 0);
@@ -575,15 +669,25 @@ int vy_lod_cut(const vy_scene* scene, const vy_camera* cam, float tau, vy_cut* p
                                          o->fbits, o->cbits);
       VY_LAUNCHED();
     }
-    // enough level launches for the deepest possible descent
-    const int launches = (s->levels + kLocalLevels - 1) / kLocalLevels;
     const int blocks = (int)((s->n + 255) / 256 < 1024 ? (s->n + 255) / 256 : 1024);
-    for (int j = 0; j < launches; ++j) {
-      ProfScope ps(VY_STAGE_LOD_TRAVERSE, st);
-      lod_level<kLocalLevels><<<blocks, 256, 0, st>>>(o->q[j & 1], o->ctr + kQ0, j, o->q[(j + 1) & 1], s->lod,
-                                                      s->ccount, L, cap, o->fbits, o->cbits, o->ctr + kErr,
-                                                      j + 1 == launches);
-      VY_LAUNCHED();
+    if (dfs) {
+      // enough level launches for the deepest possible descent
+      const int launches = (s->levels + kLocalLevels - 1) / kLocalLevels;
+      for (int j = 0; j < launches; ++j) {
+        ProfScope ps(VY_STAGE_LOD_TRAVERSE, st);
+        lod_level<kLocalLevels><<<blocks, 256, 0, st>>>(o->q[j & 1], o->ctr + kQ0, j, o->q[(j + 1) & 1], s->lod,
+                                                        s->ccount, L, cap, o->fbits, o->cbits, o->ctr + kErr,
+                                                        j + 1 == launches);
+        VY_LAUNCHED();
+      }
+    } else {
+      const int launches = (s->levels + kBfsLevels - 1) / kBfsLevels;
+      for (int j = 0; j < launches; ++j) {
+        ProfScope ps(VY_STAGE_LOD_TRAVERSE, st);
+        lod_bfs<<<blocks, 256, 0, st>>>(o->q[j & 1], o->ctr + kQ0, j, o->q[(j + 1) & 1], s->lod, s->ccount, L, cap,
+                                        o->fbits, o->cbits, o->ctr + kErr, j + 1 == launches);
+        VY_LAUNCHED();
+      }
     }
   }
   {

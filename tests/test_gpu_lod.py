@@ -44,6 +44,47 @@ def test_flat_equals_frontier_bitwise(tiny):
             assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
+def test_bfs_and_dfs_traversals_agree(tiny):
+    """The workgroup breadth-first traversal (default) and the per-thread
+    depth-first one give the same cut, bitwise, for full and temporal searches."""
+    vy, sc, host = tiny
+    cams = random_cameras(scenegen.CONFIGS["tiny"], 6, 41)
+    for cam in cams:
+        for tau in (0.0, 0.7, 2.0, 16.0):
+            a = vy.vy_lod_cut(sc, cam, tau).ids()
+            b = vy.vy_lod_cut(sc, cam, tau, mode=vy.VY_CUT_DFS).ids()
+            c = vy.vy_lod_cut(sc, cam, tau, mode=vy.VY_CUT_FLAT).ids()
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+            assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1])
+    q, lv = vy.vy_lod_cut(sc, cams[0], 2.0), vy.vy_lod_cut(sc, cams[0], 2.0, mode=vy.VY_CUT_DFS)
+    for cam in cams[1:]:
+        q = vy.vy_lod_cut(sc, cam, 2.0, prev=q, out=q)
+        lv = vy.vy_lod_cut(sc, cam, 2.0, prev=lv, out=lv, mode=vy.VY_CUT_DFS)
+        a, b = q.ids(), lv.ids()
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_traversals_on_a_larger_city():
+    """200k leaves along a walkthrough: temporal == full (breadth-first) ==
+    full (depth-first), and the full search matches the oracle."""
+    vy = require_gpu()
+    cfg = scenegen.scaled_config("med", 200_000)
+    host = scenegen.make_city(cfg)
+    sc = vy.Scene(host)
+    cams = scenegen.walkthrough(cfg, frames=12, width=640, height=360)
+    state = None
+    for i, cam in enumerate(cams):
+        state = vy.vy_lod_cut(sc, cam, 2.0, prev=state, out=state) if state is not None else vy.vy_lod_cut(sc, cam, 2.0)
+        a = state.ids()
+        b = vy.vy_lod_cut(sc, cam, 2.0).ids()
+        c = vy.vy_lod_cut(sc, cam, 2.0, mode=vy.VY_CUT_DFS).ids()
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), i
+        assert np.array_equal(b[0], c[0]) and np.array_equal(b[1], c[1]), i
+        if i % 6 == 0:
+            res = olod.compare_cut(host, cam, 2.0, b[0], b[1])
+            assert res["ok"], res
+
+
 def test_temporal_equals_full_along_walkthrough(tiny, tiny_cams):
     vy, sc, host = tiny
     state = vy.vy_lod_cut(sc, tiny_cams[0], 2.0)

@@ -59,7 +59,7 @@ def test_adam_steps_reduce_l1_ssim(setup):
         loss = training.loss_l1_ssim(r(params, cam), target)
         loss.backward()
         opt.step()
-        losses.append(float(loss))
+        losses.append(float(loss.detach()))
     print("loss:", [round(x, 5) for x in losses[::8]], losses[-1], flush=True)
     assert np.isfinite(losses).all()
     assert losses[-1] < 0.5 * losses[0]
