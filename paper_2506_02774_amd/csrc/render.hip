@@ -1464,6 +1464,13 @@ __global__ __launch_bounds__(256) void bwd_zero(GradAcc acc, const int32_t* n_cu
     for (int k = 0; k < 9; ++k) acc.v[k][i] = 0.f;
 }
 
+// One wave per (tile, band of 16x4 pixels) job: the wave walks its tile's
+// list back to front in chunks of 64, from the band's furthest last
+// contributor, over the entries whose pixel box may reach the band. Every lane
+// repeats the forward's decision for its pixel. Per entry, the nine sums are
+// reduced across the wave when several lanes contribute (else each
+// contributing lane adds its own) and added atomically at the entry's cut
+// position.
 __global__ __launch_bounds__(256) void blend_backward(const uint2* __restrict__ ranges,
                                                       const uint32_t* __restrict__ tval,
                                                       const float4* __restrict__ pg0, const float4* __restrict__ pg1,
@@ -1471,15 +1478,15 @@ __global__ __launch_bounds__(256) void blend_backward(const uint2* __restrict__ 
                                                       const float* __restrict__ dimg, const float* __restrict__ Tfin,
                                                       const int32_t* __restrict__ last, uint32_t n_g,
                                                       uint32_t n_pairs_cap, GradAcc acc) {
-  __shared__ float4 s0[256], s1[256], s2[256];
-  __shared__ uint32_t s_g[256];
-  __shared__ float s_acc[9][256];
-  __shared__ int s_max;
-  const int l = (int)(threadIdx.x & 63);
+  __shared__ float4 s_r[4][3][64];
+  __shared__ uint32_t s_g[4][64];
+  const int w = (int)(threadIdx.x >> 6), l = (int)(threadIdx.x & 63);
   const size_t hw = (size_t)cam.W * cam.H;
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  const int njobs = 4 * ntiles;
+  for (int job = blockIdx.x * 4 + w; job < njobs; job += gridDim.x * 4) {
+    const int tile = job >> 2, band = job & 3;
     const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
-    const int px = tx * kTileSize + (int)(threadIdx.x & 15), py = ty * kTileSize + (int)(threadIdx.x >> 4);
+    const int px = tx * kTileSize + (l & 15), py = ty * kTileSize + band * 4 + (l >> 4);
     const bool inside = px < cam.W && py < cam.H;
     const size_t o = (size_t)py * cam.W + px;
     const uint2 rg = ranges[tile];
@@ -1496,50 +1503,58 @@ __global__ __launch_bounds__(256) void blend_backward(const uint2* __restrict__ 
       lst = last[o];
     }
     float S0 = T * cam.bg[0], S1 = T * cam.bg[1], S2 = T * cam.bg[2];
-    if (threadIdx.x == 0) s_max = -1;
-    __syncthreads();
-    if (lst >= 0) atomicMax(&s_max, lst);
-    __syncthreads();
-    const int pend = s_max + 1;
-    const float fxp = px + 0.5f, fyp = py + 0.5f;
-    for (int bend = pend; bend > (int)pb; bend -= 256) {
-      const int b0 = bend - 256 > (int)pb ? bend - 256 : (int)pb;
-      const int cnt = bend - b0;
-      if ((int)threadIdx.x < cnt) {
-        uint32_t g = tval[b0 + threadIdx.x];
-        if (g >= n_g) g = 0;
-        s_g[threadIdx.x] = g;
-        s0[threadIdx.x] = pg0[g];
-        s1[threadIdx.x] = pg1[g];
-        s2[threadIdx.x] = pg2[g];
+    int wl = lst;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) s_acc[k][threadIdx.x] = 0.f;
+    for (int s = 32; s > 0; s >>= 1) wl = max(wl, __shfl_xor(wl, s, 64));
+    const int pend = wl + 1;   // wave-uniform: nothing past the band's last contributor
+    const float fxp = px + 0.5f, fyp = py + 0.5f;
+    const float xa = tx * kTileSize + 0.5f, ya = ty * kTileSize + band * 4 + 0.5f;
+    for (int bend = pend; bend > (int)pb; bend -= 64) {
+      const int b0 = bend - 64 > (int)pb ? bend - 64 : (int)pb;
+      const int cnt = bend - b0;
+      bool hit = false;
+      if (l < cnt) {
+        uint32_t g = tval[b0 + l];
+        if (g >= n_g) g = 0;
+        const float4 a = pg0[g], b = pg1[g], c = pg2[g];
+        hit = band_hit(a.x, a.y, c.w, xa, ya);
+        s_r[w][0][l] = a;
+        s_r[w][1][l] = b;
+        s_r[w][2][l] = c;
+        s_g[w][l] = g;
       }
-      __syncthreads();
-      for (int j = cnt - 1; j >= 0; --j) {
-        const float4 p0 = s0[j], p1 = s1[j], p2 = s2[j];
+      uint64_t mask = ballot(hit);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      while (mask != 0ull) {
+        const int j = 63 - __builtin_clzll(mask);   // back to front
+        mask &= ~(1ull << j);
+        const float4 p0 = s_r[w][0][j], p1 = s_r[w][1][j], p2 = s_r[w][2][j];
         const float dx = p0.x - fxp, dy = p0.y - fyp;
         const float raw = fmaf(dx, fmaf(p0.z, dx, p0.w * dy), (p1.x * dy) * dy);
         const float power = fminf(raw, 0.f);
         const uint32_t ext = __float_as_uint(p2.w);
-        bool on = inside && b0 + j <= lst && fabsf(dx) <= (float)(ext & 0xFFFFu) && fabsf(dy) <= (float)(ext >> 16);
+        bool on = b0 + j <= lst && fabsf(dx) <= (float)(ext & 0xFFFFu) && fabsf(dy) <= (float)(ext >> 16);
         const float e = __expf(power);
         const float araw = p1.y * e;
         const float alpha = fminf(kAlphaMax, araw);
         on = on && alpha >= kAlphaMin;   // the forward's decision, recomputed the same way
+        const uint64_t onm = ballot(on);
+        if (onm == 0ull) continue;
         float v[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         if (on) {
           const float om = 1.f - alpha;
           T = T / om;                                          // transmittance in front of this Gaussian
-          const float w = alpha * T;
-          v[6] = w * d0;
-          v[7] = w * d1;
-          v[8] = w * d2;
+          const float wgt = alpha * T;
+          v[6] = wgt * d0;
+          v[7] = wgt * d1;
+          v[8] = wgt * d2;
           const float io = 1.f / om;
           const float dla = (p2.x * T - S0 * io) * d0 + (p2.y * T - S1 * io) * d1 + (p2.z * T - S2 * io) * d2;
-          S0 = fmaf(p2.x, w, S0);
-          S1 = fmaf(p2.y, w, S1);
-          S2 = fmaf(p2.z, w, S2);
+          S0 = fmaf(p2.x, wgt, S0);
+          S1 = fmaf(p2.y, wgt, S1);
+          S2 = fmaf(p2.z, wgt, S2);
           if (araw < kAlphaMax) {
             v[5] = dla * e;                                    // d alpha / d theta = e^rho
             if (raw < 0.f) {
@@ -1552,7 +1567,14 @@ __global__ __launch_bounds__(256) void blend_backward(const uint2* __restrict__ 
             }
           }
         }
-        if (__ballot(on) != 0ull) {
+        const uint32_t g = s_g[w][j];
+        if (__popcll(onm) <= 2) {
+          if (on) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k)
+              if (v[k] != 0.f) atomicAdd(acc.v[k] + g, v[k]);
+          }
+        } else {
 #pragma unroll
           for (int k = 0; k < 9; ++k) {
             float x = v[k];
@@ -1562,20 +1584,14 @@ __global__ __launch_bounds__(256) void blend_backward(const uint2* __restrict__ 
           }
           if (l == 0) {
 #pragma unroll
-            for (int k = 0; k < 9; ++k) atomicAdd(&s_acc[k][j], v[k]);
+            for (int k = 0; k < 9; ++k)
+              if (v[k] != 0.f) atomicAdd(acc.v[k] + g, v[k]);
           }
         }
       }
-      __syncthreads();
-      if ((int)threadIdx.x < cnt) {
-        const uint32_t g = s_g[threadIdx.x];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-          const float x = s_acc[k][threadIdx.x];
-          if (x != 0.f) atomicAdd(acc.v[k] + g, x);
-        }
-      }
-      __syncthreads();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
 }
@@ -2200,8 +2216,8 @@ int vy_render_backward(const vy_scene* scene, const vy_cut* cut, const vy_camera
     ProfScope ps(VY_STAGE_BWD_BLEND, st);
     bwd_zero<<<gblocks, 256, 0, st>>>(acc, n_cut, gcap);
     VY_LAUNCHED();
-    blend_backward<<<imin(ntiles, 16384), 256, 0, st>>>(c->ranges, c->tval[0], c->pg0, c->pg1, c->pg2, rcb, ntiles,
-                                                        dL_dimage, c->T_final, c->last_contrib, gcap, pcap, acc);
+    blend_backward<<<imin(ntiles, 4096), 256, 0, st>>>(c->ranges, c->tval[0], c->pg0, c->pg1, c->pg2, rcb, ntiles,
+                                                       dL_dimage, c->T_final, c->last_contrib, gcap, pcap, acc);
     VY_LAUNCHED();
   }
   {
