@@ -11,11 +11,13 @@ namespace vysort {
 
 using namespace vyd;
 
-// 1024-thread workgroups of 16 waves, 8 keys per thread: 8192 keys per
+// 1024-thread workgroups of 16 waves, 12 keys per thread: 12288 keys per
 // partition, so that a pass over a few million keys needs a few hundred
-// partitions (a short look-back chain) that all run at once.
+// partitions (a short look-back chain) that all run at once. (8 and 16 keys
+// per thread were measured slower: a longer chain, and one workgroup per CU
+// with too little LDS left, respectively.)
 constexpr int kThreads = 1024;
-constexpr int kItems = 8;                     // keys per thread per partition
+constexpr int kItems = 12;                    // keys per thread per partition
 constexpr int kTile = kThreads * kItems;      // keys per partition
 constexpr int kWaves = kThreads / 64;
 
