@@ -335,7 +335,7 @@ __global__ __launch_bounds__(256) void big_count(const uint32_t* __restrict__ bi
 // comes out in (depth, node id) order for the stable tile sort. Big Gaussians
 // only get their offset here (offs[g]); emit_big writes their pairs. The total
 // goes to C_NPAIRS_RAW, min(total, cap) to C_NPAIRS.
-constexpr int kScanItems = 16, kScanTile = 256 * kScanItems;
+constexpr int kScanItems = 12, kScanTile = 256 * kScanItems;   // 8, 16, 24, 32 measured slower
 
 __global__ __launch_bounds__(256) void pair_emit(const uint32_t* __restrict__ sorted_val,
                                                  const uint4* __restrict__ prec, uint32_t* __restrict__ offsets,
