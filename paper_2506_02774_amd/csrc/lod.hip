@@ -664,8 +664,9 @@ int vy_lod_cut(const vy_scene* scene, const vy_camera* cam, float tau, vy_cut* p
   } else {
     if (p) {
       ProfScope ps(VY_STAGE_LOD_CLASSIFY, st);
-      // Cut::counts[src] holds |F_prev|; if p != o the worklist of o is used
-      lod_classify<<<2048, 256, 0, st>>>(p->F[src], p->counts + src, s->lod, s->ccount, L, o->q[0], o->ctr, cap,
+      // Cut::counts[src] holds |F_prev|; if p != o the worklist of o is used (4096 workgroups:
+      // 1024, 2048, 8192 and 16384 measured slower)
+      lod_classify<<<4096, 256, 0, st>>>(p->F[src], p->counts + src, s->lod, s->ccount, L, o->q[0], o->ctr, cap,
                                          o->fbits, o->cbits);
       VY_LAUNCHED();
     }
