@@ -2054,7 +2054,8 @@ int vy_render(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, co
   }
   {
     ProfScope ps(VY_STAGE_PROJECT, st);
-    const int blocks = imin(cdiv(c->max_g, 256), 2048);
+    // 512 workgroups: more pay in per-block histogram flushes (256..10240 measured)
+    const int blocks = imin(cdiv(c->max_g, 256), 512);
     if (filter)
       project<true><<<blocks, 256, 0, st>>>(cut_ids, (const int32_t*)n_cut, s->gauss, s->sh, rc, c->pg0, c->pg1,
                                             c->pg2, c->prec, c->prelax, c->dkey[0], c->ctr,
