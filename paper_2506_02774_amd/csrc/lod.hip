@@ -683,9 +683,11 @@ int vy_lod_cut(const vy_scene* scene, const vy_camera* cam, float tau, vy_cut* p
       }
     } else {
       const int launches = (s->levels + kBfsLevels - 1) / kBfsLevels;
+      // one subtree root per workgroup at a time: many workgroups (1024 and 2048 measured slower)
+      const int bfs_blocks = (int)((s->n + 255) / 256 < 4096 ? (s->n + 255) / 256 : 4096);
       for (int j = 0; j < launches; ++j) {
         ProfScope ps(VY_STAGE_LOD_TRAVERSE, st);
-        lod_bfs<<<blocks, 256, 0, st>>>(o->q[j & 1], o->ctr + kQ0, j, o->q[(j + 1) & 1], s->lod, s->ccount, L, cap,
+        lod_bfs<<<bfs_blocks, 256, 0, st>>>(o->q[j & 1], o->ctr + kQ0, j, o->q[(j + 1) & 1], s->lod, s->ccount, L, cap,
                                         o->fbits, o->cbits, o->ctr + kErr, j + 1 == launches);
         VY_LAUNCHED();
       }
