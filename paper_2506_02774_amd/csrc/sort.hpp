@@ -20,6 +20,7 @@ constexpr int kThreads = 1024;
 constexpr int kItems = 12;                    // keys per thread per partition
 constexpr int kTile = kThreads * kItems;      // keys per partition
 constexpr int kWaves = kThreads / 64;
+constexpr int kLookback = 4;                  // predecessors polled per step of a digit's look-back
 
 // Exclusive scan of one value per thread of the first 256 threads of the
 // block (all threads call it; the others pass 0 and get 0). `sh` needs 5 words.
@@ -130,14 +131,15 @@ __global__ __launch_bounds__(kThreads) void onesweep_pass(const uint32_t* __rest
       }
       dtot = run;
     }
+    // the partition's digit counts go out before anything else, so that
+    // successors looking back are held up as little as possible
+    if (tid < 256) publish_aggregate(status + tid, part, 256, epoch, dtot);
     uint32_t btot;
     const uint32_t dstart = scan_first256(dtot, s_scan, &btot);
-    if (tid < 256) {
-      s_dstart[tid] = dstart;
-      const uint64_t ex = lookback_k<8>(status + tid, part, 256, epoch, dtot, err);
-      s_gofs[tid] = s_gstart[tid] + (uint32_t)ex - dstart;
-    }
+    if (tid < 256) s_dstart[tid] = dstart;
     __syncthreads();
+    // local scatter into digit order first: the keys leave the registers
+    // before the look-back, which then polls kLookback predecessors per step
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
       const uint32_t li = w * (64 * kItems) + r * 64 + l;
@@ -147,6 +149,10 @@ __global__ __launch_bounds__(kThreads) void onesweep_pass(const uint32_t* __rest
         s_keys[pos] = key[r];
         s_vals[pos] = val[r];
       }
+    }
+    if (tid < 256) {
+      const uint64_t ex = lookback_poll<kLookback>(status + tid, part, 256, epoch, dtot, err);
+      s_gofs[tid] = s_gstart[tid] + (uint32_t)ex - dstart;
     }
     __syncthreads();
     for (uint32_t i = tid; i < cnt; i += kThreads) {

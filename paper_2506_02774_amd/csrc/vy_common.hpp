@@ -289,18 +289,22 @@ VY_DEV uint64_t lookback_wave(uint64_t* status, uint32_t part, uint32_t stride, 
   return excl;
 }
 
-// Decoupled look-back by one thread that polls K predecessors per step with
+// First half of a decoupled look-back split in two: publishes partition
+// `part`'s aggregate (the inclusive prefix for partition 0).
+VY_DEV void publish_aggregate(uint64_t* status, uint32_t part, uint32_t stride, uint32_t epoch, uint64_t aggregate) {
+  st_rel(status + (uint64_t)part * stride, pack_status(epoch, part == 0 ? kFlagInc : kFlagAgg, aggregate));
+}
+
+// Second half, by one thread that polls K predecessors per step with
 // independent loads (for the per-digit chains of the radix sort, where every
-// thread walks its own chain).
+// thread walks its own chain): sums predecessors' values back to the nearest
+// inclusive prefix, publishes the inclusive prefix and returns the exclusive
+// one. The aggregate must have been published with publish_aggregate.
 template <int K>
-VY_DEV uint64_t lookback_k(uint64_t* status, uint32_t part, uint32_t stride, uint32_t epoch, uint64_t aggregate,
-                           uint32_t* err) {
+VY_DEV uint64_t lookback_poll(uint64_t* status, uint32_t part, uint32_t stride, uint32_t epoch, uint64_t aggregate,
+                              uint32_t* err) {
   uint64_t* me = status + (uint64_t)part * stride;
-  if (part == 0) {
-    st_rel(me, pack_status(epoch, kFlagInc, aggregate));
-    return 0;
-  }
-  st_rel(me, pack_status(epoch, kFlagAgg, aggregate));
+  if (part == 0) return 0;
   uint64_t excl = 0;
   int64_t j = (int64_t)part - 1;
   uint32_t spins = 0;
