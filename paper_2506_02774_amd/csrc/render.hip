@@ -853,10 +853,10 @@ VY_DEV void blend_sparse(const Stage& S, int w, int jj, uint64_t mk, uint32_t b0
     for (int u = 0; u < 4; ++u) {
       const float dx = p0[u].x - fxp, dy = p0[u].y - fyp;
       const float power = fminf(fmaf(dx, fmaf(p0[u].z, dx, p0[u].w * dy), (p1[u].x * dy) * dy), 0.f);
-      ok[u] = vk[u];
-      if (FILTER) ok[u] = ok[u] && power >= p1[u].z;   // Eq. 4 before the exponential
+      bool o = vk[u];
+      if (FILTER) o = o & (power >= p1[u].z);   // Eq. 4 before the exponential
       al[u] = fminf(kAlphaMax, p1[u].y * exp_rho<LUT>(power, L));
-      ok[u] = ok[u] && al[u] >= kAlphaMin;
+      ok[u] = o & (al[u] >= kAlphaMin);
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -873,19 +873,21 @@ VY_DEV void blend_sparse(const Stage& S, int w, int jj, uint64_t mk, uint32_t b0
         A.nb = 0;
         A.cur_key = key;
       }
+      // the stop is taken by selects, not a branch: a stopping lane adds
+      // 0 * colour (+0, colours are >= 0), so its sums are unchanged bitwise
       const float Tn = A.Tb * (1.f - al[u]);
-      if (A.Tt * Tn < kTMin) {
-        if (SAVE) A.stop_pos = b0 + (e[u] & 255u);
-        A.done = true;
-        continue;
-      }
-      const float wgt = al[u] * A.Tb;
+      const bool stop = A.Tt * Tn < kTMin;
+      const float wgt = stop ? 0.f : al[u] * A.Tb;
       A.Cb0 = fmaf(wgt, p2[u].x, A.Cb0);
       A.Cb1 = fmaf(wgt, p2[u].y, A.Cb1);
       A.Cb2 = fmaf(wgt, p2[u].z, A.Cb2);
-      A.Tb = Tn;
-      A.nb += 1;
-      if (SAVE) A.last = b0 + (e[u] & 255u);
+      A.Tb = stop ? A.Tb : Tn;
+      A.nb += stop ? 0 : 1;
+      if (SAVE) {
+        A.last = stop ? A.last : b0 + (e[u] & 255u);
+        A.stop_pos = stop ? b0 + (e[u] & 255u) : A.stop_pos;
+      }
+      A.done = stop;
     }
     if (A.done) mk = 0ull;
   }
