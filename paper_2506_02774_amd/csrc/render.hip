@@ -938,7 +938,10 @@ VY_DEV void walk_chunk(const Stage& S, int w, int jc, int mc, uint32_t b0, float
     int mx = __popcll(mk);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
-    if (walk == 2 || mx * 5 < mc * 3) {
+    // per pixel when the busiest pixel needs under 70 % of the chunk (an
+    // entry of the per-pixel walk costs about twice one of the band walk,
+    // which needs fewer steps: measured best between 60 and 80 %)
+    if (walk == 2 || mx * 10 < mc * 7) {
       blend_sparse<FILTER, SAVE, LUT>(S, w, jc, mk, b0, fxp, fyp, A, L);
       return;
     }
