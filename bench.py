@@ -7,10 +7,15 @@ with or without the preemptive alpha filter, sort, blend). The default
 workload is the city-scale walkthrough: 1.8e7 leaf Gaussians (3.6e7 hierarchy
 nodes), 1920x1080, 300 frames, tau = 2 px, seeded synthetic scene and path.
 
-Prints ONE JSON line: FPS of temporal LoD + alpha filter (the method), with
-p50/p99 frame times, the plain full-search + unfiltered renderer on the same
-frames, the 2x2 ablation for tau in {1, 2, 4}, bitwise gates (temporal cut ==
-full cut, filtered image == unfiltered image, every frame), per-stage times,
+Prints ONE JSON line: FPS of temporal LoD + alpha filter (the method) as
+rendered by the walkthrough renderer (vy_walkthrough: --depth frames in flight
+on as many streams, every image bitwise that of the one-at-a-time loop), with
+p50/p99 frame times (GPU time from a frame's search to the end of its
+rendering), the plain full-search + unfiltered renderer on the same frames
+and in the same way, the same two with one frame in flight, the frames-in-
+flight sweep, the 2x2 ablation for tau in {1, 2, 4} (one frame in flight),
+bitwise gates (temporal cut == full cut, filtered image == unfiltered image,
+walkthrough renderer == frame loop, every frame), per-stage times,
 the roofline of the dominant kernel, the FP64 oracle timed on the host, and
 the LUT exponential of Section 4.2 (FPS and PSNR / SSIM against the exact
 image for table sizes 8..128). Then, in a child process once the walkthrough's buffers are freed, the
@@ -60,6 +65,8 @@ def parse():
     ap.add_argument("--cpu-tiles", type=int, default=16, help="tiles the oracle renders for the CPU baseline")
     ap.add_argument("--max-pairs", type=int, default=96 << 20)
     ap.add_argument("--copy-mib", type=int, default=1024, help="size of the HBM copy used as the traffic reference")
+    ap.add_argument("--depth", type=int, default=3, help="frames in flight of the headline walkthrough")
+    ap.add_argument("--walk-depths", default="1,2,3,4", help="frames in flight swept for the walkthrough table")
     return ap.parse_args()
 
 
@@ -97,6 +104,39 @@ def timed(vy, torch, scene, cams, tau, temporal, filt, state, full_cut, ctx, img
     ms = np.array([a.elapsed_time(b) for a, b in ev])
     rc, npairs, nvis = ctx.status()
     vy.check(rc, "vy_render_status")
+    return dict(fps=len(cams) / wall, ms_per_step=1e3 * wall / len(cams), p50_ms=float(np.percentile(ms, 50)),
+                p99_ms=float(np.percentile(ms, 99)), p99_ms_frames_1_on=float(np.percentile(ms[1:], 99))
+                if len(ms) > 1 else float(ms[0]), mean_event_ms=float(ms.mean()))
+
+
+def make_slots(vy, torch, scene, W, H, max_pairs, n):
+    """Per-slot state of the walkthrough renderer: a cut, a render context, a
+    stream and an image for each of n frames in flight."""
+    return dict(cuts=[vy.Cut(scene) for _ in range(n)],
+                ctxs=[vy.RenderContext(scene.n, W, H, max_pairs) for _ in range(n)],
+                streams=[torch.cuda.Stream() for _ in range(n)],
+                images=[torch.empty((3, H, W), dtype=torch.float32, device="cuda") for _ in range(n)])
+
+
+def walk_timed(vy, torch, scene, cams, tau, slots, depth, temporal=True, filt=True):
+    """vy_walkthrough over the path with `depth` frames in flight: throughput
+    from the wall clock of one pass; per-frame GPU time (search start to
+    render end, HIP events on the frame's stream) and the per-frame records
+    (no capacity or wait flag on any frame) from a second pass."""
+    from paper_2506_02774_amd.serving import STATS_DTYPE
+    mode = 0 if temporal else vy.VY_WALK_FULL_EACH
+    a = (scene, cams, tau, slots["cuts"][:depth], slots["ctxs"][:depth], slots["images"][:depth])
+    kw = dict(streams=slots["streams"][:depth], mode=mode, alpha_filter=filt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    vy.vy_walkthrough(*a, **kw)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = torch.zeros((len(cams), 4), dtype=torch.int64, device="cuda")
+    ms = vy.vy_walkthrough(*a, stats=st, frame_ms=True, **kw)
+    flags = np.frombuffer(st.cpu().numpy().tobytes(), dtype=STATS_DTYPE)["flags"]
+    if flags.any():
+        raise RuntimeError(f"walkthrough depth {depth}: {int((flags != 0).sum())} frames flagged (capacity or wait)")
     return dict(fps=len(cams) / wall, ms_per_step=1e3 * wall / len(cams), p50_ms=float(np.percentile(ms, 50)),
                 p99_ms=float(np.percentile(ms, 99)), p99_ms_frames_1_on=float(np.percentile(ms[1:], 99))
                 if len(ms) > 1 else float(ms[0]), mean_event_ms=float(ms.mean()))
@@ -182,10 +222,31 @@ def main():
     log("warmup done")
 
     # ------------------------------------------------------------ headline
-    head = timed(vy, torch, scene, cams, args.tau, True, True, state, full_cut, ctx, img)
+    # one frame at a time (a host loop over vy_lod_cut + vy_render on one stream)
+    seq = timed(vy, torch, scene, cams, args.tau, True, True, state, full_cut, ctx, img)
+    log(f"one frame in flight, temporal + alpha filter: {seq['fps']:.1f} FPS, p50 {seq['p50_ms']:.3f} ms, "
+        f"p99 {seq['p99_ms']:.3f} ms")
+    seq_base = timed(vy, torch, scene, cams, args.tau, False, False, state, full_cut, ctx, img)
+    log(f"one frame in flight, full + unfiltered: {seq_base['fps']:.1f} FPS, p50 {seq_base['p50_ms']:.3f} ms, "
+        f"p99 {seq_base['p99_ms']:.3f} ms")
+    # the walkthrough renderer: frames in flight on several streams (vy_walkthrough)
+    depths = sorted({int(d) for d in args.walk_depths.split(",") if d} | {args.depth})
+    slots = make_slots(vy, torch, scene, Wd, Hd, args.max_pairs, max(depths))
+    # warm-up on the path itself, so that every slot's buffers have been touched at full size
+    for filt in (True, False):
+        vy.vy_walkthrough(scene, cams, args.tau, slots["cuts"], slots["ctxs"], slots["images"],
+                          streams=slots["streams"], alpha_filter=filt)
+    torch.cuda.synchronize()
+    walk = {}
+    for d in depths:
+        walk[d] = walk_timed(vy, torch, scene, cams, args.tau, slots, d)
+        log(f"walkthrough, {d} frame(s) in flight, temporal + alpha filter: {walk[d]['fps']:.1f} FPS, "
+            f"frame p50 {walk[d]['p50_ms']:.3f} ms, p99 {walk[d]['p99_ms']:.3f} ms")
+    head = walk[args.depth]
+    base = walk_timed(vy, torch, scene, cams, args.tau, slots, args.depth, temporal=False, filt=False)
+    log(f"walkthrough, {args.depth} frame(s) in flight, full + unfiltered: {base['fps']:.1f} FPS, "
+        f"frame p50 {base['p50_ms']:.3f} ms, p99 {base['p99_ms']:.3f} ms")
     log(f"temporal + alpha filter: {head['fps']:.1f} FPS, p50 {head['p50_ms']:.3f} ms, p99 {head['p99_ms']:.3f} ms")
-    base = timed(vy, torch, scene, cams, args.tau, False, False, state, full_cut, ctx, img)
-    log(f"full + unfiltered: {base['fps']:.1f} FPS, p50 {base['p50_ms']:.3f} ms, p99 {base['p99_ms']:.3f} ms")
 
     # ------------------------------------------------------------ ablation
     ablation = {}
@@ -222,8 +283,15 @@ def main():
     lut = {} if args.no_lut else lut_study(vy, torch, scene, cams, args.tau, state, full_cut, ctx, img, img2)
 
     # ------------------------------------------------ gates + per-frame counts
-    log("verification pass (temporal cut == full cut, filtered == unfiltered, every frame)")
-    gates = dict(frames=0, cut_mismatch=0, image_mismatch=0)
+    log("verification pass (temporal cut == full cut, filtered == unfiltered, walkthrough renderer == "
+        "frame loop, every frame)")
+    gates = dict(frames=0, cut_mismatch=0, image_mismatch=0, walkthrough_image_mismatch=0)
+    # every frame of the headline configuration, each into its own image
+    walk_imgs = [torch.empty((3, Hd, Wd), dtype=torch.float32, device="cuda")
+                 for _ in range(-(-K // args.depth) * args.depth)]
+    vy.vy_walkthrough(scene, cams, args.tau, slots["cuts"][:args.depth], slots["ctxs"][:args.depth], walk_imgs,
+                      streams=slots["streams"][:args.depth], alpha_filter=True)
+    torch.cuda.synchronize()
     counts = dict(F=0.0, C=0.0, V=0.0, P=0.0, P_unf=0.0, evals=0.0, contribs=0.0)
     tst = vy.Cut(scene)
     for i, cam in enumerate(cams):
@@ -252,12 +320,15 @@ def main():
         counts["contribs"] += float(Nc.sum())
         if not torch.equal(img.view(torch.int32), img2.view(torch.int32)):
             gates["image_mismatch"] += 1
+        if not torch.equal(walk_imgs[i].view(torch.int32), img2.view(torch.int32)):
+            gates["walkthrough_image_mismatch"] += 1
         gates["frames"] += 1
         counts["F"] += nf_t
         counts["C"] += nc_t
         counts["V"] += v_f
         counts["P"] += p_f
         counts["P_unf"] += p_unf
+    del walk_imgs
     nfr = max(1, gates["frames"])
     avg = {k: v / nfr for k, v in counts.items()}
     log(f"gates: {gates}; mean |F| {avg['F']:.0f} |C| {avg['C']:.0f} visible {avg['V']:.0f} "
@@ -321,12 +392,19 @@ def main():
         "ms_per_step": round(head["ms_per_step"], 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"city-{cfg.name}: {cfg.n_leaf} leaves ({scene.n} nodes), {Wd}x{Hd}, "
-                               f"{K}-frame walkthrough, tau={args.tau:g} px, temporal LoD + alpha filter",
-                   "leaves": cfg.n_leaf, "nodes": scene.n, "width": Wd, "height": Hd, "frames": K, "tau": args.tau},
+                               f"{K}-frame walkthrough, tau={args.tau:g} px, temporal LoD + alpha filter, "
+                               f"{args.depth} frames in flight",
+                   "leaves": cfg.n_leaf, "nodes": scene.n, "width": Wd, "height": Hd, "frames": K, "tau": args.tau,
+                   "frames_in_flight": args.depth},
         "p50_ms": round(head["p50_ms"], 4), "p99_ms": round(head["p99_ms"], 4),
         "p99_ms_frames_1_on": round(head["p99_ms_frames_1_on"], 4),
         "full_unfiltered": {k: round(v, 4) for k, v in base.items()},
         "speedup_vs_full_unfiltered": round(head["fps"] / base["fps"], 3),
+        "one_frame_in_flight": {"temporal+filter": {k: round(v, 4) for k, v in seq.items()},
+                                "full+unfiltered": {k: round(v, 4) for k, v in seq_base.items()},
+                                "speedup": round(seq["fps"] / seq_base["fps"], 3)},
+        "walkthrough_frames_in_flight": {str(d): {k: round(v, 4) for k, v in r.items() if k != "ms_per_step"}
+                                         for d, r in walk.items()},
         "ablation": ablation,
         "lut": lut,
         "lod_traversal": traversal,
@@ -340,7 +418,7 @@ def main():
         "parity": parity,
     }
     if not args.no_serving and args.config == "full":
-        del ctx, state, full_cut, img, scene
+        del ctx, state, full_cut, img, scene, slots
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
         out["serving"] = serving_child()

@@ -1,5 +1,7 @@
 /*
- * vy_serve.h - C ABI of the multi-viewer serving runtime built on vy.h.
+ * vy_serve.h - C ABI of the runtimes built on vy.h: the multi-viewer serving
+ * runtime, and the walkthrough renderer that keeps several frames of one
+ * viewer's camera path in flight.
  *
  * Many viewers, each walking through one of several resident scenes at its
  * own resolution, ask for frames at their own times. The runtime
@@ -188,6 +190,57 @@ int vy_server_last_run(const vy_server* server, int64_t* n_admitted, int64_t* n_
 int vy_server_simulate(const vy_server_config* config, const int64_t* session_bytes, const int64_t* pair_capacity,
                        int32_t n_sessions, const vy_frame_req* reqs, int64_t n_reqs, const double* service_s,
                        const uint32_t* need_pairs, int32_t flags, vy_frame_result* results, int64_t* counters);
+
+/* ------------------------------------------------------------------------ */
+/* Walkthrough: one viewer's camera path with several frames in flight      */
+/* ------------------------------------------------------------------------ */
+
+enum {
+  VY_WALK_FULL_EACH = 256  /* in vy_walkthrough's full_mode: every frame is a
+                              full search (prev is not used), and the frames do
+                              not wait for each other */
+};
+
+/* Renders frames i = 0..n_frames-1 of one camera path. Frame i is
+ * vy_lod_cut(scene, cams[i], tau, from, cut_i, full_mode) with `from` =
+ * frame i-1's cut (the temporal search of Algorithm 1, Section 4.1), or
+ * `prev` for frame 0 (NULL: a full search), followed by
+ * vy_render(scene, cut_i, cams[i], opts, images[i % n_images], ctx_i) (Section
+ * 3.1, with Section 4.2 per opts). Every cut and image is therefore bit for bit
+ * the one a loop over those two calls produces.
+ * full_mode: as in vy_lod_cut for the full searches (VY_CUT_FRONTIER,
+ * VY_CUT_FLAT, | VY_CUT_DFS), optionally | VY_WALK_FULL_EACH.
+ * Up to `depth` frames are in flight. Frame i uses slot i % depth: the cut
+ * cuts[slot], the context ctxs[slot], the stream streams[slot]. Its search
+ * waits (a HIP event) only for frame i-1's search, so frame i's rendering
+ * overlaps the searches and renderings of the next depth - 1 frames. With
+ * depth = 1 the frames run one after the other on streams[0].
+ *   cams: host [n_frames], each no larger than its slot's context.
+ *   cuts, ctxs, streams: host arrays of `depth` (1..16) distinct handles /
+ *     hipStream_t (borrowed; one stream may be NULL, the null stream). prev
+ *     may be one of cuts. After the call the
+ *     last frame's cut is in cuts[(n_frames - 1) % depth].
+ *   images: host array of n_images device images [3][H][W] (caller-owned);
+ *     n_images must be a positive multiple of depth, so that an image is only
+ *     written by one slot.
+ *   stats: device [n_frames] or NULL: zeroed, then frame i's record as in
+ *     vy_server_run (image hash, |C|, pairs, flags: a capacity or wait bound
+ *     hit by any frame shows there, whereas vy_render_status of a context only
+ *     reports the last frame it rendered).
+ *   frame_ms: host [n_frames] or NULL: GPU time of each frame from the start
+ *     of its search to the end of its rendering (HIP timing events on its
+ *     stream); the call then synchronises `stream` before returning.
+ *   stream: the caller's stream. The frames start after the work already
+ *     enqueued on it, and work enqueued on it after the call starts after
+ *     every frame.
+ * Returns VY_ERR_ARG for invalid arguments (nothing is enqueued). An error of
+ * vy_lod_cut or vy_render for frame i (argument checks, HIP) stops the call
+ * there and is returned; frames before i still complete and `stream` still
+ * waits for them. Not thread-safe with respect to the handles it uses. */
+int vy_walkthrough(const vy_scene* scene, const vy_camera* cams, int64_t n_frames, float tau, int32_t full_mode,
+                   const vy_render_opts* opts, vy_cut* prev, int32_t depth, vy_cut* const* cuts,
+                   vy_render_ctx* const* ctxs, void* const* streams, float* const* images, int64_t n_images,
+                   vy_frame_stats* stats, float* frame_ms, void* stream);
 
 #ifdef __cplusplus
 }

@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(HERE, "libvoyager.so")
 
 VY_OK, VY_ERR_ARG, VY_ERR_HIP, VY_ERR_CAPACITY, VY_ERR_STATE, VY_ERR_DEVICE = 0, -1, -2, -3, -4, -5
 VY_CUT_FRONTIER, VY_CUT_FLAT, VY_CUT_DFS = 0, 1, 2
+VY_WALK_FULL_EACH = 256
 STAGES = ["lod_setup", "lod_flat", "lod_classify", "lod_traverse", "lod_compact", "render_setup", "project",
           "depth_sort", "pair_scan", "emit", "tile_sort", "ranges", "blend_plan", "blend", "bwd_blend", "bwd_project"]
 
@@ -143,6 +144,9 @@ def lib():
                                 ctypes.POINTER(vy_frame_req), I64, ctypes.POINTER(ctypes.c_double),
                                 ctypes.POINTER(ctypes.c_uint32), I32, ctypes.POINTER(vy_frame_result),
                                 ctypes.POINTER(I64)], ctypes.c_int),
+        "vy_walkthrough": ([P, ctypes.POINTER(vy_camera), I64, F32, I32, ctypes.POINTER(vy_render_opts), P, I32,
+                            ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), I64, P,
+                            ctypes.POINTER(F32), P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -441,6 +445,14 @@ def vy_render(scene: Scene, cut: Cut, cam, ctx: RenderContext, image=None, alpha
         image = torch.empty((3, int(cam.height), int(cam.width)), dtype=torch.float32, device="cuda")
     if image.dtype != torch.float32 or not image.is_contiguous() or tuple(image.shape) != (3, cam.height, cam.width):
         raise VoyagerError(VY_ERR_ARG, "image must be a contiguous float32 tensor of shape (3, H, W)")
+    o = _render_opts(alpha_filter, bg, save_state, split_min_pairs, walk, lut_entries)
+    c = make_camera(cam)
+    check(lib().vy_render(scene.handle, cut.handle, ctypes.byref(c), ctypes.byref(o),
+                          ctypes.c_void_p(image.data_ptr()), ctx.handle, _stream(stream)), "vy_render")
+    return image
+
+
+def _render_opts(alpha_filter=False, bg=(0.0, 0.0, 0.0), save_state=False, split_min_pairs=0, walk=0, lut_entries=0):
     o = vy_render_opts()
     o.alpha_filter = 1 if alpha_filter else 0
     for i in range(3):
@@ -449,10 +461,52 @@ def vy_render(scene: Scene, cut: Cut, cam, ctx: RenderContext, image=None, alpha
     o.split_min_pairs = int(split_min_pairs)
     o.walk = int(walk)
     o.lut_entries = int(lut_entries)
-    c = make_camera(cam)
-    check(lib().vy_render(scene.handle, cut.handle, ctypes.byref(c), ctypes.byref(o),
-                          ctypes.c_void_p(image.data_ptr()), ctx.handle, _stream(stream)), "vy_render")
-    return image
+    return o
+
+
+def vy_walkthrough(scene: Scene, cams, tau: float, cuts, ctxs, images, streams=None, prev: Cut | None = None,
+                   mode: int = VY_CUT_FRONTIER, alpha_filter=False, bg=(0.0, 0.0, 0.0), walk=0, lut_entries=0,
+                   stats=None, frame_ms=False, stream=None):
+    """Enqueue the frames of a camera path with len(cuts) frames in flight.
+    Frame i searches its cut from frame i-1's (from `prev` for frame 0, a full
+    search when None) into cuts[i % depth] and renders it with ctxs[i % depth]
+    on streams[i % depth] (torch streams; default: the current stream, depth
+    1) into images[i % len(images)] (torch float32 [3, H, W]; len(images) a
+    multiple of depth). `stats`: a device tensor of at least 32 bytes per frame
+    for the per-frame records (decode with serving.STATS_DTYPE), or None.
+    Returns the per-frame GPU milliseconds (numpy, after synchronising) when
+    `frame_ms`, else None."""
+    import torch
+    depth = len(cuts)
+    if streams is None:
+        if depth != 1:
+            raise VoyagerError(VY_ERR_ARG, "vy_walkthrough: give one stream per slot when depth > 1")
+        streams = [torch.cuda.current_stream()]
+    if len(ctxs) != depth or len(streams) != depth:
+        raise VoyagerError(VY_ERR_ARG, "vy_walkthrough: cuts, ctxs and streams must have the same length")
+    n = len(cams)
+    for im in images:
+        if im.dtype != torch.float32 or not im.is_contiguous() or im.dim() != 3 or im.shape[0] != 3:
+            raise VoyagerError(VY_ERR_ARG, "images must be contiguous float32 tensors of shape (3, H, W)")
+    for i, cam in enumerate(cams):
+        im = images[i % len(images)]
+        if (im.shape[1], im.shape[2]) != (cam.height, cam.width):
+            raise VoyagerError(VY_ERR_ARG, f"frame {i}: image shape differs from the camera's size")
+    if stats is not None and stats.numel() * stats.element_size() < 32 * n:
+        raise VoyagerError(VY_ERR_ARG, "stats needs 32 bytes per frame")
+    cam_arr = (vy_camera * max(1, n))(*[make_camera(c) for c in cams])
+    o = _render_opts(alpha_filter, bg, False, 0, walk, lut_entries)
+    P = ctypes.c_void_p
+    cut_arr = (P * depth)(*[c.handle for c in cuts])
+    ctx_arr = (P * depth)(*[c.handle for c in ctxs])
+    st_arr = (P * depth)(*[s.cuda_stream for s in streams])
+    img_arr = (P * max(1, len(images)))(*[im.data_ptr() for im in images])
+    ms = (ctypes.c_float * max(1, n))() if frame_ms else None
+    check(lib().vy_walkthrough(scene.handle, cam_arr, n, float(tau), int(mode), ctypes.byref(o),
+                               prev.handle if prev is not None else None, depth, cut_arr, ctx_arr, st_arr, img_arr,
+                               len(images), P(stats.data_ptr()) if stats is not None else None, ms, _stream(stream)),
+          "vy_walkthrough")
+    return np.frombuffer(bytes(ms), dtype=np.float32)[:n].copy() if frame_ms else None
 
 
 def vy_render_backward(scene: Scene, cut: Cut, cam, ctx: RenderContext, dL_dimage, quat_raw=None,

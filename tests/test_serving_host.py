@@ -279,3 +279,36 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert int(c[s]) == ctypes.sizeof(cls), s
         for f in fs:
             assert int(c[f"{s}.{f}"]) == getattr(cls, f).offset, (s, f)
+
+
+# ------------------------------------------------------------ walkthrough ----
+
+def _walk_call(vy, n_frames, depth, cuts, ctxs, streams, images, scene=FAKE_BASE):
+    """vy_walkthrough with stand-in handles: every call here must fail (or
+    return) in the argument checks, before any handle is used."""
+    P = ctypes.c_void_p
+    cams = (vy.vy_camera * max(1, n_frames))()
+    arr = lambda xs: (P * max(1, len(xs)))(*xs) if xs is not None else None
+    return vy.lib().vy_walkthrough(P(scene) if scene else None, cams, n_frames, 2.0, 0, None, None, depth,
+                                   arr(cuts), arr(ctxs), arr(streams), arr(images),
+                                   len(images) if images is not None else 0, None, None, None)
+
+
+def test_walkthrough_argument_checks():
+    vy, _ = _vy()
+    c, x, s, im = [FAKE_BASE + 16 * k for k in range(8)], [FAKE_BASE + 4096 + 16 * k for k in range(8)], \
+        [FAKE_BASE + 8192 + 16 * k for k in range(8)], [FAKE_BASE + 65536 * (k + 1) for k in range(8)]
+    E = vy.VY_ERR_ARG
+    assert _walk_call(vy, 4, 2, c[:2], x[:2], s[:2], im[:2], scene=0) == E            # no scene
+    assert _walk_call(vy, -1, 2, c[:2], x[:2], s[:2], im[:2]) == E                     # negative count
+    assert _walk_call(vy, 4, 0, c[:2], x[:2], s[:2], im[:2]) == E                      # depth 0
+    assert _walk_call(vy, 4, 17, c * 3, x * 3, s * 3, im[:1] * 17) == E                # depth above 16
+    assert _walk_call(vy, 4, 2, [c[0], c[0]], x[:2], s[:2], im[:2]) == E               # a cut twice
+    assert _walk_call(vy, 4, 2, c[:2], [x[1], x[1]], s[:2], im[:2]) == E               # a context twice
+    assert _walk_call(vy, 4, 2, c[:2], x[:2], [s[0], s[0]], im[:2]) == E               # a stream twice
+    assert _walk_call(vy, 4, 2, c[:2], x[:2], s[:2], im[:3]) == E                      # 3 images, 2 slots
+    assert _walk_call(vy, 4, 2, c[:2], x[:2], s[:2], [im[0], 0]) == E                  # a NULL image
+    assert _walk_call(vy, 4, 2, c[:2], x[:2], None, im[:2]) == E                       # no streams
+    assert "depth" in vy.lib().vy_last_error().decode() or "distinct" in vy.lib().vy_last_error().decode()
+    # nothing to render: returns before touching any handle or stream
+    assert _walk_call(vy, 0, 3, c[:3], x[:3], s[:3], im[:6]) == vy.VY_OK
