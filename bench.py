@@ -65,7 +65,7 @@ def parse():
     ap.add_argument("--cpu-tiles", type=int, default=16, help="tiles the oracle renders for the CPU baseline")
     ap.add_argument("--max-pairs", type=int, default=96 << 20)
     ap.add_argument("--copy-mib", type=int, default=1024, help="size of the HBM copy used as the traffic reference")
-    ap.add_argument("--depth", type=int, default=3, help="frames in flight of the headline walkthrough")
+    ap.add_argument("--depth", type=int, default=4, help="frames in flight of the headline walkthrough")
     ap.add_argument("--walk-depths", default="1,2,3,4", help="frames in flight swept for the walkthrough table")
     return ap.parse_args()
 
@@ -111,10 +111,13 @@ def timed(vy, torch, scene, cams, tau, temporal, filt, state, full_cut, ctx, img
 
 def make_slots(vy, torch, scene, W, H, max_pairs, n):
     """Per-slot state of the walkthrough renderer: a cut, a render context, a
-    stream and an image for each of n frames in flight."""
+    stream and an image for each of n frames in flight. The first slot runs
+    on the caller's stream: HIP gives a process 4 hardware queues by default,
+    so 4 frames in flight then use exactly the 4 queues (a fifth stream would
+    share one and serialise with it)."""
     return dict(cuts=[vy.Cut(scene) for _ in range(n)],
                 ctxs=[vy.RenderContext(scene.n, W, H, max_pairs) for _ in range(n)],
-                streams=[torch.cuda.Stream() for _ in range(n)],
+                streams=[torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(n - 1)],
                 images=[torch.empty((3, H, W), dtype=torch.float32, device="cuda") for _ in range(n)])
 
 

@@ -230,9 +230,13 @@ enum {
  *   frame_ms: host [n_frames] or NULL: GPU time of each frame from the start
  *     of its search to the end of its rendering (HIP timing events on its
  *     stream); the call then synchronises `stream` before returning.
- *   stream: the caller's stream. The frames start after the work already
- *     enqueued on it, and work enqueued on it after the call starts after
- *     every frame.
+ *   stream: the caller's stream; it may also be one of streams. The frames
+ *     start after the work already enqueued on it, and work enqueued on it
+ *     after the call starts after every frame. (HIP maps a process's streams
+ *     onto a few hardware queues, 4 by default, and streams beyond that share
+ *     a queue, where their frames no longer overlap: keep the distinct
+ *     streams among `streams` and `stream` within the queue count, for
+ *     example by passing `stream` as streams[0].)
  * Returns VY_ERR_ARG for invalid arguments (nothing is enqueued). An error of
  * vy_lod_cut or vy_render for frame i (argument checks, HIP) stops the call
  * there and is returned; frames before i still complete and `stream` still
