@@ -229,7 +229,8 @@ enum {
  *     reports the last frame it rendered).
  *   frame_ms: host [n_frames] or NULL: GPU time of each frame from the start
  *     of its search to the end of its rendering (HIP timing events on its
- *     stream); the call then synchronises `stream` before returning.
+ *     stream); the call then synchronises `stream` and fills it before
+ *     returning VY_OK (it is left as is when the call fails).
  *   stream: the caller's stream; it may also be one of streams. The frames
  *     start after the work already enqueued on it, and work enqueued on it
  *     after the call starts after every frame. (HIP maps a process's streams
@@ -239,8 +240,9 @@ enum {
  *     example by passing `stream` as streams[0].)
  * Returns VY_ERR_ARG for invalid arguments (nothing is enqueued). An error of
  * vy_lod_cut or vy_render for frame i (argument checks, HIP) stops the call
- * there and is returned; frames before i still complete and `stream` still
- * waits for them. Not thread-safe with respect to the handles it uses. */
+ * there and is returned; frames before i still complete, `stream` still
+ * waits for them, and the records of frames from i on stay zero. Not
+ * thread-safe with respect to the handles it uses. */
 int vy_walkthrough(const vy_scene* scene, const vy_camera* cams, int64_t n_frames, float tau, int32_t full_mode,
                    const vy_render_opts* opts, vy_cut* prev, int32_t depth, vy_cut* const* cuts,
                    vy_render_ctx* const* ctxs, void* const* streams, float* const* images, int64_t n_images,

@@ -13,6 +13,11 @@
         and one JSON line for the named kernel, tagged with the SHA-1 of the
         source file that holds it, so that a reader can tell whether the
         counters are still those of the current kernel.
+
+    python -m paper_2506_02774_amd.rocprof_summary counters A.csv [B.csv ...] --kernels 'k1;k2'
+
+        average per dispatch of every counter found in the given
+        counter_collection CSVs, for the named kernels (markdown table).
 """
 from __future__ import annotations
 
@@ -90,6 +95,22 @@ def traffic(fetch_csv, write_csv, copy_mib, copy_regex, kernel, stage, source):
                           write_factor=round(f_write, 4), dispatches=fe[kernel][0])))
 
 
+def counters(paths, kernels):
+    vals = collections.defaultdict(lambda: collections.defaultdict(list))
+    for p in paths:
+        for r in csv.DictReader(open(p)):
+            vals[short(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    names = sorted({c for k in kernels if k in vals for c in vals[k]})
+    print("| kernel | dispatches | " + " | ".join(names) + " |")
+    print("|---|---|" + "---|" * len(names))
+    for k in kernels:
+        if k not in vals:
+            continue
+        n = max(len(v) for v in vals[k].values())
+        cells = [f"{sum(vals[k][c]) / len(vals[k][c]):.4g}" if vals[k].get(c) else "" for c in names]
+        print(f"| `{k[:60]}` | {n} | " + " | ".join(cells) + " |")
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -104,9 +125,14 @@ def main():
     b.add_argument("--kernel", default="blend_jobs<true, false, false>")
     b.add_argument("--stage", default="blend")
     b.add_argument("--source", default=os.path.join(HERE, "csrc", "render.hip"))
+    c = sub.add_parser("counters")
+    c.add_argument("csv", nargs="+")
+    c.add_argument("--kernels", default="blend_jobs<true, false, false>")
     args = ap.parse_args()
     if args.cmd == "stats":
         stats(args.csv, args.top)
+    elif args.cmd == "counters":
+        counters(args.csv, [k for k in args.kernels.split(";") if k])
     else:
         traffic(args.fetch_csv, args.write_csv, args.copy_mib, args.copy_regex, args.kernel, args.stage, args.source)
 
