@@ -121,20 +121,23 @@ def make_slots(vy, torch, scene, W, H, max_pairs, n):
                 images=[torch.empty((3, H, W), dtype=torch.float32, device="cuda") for _ in range(n)])
 
 
-def walk_timed(vy, torch, scene, cams, tau, slots, depth, temporal=True, filt=True):
+def walk_timed(vy, torch, scene, cams, tau, slots, depth, temporal=True, filt=True, passes=1):
     """vy_walkthrough over the path with `depth` frames in flight: throughput
-    from the wall clock of one pass; per-frame GPU time (search start to
-    render end, HIP events on the frame's stream) and the per-frame records
-    (no capacity or wait flag on any frame) from a second pass."""
+    from the wall clock of a pass over all frames (the fastest of `passes`);
+    per-frame GPU time (search start to render end, HIP events on the frame's
+    stream) and the per-frame records (no capacity or wait flag on any frame)
+    from a further pass."""
     from paper_2506_02774_amd.serving import STATS_DTYPE
     mode = 0 if temporal else vy.VY_WALK_FULL_EACH
     a = (scene, cams, tau, slots["cuts"][:depth], slots["ctxs"][:depth], slots["images"][:depth])
     kw = dict(streams=slots["streams"][:depth], mode=mode, alpha_filter=filt)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    vy.vy_walkthrough(*a, **kw)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    wall = float("inf")
+    for _ in range(passes):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        vy.vy_walkthrough(*a, **kw)
+        torch.cuda.synchronize()
+        wall = min(wall, time.perf_counter() - t0)
     st = torch.zeros((len(cams), 4), dtype=torch.int64, device="cuda")
     ms = vy.vy_walkthrough(*a, stats=st, frame_ms=True, **kw)
     flags = np.frombuffer(st.cpu().numpy().tobytes(), dtype=STATS_DTYPE)["flags"]
@@ -241,11 +244,12 @@ def main():
                           streams=slots["streams"], alpha_filter=filt)
     torch.cuda.synchronize()
     walk = {}
-    for d in depths:
-        walk[d] = walk_timed(vy, torch, scene, cams, args.tau, slots, d)
+    for d in depths:   # the sweep: fastest of two passes per depth
+        walk[d] = walk_timed(vy, torch, scene, cams, args.tau, slots, d, passes=2)
         log(f"walkthrough, {d} frame(s) in flight, temporal + alpha filter: {walk[d]['fps']:.1f} FPS, "
             f"frame p50 {walk[d]['p50_ms']:.3f} ms, p99 {walk[d]['p99_ms']:.3f} ms")
-    head = walk[args.depth]
+    # the headline and its plain-renderer baseline: one timed pass of the K frames each
+    head = walk_timed(vy, torch, scene, cams, args.tau, slots, args.depth)
     base = walk_timed(vy, torch, scene, cams, args.tau, slots, args.depth, temporal=False, filt=False)
     log(f"walkthrough, {args.depth} frame(s) in flight, full + unfiltered: {base['fps']:.1f} FPS, "
         f"frame p50 {base['p50_ms']:.3f} ms, p99 {base['p99_ms']:.3f} ms")
