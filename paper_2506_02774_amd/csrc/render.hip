@@ -1469,6 +1469,24 @@ __global__ __launch_bounds__(256) void bwd_zero(GradAcc acc, const int32_t* n_cu
     for (int k = 0; k < 9; ++k) acc.v[k][i] = 0.f;
 }
 
+// Sum of x over the 64 lanes of a fully active wave, complete in lane 63:
+// butterflies within quads, mirrors within rows of 16, then the row
+// broadcasts of lane 15 into rows 1 and 3 and of lane 31 into rows 2 and 3
+// (DPP, no LDS traffic). A lane outside the enabled rows adds 0.
+template <int CTRL, int ROWS>
+VY_DEV float dpp_plus(float x) {
+  return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROWS, 0xF, false));
+}
+VY_DEV float wave_sum_to_last(float x) {
+  x = dpp_plus<0xB1, 0xF>(x);    // quad_perm [1, 0, 3, 2]
+  x = dpp_plus<0x4E, 0xF>(x);    // quad_perm [2, 3, 0, 1]
+  x = dpp_plus<0x141, 0xF>(x);   // row_half_mirror
+  x = dpp_plus<0x140, 0xF>(x);   // row_mirror: every lane holds its row's sum
+  x = dpp_plus<0x142, 0xA>(x);   // row_bcast:15 into rows 1 and 3
+  x = dpp_plus<0x143, 0xC>(x);   // row_bcast:31 into rows 2 and 3
+  return x;
+}
+
 // One wave per (tile, band of 16x4 pixels) job: the wave walks its tile's
 // list back to front in chunks of 64, from the band's furthest last
 // contributor, over the entries whose pixel box may reach the band. Every lane
@@ -1581,13 +1599,8 @@ __global__ __launch_bounds__(256) void blend_backward(const uint2* __restrict__ 
           }
         } else {
 #pragma unroll
-          for (int k = 0; k < 9; ++k) {
-            float x = v[k];
-#pragma unroll
-            for (int s = 32; s > 0; s >>= 1) x += __shfl_xor(x, s, 64);
-            v[k] = x;
-          }
-          if (l == 0) {
+          for (int k = 0; k < 9; ++k) v[k] = wave_sum_to_last(v[k]);
+          if (l == 63) {
 #pragma unroll
             for (int k = 0; k < 9; ++k)
               if (v[k] != 0.f) atomicAdd(acc.v[k] + g, v[k]);
