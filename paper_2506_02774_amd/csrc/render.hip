@@ -935,9 +935,13 @@ VY_DEV void walk_chunk(const Stage& S, int w, int jc, int mc, uint32_t b0, float
     if (__ballot(!A.done) == 0ull) return;
     uint64_t mk = cover_masks(S, w, jc, mc, xa, ya, (int)(threadIdx.x & 63));
     if (A.done) mk = 0ull;
-    int mx = __popcll(mk);
+    // the busiest pixel's entry count (0..64), by a binary search over
+    // ballots: wave-uniform, and no LDS round trips on the critical path
+    const int pc = __popcll(mk);
+    int mx = 0;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+    for (int b = 6; b >= 0; --b)
+      if (__ballot(pc >= (mx | (1 << b))) != 0ull) mx |= 1 << b;
     // per pixel when the busiest pixel needs under 70 % of the chunk (an
     // entry of the per-pixel walk costs about twice one of the band walk,
     // which needs fewer steps: measured best between 60 and 80 %)
