@@ -1491,13 +1491,62 @@ VY_DEV float wave_sum_to_last(float x) {
   return x;
 }
 
+// The forward's decision at one entry for the pixel centre (fxp, fyp) and,
+// when the entry was blended there, its nine gradient terms (d/d mean2d.x,
+// mean2d.y, A, B, C, theta, r, g, b); walking back to front, T becomes the
+// transmittance in front of the entry and S the colour behind it.
+VY_DEV bool entry_grad(const float4 p0, const float4 p1, const float4 p2, float fxp, float fyp, bool in_range,
+                       float d0, float d1, float d2, float& T, float& S0, float& S1, float& S2, float v[9]) {
+  const float dx = p0.x - fxp, dy = p0.y - fyp;
+  const float raw = fmaf(dx, fmaf(p0.z, dx, p0.w * dy), (p1.x * dy) * dy);
+  const float power = fminf(raw, 0.f);
+  const uint32_t ext = __float_as_uint(p2.w);
+  bool on = in_range && fabsf(dx) <= (float)(ext & 0xFFFFu) && fabsf(dy) <= (float)(ext >> 16);
+  const float e = __expf(power);
+  const float araw = p1.y * e;
+  const float alpha = fminf(kAlphaMax, araw);
+  on = on && alpha >= kAlphaMin;   // the forward's decision, recomputed the same way
+#pragma unroll
+  for (int k = 0; k < 9; ++k) v[k] = 0.f;
+  if (on) {
+    const float om = 1.f - alpha;
+    T = T / om;                                          // transmittance in front of this Gaussian
+    const float wgt = alpha * T;
+    v[6] = wgt * d0;
+    v[7] = wgt * d1;
+    v[8] = wgt * d2;
+    const float io = 1.f / om;
+    const float dla = (p2.x * T - S0 * io) * d0 + (p2.y * T - S1 * io) * d1 + (p2.z * T - S2 * io) * d2;
+    S0 = fmaf(p2.x, wgt, S0);
+    S1 = fmaf(p2.y, wgt, S1);
+    S2 = fmaf(p2.z, wgt, S2);
+    if (araw < kAlphaMax) {
+      v[5] = dla * e;                                    // d alpha / d theta = e^rho
+      if (raw < 0.f) {
+        const float gr = dla * alpha;                    // d alpha / d rho = alpha
+        v[0] = gr * fmaf(2.f * p0.z, dx, p0.w * dy);
+        v[1] = gr * fmaf(p0.w, dx, 2.f * p1.x * dy);
+        v[2] = gr * dx * dx;
+        v[3] = gr * dx * dy;
+        v[4] = gr * dy * dy;
+      }
+    }
+  }
+  return on;
+}
+
 // One wave per (tile, band of 16x4 pixels) job: the wave walks its tile's
 // list back to front in chunks of 64, from the band's furthest last
 // contributor, over the entries whose pixel box may reach the band. Every lane
-// repeats the forward's decision for its pixel. Per entry, the nine sums are
-// reduced across the wave when several lanes contribute (else each
-// contributing lane adds its own) and added atomically at the entry's cut
-// position.
+// repeats the forward's decision for its pixel. A chunk is walked in one of
+// two ways, with the same per-pixel arithmetic in the same order:
+//   - together (most entries cover most pixels of the band): entry by entry,
+//     the nine sums are reduced across the wave when several lanes contribute
+//     (else each contributing lane adds its own) and added atomically at the
+//     entry's cut position;
+//   - per pixel (far, small Gaussians): each lane walks only the entries whose
+//     pixel box holds its pixel centre, back to front, adding its terms into
+//     per-entry LDS sums, which are then added at the entries' cut positions.
 __global__ __launch_bounds__(256) void blend_backward(const uint2* __restrict__ ranges,
                                                       const uint32_t* __restrict__ tval,
                                                       const float4* __restrict__ pg0, const float4* __restrict__ pg1,
@@ -1507,6 +1556,7 @@ __global__ __launch_bounds__(256) void blend_backward(const uint2* __restrict__ 
                                                       uint32_t n_pairs_cap, GradAcc acc) {
   __shared__ float4 s_r[4][3][64];
   __shared__ uint32_t s_g[4][64];
+  __shared__ float s_acc[4][9][64];   // per-entry sums of the per-pixel walk
   const int w = (int)(threadIdx.x >> 6), l = (int)(threadIdx.x & 63);
   const size_t hw = (size_t)cam.W * cam.H;
   const int njobs = 4 * ntiles;
@@ -1540,6 +1590,7 @@ __global__ __launch_bounds__(256) void blend_backward(const uint2* __restrict__ 
       const int b0 = bend - 64 > (int)pb ? bend - 64 : (int)pb;
       const int cnt = bend - b0;
       bool hit = false;
+      float bx = 0.f, by = 0.f, brx = -1.f, bry = -1.f;   // this lane's entry's pixel box (empty if none)
       if (l < cnt) {
         uint32_t g = tval[b0 + l];
         if (g >= n_g) g = 0;
@@ -1549,65 +1600,98 @@ __global__ __launch_bounds__(256) void blend_backward(const uint2* __restrict__ 
         s_r[w][1][l] = b;
         s_r[w][2][l] = c;
         s_g[w][l] = g;
+        if (hit) {
+          const uint32_t ext = __float_as_uint(c.w);
+          bx = a.x;
+          by = a.y;
+          brx = (float)(ext & 0xFFFFu);
+          bry = (float)(ext >> 16);
+        }
       }
       uint64_t mask = ballot(hit);
+      // per lane: the chunk's entries whose box holds the lane's pixel centre
+      // (the pixel rule, with the same float expressions), up to its last contributor
+      const int cc = l & 15, cr = l >> 4;
+      uint64_t mc = 0ull, mr = 0ull;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const uint64_t bb = ballot(fabsf(bx - (xa + (float)i)) <= brx);
+        mc = cc == i ? bb : mc;
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint64_t bb = ballot(fabsf(by - (ya + (float)i)) <= bry);
+        mr = cr == i ? bb : mr;
+      }
+      uint64_t mk = mc & mr;
+      const int lim = lst - b0;   // entries j <= lim may have been blended at this pixel
+      mk = lim < 0 ? 0ull : (lim >= 63 ? mk : mk & ((2ull << lim) - 1ull));
+      const int pc = __popcll(mk);
+      int mx = 0;
+#pragma unroll
+      for (int bt = 6; bt >= 0; --bt)
+        if (ballot(pc >= (mx | (1 << bt))) != 0ull) mx |= 1 << bt;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      while (mask != 0ull) {
-        const int j = 63 - __builtin_clzll(mask);   // back to front
-        mask &= ~(1ull << j);
-        const float4 p0 = s_r[w][0][j], p1 = s_r[w][1][j], p2 = s_r[w][2][j];
-        const float dx = p0.x - fxp, dy = p0.y - fyp;
-        const float raw = fmaf(dx, fmaf(p0.z, dx, p0.w * dy), (p1.x * dy) * dy);
-        const float power = fminf(raw, 0.f);
-        const uint32_t ext = __float_as_uint(p2.w);
-        bool on = b0 + j <= lst && fabsf(dx) <= (float)(ext & 0xFFFFu) && fabsf(dy) <= (float)(ext >> 16);
-        const float e = __expf(power);
-        const float araw = p1.y * e;
-        const float alpha = fminf(kAlphaMax, araw);
-        on = on && alpha >= kAlphaMin;   // the forward's decision, recomputed the same way
-        const uint64_t onm = ballot(on);
-        if (onm == 0ull) continue;
-        float v[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        if (on) {
-          const float om = 1.f - alpha;
-          T = T / om;                                          // transmittance in front of this Gaussian
-          const float wgt = alpha * T;
-          v[6] = wgt * d0;
-          v[7] = wgt * d1;
-          v[8] = wgt * d2;
-          const float io = 1.f / om;
-          const float dla = (p2.x * T - S0 * io) * d0 + (p2.y * T - S1 * io) * d1 + (p2.z * T - S2 * io) * d2;
-          S0 = fmaf(p2.x, wgt, S0);
-          S1 = fmaf(p2.y, wgt, S1);
-          S2 = fmaf(p2.z, wgt, S2);
-          if (araw < kAlphaMax) {
-            v[5] = dla * e;                                    // d alpha / d theta = e^rho
-            if (raw < 0.f) {
-              const float gr = dla * alpha;                    // d alpha / d rho = alpha
-              v[0] = gr * fmaf(2.f * p0.z, dx, p0.w * dy);
-              v[1] = gr * fmaf(p0.w, dx, 2.f * p1.x * dy);
-              v[2] = gr * dx * dx;
-              v[3] = gr * dx * dy;
-              v[4] = gr * dy * dy;
+      // per pixel when the busiest pixel needs under 70 % of the band's entries
+      // (measured: 35 % 2.9 ms, 50 % 2.0, 70 % 1.86, 85 % 1.92, always 2.1 per 1080p frame)
+      if (mx * 10 < __popcll(mask) * 7) {
+        // per pixel: each lane over its own entries, back to front
+#pragma unroll
+        for (int k = 0; k < 9; ++k) s_acc[w][k][l] = 0.f;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        while (ballot(mk != 0ull) != 0ull) {
+          if (mk != 0ull) {
+            const int j = 63 - __builtin_clzll(mk);
+            mk &= ~(1ull << j);
+            float v[9];
+            if (entry_grad(s_r[w][0][j], s_r[w][1][j], s_r[w][2][j], fxp, fyp, true, d0, d1, d2, T, S0, S1, S2,
+                           v)) {
+#pragma unroll
+              for (int k = 0; k < 9; ++k)
+                if (v[k] != 0.f) atomicAdd(&s_acc[w][k][j], v[k]);
             }
           }
         }
-        const uint32_t g = s_g[w][j];
-        if (__popcll(onm) <= 2) {
-          if (on) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (l < cnt) {
+          const uint32_t g = s_g[w][l];
 #pragma unroll
-            for (int k = 0; k < 9; ++k)
-              if (v[k] != 0.f) atomicAdd(acc.v[k] + g, v[k]);
+          for (int k = 0; k < 9; ++k) {
+            const float x = s_acc[w][k][l];
+            if (x != 0.f) atomicAdd(acc.v[k] + g, x);
           }
-        } else {
+        }
+      } else {
+        // together: entry by entry, back to front
+        while (mask != 0ull) {
+          const int j = 63 - __builtin_clzll(mask);
+          mask &= ~(1ull << j);
+          float v[9];
+          const bool on = entry_grad(s_r[w][0][j], s_r[w][1][j], s_r[w][2][j], fxp, fyp, b0 + j <= lst, d0, d1,
+                                     d2, T, S0, S1, S2, v);
+          const uint64_t onm = ballot(on);
+          if (onm == 0ull) continue;
+          const uint32_t g = s_g[w][j];
+          if (__popcll(onm) <= 2) {
+            if (on) {
 #pragma unroll
-          for (int k = 0; k < 9; ++k) v[k] = wave_sum_to_last(v[k]);
-          if (l == 63) {
+              for (int k = 0; k < 9; ++k)
+                if (v[k] != 0.f) atomicAdd(acc.v[k] + g, v[k]);
+            }
+          } else {
 #pragma unroll
-            for (int k = 0; k < 9; ++k)
-              if (v[k] != 0.f) atomicAdd(acc.v[k] + g, v[k]);
+            for (int k = 0; k < 9; ++k) v[k] = wave_sum_to_last(v[k]);
+            if (l == 63) {
+#pragma unroll
+              for (int k = 0; k < 9; ++k)
+                if (v[k] != 0.f) atomicAdd(acc.v[k] + g, v[k]);
+            }
           }
         }
       }
