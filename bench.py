@@ -169,8 +169,9 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU: the per-frame path is measured on one "
-                                   "MI355X; see DESIGN.md for how it would shard", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the per-frame path is measured on exactly one MI355X; several GPUs would "
+                                   "take independent viewers, or screen-space bands of one frame, each",
+                          "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
 
