@@ -1,5 +1,5 @@
 """CPU checks of bench.py's contract: runs on more than one GPU are refused
-with a message (this build measures one GPU), before anything touches a GPU."""
+with a message (the path is measured on one GPU), before anything touches a GPU."""
 import json
 import os
 import subprocess
