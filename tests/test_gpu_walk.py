@@ -134,6 +134,28 @@ def test_error_stops_and_joins(world):
     assert np.array_equal(images[1].cpu().numpy().view(np.uint32), ref[1].view(np.uint32))
 
 
+def test_full_search_each_frame(world):
+    """VY_WALK_FULL_EACH: every frame a full search, unfiltered, the frames not
+    chained: cuts and images equal the temporal loop's (the search and the
+    filter change neither, bit for bit)."""
+    vy, torch, scene, cams, ref, ids, host = world
+    from paper_2506_02774_amd.serving import STATS_DTYPE
+    depth = 3
+    cuts, ctxs, streams = _slots(vy, torch, scene, depth)
+    n = 9
+    images = [torch.full((3, H, W), float("nan"), device="cuda") for _ in range(n)]
+    stats = torch.zeros((n, 4), dtype=torch.int64, device="cuda")
+    vy.vy_walkthrough(scene, cams[:n], 2.0, cuts, ctxs, images, streams=streams, mode=vy.VY_WALK_FULL_EACH,
+                      alpha_filter=False, stats=stats)
+    torch.cuda.synchronize()
+    st = np.frombuffer(stats.cpu().numpy().tobytes(), dtype=STATS_DTYPE)
+    for i in range(n):
+        assert np.array_equal(images[i].cpu().numpy().view(np.uint32), ref[i].view(np.uint32)), i
+        assert st["n_cut"][i] == len(ids[i][1]) and st["n_frontier"][i] == len(ids[i][0]), i
+    F, C = cuts[(n - 1) % depth].ids()
+    assert np.array_equal(F, ids[n - 1][0]) and np.array_equal(C, ids[n - 1][1])
+
+
 def test_bad_arguments(world):
     vy, torch, scene, cams, ref, ids, host = world
     cuts, ctxs, streams = _slots(vy, torch, scene, 2)

@@ -283,13 +283,13 @@ def test_struct_layouts_match_the_header(tmp_path):
 
 # ------------------------------------------------------------ walkthrough ----
 
-def _walk_call(vy, n_frames, depth, cuts, ctxs, streams, images, scene=FAKE_BASE):
+def _walk_call(vy, n_frames, depth, cuts, ctxs, streams, images, scene=FAKE_BASE, mode=0):
     """vy_walkthrough with stand-in handles: every call here must fail (or
     return) in the argument checks, before any handle is used."""
     P = ctypes.c_void_p
     cams = (vy.vy_camera * max(1, n_frames))()
     arr = lambda xs: (P * max(1, len(xs)))(*xs) if xs is not None else None
-    return vy.lib().vy_walkthrough(P(scene) if scene else None, cams, n_frames, 2.0, 0, None, None, depth,
+    return vy.lib().vy_walkthrough(P(scene) if scene else None, cams, n_frames, 2.0, mode, None, None, depth,
                                    arr(cuts), arr(ctxs), arr(streams), arr(images),
                                    len(images) if images is not None else 0, None, None, None)
 
@@ -310,5 +310,7 @@ def test_walkthrough_argument_checks():
     assert _walk_call(vy, 4, 2, c[:2], x[:2], s[:2], [im[0], 0]) == E                  # a NULL image
     assert _walk_call(vy, 4, 2, c[:2], x[:2], None, im[:2]) == E                       # no streams
     assert "depth" in vy.lib().vy_last_error().decode() or "distinct" in vy.lib().vy_last_error().decode()
+    assert _walk_call(vy, 4, 2, c[:2], x[:2], s[:2], im[:2], mode=1 << 10) == E        # unknown mode bit
+    assert _walk_call(vy, 0, 2, c[:2], x[:2], s[:2], im[:2], mode=vy.VY_WALK_FULL_EACH | vy.VY_CUT_DFS) == vy.VY_OK
     # nothing to render: returns before touching any handle or stream
     assert _walk_call(vy, 0, 3, c[:3], x[:3], s[:3], im[:6]) == vy.VY_OK
