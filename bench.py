@@ -218,6 +218,9 @@ def main():
     copy_gbs = 2 * nb * 5 / (ce0.elapsed_time(ce1) * 1e-3) / 1e9
     del src, dst
     log(f"reference copy {args.copy_mib} MiB: {copy_gbs:.0f} GB/s (read + write)")
+    peaks = vy.measure_peaks()
+    log(f"measured vector peaks: FP32 FMA {peaks['fma_fp32_tflops']:.1f} TFLOP/s (no packed FP32), "
+        f"v_exp_f32 {peaks['exp_f32_gops']:.0f} G/s")
 
     # ---------------------------------------------------------------- warmup
     for temporal, filt in ((True, True), (False, False)):
@@ -373,7 +376,9 @@ def main():
         achieved = flops_per_launch / (launch_ms * 1e-3) / 1e12
         roofline = dict(kernel="blend_jobs<true,false,false>", bound="alu", achieved=round(achieved, 3),
                         peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s", frac=round(achieved / FP32_VECTOR_PEAK_TFLOPS, 5),
-                        traffic=traffic, launch_ms=round(launch_ms, 5), flops_per_launch=round(flops_per_launch),
+                        traffic=traffic, peak_measured=round(peaks["fma_fp32_tflops"], 2),
+                        frac_of_measured=round(achieved / peaks["fma_fp32_tflops"], 5),
+                        launch_ms=round(launch_ms, 5), flops_per_launch=round(flops_per_launch),
                         evals_per_launch=round(avg["evals"]), contribs_per_launch=round(avg["contribs"]),
                         algorithmic_bytes_per_launch=round(stage_bytes("blend", cnt)))
         log(f"dominant kernel blend: {launch_ms:.4f} ms/launch, {achieved:.2f} TFLOP/s algorithmic")
@@ -422,6 +427,8 @@ def main():
         "stages_full_unfiltered_ms_per_frame": {k: round(ms / K, 5) for k, (ms, n) in prof["full"].items() if n},
         "roofline": roofline,
         "reference_copy_GBps": round(copy_gbs, 1),
+        "measured_peaks": {"fma_fp32_tflops": round(peaks["fma_fp32_tflops"], 2),
+                           "exp_f32_gops": round(peaks["exp_f32_gops"], 1), "copy_GBps": round(copy_gbs, 1)},
         "cpu_baseline": cpu,
         "parity": parity,
     }

@@ -325,6 +325,16 @@ int vy_profile_begin(int64_t capacity);
 int vy_profile_end(double* stage_ms, int64_t* stage_launches);
 const char* vy_stage_name(int stage);
 
+/* Practical vector peaks of the current device, for the rooflines: probe
+ * kernels time FP32 fused multiply-adds (8 independent chains per lane,
+ * compiled like every kernel of the library, i.e. without packed FP32
+ * instructions) and the hardware exponential (v_exp_f32). Writes TFLOP/s
+ * (2 per FMA) and G exponentials/s. scratch: device, at least
+ * vy_measure_peaks_bytes() bytes (overwritten). Runs on `stream` and
+ * synchronises it. VY_ERR_ARG for a NULL or short argument. */
+size_t vy_measure_peaks_bytes(void);
+int vy_measure_peaks(float* scratch, size_t scratch_bytes, double* fma_tflops, double* exp_gops, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -126,6 +126,9 @@ def lib():
         "vy_profile_begin": ([I64], ctypes.c_int),
         "vy_profile_end": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)], ctypes.c_int),
         "vy_stage_name": ([ctypes.c_int], ctypes.c_char_p),
+        "vy_measure_peaks_bytes": ([], SZ),
+        "vy_measure_peaks": ([P, SZ, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), P],
+                             ctypes.c_int),
         # vy_serve.h
         "vy_arena_create": ([P, SZ, ctypes.POINTER(P)], ctypes.c_int),
         "vy_arena_free": ([P], ctypes.c_int),
@@ -450,6 +453,19 @@ def vy_render(scene: Scene, cut: Cut, cam, ctx: RenderContext, image=None, alpha
     check(lib().vy_render(scene.handle, cut.handle, ctypes.byref(c), ctypes.byref(o),
                           ctypes.c_void_p(image.data_ptr()), ctx.handle, _stream(stream)), "vy_render")
     return image
+
+
+def measure_peaks(stream=None):
+    """The device's practical FP32 FMA rate (TFLOP/s) and v_exp_f32 rate
+    (G/s), from the library's probe kernels (synchronises)."""
+    import torch
+    L = lib()
+    nb = int(L.vy_measure_peaks_bytes())
+    buf = torch.empty(nb // 4, dtype=torch.float32, device="cuda")
+    f, e = ctypes.c_double(), ctypes.c_double()
+    check(L.vy_measure_peaks(ctypes.c_void_p(buf.data_ptr()), nb, ctypes.byref(f), ctypes.byref(e), _stream(stream)),
+          "vy_measure_peaks")
+    return dict(fma_fp32_tflops=f.value, exp_f32_gops=e.value)
 
 
 def _render_opts(alpha_filter=False, bg=(0.0, 0.0, 0.0), save_state=False, split_min_pairs=0, walk=0, lut_entries=0):

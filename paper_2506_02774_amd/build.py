@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvoyager.so")
-SOURCES = ["api.hip", "scene.hip", "lod.hip", "render.hip", "serve.hip", "walk.hip"]
+SOURCES = ["api.hip", "scene.hip", "lod.hip", "render.hip", "serve.hip", "walk.hip", "peaks.hip"]
 HEADERS = ["vy_common.hpp", "sort.hpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=off",

@@ -64,6 +64,11 @@ def test_argument_errors_without_gpu():
     assert L.vy_render(None, None, None, None, None, None, None) == vy.VY_ERR_ARG
     assert L.vy_render_ctx_create(10, 64, 64, 100, None, 0, ctypes.byref(h)) == vy.VY_ERR_ARG
     assert L.vy_profile_begin(0) == vy.VY_ERR_ARG
+    f, e = ctypes.c_double(), ctypes.c_double()
+    nb = L.vy_measure_peaks_bytes()
+    assert nb >= 4 * 256
+    assert L.vy_measure_peaks(None, nb, ctypes.byref(f), ctypes.byref(e), None) == vy.VY_ERR_ARG
+    assert L.vy_measure_peaks(ctypes.c_void_p(1), nb - 1, ctypes.byref(f), ctypes.byref(e), None) == vy.VY_ERR_ARG
     assert L.vy_stage_name(13) == b"blend" and L.vy_stage_name(12) == b"blend_plan" and L.vy_stage_name(99) == b"?"
 
 

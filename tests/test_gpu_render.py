@@ -224,3 +224,14 @@ def test_heavy_tiles_band_jobs(n, dim):
     res = image_parity(imgs[True, 0], ref)
     print(dim, res, flush=True)
     assert res["ok"], res
+
+
+def test_measured_peaks_are_plausible():
+    """The probe kernels behind the rooflines: FP32 FMA without packed
+    instructions can reach at most half the chip's 157.3 TFLOP/s (packed)
+    peak, and the exponential runs at a quarter of the FMA rate or less."""
+    vy = require_gpu()
+    p = vy.measure_peaks()
+    print(p, flush=True)
+    assert 10.0 < p["fma_fp32_tflops"] <= 0.5 * 157.3 * 1.05
+    assert 50.0 < p["exp_f32_gops"] <= 1e3 * p["fma_fp32_tflops"] / 2
