@@ -156,6 +156,18 @@ def test_full_search_each_frame(world):
     assert np.array_equal(F, ids[n - 1][0]) and np.array_equal(C, ids[n - 1][1])
 
 
+def test_fewer_frames_than_slots(world):
+    """Two frames with four slots: the unused slots' streams only join."""
+    vy, torch, scene, cams, ref, ids, host = world
+    cuts, ctxs, streams = _slots(vy, torch, scene, 4)
+    images = [torch.full((3, H, W), float("nan"), device="cuda") for _ in range(4)]
+    vy.vy_walkthrough(scene, cams[:2], 2.0, cuts, ctxs, images, streams=streams, alpha_filter=True)
+    torch.cuda.synchronize()
+    for i in range(2):
+        assert np.array_equal(images[i].cpu().numpy().view(np.uint32), ref[i].view(np.uint32)), i
+    assert np.isnan(images[2].cpu().numpy()).all() and np.isnan(images[3].cpu().numpy()).all()
+
+
 def test_bad_arguments(world):
     vy, torch, scene, cams, ref, ids, host = world
     cuts, ctxs, streams = _slots(vy, torch, scene, 2)
