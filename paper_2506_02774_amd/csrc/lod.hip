@@ -95,8 +95,8 @@ VY_DEV void emit_wave(bool active, int32_t n, bool vis, uint32_t* fbits, uint32_
   }
 }
 
-// ctr layout: [0..2] rotating level-queue counters, [3] error count, [4] compaction ticket
-constexpr int kQ0 = 0, kErr = 3, kTicket = 4;
+// ctr layout: [0..2] rotating level-queue counters, [3] error count
+constexpr int kQ0 = 0, kErr = 3;
 
 __global__ void lod_setup(uint32_t* ctr, int32_t* q0, int seed_root) {
   if (threadIdx.x == 0) {
@@ -104,7 +104,6 @@ __global__ void lod_setup(uint32_t* ctr, int32_t* q0, int seed_root) {
     ctr[kQ0 + 1] = 0;
     ctr[kQ0 + 2] = 0;
     ctr[kErr] = 0;
-    ctr[kTicket] = 0;
     if (seed_root) q0[0] = 0;
   }
 }
@@ -395,8 +394,11 @@ __global__ __launch_bounds__(256) void lod_bfs(const int32_t* __restrict__ in_q,
   }
 }
 
-// Compaction of the F and C bitmaps into ascending ids (decoupled look-back
-// scan over partitions of 1024 words), zeroing the bitmaps as they are read.
+// Compaction of the F and C bitmaps into ascending ids over partitions of
+// 1024 words, zeroing the bitmaps as they are read: a first launch counts
+// every partition's bits, and each partition of the second sums the counts
+// of the partitions before it (at most a few thousand words, read from L2)
+// instead of waiting on a look-back chain across the partitions.
 // A partition is read as 4 rounds of 256 consecutive words (one per thread);
 // each round's ids are gathered in LDS and written out with coalesced stores.
 // The 8 per-thread counts (2 bitmaps x 4 rounds, each <= 32) are scanned in
@@ -439,19 +441,64 @@ VY_DEV uint4 block_excl_scan256_x4(uint4 v, uint4* sh, uint4* total) {
   return make_uint4(wb.x + x.x - v.x, wb.y + x.y - v.y, wb.z + x.z - v.z, wb.w + x.w - v.w);
 }
 
+// Frontier and cut bit counts of every compaction partition, so that a
+// partition's output offset is a plain sum over the partitions before it.
+__global__ __launch_bounds__(256) void lod_part_totals(int64_t n_words, const uint32_t* __restrict__ fbits,
+                                                       const uint32_t* __restrict__ cbits,
+                                                       uint32_t* __restrict__ part_tot) {
+  __shared__ uint32_t s_sum[2];
+  if (threadIdx.x < 2) s_sum[threadIdx.x] = 0u;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kWordsPerPart;
+  uint32_t a = 0u, b = 0u;
+#pragma unroll
+  for (int k = 0; k < kWordsPerThread; ++k) {
+    const int64_t w = base + k * 256 + threadIdx.x;
+    if (w < n_words) {
+      a += (uint32_t)__popc(fbits[w]);
+      b += (uint32_t)__popc(cbits[w]);
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o, 64);
+    b += __shfl_xor(b, o, 64);
+  }
+  if (lane() == 0) {
+    atomicAdd(&s_sum[0], a);
+    atomicAdd(&s_sum[1], b);
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) part_tot[2 * (int64_t)blockIdx.x + threadIdx.x] = s_sum[threadIdx.x];
+}
+
 __global__ __launch_bounds__(256) void lod_compact(int64_t n_words, uint32_t* __restrict__ fbits,
                                                    uint32_t* __restrict__ cbits, int32_t* __restrict__ Fout,
                                                    int32_t* __restrict__ Cout, int32_t* counts, int f_slot,
-                                                   uint32_t* ctr, uint64_t* status, uint32_t epoch,
-                                                   uint32_t n_parts) {
+                                                   const uint32_t* __restrict__ part_tot, uint32_t n_parts) {
   __shared__ uint4 s_scan4[4];
-  __shared__ uint32_t s_part;
-  __shared__ uint64_t s_ex[2];
+  __shared__ uint32_t s_ex[2];
   __shared__ int32_t s_ids[256 * 32];
-  if (threadIdx.x == 0) s_part = fetch_add(ctr + kTicket, 1u);
+  const uint32_t part = blockIdx.x;
+  if (threadIdx.x < 2) s_ex[threadIdx.x] = 0u;
   __syncthreads();
-  const uint32_t part = s_part;
-  if (part >= n_parts) return;
+  {
+    // the offsets of this partition's ids: totals of the partitions before it
+    uint32_t pa = 0u, pb = 0u;
+    for (uint32_t j = threadIdx.x; j < part; j += 256) {
+      pa += part_tot[2 * (size_t)j];
+      pb += part_tot[2 * (size_t)j + 1];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      pa += __shfl_xor(pa, o, 64);
+      pb += __shfl_xor(pb, o, 64);
+    }
+    if (lane() == 0) {
+      atomicAdd(&s_ex[0], pa);
+      atomicAdd(&s_ex[1], pb);
+    }
+  }
   const int64_t base = (int64_t)part * kWordsPerPart;
   uint32_t wd[2][kWordsPerThread];
 #pragma unroll
@@ -479,13 +526,6 @@ __global__ __launch_bounds__(256) void lod_compact(int64_t n_words, uint32_t* __
       }
       tot[q] = rt[q][0] + rt[q][1] + rt[q][2] + rt[q][3];
     }
-  }
-  if (threadIdx.x < 64) {   // wave 0 walks the F chain, wave 1 the C chain
-    const uint64_t e = lookback_wave(status, part, 2, epoch, tot[0], ctr + kErr);
-    if (threadIdx.x == 0) s_ex[0] = e;
-  } else if (threadIdx.x < 128) {
-    const uint64_t e = lookback_wave(status + 1, part, 2, epoch, tot[1], ctr + kErr);
-    if (threadIdx.x == 64) s_ex[1] = e;
   }
   __syncthreads();
 #pragma unroll
@@ -555,7 +595,7 @@ size_t vy_cut_workspace_bytes(int64_t n) {
   return (size_t)n * 4 * 5        // F[2], C, two level queues
          + (size_t)n_words * 4 * 2 // bitmaps
          + 64 * 4 + 64 * 4         // counts, ctr
-         + (size_t)n_parts * 16    // status
+         + (size_t)n_parts * 16    // per-partition bit counts
          + 16 * 256;               // alignment slack
 }
 
@@ -592,12 +632,11 @@ int cut_create_on(const vy_scene* scene, void* ws, size_t ws_bytes, hipStream_t 
   c->ctr = cv.take<uint32_t>(64);
   c->status = cv.take<uint64_t>(2 * c->n_parts);
   c->cur = -1;
-  c->epoch = 0;
   if (!cv.ok()) {
     free(c);
     return fail(VY_ERR_ARG, "vy_cut_create: workspace layout overflow");
   }
-  // one-time initialisation: bitmaps, counters and look-back status zero
+  // one-time initialisation: bitmaps, counters and partition counts zero
   hipError_t e = hipMemsetAsync(c->fbits, 0, sizeof(uint32_t) * c->n_words, st);
   if (e == hipSuccess) e = hipMemsetAsync(c->cbits, 0, sizeof(uint32_t) * c->n_words, st);
   if (e == hipSuccess) e = hipMemsetAsync(c->counts, 0, 64 * 4, st);
@@ -695,10 +734,11 @@ int vy_lod_cut(const vy_scene* scene, const vy_camera* cam, float tau, vy_cut* p
   }
   {
     ProfScope ps(VY_STAGE_LOD_COMPACT, st);
-    const uint32_t ep = next_epoch(o->epoch);
-    if (ep == 1) VY_HIP(hipMemsetAsync(o->status, 0, 16 * o->n_parts, st));
+    uint32_t* part_tot = reinterpret_cast<uint32_t*>(o->status);   // 2 words per partition
+    lod_part_totals<<<(int)o->n_parts, 256, 0, st>>>(o->n_words, o->fbits, o->cbits, part_tot);
+    VY_LAUNCHED();
     lod_compact<<<(int)o->n_parts, 256, 0, st>>>(o->n_words, o->fbits, o->cbits, o->F[dst], o->C, o->counts, dst,
-                                                 o->ctr, o->status, ep, (uint32_t)o->n_parts);
+                                                 part_tot, (uint32_t)o->n_parts);
     VY_LAUNCHED();
   }
   o->cur = dst;

@@ -89,10 +89,9 @@ struct Cut {
   uint32_t* cbits;      // cut bitmap
   int64_t n_words;
   int32_t* q[2];        // level queues of the top-down traversal
-  uint32_t* ctr;        // device counters: [0..2] rotating queue counts [3] error [4] compaction ticket
-  uint64_t* status;     // look-back status of the compaction scan (2 per partition)
+  uint32_t* ctr;        // device counters: [0..2] rotating queue counts [3] error
+  uint64_t* status;     // compaction: bit counts of every partition (F, C as uint32)
   int64_t n_parts;      // compaction partitions
-  uint32_t epoch;
   uint64_t version;     // counts the cuts written into this handle
 };
 
