@@ -10,7 +10,13 @@
  *                 Algorithm 1 seeded with the previous frame's cut;
  *   vy_render   - Section 3.1 "Culling & Projection", "Sorting" and
  *                 "Rasterization", optionally with the preemptive alpha-filtering
- *                 of Section 4.2 (Eq. 3 and Eq. 4 moved to culling/projection).
+ *                 of Section 4.2 (Eq. 3 and Eq. 4 moved to culling/projection)
+ *                 and the lookup-table exponential of Eq. 5;
+ *   vy_render_backward - gradients of a rendered image with respect to the
+ *                 cut's Gaussians (the adjoint of vy_render);
+ *   inspection, stage timing and vy_measure_peaks - for tests and rooflines.
+ * vy_serve.h builds two runtimes on these calls: a multi-viewer server and a
+ * walkthrough renderer that keeps several frames of one camera path in flight.
  *
  * Conventions
  *   - Every entry point returns VY_OK (0) or a negative VY_ERR_* code; the
