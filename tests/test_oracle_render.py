@@ -171,3 +171,41 @@ def test_lut_midpoint_is_ambiguous():
     assert r["ambiguous"][0]
     r2 = render.render_pixels(p, [0], [0], lut_m=0)
     assert not r2["ambiguous"][0]
+
+
+def _centre(theta, depth, rgb=(1.0, 1.0, 1.0)):
+    """Gaussians centred on pixel (0, 0)'s centre with a flat conic: rho = 0
+    there, so alpha = min(0.99, theta) exactly."""
+    n = len(theta)
+    return _proj([0.5] * n, [0.5] * n, [[1e-12, 0, 1e-12]] * n, theta, [rgb] * n, depth)
+
+
+def test_t_min_crossing_is_flagged():
+    """A blend that takes T within float32 reach of 1e-4 (here 5e-6 relative,
+    on either side) is ambiguous; clear crossings and clear blends are not.
+    T = 0.1 * 0.05 = 0.005 after alphas 0.9 and 0.95, then the third Gaussian
+    takes it to 0.005 (1 - theta3) = 1e-4 (1 + rel) (theta3 ~ 0.98, below the
+    0.99 clamp)."""
+    for rel, amb, n in [(5e-6, True, 3), (-5e-6, True, 2), (1e-2, False, 3), (-1e-2, False, 2),
+                        (0.5, False, 3)]:
+        theta3 = 1.0 - 0.02 * (1.0 + rel)
+        r = render.render_pixels(_centre([0.9, 0.95, theta3], [1.0, 2.0, 3.0]), [0], [0])
+        assert r["n_contrib"][0] == n, (rel, r["n_contrib"][0])
+        assert r["ambiguous"][0] == amb, rel
+
+
+def test_depth_tie_between_contributors_is_flagged():
+    """Two consecutive contributors within 1e-6 relative in depth are
+    ambiguous (float32 depth keys may order them either way); 1e-5 apart they
+    are not, and a tie with a Gaussian below alpha* (no contribution) is not."""
+    for d2, amb in [(5.0 * (1 + 5e-7), True), (5.0 * (1 - 5e-7), True), (5.0 * (1 + 1e-5), False),
+                    (6.0, False)]:
+        r = render.render_pixels(_centre([0.5, 0.5], [5.0, d2]), [0], [0])
+        assert r["n_contrib"][0] == 2
+        assert r["ambiguous"][0] == amb, d2
+    # the tied Gaussian does not blend (theta below alpha* = 1/255): no flag
+    r = render.render_pixels(_centre([0.5, 1e-3, 0.5], [5.0, 5.0 * (1 + 5e-7), 6.0]), [0], [0])
+    assert r["n_contrib"][0] == 2 and not r["ambiguous"][0]
+    # ... nor a tie that lies past the T stop
+    r = render.render_pixels(_centre([0.9, 0.95, 0.99, 0.5], [1.0, 2.0, 3.0, 3.0 * (1 + 5e-7)]), [0], [0])
+    assert r["n_contrib"][0] == 2 and not r["ambiguous"][0]
