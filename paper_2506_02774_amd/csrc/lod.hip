@@ -236,7 +236,7 @@ __global__ __launch_bounds__(256) void lod_level(const int32_t* __restrict__ in_
                                                  uint32_t* fbits, uint32_t* cbits, uint32_t* err, int last) {
   __shared__ int32_t s_out[kOutPerBlock];
   __shared__ uint32_t s_n, s_base;
-  const uint32_t n_in = ld_acq(cnt3 + (j % 3));
+  const uint32_t n_in = ld_relaxed(cnt3 + (j % 3));
   if (blockIdx.x == 0 && threadIdx.x == 0) cnt3[(j + 2) % 3] = 0;
   const uint32_t stride = gridDim.x * blockDim.x;
   const uint32_t trips = (n_in + stride - 1) / stride;
@@ -320,7 +320,7 @@ __global__ __launch_bounds__(256) void lod_bfs(const int32_t* __restrict__ in_q,
                                                uint32_t* fbits, uint32_t* cbits, uint32_t* err, int last) {
   __shared__ int32_t s_f[2][kBfsSlots];
   __shared__ uint32_t s_n[2], s_scan[8], s_tail[1];
-  const uint32_t n_in = ld_acq(cnt3 + (j % 3));
+  const uint32_t n_in = ld_relaxed(cnt3 + (j % 3));
   if (blockIdx.x == 0 && threadIdx.x == 0) cnt3[(j + 2) % 3] = 0;
   uint32_t* out_cnt = cnt3 + ((j + 1) % 3);
   const uint32_t tid = threadIdx.x;
@@ -391,6 +391,10 @@ __global__ __launch_bounds__(256) void lod_bfs(const int32_t* __restrict__ in_q,
       cur ^= 1;
       __syncthreads();
     }
+    // a level loop that ended on an empty level (nc == 0) ran no barrier after
+    // its read of s_n: the next chunk's seeding must not overwrite s_n or s_f
+    // before every wave has read them
+    __syncthreads();
   }
 }
 

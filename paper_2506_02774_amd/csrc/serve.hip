@@ -265,9 +265,23 @@ struct Runner {
       q = std::min<int64_t>(kMaxPairsCap, std::max<int64_t>(2 * r.cap_pairs, r.need_pairs + r.need_pairs / 4));
     void* mem = nullptr;
     const size_t want = ex.render_bytes(r.session, g, q);
+    // no frame of the session is in flight: its render block goes back first,
+    // so that the larger one may take its place
+    const size_t had = r.rmem ? ex.render_bytes(r.session, r.cap_g, r.cap_pairs) : 0;
+    ex.drop_render(r);
+    if (r.rmem) (void)arena->release(r.rmem);
+    r.rmem = nullptr;
     if (arena->alloc(want, &mem) != VY_OK) {
-      if (resident > 1 || want + p.fixed <= arena->bytes) return false;   // wait for memory
-      // larger than the whole arena: keep the frames as they are (flagged)
+      // the old size fits again: the block just released (merged with free
+      // neighbours) holds it
+      if (had && arena->alloc(had, &r.rmem) != VY_OK) return false;
+      // wait while another resident session can still run and give memory back
+      bool others_run = false;
+      for (int o = 0; o < max_viewers; ++o)
+        if (o != slot && res[o].session >= 0 && (!res[o].grow || res[o].inflight > 0)) others_run = true;
+      if (others_run && want + p.fixed <= arena->bytes) return false;
+      // never fits (larger than the arena, or every other resident session is
+      // itself paused for memory): keep the frames as they are (flagged)
       r.grow = false;
       r.need_g = r.need_pairs = 0;
       n_done += (int64_t)r.redo.size();
@@ -276,8 +290,6 @@ struct Runner {
       if (r.left == 0) release(slot);
       return true;
     }
-    ex.drop_render(r);
-    if (r.rmem) (void)arena->release(r.rmem);
     r.rmem = mem;
     r.cap_g = g;
     r.cap_pairs = q;

@@ -178,12 +178,16 @@ VY_DEV uint32_t lane() { return __lane_id(); }
 VY_DEV uint64_t ballot(bool p) { return __ballot(p); }
 VY_DEV uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
 
+// Relaxed device-scope atomics. No acquire/release ordering is needed where
+// they are used: a look-back status word packs its flag and value into one
+// 64-bit word (read and written whole), and queue counters written by an
+// earlier launch are ordered by the kernel boundary.
 template <class T>
-VY_DEV T ld_acq(const T* p) {
+VY_DEV T ld_relaxed(const T* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 template <class T>
-VY_DEV void st_rel(T* p, T v) {
+VY_DEV void st_relaxed(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 template <class T>
@@ -208,15 +212,15 @@ VY_DEV uint64_t lookback(uint64_t* status, uint32_t part, uint32_t stride, uint3
                          uint32_t* err) {
   uint64_t* me = status + (uint64_t)part * stride;
   if (part == 0) {
-    st_rel(me, pack_status(epoch, kFlagInc, aggregate));
+    st_relaxed(me, pack_status(epoch, kFlagInc, aggregate));
     return 0;
   }
-  st_rel(me, pack_status(epoch, kFlagAgg, aggregate));
+  st_relaxed(me, pack_status(epoch, kFlagAgg, aggregate));
   uint64_t excl = 0;
   int64_t j = (int64_t)part - 1;
   uint32_t spins = 0;
   while (j >= 0) {
-    uint64_t w = ld_acq(status + (uint64_t)j * stride);
+    uint64_t w = ld_relaxed(status + (uint64_t)j * stride);
     uint64_t flag = (w >> 38) & 3ull;
     if ((uint32_t)(w >> 40) != epoch || flag == 0) {
       if (++spins > kSpinLimit) {
@@ -230,7 +234,7 @@ VY_DEV uint64_t lookback(uint64_t* status, uint32_t part, uint32_t stride, uint3
     if (flag == kFlagInc) break;
     --j;
   }
-  st_rel(me, pack_status(epoch, kFlagInc, excl + aggregate));
+  st_relaxed(me, pack_status(epoch, kFlagInc, excl + aggregate));
   return excl;
 }
 
@@ -245,10 +249,10 @@ VY_DEV uint64_t lookback_wave(uint64_t* status, uint32_t part, uint32_t stride, 
   const uint32_t l = lane();
   uint64_t* me = status + (uint64_t)part * stride;
   if (part == 0) {
-    if (l == 0) st_rel(me, pack_status(epoch, kFlagInc, aggregate));
+    if (l == 0) st_relaxed(me, pack_status(epoch, kFlagInc, aggregate));
     return 0;
   }
-  if (l == 0) st_rel(me, pack_status(epoch, kFlagAgg, aggregate));
+  if (l == 0) st_relaxed(me, pack_status(epoch, kFlagAgg, aggregate));
   uint64_t excl = 0;
   int64_t hi = (int64_t)part - 1;
   uint32_t spins = 0;
@@ -257,7 +261,7 @@ VY_DEV uint64_t lookback_wave(uint64_t* status, uint32_t part, uint32_t stride, 
     uint64_t val = 0;
     bool valid = true, inc = true;
     if (j >= 0) {
-      const uint64_t w = ld_acq(status + (uint64_t)j * stride);
+      const uint64_t w = ld_relaxed(status + (uint64_t)j * stride);
       const uint64_t flag = (w >> 38) & 3ull;
       valid = (uint32_t)(w >> 40) == epoch && flag != 0;
       inc = valid && flag == kFlagInc;
@@ -284,14 +288,14 @@ VY_DEV uint64_t lookback_wave(uint64_t* status, uint32_t part, uint32_t stride, 
     if (k < 64) break;
     hi -= 64;
   }
-  if (l == 0) st_rel(me, pack_status(epoch, kFlagInc, excl + aggregate));
+  if (l == 0) st_relaxed(me, pack_status(epoch, kFlagInc, excl + aggregate));
   return excl;
 }
 
 // First half of a decoupled look-back split in two: publishes partition
 // `part`'s aggregate (the inclusive prefix for partition 0).
 VY_DEV void publish_aggregate(uint64_t* status, uint32_t part, uint32_t stride, uint32_t epoch, uint64_t aggregate) {
-  st_rel(status + (uint64_t)part * stride, pack_status(epoch, part == 0 ? kFlagInc : kFlagAgg, aggregate));
+  st_relaxed(status + (uint64_t)part * stride, pack_status(epoch, part == 0 ? kFlagInc : kFlagAgg, aggregate));
 }
 
 // Second half, by one thread that polls K predecessors per step with
@@ -310,7 +314,7 @@ VY_DEV uint64_t lookback_poll(uint64_t* status, uint32_t part, uint32_t stride, 
   while (j >= 0) {
     uint64_t w[K];
 #pragma unroll
-    for (int i = 0; i < K; ++i) w[i] = j - i >= 0 ? ld_acq(status + (uint64_t)(j - i) * stride) : 0ull;
+    for (int i = 0; i < K; ++i) w[i] = j - i >= 0 ? ld_relaxed(status + (uint64_t)(j - i) * stride) : 0ull;
     bool done = false, stall = false;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
@@ -333,7 +337,7 @@ VY_DEV uint64_t lookback_poll(uint64_t* status, uint32_t part, uint32_t stride, 
       __builtin_amdgcn_s_sleep(1);
     }
   }
-  st_rel(me, pack_status(epoch, kFlagInc, excl + aggregate));
+  st_relaxed(me, pack_status(epoch, kFlagInc, excl + aggregate));
   return excl;
 }
 

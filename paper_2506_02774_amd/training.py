@@ -17,7 +17,7 @@ from __future__ import annotations
 
 import torch
 
-from . import RenderContext, Scene, VoyagerError, check, vy_lod_cut, vy_render, vy_render_backward
+from . import VY_ERR_STATE, RenderContext, Scene, VoyagerError, check, vy_lod_cut, vy_render, vy_render_backward
 
 PARAMS = ("mean", "log_scale", "quat", "opacity_logit", "sh")
 
@@ -28,6 +28,7 @@ class GaussianRenderFn(torch.autograd.Function):
         params = dict(mean=mean, log_scale=log_scale, quat=quat, opacity_logit=opacity_logit, sh=sh)
         image = renderer._render(params, cam)
         ctx.renderer, ctx.cam = renderer, cam
+        ctx.generation = renderer.generation
         ctx.save_for_backward(quat)
         return image
 
@@ -35,6 +36,10 @@ class GaussianRenderFn(torch.autograd.Function):
     def backward(ctx, dimage):
         (quat,) = ctx.saved_tensors
         r = ctx.renderer
+        # the renderer keeps the saved state of its latest forward only
+        if r.generation != ctx.generation:
+            raise VoyagerError(VY_ERR_STATE, "GaussianRenderFn.backward: the renderer has rendered again since this "
+                                             "forward (one forward per backward on a Renderer)")
         g = vy_render_backward(r.scene, r.cut, ctx.cam, r.ctx, dimage.contiguous(), quat_raw=quat.detach())
         return g["mean"], g["log_scale"], g["quat"], g["opacity_logit"], g["sh"], None, None
 
@@ -52,6 +57,7 @@ class Renderer:
         self.n, self.tau, self.alpha_filter, self.bg = n, float(tau), bool(alpha_filter), tuple(bg)
         self.ctx = RenderContext(n, width, height, max_pairs)
         self.scene = self.cut = None
+        self.generation = 0          # forwards rendered so far; backward differentiates the latest only
 
     def parameters_from(self, host_tree, device="cuda"):
         """Leaf tensors (requires_grad) initialised from a host tree's arrays."""
@@ -64,6 +70,7 @@ class Renderer:
         return out
 
     def _render(self, params, cam):
+        self.generation += 1
         p = {k: params[k].detach().contiguous() for k in PARAMS}
         self.scene = Scene.from_tensors(self.tree, p)
         self.cut = vy_lod_cut(self.scene, cam, self.tau)

@@ -63,3 +63,16 @@ def test_adam_steps_reduce_l1_ssim(setup):
     print("loss:", [round(x, 5) for x in losses[::8]], losses[-1], flush=True)
     assert np.isfinite(losses).all()
     assert losses[-1] < 0.5 * losses[0]
+
+
+def test_backward_after_a_second_forward_is_refused(setup):
+    vy, torch, training, host, cam = setup
+    r = training.Renderer(host, W, H, tau=0.0)
+    params = r.parameters_from(host)
+    first = r(params, cam)
+    second = r(params, cam)
+    with pytest.raises(vy.VoyagerError) as e:
+        first.sum().backward()
+    assert e.value.code == vy.VY_ERR_STATE
+    second.sum().backward()                       # the latest forward still differentiates
+    assert float(params["sh"].grad.abs().max()) > 0

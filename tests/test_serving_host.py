@@ -225,6 +225,33 @@ def test_simulated_growth_beyond_the_arena_gives_up():
     assert a.stats()["n_live"] == 0
 
 
+def test_simulated_growth_reuses_the_sessions_own_block():
+    """A lone session whose larger render block fits only once its own old
+    block is given back still grows (8192-byte arena, 4096 fixed, 64 -> 250
+    pairs: 4096 + 4000 bytes)."""
+    vy, serving = _vy()
+    a = serving.Arena(8192, base=FAKE_BASE)
+    reqs, n = _trace(serving, [(0, 0.0), (0, 0.1), (0, 0.2)])
+    res, cnt = serving.simulate(a, 1, 1, 1, [4096], reqs, n, [0.01] * n, pair_capacity=[64],
+                                need_pairs=[100, 200, 10])
+    assert cnt["regrown"] == 2 and cnt["redone"] == 2
+    assert not res["status"].any() and a.stats()["n_live"] == 0
+
+
+def test_simulated_growth_when_every_session_waits_for_memory():
+    """Two sessions overflow one after the other and neither larger block fits
+    beside the other session's memory: one of them keeps its frame as it was
+    (flagged) and runs on, and the other grows once it has left."""
+    vy, serving = _vy()
+    a = serving.Arena(16384, base=FAKE_BASE)
+    reqs, n = _trace(serving, [(0, 0.0), (1, 0.0), (0, 0.1), (1, 0.1)])
+    res, cnt = serving.simulate(a, 1, 1, 2, [4096, 4096], reqs, n, [0.01] * n, pair_capacity=[64, 64],
+                                need_pairs=[350, 350, 10, 10])
+    assert cnt["regrown"] == 1 and cnt["redone"] == 2
+    assert not res["status"].any()
+    assert a.stats()["n_live"] == 0
+
+
 def test_simulate_rejects_bad_traces():
     vy, serving = _vy()
     a = serving.Arena(1 << 20, base=FAKE_BASE)
