@@ -140,7 +140,7 @@ enum {
   VY_CUT_DFS = 2       /* flag, for the top-down traversal of a full or temporal
                           search: each thread walks its queued node's subtree
                           depth first, 4 levels per launch, instead of the
-                          default workgroup-wide breadth-first walk of 7 levels
+                          default workgroup-wide breadth-first walk of 13 levels
                           per launch (frontier in LDS). The cut is the same
                           either way. */
 };
@@ -233,6 +233,40 @@ int vy_render_ctx_free(vy_render_ctx* ctx);
  * vy_render_status (the image is then incomplete). */
 int vy_render(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, const vy_render_opts* opts,
               float* image, vy_render_ctx* ctx, void* stream);
+
+/* Rendering without allocation, for callers that cannot allocate device
+ * memory or create a context (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc). The same stages and kernels as
+ * vy_render, so the image is bitwise the one vy_render writes; the context's
+ * scratch (projected Gaussians, sort buffers, counters, look-back words,
+ * per-pixel state) is instead a static device array of
+ * VY_NOALLOC_SCRATCH_BYTES that each GPU holds from the first call on it until
+ * the process ends, laid out at fixed capacities: a cut of at most
+ * VY_NOALLOC_MAX_GAUSSIANS entries, VY_NOALLOC_MAX_PAIRS Gaussian-tile pairs,
+ * images of at most VY_NOALLOC_MAX_WIDTH x VY_NOALLOC_MAX_HEIGHT. It calls no
+ * hipMalloc/hipFree and allocates no host memory; the first call on a device
+ * looks up the array's address and clears its look-back words with a kernel on
+ * `stream`.
+ *   image  : DEVICE float32 [3][height][width], caller-owned (written).
+ *   counts : DEVICE uint32[4], caller-owned, or NULL; receives {pairs needed,
+ *            Gaussians with at least one pair, the cut size if it exceeds
+ *            VY_NOALLOC_MAX_GAUSSIANS (else 0), device-side bound hits}. A
+ *            frame whose pairs exceed VY_NOALLOC_MAX_PAIRS, or whose cut
+ *            exceeds VY_NOALLOC_MAX_GAUSSIANS, is rendered incomplete: the
+ *            caller checks counts[0] and counts[2].
+ * Errors: VY_ERR_ARG for an image larger than the maximum, save_state or
+ * split_min_pairs (they need a context), or the arguments vy_render refuses;
+ * VY_ERR_HIP if the array's address cannot be obtained.
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents: calls that overlap on one GPU (on concurrent streams or host
+ * threads) race and must be serialised by the caller. Enqueued on `stream`. */
+#define VY_NOALLOC_SCRATCH_BYTES (64u << 20)
+#define VY_NOALLOC_MAX_GAUSSIANS (1 << 18)
+#define VY_NOALLOC_MAX_PAIRS (1 << 20)
+#define VY_NOALLOC_MAX_WIDTH 1280
+#define VY_NOALLOC_MAX_HEIGHT 720
+int vy_render_noalloc(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, const vy_render_opts* opts,
+                      float* image, uint32_t* counts, void* stream);
 
 /* Synchronises `stream`; returns the last frame's pair count and number of
  * projected (non-culled) Gaussians, VY_ERR_CAPACITY if the pairs exceeded

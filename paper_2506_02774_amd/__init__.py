@@ -116,6 +116,8 @@ def lib():
         "vy_render_ctx_create": ([I64, I32, I32, I64, P, SZ, ctypes.POINTER(P)], ctypes.c_int),
         "vy_render_ctx_free": ([P], ctypes.c_int),
         "vy_render": ([P, P, ctypes.POINTER(vy_camera), ctypes.POINTER(vy_render_opts), P, P, P], ctypes.c_int),
+        "vy_render_noalloc": ([P, P, ctypes.POINTER(vy_camera), ctypes.POINTER(vy_render_opts), P, P, P],
+                              ctypes.c_int),
         "vy_render_status": ([P, ctypes.POINTER(I64), ctypes.POINTER(I64), P], ctypes.c_int),
         "vy_render_backward": ([P, P, ctypes.POINTER(vy_camera), P, ctypes.POINTER(vy_grads), P, P], ctypes.c_int),
         "vy_render_saved": ([P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P),
@@ -452,6 +454,36 @@ def vy_render(scene: Scene, cut: Cut, cam, ctx: RenderContext, image=None, alpha
     c = make_camera(cam)
     check(lib().vy_render(scene.handle, cut.handle, ctypes.byref(c), ctypes.byref(o),
                           ctypes.c_void_p(image.data_ptr()), ctx.handle, _stream(stream)), "vy_render")
+    return image
+
+
+# capacities of vy_render_noalloc's static scratch (vy.h)
+NOALLOC_SCRATCH_BYTES = 64 << 20
+NOALLOC_MAX_GAUSSIANS = 1 << 18
+NOALLOC_MAX_PAIRS = 1 << 20
+NOALLOC_MAX_WIDTH, NOALLOC_MAX_HEIGHT = 1280, 720
+
+
+def vy_render_noalloc(scene: Scene, cut: Cut, cam, image=None, counts=None, alpha_filter=False,
+                      bg=(0.0, 0.0, 0.0), walk=0, lut_entries=0, stream=None):
+    """Enqueue rendering of `cut` into `image` with the library's static
+    scratch instead of a context (no allocation inside the call). `counts`: a
+    device int32/uint32 tensor of 4 elements receiving {pairs needed,
+    Gaussians with pairs, cut size if over capacity else 0, device errors},
+    or None. Returns `image`."""
+    import torch
+    if image is None:
+        image = torch.empty((3, int(cam.height), int(cam.width)), dtype=torch.float32, device="cuda")
+    if image.dtype != torch.float32 or not image.is_contiguous() or tuple(image.shape) != (3, cam.height, cam.width):
+        raise VoyagerError(VY_ERR_ARG, "image must be a contiguous float32 tensor of shape (3, H, W)")
+    if counts is not None and (counts.numel() < 4 or counts.element_size() != 4 or not counts.is_contiguous()):
+        raise VoyagerError(VY_ERR_ARG, "counts must be a contiguous 32-bit tensor of at least 4 elements")
+    o = _render_opts(alpha_filter, bg, False, 0, walk, lut_entries)
+    c = make_camera(cam)
+    check(lib().vy_render_noalloc(scene.handle, cut.handle, ctypes.byref(c), ctypes.byref(o),
+                                  ctypes.c_void_p(image.data_ptr()),
+                                  ctypes.c_void_p(counts.data_ptr()) if counts is not None else None,
+                                  _stream(stream)), "vy_render_noalloc")
     return image
 
 

@@ -18,6 +18,7 @@
 //   ranges        [start, end) of every tile in the sorted pairs
 //   blend         one 256-thread workgroup per 16x16 tile, Gaussians staged in
 //                 LDS in batches of 256, front-to-back alpha blending (Eq. 3)
+#include <mutex>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -2031,17 +2032,31 @@ int vy_render_ctx_create(int64_t max_g, int32_t max_w, int32_t max_h, int64_t ma
 
 namespace vy {
 
-int render_ctx_create_on(int64_t max_g, int32_t max_w, int32_t max_h, int64_t max_pairs, bool split, void* ws,
-                         size_t bytes, hipStream_t st, bool sync, vy_render_ctx** out) {
-  if (!ws || !out || max_g < 1 || max_w < 1 || max_h < 1 || max_pairs < 1 || max_pairs > 0x7FFFFFFF ||
+__global__ void zero_words(uint32_t* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+// Clears n 32-bit words with a kernel (a memset node recorded into a captured
+// graph is avoided: callers of the no-allocation entry point may capture it).
+static int zero_on(void* p, int64_t words, hipStream_t st) {
+  zero_words<<<imin(cdiv(words, 256), 1024), 256, 0, st>>>((uint32_t*)p, words);
+  VY_LAUNCHED();
+  return VY_OK;
+}
+
+// Lays the context's buffers out in `ws` and enqueues the clearing of what must
+// start at zero (look-back words, counters). No host or device allocation.
+static int render_ctx_carve(RenderCtx* c, int64_t max_g, int32_t max_w, int32_t max_h, int64_t max_pairs,
+                            bool split, void* ws, size_t bytes, hipStream_t st) {
+  if (!ws || max_g < 1 || max_w < 1 || max_h < 1 || max_pairs < 1 || max_pairs > 0x7FFFFFFF ||
       max_g > 0x7FFFFFFF || max_w > 32768 || max_h > 32768)
     return fail(VY_ERR_ARG, "vy_render_ctx_create: bad argument");
   if (cdiv(max_w, kTileSize) * cdiv(max_h, kTileSize) > 65536)
     return fail(VY_ERR_ARG, "vy_render_ctx_create: more than 65536 tiles (16-bit tile keys)");
   const size_t need = render_workspace_bytes(max_g, max_w, max_h, max_pairs, split);
   if (bytes < need) return fail(VY_ERR_ARG, "vy_render_ctx_create: workspace %zu < %zu bytes", bytes, need);
-  RenderCtx* c = (RenderCtx*)calloc(1, sizeof(RenderCtx));
-  if (!c) return fail(VY_ERR_ARG, "vy_render_ctx_create: out of host memory");
+  *c = RenderCtx();
   Carver cv(ws, bytes);
   c->magic = kCtxMagic;
   c->max_g = max_g;
@@ -2087,22 +2102,64 @@ int render_ctx_create_on(int64_t max_g, int32_t max_w, int32_t max_h, int64_t ma
   c->n_eval = cv.take<int32_t>((size_t)max_w * max_h);
   c->last_contrib = cv.take<int32_t>((size_t)max_w * max_h);
   if (!cv.ok()) {
-    free(c);
+    c->magic = 0;
     return fail(VY_ERR_ARG, "vy_render_ctx_create: workspace layout overflow");
   }
-  hipError_t e = hipMemsetAsync(c->status, 0, sizeof(uint64_t) * c->status_words, st);
-  if (e == hipSuccess) e = hipMemsetAsync(c->ctr, 0, 64 * 4, st);
-  if (e == hipSuccess && sync) e = hipDeviceSynchronize();
-  if (e != hipSuccess) {
-    free(c);
-    return fail(VY_ERR_HIP, "vy_render_ctx_create: %s", hipGetErrorString(e));
-  }
+  if (int rc = zero_on(c->status, 2 * c->status_words, st)) return rc;
+  if (int rc = zero_on(c->ctr, 64, st)) return rc;
   c->epoch = 0;
+  return VY_OK;
+}
+
+int render_ctx_create_on(int64_t max_g, int32_t max_w, int32_t max_h, int64_t max_pairs, bool split, void* ws,
+                         size_t bytes, hipStream_t st, bool sync, vy_render_ctx** out) {
+  if (!out) return fail(VY_ERR_ARG, "vy_render_ctx_create: bad argument");
+  RenderCtx* c = (RenderCtx*)calloc(1, sizeof(RenderCtx));
+  if (!c) return fail(VY_ERR_ARG, "vy_render_ctx_create: out of host memory");
+  if (int rc = render_ctx_carve(c, max_g, max_w, max_h, max_pairs, split, ws, bytes, st)) {
+    free(c);
+    return rc;
+  }
+  if (sync) {
+    const hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+      free(c);
+      return fail(VY_ERR_HIP, "vy_render_ctx_create: %s", hipGetErrorString(e));
+    }
+  }
   *out = (vy_render_ctx*)c;
   return VY_OK;
 }
 
 }  // namespace vy
+
+// ------------------------------------------- rendering without allocation ----
+// The scratch of vy_render_noalloc: one context's buffers in a static device
+// array (each GPU holds its own copy from the first call until the process
+// ends), laid out once per device at a fixed capacity. Host code reaches the
+// array only through the address hipGetSymbolAddress returns for the device.
+static __device__ __align__(256) unsigned char scratch[VY_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kNoallocDevices = 64;
+struct NoallocState {
+  bool ready = false;
+  void* ptr = nullptr;   // this device's address of `scratch`
+  RenderCtx ctx;
+};
+NoallocState g_noalloc[kNoallocDevices];
+std::mutex g_noalloc_mu;
+
+__global__ void noalloc_counts(const uint32_t* __restrict__ ctr, uint32_t* __restrict__ out) {
+  if (threadIdx.x == 0) {
+    out[0] = ctr[C_NPAIRS_RAW];
+    out[1] = ctr[C_NVIS];
+    out[2] = ctr[C_GOVER];
+    out[3] = ctr[C_ERR];
+  }
+}
+}  // namespace
 
 extern "C" {
 
@@ -2117,12 +2174,55 @@ int vy_render_ctx_free(vy_render_ctx* ctx) {
 
 static int epoch_for(RenderCtx* c, hipStream_t st, uint32_t* ep) {
   *ep = next_epoch(c->epoch);
-  if (*ep == 1) VY_HIP(hipMemsetAsync(c->status, 0, sizeof(uint64_t) * c->status_words, st));
+  if (*ep == 1) return zero_on(c->status, 2 * c->status_words, st);
   return VY_OK;
 }
 
+static int render_impl(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, const vy_render_opts* opts,
+                       float* image, vy_render_ctx* ctx, void* stream);
+
 int vy_render(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, const vy_render_opts* opts,
               float* image, vy_render_ctx* ctx, void* stream) {
+  return render_impl(scene, cut, cam, opts, image, ctx, stream);
+}
+
+int vy_render_noalloc(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, const vy_render_opts* opts,
+                      float* image, uint32_t* counts, void* stream) {
+  if (!cam || !image) return fail(VY_ERR_ARG, "vy_render_noalloc: bad argument");
+  if (cam->width < 1 || cam->height < 1 || cam->width > VY_NOALLOC_MAX_WIDTH || cam->height > VY_NOALLOC_MAX_HEIGHT)
+    return fail(VY_ERR_ARG, "vy_render_noalloc: image %dx%d exceeds the static scratch's %dx%d", cam->width,
+                cam->height, VY_NOALLOC_MAX_WIDTH, VY_NOALLOC_MAX_HEIGHT);
+  if (opts && (opts->save_state || opts->split_min_pairs > 0))
+    return fail(VY_ERR_ARG, "vy_render_noalloc: save_state and split tiles need a render context (vy_render)");
+  int dev = 0;
+  VY_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoallocDevices) return fail(VY_ERR_ARG, "vy_render_noalloc: device %d not supported", dev);
+  hipStream_t st = (hipStream_t)stream;
+  NoallocState& g = g_noalloc[dev];
+  {
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g.ready) {
+      void* ptr = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !ptr)
+        return fail(VY_ERR_HIP, "vy_render_noalloc: hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+      if (int rc = render_ctx_carve(&g.ctx, VY_NOALLOC_MAX_GAUSSIANS, VY_NOALLOC_MAX_WIDTH, VY_NOALLOC_MAX_HEIGHT,
+                                    VY_NOALLOC_MAX_PAIRS, false, ptr, VY_NOALLOC_SCRATCH_BYTES, st))
+        return rc;
+      g.ptr = ptr;
+      g.ready = true;
+    }
+  }
+  if (int rc = render_impl(scene, cut, cam, opts, image, (vy_render_ctx*)&g.ctx, stream)) return rc;
+  if (counts) {
+    noalloc_counts<<<1, 64, 0, st>>>(g.ctx.ctr, counts);
+    VY_LAUNCHED();
+  }
+  return VY_OK;
+}
+
+static int render_impl(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, const vy_render_opts* opts,
+                       float* image, vy_render_ctx* ctx, void* stream) {
   const Scene* s = (const Scene*)scene;
   const Cut* ct = (const Cut*)cut;
   RenderCtx* c = (RenderCtx*)ctx;

@@ -92,3 +92,38 @@ def test_binding_matches_header_arity():
         f = getattr(L, name)
         assert f.argtypes is not None, name
         assert len(f.argtypes) == n, (name, len(f.argtypes), n)
+
+
+def test_noalloc_limits_match_the_header():
+    vy, L = _lib()
+    text = _header_text()
+    want = dict(VY_NOALLOC_SCRATCH_BYTES=vy.NOALLOC_SCRATCH_BYTES, VY_NOALLOC_MAX_GAUSSIANS=vy.NOALLOC_MAX_GAUSSIANS,
+                VY_NOALLOC_MAX_PAIRS=vy.NOALLOC_MAX_PAIRS, VY_NOALLOC_MAX_WIDTH=vy.NOALLOC_MAX_WIDTH,
+                VY_NOALLOC_MAX_HEIGHT=vy.NOALLOC_MAX_HEIGHT)
+    for name, v in want.items():
+        m = re.search(rf"#define {name} \(?([0-9]+)u? *(<< *([0-9]+))?\)?", text)
+        assert m, name
+        got = int(m.group(1)) << (int(m.group(3)) if m.group(3) else 0)
+        assert got == v, name
+    # the fixed layout fits the static array. vy_render_workspace_bytes counts the
+    # split-tile buffers (which the static layout leaves out and whose size does
+    # not depend on the arguments); the rest of a 1-Gaussian 16x16 context is
+    # more than 4096 bytes, so need - split_extra bounds the layout from above
+    need = L.vy_render_workspace_bytes(vy.NOALLOC_MAX_GAUSSIANS, vy.NOALLOC_MAX_WIDTH, vy.NOALLOC_MAX_HEIGHT,
+                                       vy.NOALLOC_MAX_PAIRS)
+    split_extra = L.vy_render_workspace_bytes(1, 16, 16, 1) - 4096
+    assert need - split_extra <= vy.NOALLOC_SCRATCH_BYTES
+
+
+def test_noalloc_rejects_before_touching_the_gpu():
+    vy, L = _lib()
+    c = vy.vy_camera()
+    c.width, c.height, c.fx, c.fy, c.znear = vy.NOALLOC_MAX_WIDTH + 1, 64, 100.0, 100.0, 0.2
+    img = ctypes.c_void_p(1 << 40)       # never dereferenced: the size check comes first
+    assert L.vy_render_noalloc(None, None, ctypes.byref(c), None, img, None, None) == vy.VY_ERR_ARG
+    assert b"static scratch" in L.vy_last_error()
+    c.width = 64
+    o = vy.vy_render_opts()
+    o.save_state = 1
+    assert L.vy_render_noalloc(None, None, ctypes.byref(c), ctypes.byref(o), img, None, None) == vy.VY_ERR_ARG
+    assert L.vy_render_noalloc(None, None, None, None, img, None, None) == vy.VY_ERR_ARG
