@@ -16,9 +16,13 @@ and in the same way, the same two with one frame in flight, the frames-in-
 flight sweep, the 2x2 ablation for tau in {1, 2, 4} (one frame in flight),
 bitwise gates (temporal cut == full cut, filtered image == unfiltered image,
 walkthrough renderer == frame loop, every frame), per-stage times,
-the roofline of the dominant kernel, the FP64 oracle timed on the host, and
-the LUT exponential of Section 4.2 (FPS and PSNR / SSIM against the exact
-image for table sizes 8..128). Then, in a child process once the walkthrough's buffers are freed, the
+the roofline of the dominant kernel and each stage's fraction of the HBM
+peak, the FP64 oracle (cut + sampled tiles of three frames at every tau,
+compared with the GPU, and timed on 16 host threads and on one), the LUT
+exponential of Section 4.2 (FPS and PSNR / SSIM against the exact image for
+table sizes 8..128), and the plain renderer's own workload (2e6 leaves,
+1280x720, 120 frames, full search + unfiltered, gated every frame and
+compared with the oracle on every tenth). Then, in a child process once the walkthrough's buffers are freed, the
 multi-viewer serving benchmark (paper_2506_02774_amd.serving: 64 viewers on 4
 resident scenes at mixed resolutions, one frame at a time against several
 streams); its JSON is embedded under "serving". Progress goes to stderr.
@@ -38,11 +42,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector
-# algorithmic FLOPs of the blend: per pixel evaluation of a tile-list entry
-# (offset 2, rho 7, clamp 1, exp 1, theta 1, clamp 1 = 13) and per blended
-# Gaussian (1 - alpha, T update, alpha T, colour 3 FMA = 10)
-BLEND_FLOPS_EVAL, BLEND_FLOPS_CONTRIB = 13.0, 10.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (counts packed FP32 instructions)
+FP32_UNPACKED_PEAK_TFLOPS = 78.6  # the same without packed FP32 (256 CUs x 4 SIMD x 16 lanes x 2 x 2.4 GHz)
+# algorithmic work of the blend: 10 vector operations per pixel evaluation of a
+# tile-list entry (offset 2, rho 5, clamp 1, pixel-box tests 2) plus one
+# exponential per evaluation that reaches it; the blended contributions are a
+# lower bound of the latter (each needed its exponential)
+BLEND_OPS_EVAL, BLEND_OPS_EXP = 10.0, 1.0
+ORACLE_THREADS = 16   # host threads for the oracle (the CPU share of one GPU on the box)
 T0 = time.time()
 
 
@@ -62,7 +69,9 @@ def parse():
     ap.add_argument("--no-serving", action="store_true", help="skip the multi-viewer serving benchmark")
     ap.add_argument("--no-lut", action="store_true", help="skip the LUT-exponential study")
     ap.add_argument("--no-backward", action="store_true", help="skip timing the backward pass")
-    ap.add_argument("--cpu-tiles", type=int, default=16, help="tiles the oracle renders for the CPU baseline")
+    ap.add_argument("--cpu-tiles", type=int, default=16, help="tiles the oracle renders per sampled frame")
+    ap.add_argument("--oracle-frames", type=int, default=3, help="frames per tau compared with the oracle")
+    ap.add_argument("--no-med", action="store_true", help="skip the 2M-leaf 720p plain-renderer workload")
     ap.add_argument("--max-pairs", type=int, default=96 << 20)
     ap.add_argument("--copy-mib", type=int, default=1024, help="size of the HBM copy used as the traffic reference")
     ap.add_argument("--depth", type=int, default=4, help="frames in flight of the headline walkthrough")
@@ -294,8 +303,8 @@ def main():
     lut = {} if args.no_lut else lut_study(vy, torch, scene, cams, args.tau, state, full_cut, ctx, img, img2)
 
     # ------------------------------------------------ gates + per-frame counts
-    log("verification pass (temporal cut == full cut, filtered == unfiltered, walkthrough renderer == "
-        "frame loop, every frame)")
+    log("verification pass (temporal cut == full cut, filtered == unfiltered, every frame at every tau; "
+        "walkthrough renderer == frame loop at the headline tau)")
     gates = dict(frames=0, cut_mismatch=0, image_mismatch=0, walkthrough_image_mismatch=0)
     # every frame of the headline configuration, each into its own image
     walk_imgs = [torch.empty((3, Hd, Wd), dtype=torch.float32, device="cuda")
@@ -303,45 +312,55 @@ def main():
     vy.vy_walkthrough(scene, cams, args.tau, slots["cuts"][:args.depth], slots["ctxs"][:args.depth], walk_imgs,
                       streams=slots["streams"][:args.depth], alpha_filter=True)
     torch.cuda.synchronize()
-    counts = dict(F=0.0, C=0.0, V=0.0, P=0.0, P_unf=0.0, evals=0.0, contribs=0.0)
+    gates_tau = {}
+    avg = None
     tst = vy.Cut(scene)
-    for i, cam in enumerate(cams):
-        if i == 0:
-            vy.vy_lod_cut(scene, cam, args.tau, out=tst)
-        else:
-            vy.vy_lod_cut(scene, cam, args.tau, prev=tst, out=tst)
-        vy.vy_lod_cut(scene, cam, args.tau, out=full_cut)
-        nf_t, nc_t = tst.counts()
-        nf_f, nc_f = full_cut.counts()
-        same = (nf_t, nc_t) == (nf_f, nc_f)
-        if same:
-            pt = [ctypes_ptr(vy, tst, k) for k in (0, 1)]
-            pf = [ctypes_ptr(vy, full_cut, k) for k in (0, 1)]
-            same = bool(torch.equal(vy.device_view(pt[0], (nf_t,)), vy.device_view(pf[0], (nf_f,)))) and \
-                bool(torch.equal(vy.device_view(pt[1], (nc_t,)), vy.device_view(pf[1], (nc_f,))))
-        gates["cut_mismatch"] += 0 if same else 1
-        vy.vy_render(scene, full_cut, cam, ctx, image=img, alpha_filter=False)
-        rc, p_unf, _ = ctx.status()
-        vy.check(rc)
-        vy.vy_render(scene, tst, cam, ctx, image=img2, alpha_filter=True, save_state=True)
-        rc, p_f, v_f = ctx.status()
-        vy.check(rc)
-        _, Nc, Ne = ctx.saved(Wd, Hd, evals=True)
-        counts["evals"] += float(Ne[Ne >= 0].sum())
-        counts["contribs"] += float(Nc.sum())
-        if not torch.equal(img.view(torch.int32), img2.view(torch.int32)):
-            gates["image_mismatch"] += 1
-        if not torch.equal(walk_imgs[i].view(torch.int32), img2.view(torch.int32)):
-            gates["walkthrough_image_mismatch"] += 1
-        gates["frames"] += 1
-        counts["F"] += nf_t
-        counts["C"] += nc_t
-        counts["V"] += v_f
-        counts["P"] += p_f
-        counts["P_unf"] += p_unf
+    for tau in sorted(set(cfg.taus) | {args.tau}):
+        head_tau = tau == args.tau
+        g = dict(frames=0, cut_mismatch=0, image_mismatch=0)
+        counts = dict(F=0.0, C=0.0, V=0.0, P=0.0, P_unf=0.0, evals=0.0, contribs=0.0)
+        for i, cam in enumerate(cams):
+            vy.vy_lod_cut(scene, cam, tau, prev=tst if i else None, out=tst)
+            vy.vy_lod_cut(scene, cam, tau, out=full_cut)
+            nf_t, nc_t = tst.counts()
+            nf_f, nc_f = full_cut.counts()
+            same = (nf_t, nc_t) == (nf_f, nc_f)
+            if same:
+                pt = [ctypes_ptr(vy, tst, k) for k in (0, 1)]
+                pf = [ctypes_ptr(vy, full_cut, k) for k in (0, 1)]
+                same = bool(torch.equal(vy.device_view(pt[0], (nf_t,)), vy.device_view(pf[0], (nf_f,)))) and \
+                    bool(torch.equal(vy.device_view(pt[1], (nc_t,)), vy.device_view(pf[1], (nc_f,))))
+            g["cut_mismatch"] += 0 if same else 1
+            vy.vy_render(scene, full_cut, cam, ctx, image=img, alpha_filter=False)
+            rc, p_unf, _ = ctx.status()
+            vy.check(rc)
+            vy.vy_render(scene, tst, cam, ctx, image=img2, alpha_filter=True, save_state=head_tau)
+            rc, p_f, v_f = ctx.status()
+            vy.check(rc)
+            if head_tau:
+                _, Nc, Ne = ctx.saved(Wd, Hd, evals=True)
+                counts["evals"] += float(Ne[Ne >= 0].sum())
+                counts["contribs"] += float(Nc.sum())
+                if not torch.equal(walk_imgs[i].view(torch.int32), img2.view(torch.int32)):
+                    gates["walkthrough_image_mismatch"] += 1
+            if not torch.equal(img.view(torch.int32), img2.view(torch.int32)):
+                g["image_mismatch"] += 1
+            g["frames"] += 1
+            counts["F"] += nf_t
+            counts["C"] += nc_t
+            counts["V"] += v_f
+            counts["P"] += p_f
+            counts["P_unf"] += p_unf
+        nfr = max(1, g["frames"])
+        gates_tau[f"tau={tau:g}"] = dict(g, mean_counts={k: round(v / nfr) for k, v in counts.items()
+                                                         if k not in ("evals", "contribs") or head_tau})
+        for k in ("frames", "cut_mismatch", "image_mismatch"):
+            gates[k] += g[k]
+        if head_tau:
+            avg = {k: v / nfr for k, v in counts.items()}
+        log(f"gates tau={tau:g}: {g}")
     del walk_imgs
-    nfr = max(1, gates["frames"])
-    avg = {k: v / nfr for k, v in counts.items()}
+    gates["per_tau"] = gates_tau
     log(f"gates: {gates}; mean |F| {avg['F']:.0f} |C| {avg['C']:.0f} visible {avg['V']:.0f} "
         f"pairs {avg['P']:.0f} (unfiltered {avg['P_unf']:.0f})")
 
@@ -353,7 +372,6 @@ def main():
         torch.cuda.synchronize()
         prof[name] = vy.profile_end()
     stages = prof["temporal+filter"]
-    tot_ms = sum(ms for ms, n in stages.values())
     log("stage ms/frame (temporal+filter): " + ", ".join(
         f"{k} {ms / K:.3f}" for k, (ms, n) in stages.items() if n))
     cnt = dict(F=avg["F"], C=avg["C"], V=avg["V"], P=avg["P"], tiles=ntiles, N=scene.n, px=Wd * Hd, filter=True)
@@ -362,26 +380,33 @@ def main():
         if not n:
             continue
         b = stage_bytes(k, cnt)
+        gbs = b / (ms / K * 1e-3) / 1e9 if ms > 0 and b > 0 else None
         per_stage[k] = dict(ms_per_frame=round(ms / K, 5), launches_per_frame=n / K,
-                            algorithmic_GBps=round(b / (ms / K * 1e-3) / 1e9, 1) if ms > 0 else None)
+                            algorithmic_bytes_per_frame=round(b) if b > 0 else None,
+                            algorithmic_GBps=round(gbs, 1) if gbs else None,
+                            frac_of_hbm_peak=round(gbs / HBM_PEAK_GBS, 4) if gbs else None)
     dom = max(((k, ms) for k, (ms, n) in stages.items() if n), key=lambda t: t[1])[0]
     bwd = None if args.no_backward else backward_study(vy, torch, scene, cams, args.tau, state, ctx, img)
     dom_ms, dom_n = stages[dom]
     launch_ms = dom_ms / dom_n
     traffic = read_traffic(dom)
     if dom == "blend":
-        # compute-type kernel: algorithmic FLOPs from the per-pixel evaluation counts
-        flops = BLEND_FLOPS_EVAL * avg["evals"] + BLEND_FLOPS_CONTRIB * avg["contribs"]
-        flops_per_launch = flops * K / dom_n
-        achieved = flops_per_launch / (launch_ms * 1e-3) / 1e12
+        # ALU-bound kernel: algorithmic vector operations from the per-pixel evaluation counts
+        ops = BLEND_OPS_EVAL * avg["evals"] + BLEND_OPS_EXP * avg["contribs"]
+        ops_per_launch = ops * K / dom_n
+        achieved = ops_per_launch / (launch_ms * 1e-3) / 1e12
         roofline = dict(kernel="blend_jobs<true,false,false>", bound="alu", achieved=round(achieved, 3),
                         peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s", frac=round(achieved / FP32_VECTOR_PEAK_TFLOPS, 5),
-                        traffic=traffic, peak_measured=round(peaks["fma_fp32_tflops"], 2),
+                        traffic=traffic, peak_unpacked=FP32_UNPACKED_PEAK_TFLOPS,
+                        frac_of_unpacked=round(achieved / FP32_UNPACKED_PEAK_TFLOPS, 5),
+                        peak_measured=round(peaks["fma_fp32_tflops"], 2),
                         frac_of_measured=round(achieved / peaks["fma_fp32_tflops"], 5),
-                        launch_ms=round(launch_ms, 5), flops_per_launch=round(flops_per_launch),
+                        launch_ms=round(launch_ms, 5), ops_per_launch=round(ops_per_launch),
+                        ops_formula="10 * evals + contribs (exponentials, lower bound)",
                         evals_per_launch=round(avg["evals"]), contribs_per_launch=round(avg["contribs"]),
-                        algorithmic_bytes_per_launch=round(stage_bytes("blend", cnt)))
-        log(f"dominant kernel blend: {launch_ms:.4f} ms/launch, {achieved:.2f} TFLOP/s algorithmic")
+                        algorithmic_bytes_per_launch=round(stage_bytes("blend", cnt)),
+                        hbm_frac=round(stage_bytes("blend", cnt) / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
+        log(f"dominant kernel blend: {launch_ms:.4f} ms/launch, {achieved:.2f} T ops/s algorithmic")
     else:
         bytes_per_launch = stage_bytes(dom, cnt) * K / dom_n
         achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
@@ -394,10 +419,12 @@ def main():
     cpu = None
     parity = dict(gates)
     if not args.no_cpu_baseline:
-        from threadpoolctl import threadpool_limits
-        with threadpool_limits(limits=1):  # the oracle runs on one host thread; `cores` reports that
-            cpu, par = cpu_baseline(vy, torch, host, scene, cams, args.tau, ctx, img, args.cpu_tiles, state)
+        cpu, par = oracle_leg(vy, torch, host, scene, cams, cfg.taus, args.tau, ctx, img, full_cut, args.cpu_tiles,
+                              args.oracle_frames)
         parity.update(par)
+    med = None
+    if not args.no_med and args.config == "full":
+        med = med_study(vy, torch, args)
 
     out = {
         "metric": "FPS, 18M-Gaussian 1080p walkthrough (temporal vs full LoD); p99 frame ms",
@@ -431,6 +458,7 @@ def main():
                            "exp_f32_gops": round(peaks["exp_f32_gops"], 1), "copy_GBps": round(copy_gbs, 1)},
         "cpu_baseline": cpu,
         "parity": parity,
+        "med_plain_renderer": med,
     }
     if not args.no_serving and args.config == "full":
         del ctx, state, full_cut, img, scene, slots
@@ -563,51 +591,158 @@ def ctypes_ptr(vy, cut, which):
     return (pf.value, pc.value)[which]
 
 
-def cpu_baseline(vy, torch, host, scene, cams, tau, ctx, img, n_tiles, state):
-    """The FP64 oracle on a bounded sample of the same workload: the brute-force
-    cut of frame 0 over every node plus n_tiles 16x16 tiles of its image.
-    Also checks the GPU against it (cut and sampled tiles)."""
+def oracle_frame(vy, torch, host, scene, cam, tau, ctx, img, cut, n_tiles, threads, seed=7):
+    """One frame against the FP64 oracle: the GPU's full-search cut against the
+    brute force over every node, and n_tiles 16x16 tiles of its image (the two
+    with the longest tile lists, where the work concentrates, and random ones)
+    against the oracle's per-pixel blend of the GPU's cut. Returns the parity
+    record and the oracle's seconds per part."""
     from oracle import lod as olod, project as oproj, render as orender
-    cam = cams[0]
     W, H = cam.width, cam.height
     tx_n, ty_n = (W + 15) // 16, (H + 15) // 16
-    log("cpu baseline: oracle brute-force cut over every node")
     t0 = time.perf_counter()
-    F_or, C_or, P = olod.cut_bruteforce(host, cam, tau)
+    F_or, C_or, P = olod.cut_bruteforce(host, cam, tau, threads=threads)
     t_cut = time.perf_counter() - t0
-    # GPU frame 0 (full search) for parity
-    g = vy.vy_lod_cut(scene, cam, tau, out=state)
-    F, C = g.ids()
-    cut_cmp = olod.compare_cut(host, cam, tau, F, C, oracle=(F_or, C_or, P))
-    vy.vy_render(scene, g, cam, ctx, image=img, alpha_filter=True)
-    torch.cuda.synchronize()
+    vy.vy_lod_cut(scene, cam, tau, out=cut)
+    F, C = cut.ids()
+    cmp = olod.compare_cut(host, cam, tau, F, C, oracle=(F_or, C_or, P))
+    del P
+    vy.vy_render(scene, cut, cam, ctx, image=img, alpha_filter=True)
+    rc, n_pairs, _ = ctx.status()
+    vy.check(rc)
+    keys, vals, ranges = ctx.pairs(W, H)
+    length = ranges[:, 1].astype(np.int64) - ranges[:, 0]
     gimg = img.cpu().numpy().astype(np.float64)
-    log(f"cpu baseline: cut {t_cut:.1f}s, |C| {len(C_or)}; projecting")
+    rng = np.random.default_rng(seed)
+    heavy = {int(t) for t in np.argsort(-length)[:2]}
+    rest = [t for t in rng.permutation(tx_n * ty_n).tolist() if t not in heavy][:max(0, n_tiles - len(heavy))]
+    tiles = sorted(heavy | set(rest))
     t0 = time.perf_counter()
-    proj = oproj.project(host, C, cam)
+    proj = oproj.project_threaded(host, C, cam, threads=threads)
     t_proj = time.perf_counter() - t0
-    # evenly spread tiles, including the horizon rows where the work concentrates
-    rng = np.random.default_rng(7)
-    tiles = sorted(set(int(t) for t in rng.choice(tx_n * ty_n, size=min(n_tiles, tx_n * ty_n), replace=False)))
     t0 = time.perf_counter()
-    ref = orender.render_image(proj, W, H, tiles=tiles)
+    ref = orender.render_image(proj, W, H, tiles=tiles, threads=threads)
     t_tiles = time.perf_counter() - t0
     mask = ~np.isnan(ref["image"][0])
     err = np.abs(gimg - np.nan_to_num(ref["image"]))[:, mask]
     amb = ref["ambiguous"][mask]
     max_err = float(err[:, ~amb].max()) if (~amb).any() else 0.0
-    frame_s = t_cut + t_proj + t_tiles * (tx_n * ty_n) / len(tiles)
-    cpu = dict(value=round(1.0 / frame_s, 6), unit="FPS", cores=1, kind="oracle",
-               sample=f"frame 0: brute-force cut over all {host.n_nodes} nodes ({t_cut:.1f}s), projection of "
-                      f"{len(C)} cut Gaussians ({t_proj:.1f}s), {len(tiles)} of {tx_n * ty_n} tiles blended "
-                      f"({t_tiles:.1f}s), scaled to a whole frame; single process FP64 numpy",
-               seconds=round(t_cut + t_proj + t_tiles, 2))
-    par = dict(oracle_cut_ok=bool(cut_cmp["ok"]), oracle_cut_near_threshold=cut_cmp["expand_diff"],
-               oracle_tiles=len(tiles), oracle_max_abs=round(max_err, 6), oracle_mean_abs=float(err.mean()),
-               oracle_ambiguous_px=int(amb.sum()), oracle_px=int(mask.sum()),
-               oracle_image_ok=bool(max_err <= 2e-3 and float(err.mean()) <= 1e-4))
-    log(f"cpu baseline: {cpu['value']:.5f} FPS equivalent; parity {par}")
+    rec = dict(tau=tau, cut_ok=bool(cmp["ok"]), cut_near_threshold=cmp["expand_diff"], C=int(len(C)),
+               tiles=len(tiles), tile_pairs_max=int(length.max()), px=int(mask.sum()), max_abs=round(max_err, 6),
+               mean_abs=float(err.mean()), ambiguous_px=int(amb.sum()),
+               image_ok=bool(max_err <= 2e-3 and float(err.mean()) <= 1e-4))
+    secs = dict(cut=t_cut, project=t_proj, tiles=t_tiles, n_tiles=len(tiles), all_tiles=tx_n * ty_n,
+                n_nodes=host.n_nodes, n_cut=int(len(C)))
+    return rec, secs
+
+
+def oracle_leg(vy, torch, host, scene, cams, taus, head_tau, ctx, img, cut, n_tiles, n_frames):
+    """The FP64 oracle on the host: parity on n_frames frames spread over the
+    walkthrough at every tau (cut + sampled tiles), timed on ORACLE_THREADS
+    threads; and one frame at the headline tau on a single thread. Returns
+    (cpu_baseline record, parity record)."""
+    from threadpoolctl import threadpool_limits
+    K = len(cams)
+    frames = sorted({int(round(x)) for x in np.linspace(0, K - 1, max(1, n_frames))})
+    recs, timing = [], None
+    with threadpool_limits(limits=1):       # one BLAS thread per oracle thread
+        for tau in sorted(set(taus) | {head_tau}):
+            for f in frames:
+                rec, secs = oracle_frame(vy, torch, host, scene, cams[f], tau, ctx, img, cut, n_tiles,
+                                         ORACLE_THREADS, seed=7 + f)
+                rec["frame"] = f
+                recs.append(rec)
+                log(f"oracle tau={tau:g} frame {f}: {rec}")
+                if tau == head_tau and f == frames[0]:
+                    timing = secs
+        one, one_secs = oracle_frame(vy, torch, host, scene, cams[0], head_tau, ctx, img, cut, 4, 1, seed=99)
+
+    def frame_s(t):
+        return t["cut"] + t["project"] + t["tiles"] * t["all_tiles"] / t["n_tiles"]
+
+    def sample(t, threads):
+        return (f"frame 0, tau={head_tau:g}: brute-force cut over all {t['n_nodes']} nodes ({t['cut']:.1f}s), "
+                f"projection of {t['n_cut']} cut Gaussians ({t['project']:.1f}s), {t['n_tiles']} of "
+                f"{t['all_tiles']} tiles blended ({t['tiles']:.1f}s), scaled to a whole frame; FP64 numpy on "
+                f"{threads} host thread(s)")
+
+    cpu = dict(value=round(1.0 / frame_s(timing), 6), unit="FPS", cores=ORACLE_THREADS, kind="oracle",
+               sample=sample(timing, ORACLE_THREADS),
+               seconds=round(timing["cut"] + timing["project"] + timing["tiles"], 2),
+               single_core=dict(value=round(1.0 / frame_s(one_secs), 6), unit="FPS", cores=1,
+                                sample=sample(one_secs, 1),
+                                seconds=round(one_secs["cut"] + one_secs["project"] + one_secs["tiles"], 2)))
+    par = dict(oracle_frames=recs, oracle_cut_ok=all(r["cut_ok"] for r in recs),
+               oracle_image_ok=all(r["image_ok"] for r in recs),
+               oracle_max_abs=max(r["max_abs"] for r in recs), oracle_mean_abs_max=max(r["mean_abs"] for r in recs),
+               oracle_single_core_frame=dict(one, frame=0))
+    log(f"cpu baseline: {cpu['value']:.5f} FPS on {ORACLE_THREADS} threads, {cpu['single_core']['value']:.5f} "
+        f"FPS on one; oracle cut ok {par['oracle_cut_ok']}, image ok {par['oracle_image_ok']}")
     return cpu, par
+
+
+def med_study(vy, torch, args, tau=2.0, oracle_every=10, tiles_per_frame=4):
+    """The plain renderer's own workload: 2e6 leaves (about 4e6 nodes),
+    1280x720, the 120-frame walkthrough, tau = 2, full LoD search each frame
+    and no alpha filter, one frame at a time; beside it the temporal search +
+    filter on the same frames. Gates every frame (temporal cut == full cut,
+    filtered image == unfiltered image) and compares frames 0, 10, ..., 110
+    with the oracle (cut + sampled tiles)."""
+    import scenegen
+    from threadpoolctl import threadpool_limits
+    cfg = scenegen.CONFIGS["med"]
+    log(f"med: generating scene ({cfg.n_leaf} leaves)")
+    host = scenegen.make_city(cfg)
+    scene = vy.Scene(host)
+    assert scene.validate() == 0
+    cams = scenegen.walkthrough(cfg)
+    warm = scenegen.walkthrough(cfg, seed=cfg.path_seed + 100, frames=5)
+    W, H = cfg.width, cfg.height
+    ctx = vy.RenderContext(scene.n, W, H, 32 << 20)
+    state, full_cut = vy.Cut(scene), vy.Cut(scene)
+    img = torch.empty((3, H, W), dtype=torch.float32, device="cuda")
+    img2 = torch.empty_like(img)
+    for temporal, filt in ((False, False), (True, True)):
+        frame_loop(vy, torch, scene, warm, tau, temporal, filt, state, full_cut, ctx, img, per_frame=False)
+    torch.cuda.synchronize()
+    plain = timed(vy, torch, scene, cams, tau, False, False, state, full_cut, ctx, img)
+    method = timed(vy, torch, scene, cams, tau, True, True, state, full_cut, ctx, img)
+    log(f"med: plain renderer (full + unfiltered) {plain['fps']:.1f} FPS p99 {plain['p99_ms']:.3f} ms; "
+        f"temporal + filter {method['fps']:.1f} FPS p99 {method['p99_ms']:.3f} ms")
+    g = dict(frames=0, cut_mismatch=0, image_mismatch=0)
+    for i, cam in enumerate(cams):
+        vy.vy_lod_cut(scene, cam, tau, prev=state if i else None, out=state)
+        vy.vy_lod_cut(scene, cam, tau, out=full_cut)
+        Ft, Ct = state.ids()
+        Ff, Cf = full_cut.ids()
+        g["cut_mismatch"] += 0 if (np.array_equal(Ft, Ff) and np.array_equal(Ct, Cf)) else 1
+        vy.vy_render(scene, full_cut, cam, ctx, image=img, alpha_filter=False)
+        vy.check(ctx.status()[0])
+        vy.vy_render(scene, state, cam, ctx, image=img2, alpha_filter=True)
+        vy.check(ctx.status()[0])
+        g["image_mismatch"] += 0 if torch.equal(img.view(torch.int32), img2.view(torch.int32)) else 1
+        g["frames"] += 1
+    recs = []
+    with threadpool_limits(limits=1):
+        for f in range(0, len(cams), oracle_every):
+            rec, _ = oracle_frame(vy, torch, host, scene, cams[f], tau, ctx, img, full_cut, tiles_per_frame,
+                                  ORACLE_THREADS, seed=50 + f)
+            rec["frame"] = f
+            recs.append(rec)
+    out = dict(workload=f"city-med: {cfg.n_leaf} leaves ({scene.n} nodes), {W}x{H}, {len(cams)}-frame walkthrough, "
+                        f"tau={tau:g} px, one frame in flight",
+               plain_full_unfiltered={k: round(v, 4) for k, v in plain.items()},
+               temporal_filter={k: round(v, 4) for k, v in method.items()},
+               speedup=round(method["fps"] / plain["fps"], 3), gates=g,
+               oracle_frames=recs, oracle_cut_ok=all(r["cut_ok"] for r in recs),
+               oracle_image_ok=all(r["image_ok"] for r in recs),
+               oracle_max_abs=max(r["max_abs"] for r in recs))
+    log(f"med: gates {g}; oracle cut ok {out['oracle_cut_ok']}, image ok {out['oracle_image_ok']} "
+        f"(max abs {out['oracle_max_abs']})")
+    del ctx, state, full_cut, img, img2, scene
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
 
 
 if __name__ == "__main__":

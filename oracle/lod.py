@@ -76,12 +76,26 @@ def predicates(scene, cam, tau: float, ids=None):
                 near_tau=near_tau & internal)
 
 
-def cut_bruteforce(scene, cam, tau: float):
+def predicates_threaded(scene, cam, tau: float, threads: int = 1, chunk: int = 1 << 21):
+    """predicates() over all nodes, evaluated in chunks of nodes on `threads`
+    threads (numpy releases the GIL in its array loops). Per-node arithmetic
+    is that of predicates(); only the work is split."""
+    N = scene.n_nodes
+    if threads <= 1 or N <= chunk:
+        return predicates(scene, cam, tau)
+    from concurrent.futures import ThreadPoolExecutor
+    starts = list(range(0, N, chunk))
+    with ThreadPoolExecutor(threads) as ex:
+        parts = list(ex.map(lambda a: predicates(scene, cam, tau, np.arange(a, min(N, a + chunk))), starts))
+    return {k: np.concatenate([q[k] for q in parts]) for k in parts[0]}
+
+
+def cut_bruteforce(scene, cam, tau: float, threads: int = 1):
     """Frontier F and cut C as sorted int64 node ids, plus the predicate table.
 
     Brute force over every node: n is in F iff not expand(n) and (n is the
     root or expand(parent(n))); C = F with vis."""
-    P = predicates(scene, cam, tau)
+    P = predicates_threaded(scene, cam, tau, threads)
     e = P["expand"]
     par = scene.parent
     parent_exp = np.where(par >= 0, e[np.maximum(par, 0)], True)
@@ -151,13 +165,13 @@ def check_frontier(scene, F) -> bool:
     return bool(np.all(count[leaves] == 1))
 
 
-def compare_cut(scene, cam, tau, F_gpu, C_gpu, oracle=None):
+def compare_cut(scene, cam, tau, F_gpu, C_gpu, oracle=None, threads=1):
     """Compare a GPU cut with the brute-force one.
 
     The expanded sets (strict ancestors of each frontier) may differ only in
     near-threshold nodes; cut differences must be explained by those or by a
     near-threshold frustum test. Returns a dict with counts and `ok`."""
-    F_or, C_or, P = oracle if oracle is not None else cut_bruteforce(scene, cam, tau)
+    F_or, C_or, P = oracle if oracle is not None else cut_bruteforce(scene, cam, tau, threads)
     F_gpu = np.asarray(F_gpu, np.int64)
     C_gpu = np.asarray(C_gpu, np.int64)
     E_gpu = ancestors_of(scene, F_gpu)

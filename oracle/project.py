@@ -97,3 +97,15 @@ def project(scene, ids, cam):
     return dict(ids=ids, valid=valid, mean2d=np.stack([mx, my], 1), conic=conic, cov2d=np.stack([a, b, c], 1),
                 depth=z, radius=radius, lambda_max=lam, theta=theta, log_theta=log_theta, rgb=rgb,
                 near_margin=np.abs(z - near) / np.maximum(np.abs(z), near))
+
+
+def project_threaded(scene, ids, cam, threads: int = 1, chunk: int = 1 << 18):
+    """project() of `ids` in chunks on `threads` threads (numpy releases the
+    GIL in its array loops); the per-Gaussian arithmetic is project()'s."""
+    ids = np.asarray(ids, np.int64)
+    if threads <= 1 or len(ids) <= chunk:
+        return project(scene, ids, cam)
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(threads) as ex:
+        parts = list(ex.map(lambda a: project(scene, ids[a:a + chunk], cam), range(0, len(ids), chunk)))
+    return {k: np.concatenate([q[k] for q in parts]) for k in parts[0]}

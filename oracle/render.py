@@ -181,9 +181,11 @@ def render_pixels(proj, px, py, bg=(0.0, 0.0, 0.0), order=None, amb_alpha=2e-4, 
     return out
 
 
-def render_image(proj, width, height, bg=(0.0, 0.0, 0.0), tiles=None, tile=16, **kw):
+def render_image(proj, width, height, bg=(0.0, 0.0, 0.0), tiles=None, tile=16, threads=1, **kw):
     """Whole image (3, H, W) (or only the given tile indices, others NaN), plus
-    T_final, n_contrib and the ambiguity mask (H, W)."""
+    T_final, n_contrib and the ambiguity mask (H, W). `threads` > 1 renders
+    the tiles on that many threads (each tile's pixels as render_pixels
+    computes them; only the work is split)."""
     order = depth_order(proj)
     img = np.full((3, height, width), np.nan)
     Tf = np.full((height, width), np.nan)
@@ -192,13 +194,22 @@ def render_image(proj, width, height, bg=(0.0, 0.0, 0.0), tiles=None, tile=16, *
     sig = np.zeros((height, width), np.uint64) if kw.get("signature") else None
     tx_n = (width + tile - 1) // tile
     ty_n = (height + tile - 1) // tile
-    all_tiles = range(tx_n * ty_n) if tiles is None else tiles
-    for t in all_tiles:
+    all_tiles = list(range(tx_n * ty_n) if tiles is None else tiles)
+
+    def one(t):
         ty, tx = divmod(int(t), tx_n)
         xs = np.arange(tx * tile, min(width, (tx + 1) * tile))
         ys = np.arange(ty * tile, min(height, (ty + 1) * tile))
         PX, PY = np.meshgrid(xs, ys)
-        r = render_pixels(proj, PX.ravel(), PY.ravel(), bg=bg, order=order, **kw)
+        return PX, PY, render_pixels(proj, PX.ravel(), PY.ravel(), bg=bg, order=order, **kw)
+
+    if threads > 1 and len(all_tiles) > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(threads) as ex:
+            results = list(ex.map(one, all_tiles))
+    else:
+        results = map(one, all_tiles)
+    for PX, PY, r in results:
         img[:, PY.ravel(), PX.ravel()] = r["rgb"].T
         Tf[PY.ravel(), PX.ravel()] = r["T"]
         nc[PY.ravel(), PX.ravel()] = r["n_contrib"]

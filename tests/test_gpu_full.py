@@ -3,7 +3,8 @@
 against the oracle's brute force over every node, and sampled tiles of its
 image (the heaviest, horizon tiles among them) against the oracle; along a
 stretch of the walkthrough, temporal == full cuts and filtered == unfiltered
-images bit for bit; the walkthrough renderer with four frames in flight (the
+images bit for bit at tau = 1, 2 and 4, and one more frame against the oracle
+at tau = 1 and at tau = 4; the walkthrough renderer with four frames in flight (the
 caller's stream as the first slot) equal to the frame loop, frame by frame."""
 import numpy as np
 import pytest
@@ -54,7 +55,33 @@ def test_cut_and_sampled_tiles_match_oracle(full):
     assert r["ok"], r
 
 
-def test_temporal_equals_full_and_filter_is_lossless(full):
+@pytest.mark.parametrize("tau,frame", [(1.0, 60), (4.0, 240)])
+def test_other_taus_match_oracle(full, tau, frame):
+    """tau = 1 (the heaviest cut) and tau = 4: the cut against the brute force
+    and sampled tiles, the heaviest among them, against the oracle."""
+    vy, torch, cfg, host, scene, cams, ctx = full
+    W, H = cfg.width, cfg.height
+    cam = cams[frame]
+    cut = vy.vy_lod_cut(scene, cam, tau)
+    F, C = cut.ids()
+    res = olod.compare_cut(host, cam, tau, F, C, threads=16)
+    print(f"tau {tau} frame {frame}: |F| {len(F)} |C| {len(C)}; cut {res}", flush=True)
+    assert res["ok"], res
+    img = vy.vy_render(scene, cut, cam, ctx, alpha_filter=True).cpu().numpy()
+    vy.check(ctx.status()[0])
+    keys, vals, ranges = ctx.pairs(W, H)
+    length = ranges[:, 1].astype(np.int64) - ranges[:, 0]
+    heavy = [int(t) for t in np.argsort(-length)[:2]]
+    rng = np.random.default_rng(frame)
+    tiles = sorted(set(heavy) | {int(t) for t in rng.choice(len(ranges), size=4, replace=False)})
+    ref = orender.render_image(oproj.project_threaded(host, C, cam, threads=16), W, H, tiles=tiles, threads=16)
+    r = image_parity(img, ref)
+    print(f"tiles {tiles} (pairs {[int(length[t]) for t in tiles]}): {r}", flush=True)
+    assert r["ok"], r
+
+
+@pytest.mark.parametrize("tau", [1.0, 2.0, 4.0])
+def test_temporal_equals_full_and_filter_is_lossless(full, tau):
     vy, torch, cfg, host, scene, cams, ctx = full
     W, H = cfg.width, cfg.height
     state, whole = vy.Cut(scene), vy.Cut(scene)
@@ -62,8 +89,8 @@ def test_temporal_equals_full_and_filter_is_lossless(full):
     b = torch.empty_like(a)
     for i in range(0, 40, 4):      # every fourth frame: larger steps between the temporal searches
         cam = cams[i]
-        vy.vy_lod_cut(scene, cam, TAU, prev=state if i else None, out=state)
-        vy.vy_lod_cut(scene, cam, TAU, out=whole)
+        vy.vy_lod_cut(scene, cam, tau, prev=state if i else None, out=state)
+        vy.vy_lod_cut(scene, cam, tau, out=whole)
         Ft, Ct = state.ids()
         Ff, Cf = whole.ids()
         assert np.array_equal(Ft, Ff) and np.array_equal(Ct, Cf), i

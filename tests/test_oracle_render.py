@@ -209,3 +209,24 @@ def test_depth_tie_between_contributors_is_flagged():
     # ... nor a tie that lies past the T stop
     r = render.render_pixels(_centre([0.9, 0.95, 0.99, 0.5], [1.0, 2.0, 3.0, 3.0 * (1 + 5e-7)]), [0], [0])
     assert r["n_contrib"][0] == 2 and not r["ambiguous"][0]
+
+
+def test_threaded_oracle_equals_serial():
+    """The threaded conveniences only split the work: bitwise the same results."""
+    from oracle import lod
+    sc = scenegen.random_gaussians(300, 4, 48, 40, depth_range=(2, 10), scale_range=(-3.0, -1.0))
+    cam = scenegen.identity_camera(48, 40)
+    p1 = project.project(sc, np.arange(300), cam)
+    p4 = project.project_threaded(sc, np.arange(300), cam, threads=4, chunk=37)
+    for k in p1:
+        assert np.array_equal(p1[k], p4[k]), k
+    a = render.render_image(p1, 48, 40)
+    b = render.render_image(p1, 48, 40, threads=4)
+    for k in a:
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
+    city = scenegen.make_city("tiny")
+    cams = scenegen.walkthrough(scenegen.CONFIGS["tiny"], frames=2)
+    q1 = lod.predicates(city, cams[1], 2.0)
+    q4 = lod.predicates_threaded(city, cams[1], 2.0, threads=4, chunk=5000)
+    for k in q1:
+        assert np.array_equal(q1[k], q4[k]), k
