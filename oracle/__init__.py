@@ -20,8 +20,12 @@ It computes the PLAIN DEFINITIONS of what the method produces, in float64:
                 Gaussians with alpha below alpha* skipped; no tiles, no
                 preemptive filter (Section 4.2 claims the filter is lossless,
                 so the filtered image must equal this one) and no LUT.
+* ``grad``    - gradients of that image with respect to the Gaussians'
+                parameters (blend decisions held fixed), by automatic
+                differentiation of a torch float64 transcription on the CPU.
 
 Every function marked "parity unpinned" in its docstring lacks an
 independent pin; all others are pinned by tests/test_oracle_*.py.
 """
 from . import lod, sh, project, render  # noqa: F401
+# oracle.grad imports torch on use: `from oracle import grad`
