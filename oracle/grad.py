@@ -62,14 +62,15 @@ def _sh_basis(d):
     return torch.stack(cols, dim=1)
 
 
-def project_torch(p, cam):
+def project_torch(p, cam, dtype=None):
     """oracle.project's projection of the Gaussians whose parameters are the
     float64 tensors p[k] (k in PARAMS), differentiable. Returns a dict of
     tensors: mean2d (n, 2), conic (n, 3) = (a, b, c) of Sigma2^-1, theta,
     rgb (n, 3), and the no-grad depth, validity and pruning radius."""
     torch = _torch()
-    R = torch.as_tensor(np.asarray(cam.R, np.float64))
-    pos = torch.as_tensor(np.asarray(cam.pos, np.float64))
+    dtype = p["mean"].dtype if dtype is None else dtype
+    R = torch.as_tensor(np.asarray(cam.R, np.float64)).to(dtype)
+    pos = torch.as_tensor(np.asarray(cam.pos, np.float64)).to(dtype)
     fx, fy, cx, cy, near = (float(np.float32(v)) for v in (cam.fx, cam.fy, cam.cx, cam.cy, cam.near))
     W, H = float(cam.width), float(cam.height)
     rel = p["mean"] - pos
@@ -114,8 +115,9 @@ def blend_torch(pr, ids, px, py, bg):
     depth = pr["depth"].numpy()
     v = np.nonzero(pr["valid"].numpy())[0]
     order = v[np.lexsort((np.asarray(ids)[v], depth[v]))]
-    cxp = torch.as_tensor(np.asarray(px, np.float64) + 0.5)
-    cyp = torch.as_tensor(np.asarray(py, np.float64) + 0.5)
+    dt = pr["mean2d"].dtype
+    cxp = torch.as_tensor(np.asarray(px, np.float64) + 0.5).to(dt)
+    cyp = torch.as_tensor(np.asarray(py, np.float64) + 0.5).to(dt)
     o = torch.as_tensor(order)
     m = pr["mean2d"][o]
     r = pr["radius"][o] + _render.SLACK
@@ -151,21 +153,24 @@ def blend_torch(pr, ids, px, py, bg):
     C = w @ rgb
     T_stop = torch.where(first_stop, Tbefore, torch.zeros_like(Tbefore)).sum(dim=1)
     T = torch.where(any_stop, T_stop, Tafter[:, -1] if a.shape[1] else torch.ones(len(px), dtype=a.dtype))
-    return C + T[:, None] * torch.as_tensor(np.asarray(bg, np.float64))[None, :]
+    return C + T[:, None] * torch.as_tensor(np.asarray(bg, np.float64)).to(dt)[None, :]
 
 
-def image_and_grads(scene, ids, cam, dL_dimage, bg=(0.0, 0.0, 0.0), tile=16):
+def image_and_grads(scene, ids, cam, dL_dimage, bg=(0.0, 0.0, 0.0), tile=16, dtype="float64"):
     """Image (3, H, W) of the Gaussians `ids` of `scene` seen by `cam`, and the
     gradients of sum(dL_dimage * image) with respect to their parameters,
     as float64 numpy arrays indexed like `ids` (quat: the stored, unnormalised
     quaternion). The image is blended tile by tile (16x16 pixels); each
-    tile's contribution is differentiated in turn and accumulated."""
+    tile's contribution is differentiated in turn and accumulated. `dtype`
+    "float32" evaluates the same steps in float32 (to see how far float32
+    rounding alone moves each gradient); results are returned as float64."""
     torch = _torch()
+    tdt = getattr(torch, dtype)
     ids = np.asarray(ids, np.int64)
     shp = dict(mean=(len(ids), 3), log_scale=(len(ids), 3), quat=(len(ids), 4), opacity_logit=(len(ids),),
                sh=(len(ids), 16, 3))
-    p = {k: torch.tensor(np.asarray(getattr(scene, k))[ids].astype(np.float64).reshape(shp[k]), requires_grad=True)
-         for k in PARAMS}
+    p = {k: torch.tensor(np.asarray(getattr(scene, k))[ids].astype(np.float64).reshape(shp[k])).to(tdt)
+         .requires_grad_(True) for k in PARAMS}
     pr = project_torch(p, cam)
     diff = {k: pr[k] for k in ("mean2d", "conic", "theta", "rgb")}
     leaves = {k: t.detach().requires_grad_(True) for k, t in diff.items()}
@@ -183,7 +188,7 @@ def image_and_grads(scene, ids, cam, dL_dimage, bg=(0.0, 0.0, 0.0), tile=16):
         PX, PY = PX.ravel(), PY.ravel()
         C = blend_torch(pr_leaf, ids, PX, PY, bg)
         img[:, PY, PX] = C.detach().numpy().T
-        g = torch.as_tensor(wimg[:, PY, PX].T)
+        g = torch.as_tensor(wimg[:, PY, PX].T).to(tdt)
         loss = (C * g).sum()
         if loss.requires_grad:
             gr = torch.autograd.grad(loss, list(leaves.values()), allow_unused=True)
@@ -191,6 +196,6 @@ def image_and_grads(scene, ids, cam, dL_dimage, bg=(0.0, 0.0, 0.0), tile=16):
                 if gk is not None:
                     acc[k] += gk
     torch.autograd.backward([diff[k] for k in leaves], [acc[k] for k in leaves])
-    grads = {k: (p[k].grad.numpy().copy() if p[k].grad is not None else np.zeros(shp[k])) for k in PARAMS}
+    grads = {k: (p[k].grad.double().numpy().copy() if p[k].grad is not None else np.zeros(shp[k])) for k in PARAMS}
     grads["sh"] = grads["sh"].reshape(len(ids), 48)
     return img, grads
