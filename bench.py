@@ -425,6 +425,9 @@ def main():
     med = None
     if not args.no_med and args.config == "full":
         med = med_study(vy, torch, args)
+    train = None
+    if not args.no_backward and args.config == "full":
+        train = train_study(vy, torch)
 
     out = {
         "metric": "FPS, 18M-Gaussian 1080p walkthrough (temporal vs full LoD); p99 frame ms",
@@ -459,6 +462,7 @@ def main():
         "cpu_baseline": cpu,
         "parity": parity,
         "med_plain_renderer": med,
+        "training_500k_720p": train,
     }
     if not args.no_serving and args.config == "full":
         del ctx, state, full_cut, img, scene, slots
@@ -547,6 +551,96 @@ def backward_study(vy, torch, scene, cams, tau, state, ctx, img, n_frames=60):
            "bwd_blend_ms": round(prof["bwd_blend"][0] / K, 4), "bwd_project_ms": round(prof["bwd_project"][0] / K, 4),
            "grad_norms_last_frame": {k: float(t.norm()) for k, t in gt.items()}}
     log(f"backward: {out}")
+    return out
+
+
+def train_study(vy, torch, target_cut=500_000, iters=20, warm=3):
+    """The differentiable rendering workload: a cut of about 500,000 Gaussians
+    taken from the 2e6-leaf city at 1280x720 (street level at a corner of the
+    city looking across it; tau found by bisection), whose Gaussians become
+    the leaves of a training tree rendered at tau = 0; a target image rendered
+    from parameters perturbed by N(0, 0.01) in position and colour (SH) and
+    N(0, 0.05) in log-scale and opacity logit; the loss L1 + 0.2 (1 - SSIM).
+    One iteration: repack the parameters, render with saved state, the loss,
+    its backward (the hand-written adjoint behind the autograd function, then
+    the SSIM's), and an Adam step. Reports ms per iteration (HIP events
+    around each part, and the wall clock)."""
+    import scenegen
+    from paper_2506_02774_amd import training
+    cfg = scenegen.CONFIGS["med"]
+    log("training: generating the 2e6-leaf city")
+    host = scenegen.make_city(cfg)
+    W, H = cfg.width, cfg.height
+    e = 0.95 * cfg.extent / 2
+    cam = scenegen.look_camera([-e, -e, cfg.eye], math.atan2(e, e), 0.0, W, H, cfg.fov_x_deg)
+    probe = vy.Scene(host)
+    lo, hi, n_cut = 0.5, 64.0, 0
+    cut = vy.Cut(probe)
+    for _ in range(40):            # the cut shrinks as tau grows
+        tau = math.sqrt(lo * hi)
+        n_cut = vy.vy_lod_cut(probe, cam, tau, out=cut).counts()[1]
+        if abs(n_cut - target_cut) <= 0.005 * target_cut:
+            break
+        lo, hi = (tau, hi) if n_cut > target_cut else (lo, tau)
+    _, C = cut.ids()
+    del probe, cut
+    sub = dict(mean=host.mean[C], log_scale=host.log_scale[C], quat=host.quat[C],
+               opacity_logit=host.opacity_logit[C], sh=host.sh[C])
+    tree = scenegen.build_hierarchy(sub)
+    r = training.Renderer(tree, W, H, tau=0.0, alpha_filter=True, max_pairs=16 << 20)
+    params = r.parameters_from(tree)
+    gen = torch.Generator(device="cuda").manual_seed(4)
+    with torch.no_grad():
+        pert = {k: v.detach().clone() for k, v in params.items()}
+        pert["mean"] += 0.01 * torch.randn(pert["mean"].shape, device="cuda", generator=gen)
+        pert["sh"] += 0.01 * torch.randn(pert["sh"].shape, device="cuda", generator=gen)
+        pert["log_scale"] += 0.05 * torch.randn(pert["log_scale"].shape, device="cuda", generator=gen)
+        pert["opacity_logit"] += 0.05 * torch.randn(pert["opacity_logit"].shape, device="cuda", generator=gen)
+        target = r(pert, cam).detach().clone()
+    n_vis = r.ctx.status()[2]
+    opt = torch.optim.Adam([params[k] for k in training.PARAMS], lr=1e-3)
+    names = ("forward", "loss", "backward", "adam")
+    ev = {k: [] for k in names}
+    losses = []
+
+    def one(record):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        e[0].record()
+        img = r(params, cam)
+        e[1].record()
+        loss = training.loss_l1_ssim(img, target)
+        e[2].record()
+        opt.zero_grad(set_to_none=True)
+        loss.backward()
+        e[3].record()
+        opt.step()
+        e[4].record()
+        if record:
+            for i, k in enumerate(names):
+                ev[k].append((e[i], e[i + 1]))
+        return loss
+
+    for _ in range(warm):
+        one(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        losses.append(one(True))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = {k: float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in ev.items()}
+    out = dict(workload=f"city-med: {cfg.n_leaf} leaves, a cut of {n_cut} Gaussians (tau={tau:.3f} px) at {W}x{H} "
+                        f"as the leaves of a training tree ({tree.n_nodes} nodes), target from perturbed parameters, "
+                        f"L1 + 0.2 (1 - SSIM), Adam",
+               cut_gaussians=int(n_cut), rendered_gaussians=int(r.cut.counts()[1]), projected_gaussians=int(n_vis),
+               iters=iters,
+               ms_per_iteration=round(1e3 * wall / iters, 4), iterations_per_s=round(iters / wall, 2),
+               ms_parts={k: round(v, 4) for k, v in ms.items()},
+               loss_first_last=[round(float(losses[0]), 6), round(float(losses[-1]), 6)])
+    log(f"training: {out}")
+    del r, params, pert, target, opt
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     return out
 
 

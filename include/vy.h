@@ -114,6 +114,19 @@ int vy_scene_upload(const vy_scene_desc* desc, void* workspace, size_t workspace
  * parent/child links disagree or whose AABB is not inside the parent's.
  * Returns VY_OK with *n_bad = 0 for a valid tree. */
 int vy_scene_validate(const vy_scene* scene, int64_t* n_bad, void* stream);
+
+/* Replaces the Gaussians' parameters of an uploaded scene, keeping its tree
+ * (links, AABBs, depth): repacks means, log-scales, quaternions and opacity
+ * logits (theta and log theta recomputed, as at upload) from DEVICE arrays
+ * laid out as in vy_scene_desc, and borrows `sh` in place of the previous SH
+ * array. For training over a fixed tree (the backward pass of Section 3.1's
+ * rendering): cuts of the scene stay valid, since the cut depends on the
+ * AABBs only. A vy_render_backward of a frame rendered before the update is
+ * refused (VY_ERR_STATE). Enqueued on `stream` (no synchronisation); the
+ * arrays other than `sh` may be reused once it has run. VY_ERR_ARG for NULL
+ * arguments. */
+int vy_scene_update_gaussians(vy_scene* scene, const float* mean, const float* log_scale, const float* quat,
+                              const float* opacity_logit, const float* sh, void* stream);
 int64_t vy_scene_num_nodes(const vy_scene* scene);
 int vy_scene_free(vy_scene* scene);
 

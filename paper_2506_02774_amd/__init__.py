@@ -103,6 +103,7 @@ def lib():
         "vy_scene_workspace_bytes": ([I64], SZ),
         "vy_scene_upload": ([ctypes.POINTER(vy_scene_desc), P, SZ, P, ctypes.POINTER(P)], ctypes.c_int),
         "vy_scene_validate": ([P, ctypes.POINTER(I64), P], ctypes.c_int),
+        "vy_scene_update_gaussians": ([P, P, P, P, P, P, P], ctypes.c_int),
         "vy_scene_num_nodes": ([P], I64),
         "vy_scene_free": ([P], ctypes.c_int),
         "vy_cut_workspace_bytes": ([I64], SZ),
@@ -255,6 +256,19 @@ class Scene:
         self.handle = h
         self.arrays = {"sh": arrays["sh"]}
         return self
+
+    def update_gaussians(self, params: dict, stream=None):
+        """vy_scene_update_gaussians: repack mean [n, 3], log_scale [n, 3],
+        quat [n, 4], opacity_logit [n] and sh [n, 16, 3] (contiguous float32
+        device tensors; sh is borrowed from now on) over the same tree."""
+        for k in ("mean", "log_scale", "quat", "opacity_logit", "sh"):
+            t = params[k]
+            if not (t.is_cuda and t.is_contiguous()) or t.shape[0] != self.n:
+                raise VoyagerError(VY_ERR_ARG, f"{k} must be a contiguous device tensor with {self.n} rows")
+        check(lib().vy_scene_update_gaussians(self.handle, *[ctypes.c_void_p(params[k].data_ptr()) for k in
+                                                             ("mean", "log_scale", "quat", "opacity_logit", "sh")],
+                                              _stream(stream)), "vy_scene_update_gaussians")
+        self.arrays = {"sh": params["sh"]}
 
     def validate(self, stream=None) -> int:
         nb = ctypes.c_int64()

@@ -2342,6 +2342,7 @@ static int render_impl(const vy_scene* scene, const vy_cut* cut, const vy_camera
   c->saved_scene = s;
   c->saved_cut = ct;
   c->saved_version = ct->version;
+  c->saved_params = s->params_version;
   c->saved_cam = *cam;
   for (int k = 0; k < 3; ++k) c->saved_bg[k] = opts ? opts->bg[k] : 0.f;
   const uint32_t split_min = split_on ? (uint32_t)opts->split_min_pairs : 0xFFFFFFFFu;
@@ -2402,6 +2403,8 @@ int vy_render_backward(const vy_scene* scene, const vy_cut* cut, const vy_camera
   if (c->saved_scene != s || c->saved_cut != ct || c->saved_version != ct->version ||
       memcmp(&c->saved_cam, cam, sizeof(vy_camera)) != 0)
     return fail(VY_ERR_STATE, "vy_render_backward: the saved frame is of another scene, cut or camera");
+  if (c->saved_params != s->params_version)
+    return fail(VY_ERR_STATE, "vy_render_backward: the scene's Gaussians were updated after the saved frame");
   hipStream_t st = (hipStream_t)stream;
   const RCam rc = make_rcam(cam, nullptr);
   RCam rcb = rc;

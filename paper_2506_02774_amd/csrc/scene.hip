@@ -170,6 +170,20 @@ int vy_scene_upload(const vy_scene_desc* d, void* ws, size_t ws_bytes, void* str
   return VY_OK;
 }
 
+int vy_scene_update_gaussians(vy_scene* scene, const float* mean, const float* log_scale, const float* quat,
+                              const float* opacity_logit, const float* sh, void* stream) {
+  Scene* s = (Scene*)scene;
+  if (!s || s->magic != kSceneMagic || !mean || !log_scale || !quat || !opacity_logit || !sh)
+    return fail(VY_ERR_ARG, "vy_scene_update_gaussians: bad argument");
+  hipStream_t st = (hipStream_t)stream;
+  const int blocks = (int)((s->n + 255) / 256 < 8192 ? (s->n + 255) / 256 : 8192);
+  pack_gauss<<<blocks, 256, 0, st>>>(s->n, mean, log_scale, quat, opacity_logit, s->gauss);
+  VY_LAUNCHED();
+  s->sh = sh;
+  ++s->params_version;
+  return VY_OK;
+}
+
 int vy_scene_validate(const vy_scene* scene, int64_t* n_bad, void* stream) {
   const Scene* s = (const Scene*)scene;
   if (!s || s->magic != kSceneMagic || !n_bad) return fail(VY_ERR_ARG, "vy_scene_validate: bad argument");

@@ -75,6 +75,7 @@ struct Scene {
   const float* sh;   // borrowed [n][48]
   int levels;        // tree depth + 1 (computed at upload)
   int32_t* scratch;  // small device scratch for validate
+  uint64_t params_version;  // bumped by each vy_scene_update_gaussians
 };
 
 struct Cut {
@@ -131,6 +132,7 @@ struct RenderCtx {
   const void* saved_scene;
   const void* saved_cut;
   uint64_t saved_version; // version of that cut
+  uint64_t saved_params;  // parameter version of that scene
   vy_camera saved_cam;
   float saved_bg[3];
   // blend planning: tiles split by depth bins

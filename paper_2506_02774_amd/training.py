@@ -1,8 +1,10 @@
 """Differentiable rendering for training (torch.autograd over the C ABI).
 
 `Renderer` renders a hierarchy whose Gaussian parameters are torch tensors:
-every call uploads the current parameters (vy_scene_upload packs them on the
-device), computes the LoD cut, and renders with the state the backward pass
+the first call uploads the tree and the parameters (vy_scene_upload), later
+calls repack only the parameters (vy_scene_update_gaussians) over the same
+tree; the LoD cut is computed when the camera changes (it depends on the
+tree's boxes only), and each call renders with the state the backward pass
 needs; `GaussianRenderFn.backward` calls vy_render_backward. The loss used for
 training is L1 + 0.2 (1 - SSIM), SSIM as in Wang et al. (2004) with an 11x11
 Gaussian window of standard deviation 1.5 (the same definition as
@@ -17,7 +19,8 @@ from __future__ import annotations
 
 import torch
 
-from . import VY_ERR_STATE, RenderContext, Scene, VoyagerError, check, vy_lod_cut, vy_render, vy_render_backward
+from . import (VY_ERR_STATE, RenderContext, Scene, VoyagerError, check, make_camera, vy_lod_cut, vy_render,
+               vy_render_backward)
 
 PARAMS = ("mean", "log_scale", "quat", "opacity_logit", "sh")
 
@@ -57,6 +60,7 @@ class Renderer:
         self.n, self.tau, self.alpha_filter, self.bg = n, float(tau), bool(alpha_filter), tuple(bg)
         self.ctx = RenderContext(n, width, height, max_pairs)
         self.scene = self.cut = None
+        self._cut_key = None         # the camera the cut was computed for
         self.generation = 0          # forwards rendered so far; backward differentiates the latest only
 
     def parameters_from(self, host_tree, device="cuda"):
@@ -72,8 +76,14 @@ class Renderer:
     def _render(self, params, cam):
         self.generation += 1
         p = {k: params[k].detach().contiguous() for k in PARAMS}
-        self.scene = Scene.from_tensors(self.tree, p)
-        self.cut = vy_lod_cut(self.scene, cam, self.tau)
+        if self.scene is None:
+            self.scene = Scene.from_tensors(self.tree, p)
+        else:
+            self.scene.update_gaussians(p)
+        key = bytes(make_camera(cam))
+        if self.cut is None or key != self._cut_key:
+            self.cut = vy_lod_cut(self.scene, cam, self.tau, out=self.cut)
+            self._cut_key = key
         img = vy_render(self.scene, self.cut, cam, self.ctx, alpha_filter=self.alpha_filter, bg=self.bg,
                         save_state=True)
         rc, need, _ = self.ctx.status()

@@ -76,3 +76,29 @@ def test_backward_after_a_second_forward_is_refused(setup):
     assert e.value.code == vy.VY_ERR_STATE
     second.sum().backward()                       # the latest forward still differentiates
     assert float(params["sh"].grad.abs().max()) > 0
+
+
+def test_update_gaussians_equals_a_fresh_upload(setup):
+    """vy_scene_update_gaussians over the same tree renders bitwise what a
+    fresh upload of the new parameters renders; a backward of a frame
+    rendered before the update is refused."""
+    vy, torch, training, host, cam = setup
+    r = training.Renderer(host, W, H, tau=0.0)
+    params = r.parameters_from(host)
+    img0 = r(params, cam).detach().clone()
+    gen = torch.Generator(device="cuda").manual_seed(9)
+    new = {k: (v.detach() + 0.05 * torch.randn(v.shape, device="cuda", generator=gen)).contiguous()
+           for k, v in params.items()}
+    sc = vy.Scene.from_tensors(r.tree, new)
+    cut = vy.vy_lod_cut(sc, cam, 0.0)
+    ctx = vy.RenderContext(sc.n, W, H, 1 << 22)
+    ref = vy.vy_render(sc, cut, cam, ctx, alpha_filter=True)
+    w = torch.ones((3, H, W), device="cuda")
+    r.scene.update_gaussians(new)                        # after the forward of img0: its backward is refused
+    with pytest.raises(vy.VoyagerError) as e:
+        vy.vy_render_backward(r.scene, r.cut, cam, r.ctx, w)
+    assert e.value.code == vy.VY_ERR_STATE
+    got = vy.vy_render(r.scene, r.cut, cam, r.ctx, alpha_filter=True)
+    torch.cuda.synchronize()
+    assert torch.equal(got.view(torch.int32), ref.view(torch.int32))
+    assert not torch.equal(got, img0)
