@@ -281,6 +281,57 @@ int vy_render(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, co
 int vy_render_noalloc(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, const vy_render_opts* opts,
                       float* image, uint32_t* counts, void* stream);
 
+/* ------------------------------------------------------------------------ */
+/* Batched rendering: the frames of several viewers in one launch per stage  */
+/* ------------------------------------------------------------------------ */
+
+/* One viewer's frame in a batch: its scene, its computed cut, its camera and
+ * its image (DEVICE float32 [3][height][width], caller-owned). */
+typedef struct vy_view {
+  const vy_scene* scene;
+  const vy_cut* cut;
+  vy_camera cam;
+  float* image;
+} vy_view;
+
+typedef struct vy_batch_ctx vy_batch_ctx;
+
+#define VY_BATCH_MAX_VIEWS 64
+#define VY_BATCH_MAX_TILES 65536
+
+/* Workspace for batches of at most max_views views whose cuts hold at most
+ * max_gaussians Gaussians in all, with at most max_tiles 16x16 tiles in all
+ * (<= VY_BATCH_MAX_TILES, e.g. 8 views at 1920x1080) and max_pairs pairs.
+ * 0 for invalid arguments. */
+size_t vy_batch_workspace_bytes(int32_t max_views, int64_t max_gaussians, int64_t max_tiles, int64_t max_pairs);
+/* Also allocates a small ring of pinned HOST buffers (and events) for the
+ * batch descriptor, released by vy_batch_ctx_free; synchronises the device. */
+int vy_batch_ctx_create(int32_t max_views, int64_t max_gaussians, int64_t max_tiles, int64_t max_pairs,
+                        void* workspace, size_t workspace_bytes, vy_batch_ctx** out);
+int vy_batch_ctx_free(vy_batch_ctx* ctx);
+
+/* Renders n_views frames (Section 3.1 "Culling & Projection", "Sorting",
+ * "Rasterization"; Section 4.2 with opts->alpha_filter) with one launch per
+ * stage for the whole batch: the views' cuts are concatenated, projected with
+ * each view's own scene and camera, sorted by depth together, and their pairs
+ * keyed by global tile (view v owns the tiles after those of views 0..v-1, so
+ * the view is the key's top part) and sorted by tile; each tile is blended
+ * into its view's image. Every image is bitwise the one vy_render writes for
+ * that view alone with the same options. opts->save_state and
+ * split_min_pairs must be 0. The descriptor is copied on `stream` (a pinned
+ * ring of 4 slots: a call waits for the copy of the call 4 before it).
+ * Enqueued on `stream`; calls on one batch context must not overlap. Errors:
+ * VY_ERR_ARG for a bad view, more views or tiles than the context holds;
+ * VY_ERR_STATE for a cut never computed. Overflows of max_gaussians or
+ * max_pairs are reported by vy_batch_status (the images are then incomplete). */
+int vy_render_batch(const vy_view* views, int32_t n_views, const vy_render_opts* opts, vy_batch_ctx* ctx,
+                    void* stream);
+
+/* As vy_render_status, for the last batch: the batch's pairs and Gaussians
+ * with pairs, VY_ERR_CAPACITY when they exceeded the context. Synchronises
+ * `stream`. */
+int vy_batch_status(vy_batch_ctx* ctx, int64_t* n_pairs, int64_t* n_visible, void* stream);
+
 /* Synchronises `stream`; returns the last frame's pair count and number of
  * projected (non-culled) Gaussians, VY_ERR_CAPACITY if the pairs exceeded
  * max_pairs (then *n_pairs is the number required), VY_ERR_DEVICE if a

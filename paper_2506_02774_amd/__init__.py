@@ -39,6 +39,10 @@ class vy_camera(ctypes.Structure):
                 ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("znear", ctypes.c_float)]
 
 
+class vy_view(ctypes.Structure):
+    _fields_ = [("scene", ctypes.c_void_p), ("cut", ctypes.c_void_p), ("cam", vy_camera), ("image", ctypes.c_void_p)]
+
+
 class vy_scene_desc(ctypes.Structure):
     _fields_ = [("n_nodes", ctypes.c_int64)] + [(k, ctypes.c_void_p) for k in (
         "parent", "first_child", "child_count", "aabb_lo", "aabb_hi", "mean", "log_scale", "quat",
@@ -120,6 +124,11 @@ def lib():
         "vy_render_noalloc": ([P, P, ctypes.POINTER(vy_camera), ctypes.POINTER(vy_render_opts), P, P, P],
                               ctypes.c_int),
         "vy_render_status": ([P, ctypes.POINTER(I64), ctypes.POINTER(I64), P], ctypes.c_int),
+        "vy_batch_workspace_bytes": ([I32, I64, I64, I64], SZ),
+        "vy_batch_ctx_create": ([I32, I64, I64, I64, P, SZ, ctypes.POINTER(P)], ctypes.c_int),
+        "vy_batch_ctx_free": ([P], ctypes.c_int),
+        "vy_render_batch": ([ctypes.POINTER(vy_view), I32, ctypes.POINTER(vy_render_opts), P, P], ctypes.c_int),
+        "vy_batch_status": ([P, ctypes.POINTER(I64), ctypes.POINTER(I64), P], ctypes.c_int),
         "vy_render_backward": ([P, P, ctypes.POINTER(vy_camera), P, ctypes.POINTER(vy_grads), P, P], ctypes.c_int),
         "vy_render_saved": ([P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P),
                              ctypes.POINTER(P)],
@@ -469,6 +478,61 @@ def vy_render(scene: Scene, cut: Cut, cam, ctx: RenderContext, image=None, alpha
     check(lib().vy_render(scene.handle, cut.handle, ctypes.byref(c), ctypes.byref(o),
                           ctypes.c_void_p(image.data_ptr()), ctx.handle, _stream(stream)), "vy_render")
     return image
+
+
+BATCH_MAX_VIEWS, BATCH_MAX_TILES = 64, 65536
+
+
+class BatchContext:
+    """Buffers shared by the frames of a batch (vy_batch_ctx): at most
+    max_views views, max_gaussians cut Gaussians and max_tiles tiles in all,
+    max_pairs pairs."""
+
+    def __init__(self, max_views, max_gaussians, max_tiles, max_pairs, device="cuda"):
+        import torch
+        L = lib()
+        nb = int(L.vy_batch_workspace_bytes(int(max_views), int(max_gaussians), int(max_tiles), int(max_pairs)))
+        if nb == 0:
+            raise VoyagerError(VY_ERR_ARG, "BatchContext: invalid capacities")
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p()
+        check(L.vy_batch_ctx_create(int(max_views), int(max_gaussians), int(max_tiles), int(max_pairs),
+                                    ctypes.c_void_p(self.ws.data_ptr()), nb, ctypes.byref(h)), "vy_batch_ctx_create")
+        self.handle = h
+        self.max_views = int(max_views)
+
+    def status(self, stream=None):
+        npairs, nvis = ctypes.c_int64(), ctypes.c_int64()
+        rc = lib().vy_batch_status(self.handle, ctypes.byref(npairs), ctypes.byref(nvis), _stream(stream))
+        return rc, int(npairs.value), int(nvis.value)
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                lib().vy_batch_ctx_free(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+
+def vy_render_batch(views, ctx: BatchContext, alpha_filter=False, bg=(0.0, 0.0, 0.0), walk=0, lut_entries=0,
+                    stream=None):
+    """Enqueue one batched render of `views`: (scene, cut, cam, image) tuples,
+    image a contiguous float32 [3, H, W] device tensor. Returns the images."""
+    import torch
+    n = len(views)
+    arr = (vy_view * max(1, n))()
+    for i, (scene, cut, cam, image) in enumerate(views):
+        if image.dtype != torch.float32 or not image.is_contiguous() or \
+                tuple(image.shape) != (3, cam.height, cam.width):
+            raise VoyagerError(VY_ERR_ARG, "image must be a contiguous float32 tensor of shape (3, H, W)")
+        arr[i].scene = scene.handle.value if isinstance(scene.handle, ctypes.c_void_p) else scene.handle
+        arr[i].cut = cut.handle.value if isinstance(cut.handle, ctypes.c_void_p) else cut.handle
+        arr[i].cam = make_camera(cam)
+        arr[i].image = image.data_ptr()
+    o = _render_opts(alpha_filter, bg, False, 0, walk, lut_entries)
+    check(lib().vy_render_batch(arr, n, ctypes.byref(o), ctx.handle, _stream(stream)), "vy_render_batch")
+    return [v[3] for v in views]
 
 
 # capacities of vy_render_noalloc's static scratch (vy.h)

@@ -19,6 +19,7 @@
 //   blend         one 256-thread workgroup per 16x16 tile, Gaussians staged in
 //                 LDS in batches of 256, front-to-back alpha blending (Eq. 3)
 #include <mutex>
+#include <new>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -74,6 +75,42 @@ struct RCam {
   float bg[3];
   float ln_amin;             // log(1/255)
   float fdelta;              // margin of the preemptive check (wider with the LUT)
+};
+
+// One viewer's frame in a batch rendered with one launch per stage: its
+// camera, scene records, cut, image, and where its Gaussians and tiles start
+// in the batch (cut positions [g_off[v], g_off[v + 1]) of the concatenated
+// cuts, global tiles [tile_base, tile_base + tiles_x * tiles_y)).
+struct BView {
+  RCam cam;
+  const float4* gauss;
+  const float* sh;
+  const int32_t* cut;
+  const int32_t* n_cut;   // device count of the view's cut
+  int64_t n_nodes;
+  float* img;
+  uint32_t tile_base;
+  uint32_t pad;
+};
+constexpr int kMaxViews = 64;
+
+// The view holding batch position i: the largest v with off[v] <= i (off has
+// nv + 1 ascending entries, off[0] = 0).
+VY_DEV int view_of(const uint32_t* off, int nv, uint32_t i) {
+  int lo = 0, hi = nv - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Per-Gaussian view data of a batched launch (BATCH), or the single frame's.
+struct ViewsRef {
+  const BView* views;      // device
+  const uint32_t* g_off;   // device [nv + 1]: first batch position of each view
+  int nv;
 };
 
 __global__ void render_setup(uint32_t* ctr, uint32_t* hist, uint2* ranges, int ntiles) {
@@ -159,6 +196,138 @@ VY_DEV bool tile_keep(const float4 p0, const float4 p1, float relax, int tx, int
   return rm * (1.f - relax) >= p1.z;
 }
 
+// One cut Gaussian (cut position i, node id `node`): EWA projection, SH
+// colour, pixel extents, tile rect and (FILTER) the Eq. 4 tests; writes its
+// records at position i and returns its depth key (0xFFFFFFFF when culled) and
+// pair count. Rects of more than kBigArea tiles are appended to `big`.
+template <bool FILTER>
+VY_DEV uint32_t project_one(uint32_t i, int32_t node, const float4* __restrict__ gauss, const float* __restrict__ sh,
+                            const RCam& cam, float4* __restrict__ pg0, float4* __restrict__ pg1,
+                            float4* __restrict__ pg2, uint4* __restrict__ prec, float* __restrict__ prelax,
+                            uint32_t* ctr, uint32_t* __restrict__ big, uint32_t* count_out) {
+  const float4 g0 = gauss[3 * (int64_t)node], g1 = gauss[3 * (int64_t)node + 1], g2 = gauss[3 * (int64_t)node + 2];
+  const float dxw = g0.x - cam.px, dyw = g0.y - cam.py, dzw = g0.z - cam.pz;
+  const float x = (cam.R[0] * dxw + cam.R[1] * dyw) + cam.R[2] * dzw;
+  const float y = (cam.R[3] * dxw + cam.R[4] * dyw) + cam.R[5] * dzw;
+  const float z = (cam.R[6] * dxw + cam.R[7] * dyw) + cam.R[8] * dzw;
+  bool valid = z > cam.near;
+  uint32_t count = 0, mask = 0, key = 0xFFFFFFFFu;
+  float4 o0 = make_float4(0, 0, 0, 0), o1 = make_float4(0, 0, 0, 0), o2 = make_float4(0, 0, 0, 0);
+  uint32_t r0 = 0, r1 = 0;
+  float relax = 0.f;
+  if (valid) {
+    // Sigma3 = M M^T with M = Rq diag(s)
+    const float qw = g2.x, qx = g2.y, qy = g2.z, qz = g2.w;
+    const float Rq[9] = {1.f - 2.f * (qy * qy + qz * qz), 2.f * (qx * qy - qw * qz), 2.f * (qx * qz + qw * qy),
+                         2.f * (qx * qy + qw * qz), 1.f - 2.f * (qx * qx + qz * qz), 2.f * (qy * qz - qw * qx),
+                         2.f * (qx * qz - qw * qy), 2.f * (qy * qz + qw * qx), 1.f - 2.f * (qx * qx + qy * qy)};
+    const float s[3] = {g1.x, g1.y, g1.z};
+    const float iz = 1.f / z;
+    const float u = fminf(fmaxf(x * iz, cam.ulo), cam.uhi);
+    const float v = fminf(fmaxf(y * iz, cam.vlo), cam.vhi);
+    // T = J R (2x3): rows fx/z (R0 - u R2), fy/z (R1 - v R2)
+    float T0[3], T1[3];
+    for (int k = 0; k < 3; ++k) {
+      T0[k] = (cam.fx * iz) * (cam.R[k] - u * cam.R[6 + k]);
+      T1[k] = (cam.fy * iz) * (cam.R[3 + k] - v * cam.R[6 + k]);
+    }
+    // V = T M (2x3); Sigma2 = V V^T + lowpass
+    float V0[3], V1[3];
+    for (int j = 0; j < 3; ++j) {
+      const float m0 = Rq[0 + j] * s[j], m1 = Rq[3 + j] * s[j], m2 = Rq[6 + j] * s[j];
+      V0[j] = (T0[0] * m0 + T0[1] * m1) + T0[2] * m2;
+      V1[j] = (T1[0] * m0 + T1[1] * m1) + T1[2] * m2;
+    }
+    const float a = ((V0[0] * V0[0] + V0[1] * V0[1]) + V0[2] * V0[2]) + kLowpass;
+    const float b = (V0[0] * V1[0] + V0[1] * V1[1]) + V0[2] * V1[2];
+    const float c = ((V1[0] * V1[0] + V1[1] * V1[1]) + V1[2] * V1[2]) + kLowpass;
+    const float det = fmaf(a, c, -b * b);
+    valid = det > 0.f;
+    if (valid) {
+      const float idet = 1.f / det;
+      const float ca = c * idet, cb = -b * idet, cc = a * idet;
+      const float mx = cam.fx * x * iz + cam.cx, my = cam.fy * y * iz + cam.cy;
+      const float mid = 0.5f * (a + c);
+      const float lmax = mid + sqrtf(fmaxf(0.f, mid * mid - det));
+      const float lmin = fmaxf(det / lmax, 1e-30f);
+      // per-axis extents: the ellipse d^T Sigma2^-1 d <= K^2 (outside it alpha < 1/255)
+      // lies within |dx| <= K sqrt(Sigma2_xx), |dy| <= K sqrt(Sigma2_yy)
+      float rx = fminf(ceilf(kRadiusK * sqrtf(a)), 65535.f), ry = fminf(ceilf(kRadiusK * sqrtf(c)), 65535.f);
+      const float theta = g1.w, log_theta = g0.w;
+      const float thr = cam.ln_amin - log_theta - cam.fdelta;
+      // relative rounding bound of rho for this conic (condition number based)
+      relax = 1e-6f * (lmax / lmin);
+      if (FILTER) {
+        if (thr > 0.f) valid = false;      // theta below alpha*: never blended
+        if (valid && relax < 0.25f) {
+          // outside the box of the ellipse rho >= thr every pixel has rho < thr
+          // (margins for the rounding of the conic and of the per-pixel rho)
+          const float f = 2.f * (-thr) * ((1.f + relax) / (1.f - relax)) * 1.001f;
+          rx = fminf(rx, ceilf(sqrtf(f * a + 2.f)));
+          ry = fminf(ry, ceilf(sqrtf(f * c + 2.f)));
+        }
+      }
+      if (valid) {
+        int x0 = (int)floorf((mx - rx) / kTileSize), x1 = (int)floorf((mx + rx) / kTileSize);
+        int y0 = (int)floorf((my - ry) / kTileSize), y1 = (int)floorf((my + ry) / kTileSize);
+        x0 = max(x0, 0);
+        y0 = max(y0, 0);
+        x1 = min(x1, cam.tiles_x - 1);
+        y1 = min(y1, cam.tiles_y - 1);
+        if (x0 > x1 || y0 > y1) valid = false;
+        if (valid) {
+          // rho = A dx^2 + B dx dy + C dy^2 with (A, B, C) = (-a/2, -b, -c/2) of the conic
+          o0 = make_float4(mx, my, -0.5f * ca, -cb);
+          o1 = make_float4(-0.5f * cc, theta, thr, z);
+          const float dn = 1.f / sqrtf((dxw * dxw + dyw * dyw) + dzw * dzw);
+          const float3 rgb = sh_colour(sh + 48 * (int64_t)node, dxw * dn, dyw * dn, dzw * dn);
+          o2 = make_float4(rgb.x, rgb.y, rgb.z, __uint_as_float((uint32_t)rx | ((uint32_t)ry << 16)));
+          r0 = (uint32_t)x0 | ((uint32_t)y0 << 16);
+          r1 = (uint32_t)x1 | ((uint32_t)y1 << 16);
+          const uint32_t area = (uint32_t)(x1 - x0 + 1) * (uint32_t)(y1 - y0 + 1);
+          if (area > kBigArea) {
+            // binned by a whole workgroup (big_count / emit_big); with the filter
+            // the count is provisional until big_count applies the tile test
+            count = area;
+            big[fetch_add(ctr + C_NBIG, 1u)] = i;
+          } else if (FILTER && relax < 0.25f) {
+            uint32_t bit = 1u;
+            for (int ty = y0; ty <= y1; ++ty)
+              for (int tx = x0; tx <= x1; ++tx, bit <<= 1)
+                if (tile_keep(o0, o1, relax, tx, ty, cam.W, cam.H)) mask |= bit;
+            count = (uint32_t)__popc(mask);
+          } else {
+            count = area;
+            mask = area == 32u ? 0xFFFFFFFFu : (1u << area) - 1u;
+          }
+          if (count == 0) valid = false;
+          else key = __float_as_uint(z);
+        }
+      }
+    }
+  }
+  if (!valid) count = mask = 0;
+  pg0[i] = o0;
+  pg1[i] = o1;
+  pg2[i] = o2;
+  prec[i] = make_uint4(r0, r1, mask, count);
+  prelax[i] = relax;
+  *count_out = count;
+  return key;
+}
+
+// Histograms of the 4 depth digits and the count of visible Gaussians, per
+// block, flushed with one atomic per non-zero bin.
+VY_DEV void project_flush(uint32_t (*s_hist)[256], uint32_t nvis, uint32_t* ctr, uint32_t* hist) {
+  for (int o = 32; o > 0; o >>= 1) nvis += __shfl_xor(nvis, o, 64);
+  if (lane() == 0 && nvis) atomicAdd(ctr + C_NVIS, nvis);
+  __syncthreads();
+  for (int i = threadIdx.x; i < 4 * 256; i += blockDim.x) {
+    const uint32_t v = (&s_hist[0][0])[i];
+    if (v) atomicAdd(hist + i, v);
+  }
+}
+
 template <bool FILTER>
 __global__ __launch_bounds__(256) void project(const int32_t* __restrict__ cut, const int32_t* n_cut_ptr,
                                                const float4* __restrict__ gauss, const float* __restrict__ sh,
@@ -178,139 +347,90 @@ __global__ __launch_bounds__(256) void project(const int32_t* __restrict__ cut, 
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     int32_t node = cut[i];
     if (node < 0 || node >= n_nodes) node = 0;
-    const float4 g0 = gauss[3 * (int64_t)node], g1 = gauss[3 * (int64_t)node + 1], g2 = gauss[3 * (int64_t)node + 2];
-    const float dxw = g0.x - cam.px, dyw = g0.y - cam.py, dzw = g0.z - cam.pz;
-    const float x = (cam.R[0] * dxw + cam.R[1] * dyw) + cam.R[2] * dzw;
-    const float y = (cam.R[3] * dxw + cam.R[4] * dyw) + cam.R[5] * dzw;
-    const float z = (cam.R[6] * dxw + cam.R[7] * dyw) + cam.R[8] * dzw;
-    bool valid = z > cam.near;
-    uint32_t count = 0, mask = 0, key = 0xFFFFFFFFu;
-    float4 o0 = make_float4(0, 0, 0, 0), o1 = make_float4(0, 0, 0, 0), o2 = make_float4(0, 0, 0, 0);
-    uint32_t r0 = 0, r1 = 0;
-    float relax = 0.f;
-    if (valid) {
-      // Sigma3 = M M^T with M = Rq diag(s)
-      const float qw = g2.x, qx = g2.y, qy = g2.z, qz = g2.w;
-      const float Rq[9] = {1.f - 2.f * (qy * qy + qz * qz), 2.f * (qx * qy - qw * qz), 2.f * (qx * qz + qw * qy),
-                           2.f * (qx * qy + qw * qz), 1.f - 2.f * (qx * qx + qz * qz), 2.f * (qy * qz - qw * qx),
-                           2.f * (qx * qz - qw * qy), 2.f * (qy * qz + qw * qx), 1.f - 2.f * (qx * qx + qy * qy)};
-      const float s[3] = {g1.x, g1.y, g1.z};
-      const float iz = 1.f / z;
-      const float u = fminf(fmaxf(x * iz, cam.ulo), cam.uhi);
-      const float v = fminf(fmaxf(y * iz, cam.vlo), cam.vhi);
-      // T = J R (2x3): rows fx/z (R0 - u R2), fy/z (R1 - v R2)
-      float T0[3], T1[3];
-      for (int k = 0; k < 3; ++k) {
-        T0[k] = (cam.fx * iz) * (cam.R[k] - u * cam.R[6 + k]);
-        T1[k] = (cam.fy * iz) * (cam.R[3 + k] - v * cam.R[6 + k]);
-      }
-      // V = T M (2x3); Sigma2 = V V^T + lowpass
-      float V0[3], V1[3];
-      for (int j = 0; j < 3; ++j) {
-        const float m0 = Rq[0 + j] * s[j], m1 = Rq[3 + j] * s[j], m2 = Rq[6 + j] * s[j];
-        V0[j] = (T0[0] * m0 + T0[1] * m1) + T0[2] * m2;
-        V1[j] = (T1[0] * m0 + T1[1] * m1) + T1[2] * m2;
-      }
-      const float a = ((V0[0] * V0[0] + V0[1] * V0[1]) + V0[2] * V0[2]) + kLowpass;
-      const float b = (V0[0] * V1[0] + V0[1] * V1[1]) + V0[2] * V1[2];
-      const float c = ((V1[0] * V1[0] + V1[1] * V1[1]) + V1[2] * V1[2]) + kLowpass;
-      const float det = fmaf(a, c, -b * b);
-      valid = det > 0.f;
-      if (valid) {
-        const float idet = 1.f / det;
-        const float ca = c * idet, cb = -b * idet, cc = a * idet;
-        const float mx = cam.fx * x * iz + cam.cx, my = cam.fy * y * iz + cam.cy;
-        const float mid = 0.5f * (a + c);
-        const float lmax = mid + sqrtf(fmaxf(0.f, mid * mid - det));
-        const float lmin = fmaxf(det / lmax, 1e-30f);
-        // per-axis extents: the ellipse d^T Sigma2^-1 d <= K^2 (outside it alpha < 1/255)
-        // lies within |dx| <= K sqrt(Sigma2_xx), |dy| <= K sqrt(Sigma2_yy)
-        float rx = fminf(ceilf(kRadiusK * sqrtf(a)), 65535.f), ry = fminf(ceilf(kRadiusK * sqrtf(c)), 65535.f);
-        const float theta = g1.w, log_theta = g0.w;
-        const float thr = cam.ln_amin - log_theta - cam.fdelta;
-        // relative rounding bound of rho for this conic (condition number based)
-        relax = 1e-6f * (lmax / lmin);
-        if (FILTER) {
-          if (thr > 0.f) valid = false;      // theta below alpha*: never blended
-          if (valid && relax < 0.25f) {
-            // outside the box of the ellipse rho >= thr every pixel has rho < thr
-            // (margins for the rounding of the conic and of the per-pixel rho)
-            const float f = 2.f * (-thr) * ((1.f + relax) / (1.f - relax)) * 1.001f;
-            rx = fminf(rx, ceilf(sqrtf(f * a + 2.f)));
-            ry = fminf(ry, ceilf(sqrtf(f * c + 2.f)));
-          }
-        }
-        if (valid) {
-          int x0 = (int)floorf((mx - rx) / kTileSize), x1 = (int)floorf((mx + rx) / kTileSize);
-          int y0 = (int)floorf((my - ry) / kTileSize), y1 = (int)floorf((my + ry) / kTileSize);
-          x0 = max(x0, 0);
-          y0 = max(y0, 0);
-          x1 = min(x1, cam.tiles_x - 1);
-          y1 = min(y1, cam.tiles_y - 1);
-          if (x0 > x1 || y0 > y1) valid = false;
-          if (valid) {
-            // rho = A dx^2 + B dx dy + C dy^2 with (A, B, C) = (-a/2, -b, -c/2) of the conic
-            o0 = make_float4(mx, my, -0.5f * ca, -cb);
-            o1 = make_float4(-0.5f * cc, theta, thr, z);
-            const float dn = 1.f / sqrtf((dxw * dxw + dyw * dyw) + dzw * dzw);
-            const float3 rgb = sh_colour(sh + 48 * (int64_t)node, dxw * dn, dyw * dn, dzw * dn);
-            o2 = make_float4(rgb.x, rgb.y, rgb.z, __uint_as_float((uint32_t)rx | ((uint32_t)ry << 16)));
-            r0 = (uint32_t)x0 | ((uint32_t)y0 << 16);
-            r1 = (uint32_t)x1 | ((uint32_t)y1 << 16);
-            const uint32_t area = (uint32_t)(x1 - x0 + 1) * (uint32_t)(y1 - y0 + 1);
-            if (area > kBigArea) {
-              // binned by a whole workgroup (big_count / emit_big); with the filter
-              // the count is provisional until big_count applies the tile test
-              count = area;
-              big[fetch_add(ctr + C_NBIG, 1u)] = (uint32_t)i;
-            } else if (FILTER && relax < 0.25f) {
-              uint32_t bit = 1u;
-              for (int ty = y0; ty <= y1; ++ty)
-                for (int tx = x0; tx <= x1; ++tx, bit <<= 1)
-                  if (tile_keep(o0, o1, relax, tx, ty, cam.W, cam.H)) mask |= bit;
-              count = (uint32_t)__popc(mask);
-            } else {
-              count = area;
-              mask = area == 32u ? 0xFFFFFFFFu : (1u << area) - 1u;
-            }
-            if (count == 0) valid = false;
-            else key = __float_as_uint(z);
-          }
-        }
-      }
-    }
-    if (!valid) count = mask = 0;
-    pg0[i] = o0;
-    pg1[i] = o1;
-    pg2[i] = o2;
-    prec[i] = make_uint4(r0, r1, mask, count);
-    prelax[i] = relax;
+    uint32_t count;
+    const uint32_t key = project_one<FILTER>((uint32_t)i, node, gauss, sh, cam, pg0, pg1, pg2, prec, prelax, ctr, big,
+                                             &count);
     dkey[i] = key;
     nvis += count > 0 ? 1u : 0u;
 #pragma unroll
     for (int p = 0; p < 4; ++p) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255u], 1u);
   }
-  // block totals
-  for (int o = 32; o > 0; o >>= 1) nvis += __shfl_xor(nvis, o, 64);
-  if (lane() == 0 && nvis) atomicAdd(ctr + C_NVIS, nvis);
-  __syncthreads();
-  for (int i = threadIdx.x; i < 4 * 256; i += blockDim.x) {
-    const uint32_t v = (&s_hist[0][0])[i];
-    if (v) atomicAdd(hist + i, v);
+  project_flush(s_hist, nvis, ctr, hist);
+}
+
+// Batched frames: counters, histograms and tile ranges cleared, and the
+// views' first batch positions (prefix sums of their cut sizes, the total
+// clamped to the context's capacity, an overflow recorded in C_GOVER).
+__global__ void batch_setup(const BView* __restrict__ views, int nv, uint32_t* __restrict__ g_off, uint32_t gcap,
+                            uint32_t* ctr, uint32_t* hist, uint2* ranges, int ntiles) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int stride = gridDim.x * blockDim.x;
+  for (int i = t; i < C_COUNT; i += stride)
+    if (i != C_GOVER) ctr[i] = 0;
+  for (int i = t; i < 6 * 256; i += stride) hist[i] = 0;
+  for (int i = t; i < ntiles; i += stride) ranges[i] = make_uint2(0, 0);
+  if (t == 0) {
+    uint64_t acc = 0;
+    for (int v = 0; v < nv; ++v) {
+      g_off[v] = (uint32_t)(acc < gcap ? acc : gcap);
+      const int32_t c = *views[v].n_cut;
+      acc += c > 0 ? (uint64_t)c : 0ull;
+    }
+    g_off[nv] = (uint32_t)(acc < gcap ? acc : gcap);
+    ctr[C_GOVER] = acc > gcap ? (uint32_t)(acc < 0xFFFFFFFFull ? acc : 0xFFFFFFFFull) : 0u;
   }
+}
+
+// Projection of the concatenated cuts of a batch of views (each Gaussian with
+// its own view's scene, camera and filter), into batch positions.
+template <bool FILTER>
+__global__ __launch_bounds__(256) void project_batch(const BView* __restrict__ views, const uint32_t* __restrict__ g_off,
+                                                     int nv, float4* __restrict__ pg0, float4* __restrict__ pg1,
+                                                     float4* __restrict__ pg2, uint4* __restrict__ prec,
+                                                     float* __restrict__ prelax, uint32_t* __restrict__ dkey,
+                                                     uint32_t* ctr, uint32_t* hist, uint32_t* __restrict__ big) {
+  __shared__ uint32_t s_hist[4][256];
+  __shared__ uint32_t s_off[kMaxViews + 1];
+  __shared__ RCam s_cam[kMaxViews];
+  for (int i = threadIdx.x; i < 4 * 256; i += blockDim.x) (&s_hist[0][0])[i] = 0;
+  for (int v = threadIdx.x; v <= nv; v += blockDim.x) s_off[v] = g_off[v];
+  for (int v = threadIdx.x; v < nv; v += blockDim.x) s_cam[v] = views[v].cam;
+  __syncthreads();
+  const uint32_t n = s_off[nv];
+  uint32_t nvis = 0;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int v = view_of(s_off, nv, i);
+    const BView& V = views[v];
+    int32_t node = V.cut[i - s_off[v]];
+    if (node < 0 || node >= V.n_nodes) node = 0;
+    uint32_t count;
+    const uint32_t key = project_one<FILTER>(i, node, V.gauss, V.sh, s_cam[v], pg0, pg1, pg2, prec, prelax, ctr, big,
+                                             &count);
+    dkey[i] = key;
+    nvis += count > 0 ? 1u : 0u;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255u], 1u);
+  }
+  project_flush(s_hist, nvis, ctr, hist);
 }
 
 // Filtered pair count of the big Gaussians: one workgroup per Gaussian, its
 // rect's tiles spread over the threads.
+template <bool BATCH>
 __global__ __launch_bounds__(256) void big_count(const uint32_t* __restrict__ big, const uint32_t* ctr,
                                                  const float4* __restrict__ pg0, const float4* __restrict__ pg1,
                                                  uint4* __restrict__ prec, const float* __restrict__ prelax,
-                                                 int W, int H, uint32_t n_g) {
+                                                 int W, int H, uint32_t n_g, ViewsRef vr) {
   __shared__ uint32_t s_red[4];
   const uint32_t nb = ctr[C_NBIG];
   for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
     const uint32_t g = big[b];
     if (g >= n_g) continue;
+    if (BATCH) {
+      const int v = view_of(vr.g_off, vr.nv, g);
+      W = vr.views[v].cam.W;
+      H = vr.views[v].cam.H;
+    }
     const uint4 r = prec[g];
     const int x0 = r.x & 0xFFFF, y0 = r.x >> 16, x1 = r.y & 0xFFFF, y1 = r.y >> 16;
     const int w = x1 - x0 + 1, area = w * (y1 - y0 + 1);
@@ -338,16 +458,25 @@ __global__ __launch_bounds__(256) void big_count(const uint32_t* __restrict__ bi
 // goes to C_NPAIRS_RAW, min(total, cap) to C_NPAIRS.
 constexpr int kScanItems = 12, kScanTile = 256 * kScanItems;   // 8, 16, 24, 32 measured slower
 
+template <bool BATCH>
 __global__ __launch_bounds__(256) void pair_emit(const uint32_t* __restrict__ sorted_val,
                                                  const uint4* __restrict__ prec, uint32_t* __restrict__ offsets,
                                                  uint32_t* ctr, uint64_t* status, uint32_t epoch, int tiles_x,
                                                  int bits0, uint32_t* __restrict__ tkey, uint32_t* __restrict__ tval,
-                                                 uint32_t* hist, uint32_t cap, uint32_t n_g) {
+                                                 uint32_t* hist, uint32_t cap, uint32_t n_g, ViewsRef vr) {
   __shared__ uint32_t s_v[kScanTile];
   __shared__ uint32_t s_scan[8], s_part;
   __shared__ uint64_t s_ex;
   __shared__ uint32_t s_hist[2][256];
+  __shared__ uint32_t s_off[BATCH ? kMaxViews + 1 : 1], s_tx[BATCH ? kMaxViews : 1], s_tb[BATCH ? kMaxViews : 1];
   for (int i = threadIdx.x; i < 512; i += blockDim.x) (&s_hist[0][0])[i] = 0;
+  if (BATCH) {
+    for (int v = threadIdx.x; v <= vr.nv; v += blockDim.x) s_off[v] = vr.g_off[v];
+    for (int v = threadIdx.x; v < vr.nv; v += blockDim.x) {
+      s_tx[v] = (uint32_t)vr.views[v].cam.tiles_x;
+      s_tb[v] = vr.views[v].tile_base;
+    }
+  }
   const uint32_t n = ctr[C_NVIS];
   const uint32_t n_parts = (n + kScanTile - 1) / kScanTile;
   const uint32_t m0 = (1u << bits0) - 1u;
@@ -397,12 +526,19 @@ __global__ __launch_bounds__(256) void pair_emit(const uint32_t* __restrict__ so
       const int x0 = r.x & 0xFFFF, y0 = r.x >> 16, w = (int)(r.y & 0xFFFF) - x0 + 1;
       const uint64_t wmask = (1ull << w) - 1ull;
       uint64_t bits = r.z;
+      int tx_n = tiles_x;
+      uint32_t tbase = 0;
+      if (BATCH) {
+        const int v = view_of(s_off, vr.nv, g);
+        tx_n = (int)s_tx[v];
+        tbase = s_tb[v];
+      }
       for (int ty = y0; bits; ++ty, bits >>= w) {
         uint32_t rb = (uint32_t)(bits & wmask);
         while (rb) {
           const int b = __ffs(rb) - 1;
           rb &= rb - 1;
-          const uint32_t t = (uint32_t)(ty * tiles_x + x0 + b);
+          const uint32_t t = tbase + (uint32_t)(ty * tx_n + x0 + b);
           if (o < cap) {
             tkey[o] = t;
             tval[o] = g;
@@ -430,13 +566,14 @@ __global__ __launch_bounds__(256) void pair_emit(const uint32_t* __restrict__ so
 
 // Pair emission of the big Gaussians: one workgroup per Gaussian; the kept
 // tiles of each 256-tile chunk are placed by a block scan (row-major order).
-template <bool FILTER>
+template <bool FILTER, bool BATCH>
 __global__ __launch_bounds__(256) void emit_big(const uint32_t* __restrict__ big, const uint32_t* __restrict__ offs,
                                                 const uint4* __restrict__ prec,
                                                 const float4* __restrict__ pg0, const float4* __restrict__ pg1,
                                                 const float* __restrict__ prelax, int W, int H, int tiles_x,
                                                 int bits0, uint32_t* __restrict__ tkey, uint32_t* __restrict__ tval,
-                                                uint32_t* ctr, uint32_t* hist, uint32_t cap, uint32_t n_g) {
+                                                uint32_t* ctr, uint32_t* hist, uint32_t cap, uint32_t n_g,
+                                                ViewsRef vr) {
   __shared__ uint32_t s_hist[2][256];
   __shared__ uint32_t s_scan[8];
   for (int i = threadIdx.x; i < 512; i += blockDim.x) (&s_hist[0][0])[i] = 0;
@@ -448,6 +585,14 @@ __global__ __launch_bounds__(256) void emit_big(const uint32_t* __restrict__ big
     if (g >= n_g) continue;
     const uint4 r = prec[g];
     if (r.w == 0) continue;   // uniform over the block
+    uint32_t tbase = 0;
+    if (BATCH) {
+      const int v = view_of(vr.g_off, vr.nv, g);
+      W = vr.views[v].cam.W;
+      H = vr.views[v].cam.H;
+      tiles_x = vr.views[v].cam.tiles_x;
+      tbase = vr.views[v].tile_base;
+    }
     const int x0 = r.x & 0xFFFF, y0 = r.x >> 16, x1 = r.y & 0xFFFF, y1 = r.y >> 16;
     const int w = x1 - x0 + 1, area = w * (y1 - y0 + 1);
     const float4 p0 = pg0[g], p1 = pg1[g];
@@ -461,7 +606,7 @@ __global__ __launch_bounds__(256) void emit_big(const uint32_t* __restrict__ big
       uint32_t tot;
       const uint32_t pos = o + block_excl_scan256(keep ? 1u : 0u, s_scan, &tot);
       if (keep && pos < cap) {
-        const uint32_t t = (uint32_t)(ty * tiles_x + tx);
+        const uint32_t t = tbase + (uint32_t)(ty * tiles_x + tx);
         tkey[pos] = t;
         tval[pos] = g;
         atomicAdd(&s_hist[0][t & m0], 1u);
@@ -1167,7 +1312,9 @@ VY_DEV void blend_band(Stage& S, int w, int tx, int ty, int band, uint32_t pb, u
   if (inside) pixel_out<SAVE>(A, cam, px, py, pb, pe, img, Tout, Nout, Eout, Lout);
 }
 
-template <bool FILTER, bool SAVE, bool LUT>
+// BATCH: the tiles are the global tiles of a batch of views (ntiles in all);
+// each job finds its view (camera, image) from the views' first tiles.
+template <bool FILTER, bool SAVE, bool LUT, bool BATCH>
 __global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ ranges, const uint32_t* __restrict__ tval,
                                                   const float4* __restrict__ pg0, const float4* __restrict__ pg1,
                                                   const float4* __restrict__ pg2, RCam cam, int ntiles,
@@ -1179,18 +1326,23 @@ __global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ rang
                                                   uint32_t n_pairs_cap, float* __restrict__ img,
                                                   float* __restrict__ Tout, int32_t* __restrict__ Nout,
                                                   int32_t* __restrict__ Eout, int32_t* __restrict__ Lout, int walk,
-                                                  int band_wgs, int lut_m) {
+                                                  int band_wgs, int lut_m, const BView* __restrict__ views, int nv) {
   __shared__ Stage S;
   __shared__ uint32_t s_job;
   __shared__ float s_lut[LUT ? kLutMax + 1 : 1];
+  __shared__ uint32_t s_toff[BATCH ? kMaxViews + 1 : 1];
   ExpLut L{s_lut, 0.f, 0};
   if (LUT) {
     // table values in double, rounded once to float
     for (int k = threadIdx.x; k <= lut_m; k += blockDim.x) s_lut[k] = (float)exp(-kLutRange * k / lut_m);
     L.scale = (float)(lut_m / kLutRange);
     L.m = lut_m;
-    __syncthreads();
   }
+  if (BATCH) {
+    for (int v = threadIdx.x; v < nv; v += blockDim.x) s_toff[v] = views[v].tile_base;
+    if (threadIdx.x == 0) s_toff[nv] = (uint32_t)ntiles;
+  }
+  if (LUT || BATCH) __syncthreads();
   uint32_t njobs = ctr[C_NJOBS];
   if (njobs > kMaxHeavy * kMaxJobsPerTile) njobs = kMaxHeavy * kMaxJobsPerTile;
   const uint32_t n0 = ctr[C_NTIER], n1 = ctr[C_NTIER + 1], n2 = ctr[C_NTIER + 2];
@@ -1211,8 +1363,17 @@ __global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ rang
       uint32_t pb = rg.x, pe = rg.y;
       if (pe > n_pairs_cap) pe = n_pairs_cap;
       if (pb > pe) pb = pe;
-      blend_band<FILTER, SAVE, LUT>(S, w, (int)tile % cam.tiles_x, (int)tile / cam.tiles_x, (int)(jb & 3u), pb, pe,
-                                    tval, pg0, pg1, pg2, n_g, cam, img, Tout, Nout, Eout, Lout, walk, L);
+      RCam vc = cam;
+      float* vimg = img;
+      uint32_t lt = tile;
+      if (BATCH) {
+        const int v = __builtin_amdgcn_readfirstlane(view_of(s_toff, nv, tile));
+        vc = views[v].cam;
+        vimg = views[v].img;
+        lt = tile - s_toff[v];
+      }
+      blend_band<FILTER, SAVE, LUT>(S, w, (int)lt % vc.tiles_x, (int)lt / vc.tiles_x, (int)(jb & 3u), pb, pe,
+                                    tval, pg0, pg1, pg2, n_g, vc, vimg, Tout, Nout, Eout, Lout, walk, L);
     }
     __builtin_amdgcn_s_setprio(0);
     return;
@@ -1272,9 +1433,18 @@ __global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ rang
     }
     if (pe > n_pairs_cap) pe = n_pairs_cap;
     if (pb > pe) pb = pe;
-    const int tx = (int)tile % cam.tiles_x, ty = (int)tile / cam.tiles_x;
+    RCam vc = cam;
+    float* vimg = img;
+    uint32_t lt = tile;
+    if (BATCH) {
+      const int v = __builtin_amdgcn_readfirstlane(view_of(s_toff, nv, tile));
+      vc = views[v].cam;
+      vimg = views[v].img;
+      lt = tile - s_toff[v];
+    }
+    const int tx = (int)lt % vc.tiles_x, ty = (int)lt / vc.tiles_x;
     const int px = tx * kTileSize + (l & 15), py = ty * kTileSize + w * 4 + (l >> 4);
-    const bool inside = px < cam.W && py < cam.H;
+    const bool inside = px < vc.W && py < vc.H;
     so.pix = (w * 4 + (l >> 4)) * kTileSize + (l & 15);   // row-major in the tile
     PixAcc A;
     pix_init(A, inside);
@@ -1294,7 +1464,7 @@ __global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ rang
       for (; A.lb < so.lbin1; ++A.lb) put_bin(so, A.lb, make_float4(0.f, 0.f, 0.f, 1.f), 0);
     } else {
       blend_range<FILTER, false, SAVE, LUT>(S, pb, pe, tval, pg0, pg1, pg2, n_g, tx, ty, fxp, fyp, A, so, walk, L);
-      if (inside) pixel_out<SAVE>(A, cam, px, py, pb, pe, img, Tout, Nout, Eout, Lout);
+      if (inside) pixel_out<SAVE>(A, vc, px, py, pb, pe, vimg, Tout, Nout, Eout, Lout);
     }
     if (urgent) __builtin_amdgcn_s_setprio(0);
     __syncthreads();
@@ -2221,6 +2391,272 @@ int vy_render_noalloc(const vy_scene* scene, const vy_cut* cut, const vy_camera*
   return VY_OK;
 }
 
+// ------------------------------------------------------ batched frames ----
+
+size_t vy_batch_workspace_bytes(int32_t max_views, int64_t max_g, int64_t max_tiles, int64_t max_pairs) {
+  if (max_views < 1 || max_views > VY_BATCH_MAX_VIEWS || max_g < 1 || max_tiles < 1 ||
+      max_tiles > VY_BATCH_MAX_TILES || max_pairs < 1)
+    return 0;
+  size_t b = 0;
+  b += (size_t)max_g * (16 * 4 + 4 * 7);
+  b += (size_t)max_pairs * 4 * 4;
+  b += (size_t)max_tiles * (8 + 16);
+  b += 64 * 4 + 6 * 256 * 4;
+  b += (size_t)status_words_for(max_g, max_pairs) * 8;
+  b += (size_t)kMaxViews * (sizeof(BView) + 4) + 4;
+  b += 32 * 256;
+  return b;
+}
+
+namespace {
+constexpr int kBatchRing = 4;
+constexpr uint32_t kBatchMagic = 0x56594254u;
+struct BatchCtx {
+  uint32_t magic;
+  RenderCtx c;              // the shared buffers (no per-pixel state, no split tiles)
+  int max_views;
+  BView* d_views;           // device descriptor of the current batch
+  uint32_t* d_goff;         // device [max_views + 1]
+  BView* h_views[kBatchRing];   // pinned host copies, one per call in a ring
+  hipEvent_t copied[kBatchRing];
+  int slot;
+};
+}  // namespace
+
+int vy_batch_ctx_create(int32_t max_views, int64_t max_g, int64_t max_tiles, int64_t max_pairs, void* ws,
+                        size_t bytes, vy_batch_ctx** out) {
+  const size_t need = vy_batch_workspace_bytes(max_views, max_g, max_tiles, max_pairs);
+  if (!ws || !out || need == 0 || max_g > 0x7FFFFFFF || max_pairs > 0x7FFFFFFF)
+    return fail(VY_ERR_ARG, "vy_batch_ctx_create: bad argument");
+  if (bytes < need) return fail(VY_ERR_ARG, "vy_batch_ctx_create: workspace %zu < %zu bytes", bytes, need);
+  BatchCtx* b = new (std::nothrow) BatchCtx();
+  if (!b) return fail(VY_ERR_ARG, "vy_batch_ctx_create: out of host memory");
+  RenderCtx* c = &b->c;
+  Carver cv(ws, bytes);
+  c->magic = kCtxMagic;
+  c->max_g = max_g;
+  c->max_pairs = max_pairs;
+  c->max_tiles = max_tiles;
+  c->pg0 = cv.take<float4>(max_g);
+  c->pg1 = cv.take<float4>(max_g);
+  c->pg2 = cv.take<float4>(max_g);
+  c->prec = cv.take<uint4>(max_g);
+  c->prelax = cv.take<float>(max_g);
+  c->big = cv.take<uint32_t>(max_g);
+  c->offsets = cv.take<uint32_t>(max_g);
+  c->dkey[0] = cv.take<uint32_t>(max_g);
+  c->dkey[1] = cv.take<uint32_t>(max_g);
+  c->dval[0] = cv.take<uint32_t>(max_g);
+  c->dval[1] = cv.take<uint32_t>(max_g);
+  c->tkey[0] = cv.take<uint32_t>(max_pairs);
+  c->tkey[1] = cv.take<uint32_t>(max_pairs);
+  c->tval[0] = cv.take<uint32_t>(max_pairs);
+  c->tval[1] = cv.take<uint32_t>(max_pairs);
+  c->ranges = cv.take<uint2>(max_tiles);
+  c->ctr = cv.take<uint32_t>(64);
+  c->hist = cv.take<uint32_t>(6 * 256);
+  c->status_words = status_words_for(max_g, max_pairs);
+  c->status = cv.take<uint64_t>(c->status_words);
+  c->tile_flag = cv.take<uint32_t>(max_tiles);
+  c->tiers = cv.take<uint32_t>(3 * max_tiles);
+  b->d_views = cv.take<BView>(kMaxViews);
+  b->d_goff = cv.take<uint32_t>(kMaxViews + 1);
+  b->max_views = max_views;
+  int rc = VY_OK;
+  if (!cv.ok()) rc = fail(VY_ERR_ARG, "vy_batch_ctx_create: workspace layout overflow");
+  for (int k = 0; k < kBatchRing && rc == VY_OK; ++k) {
+    if (hipHostMalloc((void**)&b->h_views[k], sizeof(BView) * kMaxViews, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&b->copied[k], hipEventDisableTiming) != hipSuccess)
+      rc = fail(VY_ERR_HIP, "vy_batch_ctx_create: pinned descriptor or event");
+  }
+  if (rc == VY_OK) rc = zero_on(c->status, 2 * c->status_words, nullptr);
+  if (rc == VY_OK) rc = zero_on(c->ctr, 64, nullptr);
+  if (rc == VY_OK && hipDeviceSynchronize() != hipSuccess) rc = fail(VY_ERR_HIP, "vy_batch_ctx_create: sync");
+  if (rc != VY_OK) {
+    for (int k = 0; k < kBatchRing; ++k) {
+      if (b->h_views[k]) (void)hipHostFree(b->h_views[k]);
+      if (b->copied[k]) (void)hipEventDestroy(b->copied[k]);
+    }
+    delete b;
+    return rc;
+  }
+  b->magic = kBatchMagic;
+  *out = (vy_batch_ctx*)b;
+  return VY_OK;
+}
+
+int vy_batch_ctx_free(vy_batch_ctx* ctx) {
+  BatchCtx* b = (BatchCtx*)ctx;
+  if (!b) return VY_OK;
+  if (b->magic != kBatchMagic) return fail(VY_ERR_ARG, "vy_batch_ctx_free: not a batch context");
+  b->magic = 0;
+  for (int k = 0; k < kBatchRing; ++k) {
+    (void)hipEventSynchronize(b->copied[k]);
+    (void)hipHostFree(b->h_views[k]);
+    (void)hipEventDestroy(b->copied[k]);
+  }
+  delete b;
+  return VY_OK;
+}
+
+int vy_render_batch(const vy_view* views, int32_t n, const vy_render_opts* opts, vy_batch_ctx* ctx, void* stream) {
+  BatchCtx* b = (BatchCtx*)ctx;
+  if (!b || b->magic != kBatchMagic || !views || n < 1 || n > b->max_views)
+    return fail(VY_ERR_ARG, "vy_render_batch: bad argument (n_views %d)", n);
+  if (opts && (opts->save_state || opts->split_min_pairs > 0))
+    return fail(VY_ERR_ARG, "vy_render_batch: save_state and split tiles are for single frames (vy_render)");
+  const int walk = opts ? opts->walk : 0;
+  if (walk < 0 || walk > 2) return fail(VY_ERR_ARG, "vy_render_batch: walk must be 0, 1 or 2");
+  if (opts && (opts->lut_entries < 0 || opts->lut_entries > kLutMax))
+    return fail(VY_ERR_ARG, "vy_render_batch: lut_entries must be 0..%d", kLutMax);
+  RenderCtx* c = &b->c;
+  hipStream_t st = (hipStream_t)stream;
+  const int slot = b->slot = (b->slot + 1) % kBatchRing;
+  VY_HIP(hipEventSynchronize(b->copied[slot]));   // the copy of this ring slot's last batch has been read
+  BView* hv = b->h_views[slot];
+  uint32_t tiles = 0;
+  for (int v = 0; v < n; ++v) {
+    const vy_view& q = views[v];
+    const Scene* s = (const Scene*)q.scene;
+    const Cut* ct = (const Cut*)q.cut;
+    if (!s || s->magic != kSceneMagic || !ct || ct->magic != kCutMagic || !q.image)
+      return fail(VY_ERR_ARG, "vy_render_batch: view %d: bad scene, cut or image", v);
+    if (ct->scene != s) return fail(VY_ERR_ARG, "vy_render_batch: view %d: cut belongs to another scene", v);
+    if (ct->cur < 0) return fail(VY_ERR_STATE, "vy_render_batch: view %d: cut has not been computed", v);
+    if (q.cam.width < 1 || q.cam.height < 1 || q.cam.width > 32768 || q.cam.height > 32768 || !(q.cam.fx > 0.f) ||
+        !(q.cam.fy > 0.f) || !(q.cam.znear > 0.f))
+      return fail(VY_ERR_ARG, "vy_render_batch: view %d: invalid camera", v);
+    BView& o = hv[v];
+    o.cam = make_rcam(&q.cam, opts);
+    o.gauss = s->gauss;
+    o.sh = s->sh;
+    o.cut = cut_ids_dev(ct);
+    o.n_cut = cut_count_dev(ct);
+    o.n_nodes = s->n;
+    o.img = q.image;
+    o.tile_base = tiles;
+    o.pad = 0;
+    const uint64_t t = (uint64_t)tiles + (uint64_t)o.cam.tiles_x * (uint64_t)o.cam.tiles_y;
+    if (t > (uint64_t)c->max_tiles)
+      return fail(VY_ERR_ARG, "vy_render_batch: the views' %llu tiles exceed the context's %lld",
+                  (unsigned long long)t, (long long)c->max_tiles);
+    tiles = (uint32_t)t;
+  }
+  VY_HIP(hipMemcpyAsync(b->d_views, hv, sizeof(BView) * n, hipMemcpyHostToDevice, st));
+  VY_HIP(hipEventRecord(b->copied[slot], st));
+  const bool filter = opts && opts->alpha_filter;
+  const int lut_m = opts ? opts->lut_entries : 0;
+  const int ntiles = (int)tiles;
+  const uint32_t gcap = (uint32_t)c->max_g, pcap = (uint32_t)c->max_pairs;
+  const ViewsRef vr{b->d_views, b->d_goff, n};
+  int tile_bits = 1;
+  while ((1 << tile_bits) < ntiles) ++tile_bits;
+  const int bits0 = (tile_bits + 1) / 2, bits1 = tile_bits - bits0;
+  {
+    ProfScope ps(VY_STAGE_RENDER_SETUP, st);
+    batch_setup<<<16, 256, 0, st>>>(b->d_views, n, b->d_goff, gcap, c->ctr, c->hist, c->ranges, ntiles);
+    VY_LAUNCHED();
+  }
+  {
+    ProfScope ps(VY_STAGE_PROJECT, st);
+    const int blocks = imin(cdiv(c->max_g, 256), 512);
+    if (filter)
+      project_batch<true><<<blocks, 256, 0, st>>>(b->d_views, b->d_goff, n, c->pg0, c->pg1, c->pg2, c->prec,
+                                                  c->prelax, c->dkey[0], c->ctr, c->hist, c->big);
+    else
+      project_batch<false><<<blocks, 256, 0, st>>>(b->d_views, b->d_goff, n, c->pg0, c->pg1, c->pg2, c->prec,
+                                                   c->prelax, c->dkey[0], c->ctr, c->hist, c->big);
+    VY_LAUNCHED();
+    if (filter) {
+      big_count<true><<<512, 256, 0, st>>>(c->big, c->ctr, c->pg0, c->pg1, c->prec, c->prelax, 0, 0, gcap, vr);
+      VY_LAUNCHED();
+    }
+  }
+  {
+    const int blocks = imin(cdiv(c->max_g, vysort::kTile), 256);
+    const uint32_t* n_all = b->d_goff + n;   // the batch's Gaussians
+    for (int p = 0; p < 4; ++p) {
+      ProfScope ps(VY_STAGE_DEPTH_SORT, st);
+      uint32_t ep;
+      if (int rcode = epoch_for(c, st, &ep)) return rcode;
+      const uint32_t* kin = c->dkey[p & 1];
+      const uint32_t* vin = p == 0 ? nullptr : c->dval[p & 1];
+      vysort::onesweep_pass<<<blocks, vysort::kThreads, 0, st>>>(
+          kin, vin, c->dkey[(p + 1) & 1], c->dval[(p + 1) & 1], n_all, gcap, 8 * p, 255u, 8, c->hist + 256 * p,
+          c->status, ep, c->ctr + C_TICKET0 + p, c->ctr + C_ERR);
+      VY_LAUNCHED();
+    }
+  }
+  {
+    ProfScope ps(VY_STAGE_EMIT, st);
+    uint32_t ep;
+    if (int rcode = epoch_for(c, st, &ep)) return rcode;
+    const int blocks = imin(cdiv(c->max_g, kScanTile), 512);
+    pair_emit<true><<<blocks, 256, 0, st>>>(c->dval[0], c->prec, c->offsets, c->ctr, c->status, ep, 0, bits0,
+                                            c->tkey[0], c->tval[0], c->hist, pcap, gcap, vr);
+    VY_LAUNCHED();
+    if (filter)
+      emit_big<true, true><<<512, 256, 0, st>>>(c->big, c->offsets, c->prec, c->pg0, c->pg1, c->prelax, 0, 0, 0,
+                                                bits0, c->tkey[0], c->tval[0], c->ctr, c->hist, pcap, gcap, vr);
+    else
+      emit_big<false, true><<<512, 256, 0, st>>>(c->big, c->offsets, c->prec, c->pg0, c->pg1, c->prelax, 0, 0, 0,
+                                                 bits0, c->tkey[0], c->tval[0], c->ctr, c->hist, pcap, gcap, vr);
+    VY_LAUNCHED();
+  }
+  {
+    const int blocks = imin(cdiv(c->max_pairs, vysort::kTile), 256);
+    const uint32_t* np = c->ctr + C_NPAIRS;
+    for (int p = 0; p < 2; ++p) {
+      ProfScope ps(VY_STAGE_TILE_SORT, st);
+      uint32_t ep;
+      if (int rcode = epoch_for(c, st, &ep)) return rcode;
+      const int shift = p == 0 ? 0 : bits0;
+      const int nb = p == 0 ? bits0 : bits1;
+      const uint32_t mask = nb > 0 ? ((1u << nb) - 1u) : 0u;
+      vysort::onesweep_pass<<<blocks, vysort::kThreads, 0, st>>>(
+          c->tkey[p & 1], c->tval[p & 1], c->tkey[(p + 1) & 1], c->tval[(p + 1) & 1], np, pcap, shift, mask, nb,
+          c->hist + 256 * (4 + p), c->status, ep, c->ctr + C_TICKET0 + 4 + p, c->ctr + C_ERR);
+      VY_LAUNCHED();
+    }
+  }
+  {
+    ProfScope ps(VY_STAGE_RANGES, st);
+    const int blocks = imin(cdiv(c->max_pairs, 256), 4096);
+    tile_ranges<<<blocks, 256, 0, st>>>(c->tkey[0], c->ctr, c->ranges, (uint32_t)ntiles);
+    VY_LAUNCHED();
+  }
+  const int band_wgs = walk == 0 ? kBandWGs : 0;
+  {
+    ProfScope ps(VY_STAGE_BLEND_PLAN, st);
+    plan_tiles<<<imin(cdiv(ntiles, 256), 64), 256, 0, st>>>(c->ranges, ntiles, c->tile_flag, nullptr, c->tiers,
+                                                            c->ctr, 0xFFFFFFFFu);
+    VY_LAUNCHED();
+  }
+  {
+    ProfScope ps(VY_STAGE_BLEND, st);
+    const RCam none{};
+#define VY_BLEND_BATCH(F, LT)                                                                                    \
+  blend_jobs<F, false, LT, true><<<band_wgs + 2048, 256, 0, st>>>(                                             \
+      c->ranges, c->tval[0], c->pg0, c->pg1, c->pg2, none, ntiles, c->tile_flag, c->tiers, nullptr, nullptr,    \
+      nullptr, nullptr, c->ctr, gcap, pcap, nullptr, nullptr, nullptr, nullptr, nullptr, walk, band_wgs, lut_m, \
+      b->d_views, n)
+    if (filter) {
+      if (lut_m > 0) VY_BLEND_BATCH(true, true); else VY_BLEND_BATCH(true, false);
+    } else {
+      if (lut_m > 0) VY_BLEND_BATCH(false, true); else VY_BLEND_BATCH(false, false);
+    }
+#undef VY_BLEND_BATCH
+    VY_LAUNCHED();
+  }
+  return VY_OK;
+}
+
+int vy_batch_status(vy_batch_ctx* ctx, int64_t* n_pairs, int64_t* n_visible, void* stream) {
+  BatchCtx* b = (BatchCtx*)ctx;
+  if (!b || b->magic != kBatchMagic) return fail(VY_ERR_ARG, "vy_batch_status: bad argument");
+  return vy_render_status((vy_render_ctx*)&b->c, n_pairs, n_visible, stream);
+}
+
 static int render_impl(const vy_scene* scene, const vy_cut* cut, const vy_camera* cam, const vy_render_opts* opts,
                        float* image, vy_render_ctx* ctx, void* stream) {
   const Scene* s = (const Scene*)scene;
@@ -2272,7 +2708,8 @@ static int render_impl(const vy_scene* scene, const vy_cut* cut, const vy_camera
                                              c->hist, s->n, c->big, gcap);
     VY_LAUNCHED();
     if (filter) {
-      big_count<<<512, 256, 0, st>>>(c->big, c->ctr, c->pg0, c->pg1, c->prec, c->prelax, rc.W, rc.H, gcap);
+      big_count<false><<<512, 256, 0, st>>>(c->big, c->ctr, c->pg0, c->pg1, c->prec, c->prelax, rc.W, rc.H, gcap,
+                                            ViewsRef{});
       VY_LAUNCHED();
     }
   }
@@ -2298,15 +2735,17 @@ static int render_impl(const vy_scene* scene, const vy_cut* cut, const vy_camera
     uint32_t ep;
     if (int rcode = epoch_for(c, st, &ep)) return rcode;
     const int blocks = imin(cdiv(c->max_g, kScanTile), 512);
-    pair_emit<<<blocks, 256, 0, st>>>(c->dval[0], c->prec, c->offsets, c->ctr, c->status, ep, rc.tiles_x, bits0,
-                                      c->tkey[0], c->tval[0], c->hist, pcap, gcap);
+    pair_emit<false><<<blocks, 256, 0, st>>>(c->dval[0], c->prec, c->offsets, c->ctr, c->status, ep, rc.tiles_x,
+                                             bits0, c->tkey[0], c->tval[0], c->hist, pcap, gcap, ViewsRef{});
     VY_LAUNCHED();
     if (filter)
-      emit_big<true><<<512, 256, 0, st>>>(c->big, c->offsets, c->prec, c->pg0, c->pg1, c->prelax, rc.W, rc.H,
-                                          rc.tiles_x, bits0, c->tkey[0], c->tval[0], c->ctr, c->hist, pcap, gcap);
+      emit_big<true, false><<<512, 256, 0, st>>>(c->big, c->offsets, c->prec, c->pg0, c->pg1, c->prelax, rc.W, rc.H,
+                                                 rc.tiles_x, bits0, c->tkey[0], c->tval[0], c->ctr, c->hist, pcap,
+                                                 gcap, ViewsRef{});
     else
-      emit_big<false><<<512, 256, 0, st>>>(c->big, c->offsets, c->prec, c->pg0, c->pg1, c->prelax, rc.W, rc.H,
-                                           rc.tiles_x, bits0, c->tkey[0], c->tval[0], c->ctr, c->hist, pcap, gcap);
+      emit_big<false, false><<<512, 256, 0, st>>>(c->big, c->offsets, c->prec, c->pg0, c->pg1, c->prelax, rc.W,
+                                                  rc.H, rc.tiles_x, bits0, c->tkey[0], c->tval[0], c->ctr, c->hist,
+                                                  pcap, gcap, ViewsRef{});
     VY_LAUNCHED();
   }
   {
@@ -2360,11 +2799,10 @@ static int render_impl(const vy_scene* scene, const vy_cut* cut, const vy_camera
   {
     ProfScope ps(VY_STAGE_BLEND, st);
 #define VY_BLEND_JOBS(F, S, LT)                                                                                 \
-  blend_jobs<F, S, LT><<<band_wgs + 2048, 256, 0, st>>>(c->ranges, c->tval[0], c->pg0, c->pg1, c->pg2, rc, ntiles,   \
-                                                        c->tile_flag, c->tiers, c->heavy_rec, c->jobs, c->bin_c,    \
-                                                        c->bin_n, c->ctr, gcap, pcap, image, c->T_final,           \
-                                                        c->n_contrib, c->n_eval, c->last_contrib, walk, band_wgs,  \
-                                                        lut_m)
+  blend_jobs<F, S, LT, false><<<band_wgs + 2048, 256, 0, st>>>(                                                 \
+      c->ranges, c->tval[0], c->pg0, c->pg1, c->pg2, rc, ntiles, c->tile_flag, c->tiers, c->heavy_rec, c->jobs, \
+      c->bin_c, c->bin_n, c->ctr, gcap, pcap, image, c->T_final, c->n_contrib, c->n_eval, c->last_contrib, walk,  \
+      band_wgs, lut_m, nullptr, 0)
 #define VY_BLEND(F, S)                                                                                          \
   do {                                                                                                          \
     if (lut_m > 0) VY_BLEND_JOBS(F, S, true); else VY_BLEND_JOBS(F, S, false);                                  \
