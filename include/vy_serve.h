@@ -94,7 +94,8 @@ typedef struct vy_frame_req {
                          session's own buffer (overwritten by its next frame) */
 } vy_frame_req;
 
-/* Device record written by the last kernel of every frame. */
+/* Device record written by the last kernel of every frame (for a batched
+ * frame, n_pairs, n_visible and flags 1, 2, 4 are those of its batch). */
 typedef struct vy_frame_stats {
   uint64_t image_hash;  /* sum over flat index i of the image of
                            mix64((i << 32) | bits of image[i]) modulo 2^64,
@@ -131,6 +132,20 @@ typedef struct vy_server_config {
   void* const* streams;   /* n_streams distinct hipStream_t (borrowed) */
   int32_t max_inflight;   /* frames enqueued and unfinished per stream, >= 1 */
   int32_t max_viewers;    /* sessions resident at once, >= 1 */
+  int32_t max_batch;      /* 0 or 1: every frame is its own vy_render. 2..64:
+                             frames dispatched to a stream in one scheduling
+                             pass (one per session, same alpha_filter, at most
+                             VY_BATCH_MAX_TILES tiles) are fused: their
+                             vy_lod_cut calls, then one vy_render_batch over
+                             them. Sessions then hold no render workspace:
+                             each stream has one batch context, carved from the
+                             arena for the duration of the run. */
+  int32_t reserved;       /* 0 */
+  int64_t batch_gaussians; /* capacities of each stream's batch context (cut
+                              Gaussians and pairs of all its frames together);
+                              frames of a batch that overflows them are
+                              flagged (1 or 2), not rendered again */
+  int64_t batch_pairs;
 } vy_server_config;
 
 typedef struct vy_server vy_server;

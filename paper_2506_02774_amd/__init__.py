@@ -83,7 +83,8 @@ class vy_frame_result(ctypes.Structure):
 
 class vy_server_config(ctypes.Structure):
     _fields_ = [("arena", ctypes.c_void_p), ("n_streams", ctypes.c_int32), ("streams", ctypes.POINTER(ctypes.c_void_p)),
-                ("max_inflight", ctypes.c_int32), ("max_viewers", ctypes.c_int32)]
+                ("max_inflight", ctypes.c_int32), ("max_viewers", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("batch_gaussians", ctypes.c_int64), ("batch_pairs", ctypes.c_int64)]
 
 
 VY_RUN_REALTIME = 1

@@ -2938,12 +2938,19 @@ int vy_render_projected(const vy_render_ctx* ctx, const float** rec0, const floa
 
 namespace vy {
 
+int batch_frame_finish(const vy_cut* cut, const vy_batch_ctx* batch, const float* image, int32_t width,
+                       int32_t height, void* stats, hipStream_t st) {
+  const BatchCtx* b = (const BatchCtx*)batch;
+  if (!b || b->magic != kBatchMagic) return fail(VY_ERR_ARG, "frame summary: not a batch context");
+  return render_frame_finish(cut, (const vy_render_ctx*)&b->c, image, width, height, stats, st);
+}
+
 int render_frame_finish(const vy_cut* cut, const vy_render_ctx* ctx, const float* image, int32_t width,
                         int32_t height, void* stats, hipStream_t st) {
   const Cut* ct = (const Cut*)cut;
   const RenderCtx* c = (const RenderCtx*)ctx;
   if (!ct || ct->magic != kCutMagic || !c || c->magic != kCtxMagic || !image || !stats || width < 1 ||
-      height < 1 || (int64_t)width * height > (int64_t)c->max_w * c->max_h)
+      height < 1 || width > 32768 || height > 32768)
     return fail(VY_ERR_ARG, "frame summary: bad argument");
   const uint32_t n = 3u * (uint32_t)width * (uint32_t)height;
   frame_finish<<<imin(cdiv(n, 256 * 16), 1024), 256, 0, st>>>((const uint32_t*)image, n,

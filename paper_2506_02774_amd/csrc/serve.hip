@@ -109,7 +109,10 @@ size_t render_bytes_for(const vy_session* s, int64_t max_g, int64_t max_pairs) {
   return round_up(render_workspace_bytes(max_g, s->width, s->height, max_pairs, false), kGranule);
 }
 
-bool plan_session(const vy_session* s, SessionPlan* p) {
+// `batched`: frames are rendered in batches (vy_render_batch) with the
+// stream's batch context, so the session holds no render workspace and its
+// capacities are the batch's.
+bool plan_session(const vy_session* s, SessionPlan* p, bool batched = false) {
   if (!s) return false;
   const Scene* sc = (const Scene*)s->scene;
   if (!sc || sc->magic != kSceneMagic) return false;
@@ -126,8 +129,9 @@ bool plan_session(const vy_session* s, SessionPlan* p) {
   p->cut_bytes = round_up(vy_cut_workspace_bytes(sc->n), kGranule);
   p->image_bytes = round_up((size_t)px * 3 * sizeof(float), kGranule);
   p->fixed = p->cut_bytes + p->image_bytes;
-  p->render_bytes = render_bytes_for(s, p->max_g, p->max_pairs);
-  if (!p->cut_bytes || !p->render_bytes) return false;
+  p->render_bytes = batched ? 0 : render_bytes_for(s, p->max_g, p->max_pairs);
+  if (batched) p->grow_g = p->grow_pairs = false;
+  if (!p->cut_bytes || (!batched && !p->render_bytes)) return false;
   p->total = p->fixed + p->render_bytes;
   return true;
 }
@@ -397,7 +401,7 @@ struct Runner {
           const Resident& r = res[slot];
           if (r.session < 0 || r.grow || waitq[r.session].empty()) continue;
           const int k = r.inflight > 0 ? r.stream : least;
-          if (k < 0 || (int)fl[k].size() >= max_inflight) continue;
+          if (k < 0 || (int)fl[k].size() >= max_inflight || !ex.can_take(r, k)) continue;
           const int64_t q = waitq[r.session].front();
           if (q < best_req) {
             best_req = q;
@@ -427,6 +431,8 @@ struct Runner {
         fl[best_stream].push_back(t);
         progress = true;
       }
+      // 6. enqueue what the executor gathered (batched frames)
+      if (int rc = ex.flush()) return abandon(rc);
       if (n_done == n_reqs) break;
       if (!progress) {
         const double next = next_rel < n_reqs && realtime ? reqs[next_rel].t_arrival : INFINITY;
@@ -546,6 +552,134 @@ struct HipExec {
   void drain() {
     for (int k = 0; k < n_streams; ++k) (void)hipStreamSynchronize(streams[k]);
   }
+
+  bool can_take(const Resident&, int) const { return true; }
+  int flush() { return VY_OK; }
+};
+
+// Batched frames: dispatch gathers frames per stream (one per session, one
+// alpha_filter, at most max_batch frames and VY_BATCH_MAX_TILES tiles), and a
+// gathered batch is enqueued on its stream when it is full or when the
+// stream's previous batch has finished (so that one batch runs while the next
+// one gathers the frames that arrive or become ready meanwhile): the frames'
+// searches (vy_lod_cut, each from its session's previous frontier), one
+// vy_render_batch with the stream's batch context, and the frames' records.
+// A frame's start event is recorded before its batch's searches, its done
+// event after its record; a gathered frame is not finished until then.
+struct BatchExec : HipExec {
+  struct Item {
+    Resident* r;
+    int64_t req;
+    hipEvent_t start, done;
+  };
+  int max_batch = 2;
+  std::vector<vy_batch_ctx*> bctx;        // one per stream
+  std::vector<std::vector<Item>> gather;  // per stream
+  std::vector<int> gather_filter;
+  std::vector<uint32_t> gather_tiles;
+  std::vector<int> open;                  // per stream: frames enqueued and not seen finished
+  std::vector<int> stream_of;             // per request: its stream
+  std::vector<char> enqueued;             // per request: its batch has been enqueued
+  std::vector<vy_view> views;
+
+  static uint32_t tiles_of(const vy_session& ss) {
+    return (uint32_t)(((ss.width + 15) / 16) * ((ss.height + 15) / 16));
+  }
+
+  // a session's next frame may join the stream's batch only if it has none there
+  bool can_take(const Resident& r, int k) const {
+    for (const Item& it : gather[k])
+      if (it.r == &r) return false;
+    return true;
+  }
+
+  int dispatch(Resident& r, int64_t i, int k, Ticket* t, int32_t* status) {
+    const vy_session& ss = sessions[r.session];
+    const SessionPlan& p = plans[r.session];
+    hipStream_t st = streams[k];
+    if (!r.cut && cut_create_on(ss.scene, (char*)r.mem, p.cut_bytes, st, false, &r.cut) != VY_OK) return VY_ERR_HIP;
+    if (pool->size() < 2) return fail(VY_ERR_HIP, "vy_server_run: event pool exhausted");
+    // a full batch, or one of the other filter, or too many tiles: enqueue it first
+    if (!gather[k].empty() && ((int)gather[k].size() >= max_batch || gather_filter[k] != ss.alpha_filter ||
+                               gather_tiles[k] + tiles_of(ss) > VY_BATCH_MAX_TILES))
+      if (int rc = flush_stream(k)) return rc;
+    t->start = pool->back();
+    pool->pop_back();
+    t->done = pool->back();
+    pool->pop_back();
+    gather[k].push_back(Item{&r, i, t->start, t->done});
+    gather_filter[k] = ss.alpha_filter;
+    gather_tiles[k] += tiles_of(ss);
+    stream_of[i] = k;
+    enqueued[i] = 0;
+    *status = VY_OK;
+    return VY_OK;
+  }
+
+  int poll(const Ticket& t, Outcome* o) {
+    if (!enqueued[t.req]) return 0;   // still gathering: its events are not recorded yet
+    const int rc = HipExec::poll(t, o);
+    if (rc == 1) --open[stream_of[t.req]];
+    return rc;
+  }
+
+  int flush_stream(int k) {
+    std::vector<Item>& g = gather[k];
+    if (g.empty()) return VY_OK;
+    hipStream_t st = streams[k];
+    views.clear();
+    int err = VY_OK;
+    for (const Item& it : g) VY_HIP(hipEventRecord(it.start, st));
+    // a record may hold an earlier attempt of its frame: the hash is summed into it
+    for (const Item& it : g) VY_HIP(hipMemsetAsync(stats + it.req, 0, sizeof(vy_frame_stats), st));
+    for (const Item& it : g) {
+      Resident& r = *it.r;
+      const vy_frame_req& q = reqs[it.req];
+      const vy_session& ss = sessions[r.session];
+      const int rc = vy_lod_cut(ss.scene, &q.cam, ss.tau, r.has_cut ? r.cut : nullptr, r.cut, VY_CUT_FRONTIER, st);
+      if (rc == VY_ERR_HIP) return rc;
+      if (rc != VY_OK) err = rc;
+      r.has_cut = true;
+      const SessionPlan& p = plans[r.session];
+      views.push_back(vy_view{ss.scene, r.cut, q.cam, q.image ? q.image : (float*)((char*)r.mem + p.cut_bytes)});
+    }
+    if (err == VY_OK) {
+      vy_render_opts o;
+      memset(&o, 0, sizeof(o));
+      o.alpha_filter = gather_filter[k];
+      err = vy_render_batch(views.data(), (int32_t)views.size(), &o, bctx[k], st);
+      if (err == VY_ERR_HIP) return err;
+    }
+    for (size_t j = 0; j < g.size(); ++j) {
+      const Item& it = g[j];
+      const vy_session& ss = sessions[it.r->session];
+      if (err == VY_OK) {
+        const int rc = batch_frame_finish(it.r->cut, bctx[k], views[j].image, ss.width, ss.height, stats + it.req, st);
+        if (rc != VY_OK) return rc;
+      }
+      VY_HIP(hipMemcpyAsync(host_stats + it.req, stats + it.req, sizeof(vy_frame_stats), hipMemcpyDeviceToHost, st));
+      VY_HIP(hipEventRecord(it.done, st));
+    }
+    if (err != VY_OK) return err;
+    for (const Item& it : g) enqueued[it.req] = 1;
+    open[k] += (int)g.size();
+    g.clear();
+    gather_tiles[k] = 0;
+    return VY_OK;
+  }
+
+  int flush() {
+    for (int k = 0; k < n_streams; ++k)
+      if (!gather[k].empty() && ((int)gather[k].size() >= max_batch || open[k] == 0))
+        if (int rc = flush_stream(k)) return rc;
+    return VY_OK;
+  }
+
+  void drop_render(Resident&) {}
+  void release(Resident& r) {
+    if (r.cut) vy_cut_free(r.cut);
+    r.cut = nullptr;
+  }
 };
 
 // Model: a frame keeps its stream busy for its service time; a session's
@@ -588,6 +722,8 @@ struct SimExec {
   void drop_render(Resident&) {}
   void release(Resident&) {}
   void drain() {}
+  bool can_take(const Resident&, int) const { return true; }
+  int flush() { return VY_OK; }
 
   int wait(double next_arrival, int64_t) {
     const double next_done = done_times.empty() ? INFINITY : *done_times.begin();
@@ -605,6 +741,8 @@ struct Server {
   Arena* arena = nullptr;
   std::vector<hipStream_t> streams;
   int max_inflight = 1, max_viewers = 1;
+  int max_batch = 0;
+  int64_t batch_g = 0, batch_pairs = 0;
   std::vector<hipEvent_t> pool;
   hipEvent_t t0_event = nullptr;
   RunCounters last;
@@ -615,6 +753,11 @@ int check_config(const vy_server_config* c, bool need_streams, const char* who) 
   if (c->n_streams < 1 || c->n_streams > 16) return fail(VY_ERR_ARG, "%s: n_streams must be 1..16", who);
   if (c->max_inflight < 1 || c->max_inflight > 64) return fail(VY_ERR_ARG, "%s: max_inflight must be 1..64", who);
   if (c->max_viewers < 1 || c->max_viewers > 4096) return fail(VY_ERR_ARG, "%s: max_viewers must be 1..4096", who);
+  if (c->max_batch < 0 || c->max_batch > VY_BATCH_MAX_VIEWS || c->reserved != 0)
+    return fail(VY_ERR_ARG, "%s: max_batch must be 0..%d (reserved 0)", who, VY_BATCH_MAX_VIEWS);
+  if (c->max_batch > 1 && (c->batch_gaussians < 1 || c->batch_gaussians > 0x7FFFFFFF || c->batch_pairs < 1 ||
+                           c->batch_pairs > 0x7FFFFFFF))
+    return fail(VY_ERR_ARG, "%s: batching needs batch_gaussians and batch_pairs in 1..2^31-1", who);
   if (need_streams) {
     if (!c->streams) return fail(VY_ERR_ARG, "%s: NULL streams", who);
     for (int i = 0; i < c->n_streams; ++i) {
@@ -707,6 +850,9 @@ int vy_server_create(const vy_server_config* config, vy_server** out) {
   for (int i = 0; i < config->n_streams; ++i) s->streams.push_back((hipStream_t)config->streams[i]);
   s->max_inflight = config->max_inflight;
   s->max_viewers = config->max_viewers;
+  s->max_batch = config->max_batch > 1 ? config->max_batch : 0;
+  s->batch_g = config->batch_gaussians;
+  s->batch_pairs = config->batch_pairs;
   const int n_ev = 2 * config->n_streams * config->max_inflight;
   hipError_t e = hipEventCreate(&s->t0_event);
   for (int i = 0; i < n_ev && e == hipSuccess; ++i) {
@@ -739,11 +885,21 @@ int vy_server_run(vy_server* server, const vy_session* sessions, int32_t n_sessi
   if (!s || s->magic != kServerMagic) return fail(VY_ERR_ARG, "vy_server_run: bad server");
   if (int rc = check_trace(n_sessions, reqs, n_reqs, results, "vy_server_run")) return rc;
   if (n_sessions > 0 && !sessions) return fail(VY_ERR_ARG, "vy_server_run: NULL sessions");
+  const bool batched = s->max_batch > 1;
   std::vector<SessionPlan> plans(n_sessions);
   for (int i = 0; i < n_sessions; ++i)
-    if (!plan_session(&sessions[i], &plans[i])) return fail(VY_ERR_ARG, "vy_server_run: session %d is invalid", i);
+    if (!plan_session(&sessions[i], &plans[i], batched))
+      return fail(VY_ERR_ARG, "vy_server_run: session %d is invalid", i);
   const size_t rec_bytes = round_up(sizeof(vy_frame_stats) * (size_t)std::max<int64_t>(n_reqs, 1), kGranule);
-  const size_t room = s->arena->bytes - (stats ? 0 : rec_bytes);
+  const size_t batch_bytes =
+      batched ? round_up(vy_batch_workspace_bytes(s->max_batch, s->batch_g, VY_BATCH_MAX_TILES, s->batch_pairs),
+                         kGranule)
+              : 0;
+  const size_t reserve = (stats ? 0 : rec_bytes) + batch_bytes * s->streams.size();
+  if (reserve > s->arena->bytes)
+    return fail(VY_ERR_CAPACITY, "vy_server_run: the batch contexts and records need %zu bytes, the arena has %zu",
+                reserve, s->arena->bytes);
+  const size_t room = s->arena->bytes - reserve;
   for (int64_t i = 0; i < n_reqs; ++i) {
     const vy_session& ss = sessions[reqs[i].session];
     if (reqs[i].cam.width != ss.width || reqs[i].cam.height != ss.height || reqs[i].reserved != 0)
@@ -772,7 +928,7 @@ int vy_server_run(vy_server* server, const vy_session* sessions, int32_t n_sessi
     if (own) (void)s->arena->release(own);
     return fail(VY_ERR_HIP, "vy_server_run: hipHostMalloc: %s", hipGetErrorString(e));
   }
-  HipExec ex;
+  BatchExec ex;
   ex.sessions = sessions;
   ex.plans = plans.data();
   ex.reqs = reqs;
@@ -783,20 +939,52 @@ int vy_server_run(vy_server* server, const vy_session* sessions, int32_t n_sessi
   ex.pool = &s->pool;
   ex.t0_event = s->t0_event;
   int rc = VY_OK;
-  e = hipMemsetAsync(stats, 0, sizeof(vy_frame_stats) * n_reqs, s->streams[0]);
+  // batching: one batch context per stream, carved from the arena for the run
+  std::vector<void*> bmem;
+  if (batched) {
+    ex.max_batch = s->max_batch;
+    ex.gather.assign(ns, {});
+    ex.gather_filter.assign(ns, 0);
+    ex.gather_tiles.assign(ns, 0);
+    ex.open.assign(ns, 0);
+    ex.stream_of.assign(n_reqs, 0);
+    ex.enqueued.assign(n_reqs, 0);
+    for (int k = 0; k < ns && rc == VY_OK; ++k) {
+      void* m = nullptr;
+      vy_batch_ctx* b = nullptr;
+      rc = s->arena->alloc(batch_bytes, &m);
+      if (rc == VY_OK) {
+        bmem.push_back(m);
+        rc = vy_batch_ctx_create(s->max_batch, s->batch_g, VY_BATCH_MAX_TILES, s->batch_pairs, m, batch_bytes, &b);
+      }
+      if (rc == VY_OK) ex.bctx.push_back(b);
+    }
+  }
+  if (rc == VY_OK) e = hipMemsetAsync(stats, 0, sizeof(vy_frame_stats) * n_reqs, s->streams[0]);
   for (int k = 0; k < ns && e == hipSuccess; ++k) e = hipStreamSynchronize(s->streams[k]);
   if (e == hipSuccess) e = hipEventRecord(s->t0_event, s->streams[0]);
   if (e == hipSuccess) e = hipEventSynchronize(s->t0_event);
-  if (e != hipSuccess) {
+  if (rc != VY_OK) {
+    // a batch context could not be set up: nothing ran
+  } else if (e != hipSuccess) {
     rc = fail(VY_ERR_HIP, "vy_server_run: start: %s", hipGetErrorString(e));
-  } else {
+  } else if (batched) {
     ex.t0 = host_seconds();
-    Runner<HipExec> run(ex, s->arena, ns, s->max_inflight, s->max_viewers, reqs, n_reqs, n_sessions, plans.data(),
+    Runner<BatchExec> run(ex, s->arena, ns, s->max_inflight, s->max_viewers, reqs, n_reqs, n_sessions, plans.data(),
+                          (flags & VY_RUN_REALTIME) != 0, results);
+    rc = run.run();
+    s->last = run.cnt;
+  } else {
+    HipExec& hx = ex;
+    hx.t0 = host_seconds();
+    Runner<HipExec> run(hx, s->arena, ns, s->max_inflight, s->max_viewers, reqs, n_reqs, n_sessions, plans.data(),
                         (flags & VY_RUN_REALTIME) != 0, results);
     rc = run.run();
     s->last = run.cnt;
   }
   ex.drain();
+  for (vy_batch_ctx* b : ex.bctx) (void)vy_batch_ctx_free(b);
+  for (void* m : bmem) (void)s->arena->release(m);
   (void)hipHostFree(host);
   if (own) (void)s->arena->release(own);
   return rc;

@@ -165,6 +165,9 @@ const int32_t* cut_frontier_count_dev(const Cut* c);   // |F| of the latest fron
 const uint32_t* cut_err_dev(const Cut* c);             // device-side bound hits of the last cut
 // Enqueues the kernel that writes a frame's summary record (32 bytes, see
 // vy_frame_stats in vy_serve.h): image hash, cut and pair counts, flags.
+// The same record for a frame of the last batch rendered with `batch`.
+int batch_frame_finish(const vy_cut* cut, const vy_batch_ctx* batch, const float* image, int32_t width,
+                       int32_t height, void* stats, hipStream_t st);
 int render_frame_finish(const vy_cut* cut, const vy_render_ctx* ctx, const float* image, int32_t width,
                         int32_t height, void* stats, hipStream_t st);
 

@@ -105,27 +105,44 @@ def build_requests(reqs) -> ctypes.Array:
     return arr, len(reqs)
 
 
-def _config(arena: Arena, n_streams, stream_ptrs, max_inflight, max_viewers):
+def _config(arena: Arena, n_streams, stream_ptrs, max_inflight, max_viewers, max_batch=0, batch_gaussians=0,
+            batch_pairs=0):
     c = vy_server_config()
     c.arena = arena.handle
     c.n_streams = int(n_streams)
     c.streams = stream_ptrs
     c.max_inflight = int(max_inflight)
     c.max_viewers = int(max_viewers)
+    c.max_batch = int(max_batch)
+    c.reserved = 0
+    c.batch_gaussians = int(batch_gaussians)
+    c.batch_pairs = int(batch_pairs)
     return c
 
 
-class Server:
-    """vy_server over an arena and `n_streams` torch streams of default priority."""
+def batch_capacity(max_batch):
+    """Capacities of a stream's batch context for max_batch frames of the
+    serving workload: 3.5e6 cut Gaussians and 8e6 pairs per frame (above the
+    largest measured, an 18M-leaf scene at 1920x1080)."""
+    return min(max_batch * 3_500_000, 0x7FFFFFFF), min(max_batch * 8_000_000, 0x7FFFFFFF)
 
-    def __init__(self, arena: Arena, n_streams=4, max_inflight=2, max_viewers=64):
+
+class Server:
+    """vy_server over an arena and `n_streams` torch streams of default
+    priority; max_batch > 1 fuses the frames dispatched to a stream in one
+    scheduling pass into one batched render (vy_render_batch)."""
+
+    def __init__(self, arena: Arena, n_streams=4, max_inflight=2, max_viewers=64, max_batch=0, batch_gaussians=0,
+                 batch_pairs=0):
         import torch
         L = lib()
         self.arena = arena
         self.streams = [torch.cuda.Stream() for _ in range(int(n_streams))]
         self._ptrs = (ctypes.c_void_p * len(self.streams))(*[s.cuda_stream for s in self.streams])
+        bg, bp = batch_capacity(max_batch) if max_batch > 1 else (0, 0)
+        bg, bp = batch_gaussians or bg, batch_pairs or bp
         self.config = _config(arena, len(self.streams), ctypes.cast(self._ptrs, ctypes.POINTER(ctypes.c_void_p)),
-                              max_inflight, max_viewers)
+                              max_inflight, max_viewers, max_batch, bg, bp)
         h = ctypes.c_void_p()
         check(L.vy_server_create(ctypes.byref(self.config), ctypes.byref(h)), "vy_server_create")
         self.handle = h
@@ -254,8 +271,12 @@ def main(argv=None):
     ap.add_argument("--rate", type=float, default=30.0, help="frame requests per second per viewer")
     ap.add_argument("--leaves", default="1000000,4000000,8000000,18000000", help="leaves of the resident scenes")
     ap.add_argument("--tau", type=float, default=2.0)
-    ap.add_argument("--modes", default="1x1,1x2,4x2,8x2",
-                    help="server shapes to compare, STREAMSxINFLIGHT; the first is the one-at-a-time baseline")
+    ap.add_argument("--modes", default="1x1,8x2,2x16b8,4x16b8",
+                    help="server shapes to compare, STREAMSxINFLIGHT[bBATCH]; the first is the one-at-a-time "
+                         "baseline; bBATCH fuses up to BATCH frames per stream into one batched render")
+    ap.add_argument("--sustainable-rate", type=float, default=15.0,
+                    help="a second, lighter trace (frame requests per second per viewer) that the one-at-a-time "
+                         "baseline can keep up with, for the latency comparison")
     ap.add_argument("--budget-gib", type=float, default=160.0, help="device memory for resident viewers")
     ap.add_argument("--seed", type=int, default=3000)
     args = ap.parse_args(argv)
@@ -281,29 +302,47 @@ def main(argv=None):
     arena = Arena(int(args.budget_gib * 2**30))
     reqs, n = build_requests((s, t, cam, 0) for (s, t, cam) in trace)
     arrivals = np.array([t for (_, t, _) in trace])
+    # the lighter trace: same seats and scenes, fewer requests per second
+    sessions_l, trace_l = make_trace(cfgs, args.viewers, args.seconds, args.sustainable_rate, seed=args.seed + 1)
+    sess_l = [session_struct(scenes[s["scene"]], s["width"], s["height"], args.tau, True) for s in sessions_l]
+    reqs_l, n_l = build_requests((s, t, cam, 0) for (s, t, cam) in trace_l)
+    arrivals_l = np.array([t for (_, t, _) in trace_l])
+    log(f"lighter trace: {len(sessions_l)} sessions, {n_l} frame requests at {args.sustainable_rate:g} Hz per viewer "
+        f"({n_l / args.seconds:.0f} requests/s offered)")
 
     modes = []
     for m in args.modes.split(","):
-        ns, inflight = (int(x) for x in m.lower().split("x"))
-        modes.append((f"streams={ns},inflight={inflight}", ns, inflight))
+        m = m.lower()
+        batch = 0
+        if "b" in m:
+            m, b = m.split("b")
+            batch = int(b)
+        ns, inflight = (int(x) for x in m.split("x"))
+        name = f"streams={ns},inflight={inflight}" + (f",batch={batch}" if batch > 1 else "")
+        modes.append((name, ns, inflight, batch))
     px = np.array([sessions[q]["width"] * sessions[q]["height"] for (q, _, _) in trace], np.float64)
     out = dict(viewers=args.viewers, sessions=len(sessions), frames=n, seconds=args.seconds, rate_hz=args.rate,
                scenes=[c.n_leaf for c in cfgs], scene_gib=round(node_bytes / 2**30, 2), tau=args.tau,
                resolutions=sorted({s["res"] for s in sessions}), budget_gib=args.budget_gib,
                session_mib_mean=round(float(np.mean(need)) / 2**20, 1), baseline=modes[0][0], modes={})
+    out["sustainable_trace"] = dict(rate_hz=args.sustainable_rate, sessions=len(sessions_l), frames=n_l,
+                                    offered_fps=round(n_l / args.seconds, 1))
     hashes = {}
-    for name, ns, inflight in modes:
-        srv = Server(arena, ns, inflight, args.viewers)
+    for name, ns, inflight, batch in modes:
+        srv = Server(arena, ns, inflight, args.viewers, batch)
         row = {}
-        for realtime in (False, True):
-            res, st = srv.run(sess, reqs, n, realtime=realtime, stats=True)
-            key = "realtime" if realtime else "saturated"
-            row[key] = latency_summary(res, arrivals if realtime else None)
+        for key in ("saturated", "realtime", "realtime_sustainable"):
+            realtime = key != "saturated"
+            light = key == "realtime_sustainable"
+            res, st = srv.run(sess_l if light else sess, reqs_l if light else reqs, n_l if light else n,
+                              realtime=realtime, stats=True)
+            row[key] = latency_summary(res, (arrivals_l if light else arrivals) if realtime else None)
             row[key]["frame_errors"] = int(np.count_nonzero(res["status"] != 0))
             row[key]["frames_flagged"] = {k: int(np.count_nonzero(st["flags"] & b))
                                           for k, b in (("pairs", 1), ("cut", 2), ("render_wait", 4), ("cut_wait", 8))}
             row[key].update(srv.last_run())
-            hashes[(name, key)] = st["image_hash"].copy()
+            if not light:
+                hashes[(name, key)] = st["image_hash"].copy()
             log(f"{name} {key}: {row[key]}")
             if "per_pixel" not in out:
                 # cut and pair counts per pixel, by scene and resolution
@@ -322,7 +361,7 @@ def main(argv=None):
         out["modes"][name] = row
         del srv
     base = out["modes"][modes[0][0]]["saturated"]["fps"]
-    for name, _, _ in modes:
+    for name, _, _, _ in modes:
         out["modes"][name]["saturated"]["speedup_vs_baseline"] = round(out["modes"][name]["saturated"]["fps"] / base, 3)
     ref = hashes[(modes[0][0], "saturated")]
     out["images_identical_across_modes"] = bool(all(np.array_equal(ref, h) for h in hashes.values()))

@@ -79,20 +79,30 @@ def _alone(world, sessions):
     return out
 
 
-def _serve(world, sessions, items, n_streams, inflight, budget, max_viewers, realtime):
+BATCH_G, BATCH_P = 1 << 20, 1 << 22      # batch context capacities of the batched servers here
+
+
+def _batch_bytes(vy, max_batch):
+    return int(vy.lib().vy_batch_workspace_bytes(max_batch, BATCH_G, vy.BATCH_MAX_TILES, BATCH_P) + 255) // 256 * 256
+
+
+def _serve(world, sessions, items, n_streams, inflight, budget, max_viewers, realtime, max_batch=0):
     import torch
     vy, serving, scenes, hosts, cfgs = world
     sess = [serving.session_struct(scenes[d["scene"]], d["W"], d["H"], 2.0, d["filt"]) for d in sessions]
     need = [serving.session_bytes(x) for x in sess]
     assert all(b > 0 for b in need)
-    arena = serving.Arena(budget if budget else sum(need) + (1 << 20))
+    extra = n_streams * _batch_bytes(vy, max_batch) if max_batch > 1 else 0
+    arena = serving.Arena(budget if budget else sum(need) + extra + (1 << 20))
     images = [torch.full((3, sessions[s]["H"], sessions[s]["W"]), float("nan"), device="cuda") for s, _, _ in items]
     reqs, n = serving.build_requests((s, t, sessions[s]["cams"][j], images[i].data_ptr())
                                      for i, (s, j, t) in enumerate(items))
-    srv = serving.Server(arena, n_streams, inflight, max_viewers)
+    srv = serving.Server(arena, n_streams, inflight, max_viewers, max_batch, BATCH_G, BATCH_P)
     torch.cuda.synchronize()
+    vy.profile_begin(1 << 16)        # launches by stage: one render setup per render (per batch when batched)
     res, st = srv.run(sess, reqs, n, realtime=realtime, stats=True)
     info = srv.last_run()
+    info["renders"] = vy.profile_end()["render_setup"][1]
     assert arena.stats()["n_live"] == 0
     return res, st, [im.cpu().numpy() for im in images], info, need
 
@@ -117,6 +127,44 @@ def test_served_images_equal_alone(world, n_streams, inflight, squeeze, realtime
         assert info["waited"] > 0 and info["peak_resident"] < len(sessions) and info["peak_bytes"] <= budget
     assert set(res["stream"].tolist()) <= set(range(n_streams))
     assert np.all(res["t_done"] >= res["t_start"]) and np.all(res["t_dispatch"] >= res["t_admit"])
+    for i, (s, j, t) in enumerate(items):
+        ref, nc, nf = alone[(s, j)]
+        assert np.array_equal(images[i].view(np.uint32), ref.view(np.uint32)), (s, j)
+        assert st["image_hash"][i] == host_hash(images[i]), (s, j)
+        assert st["n_cut"][i] == nc and st["n_frontier"][i] == nf, (s, j)
+        if realtime:
+            assert res["t_dispatch"][i] >= t - 1e-3
+
+
+@pytest.mark.parametrize("n_streams,inflight,batch,squeeze,realtime", [(1, 8, 8, False, False),
+                                                                       (2, 8, 4, False, True),
+                                                                       (1, 6, 3, True, False),
+                                                                       (3, 6, 3, False, False),
+                                                                       (1, 4, 2, True, True)])
+def test_batched_served_images_equal_alone(world, n_streams, inflight, batch, squeeze, realtime):
+    """Frames of several viewers fused into batched renders (one launch per
+    stage per batch): every image bitwise the viewer's own, alone. A batch is
+    enqueued when full or when its stream's previous batch has finished, so
+    frames are fused when they wait for the stream (all released at once on
+    one stream), and a lightly loaded server renders them as they come."""
+    vy, serving, scenes, hosts, cfgs = world
+    sessions, items = _trace(world, seed=11)
+    alone = _alone(world, sessions)
+    if squeeze:   # room for the batch contexts and the two largest sessions (cut workspace + image)
+        own = sorted((int(vy.lib().vy_cut_workspace_bytes(scenes[d["scene"]].n)) + 255) // 256 * 256 +
+                     (12 * d["W"] * d["H"] + 255) // 256 * 256 for d in sessions)
+        budget, max_viewers = n_streams * _batch_bytes(vy, batch) + own[-1] + own[-2] + 4096, 8
+    else:
+        budget, max_viewers = 0, 8
+    res, st, images, info, need = _serve(world, sessions, items, n_streams, inflight, budget, max_viewers, realtime,
+                                         max_batch=batch)
+    print(f"streams {n_streams} inflight {inflight} batch {batch} squeeze {squeeze}: {info}", flush=True)
+    assert not res["status"].any() and not st["flags"].any()
+    assert info["admitted"] == len(sessions)
+    if squeeze:
+        assert info["waited"] > 0 and info["peak_resident"] < len(sessions) and info["peak_bytes"] <= budget
+    if not realtime and n_streams == 1:        # frames were fused: fewer renders than frames
+        assert info["renders"] < 0.8 * len(items)
     for i, (s, j, t) in enumerate(items):
         ref, nc, nf = alone[(s, j)]
         assert np.array_equal(images[i].view(np.uint32), ref.view(np.uint32)), (s, j)

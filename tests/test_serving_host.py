@@ -286,8 +286,10 @@ def test_struct_layouts_match_the_header(tmp_path):
         "vy_frame_req": ["session", "reserved", "t_arrival", "cam", "image"],
         "vy_frame_stats": ["image_hash", "n_cut", "n_pairs", "n_visible", "flags", "n_frontier", "reserved"],
         "vy_frame_result": ["t_admit", "t_dispatch", "t_start", "t_done", "status", "stream"],
-        "vy_server_config": ["arena", "n_streams", "streams", "max_inflight", "max_viewers"],
+        "vy_server_config": ["arena", "n_streams", "streams", "max_inflight", "max_viewers", "max_batch", "reserved",
+                             "batch_gaussians", "batch_pairs"],
         "vy_camera": ["R", "pos", "fx", "fy", "cx", "cy", "width", "height", "znear"],
+        "vy_view": ["scene", "cut", "cam", "image"],
         "vy_render_opts": ["alpha_filter", "bg", "save_state", "split_min_pairs", "walk", "lut_entries"],
         "vy_grads": ["mean", "log_scale", "quat", "opacity_logit", "sh", "mean2d", "quat_raw"],
     }
