@@ -150,13 +150,49 @@ enum {
                           "Fully-Streaming LoD Tree Traversal") */
   VY_CUT_FLAT = 1,     /* full search: exhaustive test of every node (the baseline
                           exhaustive search of Section 3.2 "Cut Finding") */
-  VY_CUT_DFS = 2       /* flag, for the top-down traversal of a full or temporal
+  VY_CUT_DFS = 2,      /* flag, for the top-down traversal of a full or temporal
                           search: each thread walks its queued node's subtree
                           depth first, 4 levels per launch, instead of the
                           default workgroup-wide breadth-first walk of 13 levels
                           per launch (frontier in LDS). The cut is the same
                           either way. */
+  VY_CUT_CHUNKED = 4   /* flag: the traversal of Section 4.1 over the scene's
+                          subtree partition (vy_scene_partition): a full search
+                          streams chunks of height-2 subtrees in BFS order
+                          through LDS on persistent workgroups that take the
+                          chunks from an atomic queue; a temporal search runs
+                          Algorithm 1 per subtree (TOP: the parent subtree is
+                          searched, BOTTOM: the child subtrees). The cut is the
+                          same. Searches of one scene in this mode share the
+                          partition's per-subtree stamps and must not overlap.
+                          Not with VY_CUT_FLAT or VY_CUT_DFS. */
 };
+
+/* Subtree partition of a scene's tree for VY_CUT_CHUNKED (Section 4.1, "LoD
+ * Tree Partitioning"): the tree is split into subtrees of height 2 (a root at
+ * depth 0, 3, 6, ... with its children and grandchildren), ordered by root id
+ * (BFS order for a breadth-first numbering), their nodes stored subtree after
+ * subtree (32 bytes per node), and packed greedily into chunks of consecutive
+ * subtrees of at most 2048 nodes (64 KB of LDS), which for contiguous chunks
+ * gives the fewest chunks, the optimum of the paper's packing problem (Eq. 1
+ * and 2). Built on the host from the uploaded scene (copied back), then copied
+ * into `workspace` (DEVICE, caller-owned, >= vy_scene_partition_bytes(n_nodes)
+ * bytes) and attached to the scene until vy_scene_free or the next call.
+ * Synchronises `stream`. Errors: VY_ERR_ARG for a short workspace, a tree whose
+ * parents are not numbered before their children, a subtree of more than 64
+ * nodes (fanout above 7) or a node with more than 2047 children. */
+size_t vy_scene_partition_bytes(int64_t n_nodes);
+int vy_scene_partition(vy_scene* scene, void* workspace, size_t workspace_bytes, void* stream);
+
+/* The host half of vy_scene_partition, exposed for checking without a GPU:
+ * from HOST arrays parent, first_child, child_count [n] it writes sub_of [n]
+ * (each node's subtree), local [n] (each node's position in the subtree-major
+ * order), sub_root [n] and sub_rec [n + 1] (each subtree's root and first
+ * position; *n_sub subtrees) and chunk_sub [n + 1] (each chunk's first
+ * subtree; *n_chunks chunks). Errors as vy_scene_partition. */
+int vy_partition_plan(int64_t n, const int32_t* parent, const int32_t* first_child, const int32_t* child_count,
+                      int32_t* sub_of, int32_t* local, int64_t* n_sub, int32_t* sub_root, int32_t* sub_rec,
+                      int32_t* chunk_sub, int64_t* n_chunks);
 
 /* Computes the cut for `cam` at LoD granularity `tau` (pixels).
  * Predicate (Section 3.1): node n expands iff it has children, its AABB is not

@@ -21,7 +21,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvoyager.so")
 
 VY_OK, VY_ERR_ARG, VY_ERR_HIP, VY_ERR_CAPACITY, VY_ERR_STATE, VY_ERR_DEVICE = 0, -1, -2, -3, -4, -5
-VY_CUT_FRONTIER, VY_CUT_FLAT, VY_CUT_DFS = 0, 1, 2
+VY_CUT_FRONTIER, VY_CUT_FLAT, VY_CUT_DFS, VY_CUT_CHUNKED = 0, 1, 2, 4
 VY_WALK_FULL_EACH = 256
 STAGES = ["lod_setup", "lod_flat", "lod_classify", "lod_traverse", "lod_compact", "render_setup", "project",
           "depth_sort", "pair_scan", "emit", "tile_sort", "ranges", "blend_plan", "blend", "bwd_blend", "bwd_project"]
@@ -109,6 +109,9 @@ def lib():
         "vy_scene_upload": ([ctypes.POINTER(vy_scene_desc), P, SZ, P, ctypes.POINTER(P)], ctypes.c_int),
         "vy_scene_validate": ([P, ctypes.POINTER(I64), P], ctypes.c_int),
         "vy_scene_update_gaussians": ([P, P, P, P, P, P, P], ctypes.c_int),
+        "vy_scene_partition_bytes": ([I64], SZ),
+        "vy_scene_partition": ([P, P, SZ, P], ctypes.c_int),
+        "vy_partition_plan": ([I64, P, P, P, P, P, ctypes.POINTER(I64), P, P, P, ctypes.POINTER(I64)], ctypes.c_int),
         "vy_scene_num_nodes": ([P], I64),
         "vy_scene_free": ([P], ctypes.c_int),
         "vy_cut_workspace_bytes": ([I64], SZ),
@@ -279,6 +282,15 @@ class Scene:
                                                              ("mean", "log_scale", "quat", "opacity_logit", "sh")],
                                               _stream(stream)), "vy_scene_update_gaussians")
         self.arrays = {"sh": params["sh"]}
+
+    def partition(self, device="cuda", stream=None):
+        """vy_scene_partition: the subtree partition that VY_CUT_CHUNKED
+        searches use (its workspace is kept with the scene)."""
+        import torch
+        nb = int(lib().vy_scene_partition_bytes(self.n))
+        self.part_ws = torch.empty(nb, dtype=torch.uint8, device=device)
+        check(lib().vy_scene_partition(self.handle, ctypes.c_void_p(self.part_ws.data_ptr()), nb, _stream(stream)),
+              "vy_scene_partition")
 
     def validate(self, stream=None) -> int:
         nb = ctypes.c_int64()
@@ -534,6 +546,26 @@ def vy_render_batch(views, ctx: BatchContext, alpha_filter=False, bg=(0.0, 0.0, 
     o = _render_opts(alpha_filter, bg, False, 0, walk, lut_entries)
     check(lib().vy_render_batch(arr, n, ctypes.byref(o), ctx.handle, _stream(stream)), "vy_render_batch")
     return [v[3] for v in views]
+
+
+def partition_plan(parent, first_child, child_count):
+    """vy_partition_plan on host arrays: dict of sub_of, local, sub_root,
+    sub_rec and chunk_sub (numpy int32)."""
+    parent = np.ascontiguousarray(parent, np.int32)
+    first_child = np.ascontiguousarray(first_child, np.int32)
+    child_count = np.ascontiguousarray(child_count, np.int32)
+    n = len(parent)
+    out = {k: np.empty(n + (1 if k in ("sub_rec", "chunk_sub") else 0), np.int32)
+           for k in ("sub_of", "local", "sub_root", "sub_rec", "chunk_sub")}
+    ns, nc = ctypes.c_int64(), ctypes.c_int64()
+    ptr = lambda a: ctypes.c_void_p(a.ctypes.data)   # noqa: E731
+    check(lib().vy_partition_plan(n, ptr(parent), ptr(first_child), ptr(child_count), ptr(out["sub_of"]),
+                                  ptr(out["local"]), ctypes.byref(ns), ptr(out["sub_root"]), ptr(out["sub_rec"]),
+                                  ptr(out["chunk_sub"]), ctypes.byref(nc)), "vy_partition_plan")
+    out["sub_root"] = out["sub_root"][:ns.value]
+    out["sub_rec"] = out["sub_rec"][:ns.value + 1]
+    out["chunk_sub"] = out["chunk_sub"][:nc.value + 1]
+    return out
 
 
 # capacities of vy_render_noalloc's static scratch (vy.h)

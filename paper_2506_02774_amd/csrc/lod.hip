@@ -23,8 +23,12 @@
 // State kept per cut: the frontier F (non-expanded nodes whose ancestors all
 // expand, frustum-culled ones included) and C = F with vis. New F/C are
 // collected as bitmaps and compacted to ascending ids (canonical order).
+#include <algorithm>
+#include <climits>
 #include <cstdlib>
 #include <cstring>
+#include <new>
+#include <vector>
 
 #include "vy_common.hpp"
 
@@ -33,6 +37,8 @@
 namespace {
 
 using namespace vyd;
+using vy::kChunkNodes;
+using vy::Partition;
 
 struct LodCam {
   float4 pl[5];  // world normal (x, y, z) and offset w: inside iff n.(v - pos) >= w
@@ -558,6 +564,308 @@ __global__ __launch_bounds__(256) void lod_compact(int64_t n_words, uint32_t* __
   }
 }
 
+// ------------------------------------------------ subtree-chunk traversal ----
+//
+// Section 4.1 on a partition of the tree (Partition, built once per scene by
+// vy_scene_partition): height-2 subtrees in BFS order, stored subtree after
+// subtree, packed into chunks of consecutive subtrees of at most kChunkNodes
+// nodes. Record meta bits: [0, 8) local index of the parent within the
+// subtree (255 at the subtree's root), 8 internal node, 9 bottom node (its
+// children root other subtrees), [10, 21) the subtree's index within its
+// chunk, [21, 32) the number of children (up to 2047).
+//
+// Full search ("Fully-Streaming LoD Tree Traversal"): persistent workgroups
+// take chunks in BFS order from an atomic ticket. A chunk waits until the
+// chunks holding the parents of its subtrees are done, streams its records
+// into LDS with coalesced loads, and evaluates the subtrees that are reached
+// (the root's subtree, or one whose root's parent expands: stamped with the
+// search's epoch by the parent's chunk). Within a subtree a node is on the
+// frontier when it does not expand and its parent in the subtree does (or it
+// is the subtree's root); an expanding bottom node stamps its children's
+// subtrees as reached. The search ends as soon as every reached subtree has
+// been evaluated: a clean cut then separates the top of the tree from the
+// bottom, and the remaining chunks are skipped.
+//
+// Temporal search (Algorithm 1 per subtree): the subtrees holding the nodes of
+// the previous frontier are evaluated; a subtree whose root's parent does not
+// expand signals TOP (its local result is dropped and its parent subtree is
+// queued, once), an expanding bottom node signals BOTTOM (its children's
+// subtrees are queued, once); the others give their local frontier nodes.
+// Rounds of one launch each run until the queue is empty.
+constexpr uint32_t kMetaRootParent = 255u;
+constexpr int kChunkCtrTicket = 0, kChunkCtrReached = 1, kChunkCtrFinished = 2,
+              kChunkCtrQ = 4;   // 4..6: rotating round-queue counts
+constexpr int kMaxSubNodes = 64;   // a subtree's nodes fit a 64-bit mask (fanout <= 7)
+
+VY_DEV bool rec_expand(float4 a, float4 b, const LodCam& cam, bool& vis) {
+  const uint32_t meta = __float_as_uint(b.w);
+  const float4 a2 = make_float4(a.x, a.y, a.z, __int_as_float(((meta >> 8) & 1u) ? 0 : -1));
+  return lod_expand(a2, b, cam, vis);
+}
+
+__global__ void lod_chunk_setup(uint32_t* ctr, uint32_t* stamp, uint32_t epoch, int full) {
+  if (threadIdx.x == 0) {
+    ctr[kChunkCtrTicket] = 0;
+    ctr[kChunkCtrReached] = full ? 1u : 0u;
+    ctr[kChunkCtrFinished] = 0;
+    ctr[kChunkCtrQ] = ctr[kChunkCtrQ + 1] = ctr[kChunkCtrQ + 2] = 0;
+    if (full) stamp[0] = epoch;   // the root's subtree is reached
+  }
+}
+
+struct ChunkArgs {
+  const float4* rec;
+  const int32_t* aux;
+  const int32_t* sub_rec;
+  const int32_t* sub_up;
+  const int32_t* sub_of;
+  const int32_t* chunk_sub;
+  const int2* chunk_dep;
+  uint32_t* stamp;
+  uint32_t* done;
+  uint32_t* ctr;
+  int32_t* queue0;
+  int32_t* queue1;
+  int64_t n_chunks, n_sub;
+};
+
+__global__ __launch_bounds__(256) void lod_chunk_stream(ChunkArgs P, LodCam cam, uint32_t epoch,
+                                                        uint32_t* __restrict__ fbits, uint32_t* __restrict__ cbits,
+                                                        uint32_t* err) {
+  __shared__ float4 s_a[kChunkNodes], s_b[kChunkNodes];
+  __shared__ uint16_t s_first[kChunkNodes + 1];   // first record of each subtree of the chunk
+  __shared__ uint8_t s_flag[kChunkNodes];         // 1 evaluated, 2 expands, 4 visible, 8 emitted
+  __shared__ uint8_t s_reached[kChunkNodes];      // per subtree of the chunk
+  __shared__ uint32_t s_c, s_go, s_changed, s_any, s_eval, s_reach;
+  const uint32_t tid = threadIdx.x;
+  for (;;) {
+    if (tid == 0) {
+      s_c = fetch_add(P.ctr + kChunkCtrTicket, 1u);
+      // every reached subtree evaluated already: nothing further down is reachable
+      const uint32_t fin = ld_relaxed(P.ctr + kChunkCtrFinished);
+      __threadfence();
+      const uint32_t rea = ld_relaxed(P.ctr + kChunkCtrReached);
+      s_go = fin != rea ? 1u : 0u;
+    }
+    __syncthreads();
+    const uint32_t c = s_c;
+    if (c >= (uint32_t)P.n_chunks) break;
+    if (!s_go) {
+      if (tid == 0) st_relaxed(P.done + c, epoch);
+      break;
+    }
+    // wait for the chunks that hold the parents of this chunk's subtrees
+    if (tid == 0) {
+      const int2 dep = P.chunk_dep[c];
+      for (int d = dep.x; d <= dep.y; ++d) {
+        uint32_t spins = 0;
+        while (ld_relaxed(P.done + d) != epoch) {
+          if (++spins > (1u << 20)) {
+            fetch_add(err, 1u);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      __threadfence();
+      s_any = 0;
+      s_eval = 0;
+      s_reach = 0;
+    }
+    __syncthreads();
+    const int32_t s0 = P.chunk_sub[c], s1 = P.chunk_sub[c + 1];
+    const int32_t r0 = P.sub_rec[s0], nrec = P.sub_rec[s1] - r0;
+    for (int j = tid; j <= s1 - s0; j += blockDim.x) {
+      s_first[j] = (uint16_t)(P.sub_rec[s0 + j] - r0);
+      if (j < s1 - s0) {
+        const bool rch = ld_relaxed(P.stamp + s0 + j) == epoch;
+        s_reached[j] = rch ? 1 : 0;
+        if (rch) s_any = 1;
+      }
+    }
+    __syncthreads();
+    if (s_any) {
+      for (int k = tid; k < nrec; k += blockDim.x) {   // stream the chunk's records into LDS
+        s_a[k] = P.rec[2 * (int64_t)(r0 + k)];
+        s_b[k] = P.rec[2 * (int64_t)(r0 + k) + 1];
+        s_flag[k] = 0;
+      }
+      uint32_t my_eval = 0, my_reach = 0;
+      const int trips = (nrec + (int)blockDim.x - 1) / (int)blockDim.x;
+      // passes: a subtree reached from a parent in this chunk is evaluated in the next pass
+      for (;;) {
+        __syncthreads();
+        if (tid == 0) s_changed = 0;
+        for (int k = tid; k < nrec; k += blockDim.x) {
+          const uint32_t meta = __float_as_uint(s_b[k].w);
+          if (s_reached[(meta >> 10) & 2047u] && !(s_flag[k] & 1u)) {
+            bool vis;
+            const bool e = rec_expand(s_a[k], s_b[k], cam, vis);
+            s_flag[k] = (uint8_t)(1u | (e ? 2u : 0u) | (vis ? 4u : 0u));
+          }
+        }
+        __syncthreads();
+        for (int t = 0; t < trips; ++t) {
+          const int k = t * (int)blockDim.x + (int)tid;
+          bool em = false, em_vis = false;
+          int32_t id = 0;
+          if (k < nrec && (s_flag[k] & 9u) == 1u) {
+            s_flag[k] |= 8u;
+            const uint32_t meta = __float_as_uint(s_b[k].w);
+            const uint32_t lp = meta & 255u, j = (meta >> 10) & 2047u;
+            const bool e = (s_flag[k] & 2u) != 0;
+            if (lp == kMetaRootParent) ++my_eval;
+            const bool pe = lp == kMetaRootParent || (s_flag[s_first[j] + lp] & 2u);
+            if (!e && pe) {
+              em = true;
+              id = __float_as_int(s_a[k].w);
+              em_vis = (s_flag[k] & 4u) != 0;
+            }
+            if (e && ((meta >> 9) & 1u)) {   // BOTTOM: the children's subtrees are reached
+              const uint32_t cnt = meta >> 21;
+              const int32_t cs0 = P.aux[r0 + k];
+              for (uint32_t i = 0; i < cnt; ++i) {
+                const int32_t cs = cs0 + (int32_t)i;
+                if (cs < s1) {
+                  s_reached[cs - s0] = 1;
+                  s_changed = 1;
+                } else {
+                  st_relaxed(P.stamp + cs, epoch);
+                }
+              }
+              my_reach += cnt;
+            }
+          }
+          emit_wave(em, id, em_vis, fbits, cbits);
+        }
+        __syncthreads();
+        if (!s_changed) break;
+      }
+      if (my_eval) atomicAdd(&s_eval, my_eval);
+      if (my_reach) atomicAdd(&s_reach, my_reach);
+      __syncthreads();
+      if (tid == 0) {
+        // reached before finished: a reader that sees finished == reached sees no work left
+        __threadfence();
+        if (s_reach) fetch_add(P.ctr + kChunkCtrReached, s_reach);
+        __threadfence();
+        if (s_eval) fetch_add(P.ctr + kChunkCtrFinished, s_eval);
+      }
+    }
+    if (tid == 0) {
+      __threadfence();
+      st_relaxed(P.done + c, epoch);
+    }
+    __syncthreads();
+  }
+}
+
+// Wave-aggregated append of one id per pushing lane.
+VY_DEV void push_wave(bool push, int32_t id, int32_t* q, uint32_t* qcnt, uint32_t cap, uint32_t* err) {
+  const uint64_t m = ballot(push);
+  if (!m) return;
+  const uint32_t leader = (uint32_t)__builtin_ctzll(m);
+  uint32_t base = 0;
+  if (lane() == leader) base = fetch_add(qcnt, (uint32_t)__popcll(m));
+  base = __shfl(base, (int)leader, 64);
+  if (push) {
+    const uint32_t pos = base + (uint32_t)__popcll(m & lanemask_lt());
+    if (pos < cap) q[pos] = id;
+    else fetch_add(err, 1u);
+  }
+}
+
+// The subtrees of the previous frontier's nodes, each queued once.
+__global__ __launch_bounds__(256) void lod_sub_identify(ChunkArgs P, const int32_t* __restrict__ Fprev,
+                                                        const int32_t* n_prev_ptr, uint32_t epoch, uint32_t cap_nodes,
+                                                        uint32_t* err) {
+  const int64_t n_prev = *n_prev_ptr;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t trips = (n_prev + stride - 1) / stride;
+  for (int64_t t = 0; t < trips; ++t) {
+    const int64_t i = t * stride + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    bool push = false;
+    int32_t sid = 0;
+    if (i < n_prev) {
+      const int32_t nd = Fprev[i];
+      if (nd < 0 || (uint32_t)nd >= cap_nodes) {
+        fetch_add(err, 1u);
+      } else {
+        sid = P.sub_of[nd];
+        push = atomicExch(P.stamp + sid, epoch) != epoch;
+      }
+    }
+    push_wave(push, sid, P.queue0, P.ctr + kChunkCtrQ, (uint32_t)P.n_sub, err);
+  }
+}
+
+// One round of Algorithm 1 over queued subtrees (one thread per subtree).
+__global__ __launch_bounds__(256) void lod_sub_round(ChunkArgs P, const float4* __restrict__ lod, LodCam cam,
+                                                     uint32_t epoch, int j, int last, uint32_t* __restrict__ fbits,
+                                                     uint32_t* __restrict__ cbits, uint32_t* err) {
+  uint32_t* cnt3 = P.ctr + kChunkCtrQ;
+  const uint32_t n_in = ld_relaxed(cnt3 + (j % 3));
+  if (blockIdx.x == 0 && threadIdx.x == 0) cnt3[(j + 2) % 3] = 0;
+  uint32_t* out_cnt = cnt3 + ((j + 1) % 3);
+  const int32_t* in_q = (j & 1) ? P.queue1 : P.queue0;
+  int32_t* out_q = (j & 1) ? P.queue0 : P.queue1;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  const uint32_t trips = (n_in + stride - 1) / stride;
+  for (uint32_t t = 0; t < trips; ++t) {
+    const uint32_t i = t * stride + blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t top = -1;                 // TOP: the parent subtree to queue
+    int32_t bot_first = -1;           // BOTTOM: children's subtrees to queue, in runs
+    if (i < n_in) {
+      const int32_t sid = in_q[i];
+      const int32_t rs = P.sub_rec[sid], m = P.sub_rec[sid + 1] - rs;
+      const int32_t up = P.sub_up[sid];
+      bool clean = up < 0;
+      if (!clean) {
+        bool pvis;
+        clean = lod_expand(lod[2 * (int64_t)up], lod[2 * (int64_t)up + 1], cam, pvis);
+      }
+      if (!clean) {
+        const int32_t ps = P.sub_of[up];
+        if (atomicExch(P.stamp + ps, epoch) != epoch) top = ps;
+      } else {
+        uint64_t emask = 0;
+        for (int k = 0; k < m && k < kMaxSubNodes; ++k) {
+          const float4 a = P.rec[2 * (int64_t)(rs + k)], b = P.rec[2 * (int64_t)(rs + k) + 1];
+          const uint32_t meta = __float_as_uint(b.w);
+          const uint32_t lp = meta & 255u;
+          bool vis;
+          const bool e = rec_expand(a, b, cam, vis);
+          const bool pe = lp == kMetaRootParent || ((emask >> lp) & 1ull);
+          if (e) emask |= 1ull << k;
+          if (!e && pe) emit_node(__float_as_int(a.w), vis, fbits, cbits);
+          if (e && ((meta >> 9) & 1u)) {
+            const uint32_t cnt = meta >> 21;
+            const int32_t cs0 = P.aux[rs + k];
+            for (uint32_t q = 0; q < cnt; ++q) {
+              const int32_t cs = cs0 + (int32_t)q;
+              if (atomicExch(P.stamp + cs, epoch) != epoch) {
+                if (last) {
+                  fetch_add(err, 1u);   // deeper than the rounds cover
+                } else {
+                  const uint32_t pos = fetch_add(out_cnt, 1u);
+                  if (pos < (uint32_t)P.n_sub) out_q[pos] = cs;
+                  else fetch_add(err, 1u);
+                }
+              }
+            }
+          }
+        }
+        (void)bot_first;
+      }
+    }
+    if (last) {
+      if (top >= 0) fetch_add(err, 1u);
+    } else {
+      push_wave(top >= 0, top, out_q, out_cnt, (uint32_t)P.n_sub, err);
+    }
+  }
+}
+
 __global__ void fill_i32(int32_t* p, int64_t n, int32_t v) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = v;
@@ -683,8 +991,13 @@ int vy_lod_cut(const vy_scene* scene, const vy_camera* cam, float tau, vy_cut* p
     if (p->scene != s) return fail(VY_ERR_ARG, "vy_lod_cut: prev cut belongs to another scene");
     if (p->cur < 0) return fail(VY_ERR_STATE, "vy_lod_cut: prev cut has no frontier yet");
   }
-  if ((full_mode & ~(VY_CUT_FLAT | VY_CUT_DFS)) != 0)
+  if ((full_mode & ~(VY_CUT_FLAT | VY_CUT_DFS | VY_CUT_CHUNKED)) != 0)
     return fail(VY_ERR_ARG, "vy_lod_cut: unknown mode %d", full_mode);
+  const bool chunked = (full_mode & VY_CUT_CHUNKED) != 0;
+  if (chunked && (full_mode & (VY_CUT_FLAT | VY_CUT_DFS)) != 0)
+    return fail(VY_ERR_ARG, "vy_lod_cut: VY_CUT_CHUNKED is a traversal of its own");
+  if (chunked && !s->part)
+    return fail(VY_ERR_STATE, "vy_lod_cut: VY_CUT_CHUNKED needs the scene's partition (vy_scene_partition)");
   hipStream_t st = (hipStream_t)stream;
   const LodCam L = make_cam(cam, tau);
   const uint32_t cap = (uint32_t)s->n;
@@ -695,10 +1008,44 @@ int vy_lod_cut(const vy_scene* scene, const vy_camera* cam, float tau, vy_cut* p
   const bool dfs = (full_mode & VY_CUT_DFS) != 0;
   {
     ProfScope ps(VY_STAGE_LOD_SETUP, st);
-    lod_setup<<<1, 64, 0, st>>>(o->ctr, o->q[0], (!p && !flat) ? 1 : 0);
+    lod_setup<<<1, 64, 0, st>>>(o->ctr, o->q[0], (!p && !flat && !chunked) ? 1 : 0);
     VY_LAUNCHED();
   }
-  if (flat) {
+  if (chunked) {
+    Partition* P = s->part;
+    if (++P->epoch == 0) {   // the stamps would repeat: clear them (once in 2^32 searches)
+      VY_HIP(hipMemsetAsync(P->stamp, 0, sizeof(uint32_t) * P->n_nodes, st));
+      VY_HIP(hipMemsetAsync(P->done, 0, sizeof(uint32_t) * P->n_nodes, st));
+      P->epoch = 1;
+    }
+    const ChunkArgs A{P->rec, P->aux, P->sub_rec, P->sub_up, P->sub_of, P->chunk_sub, P->chunk_dep, P->stamp,
+                      P->done, P->ctr, P->queue[0], P->queue[1], P->n_chunks, P->n_sub};
+    {
+      ProfScope ps(VY_STAGE_LOD_SETUP, st);
+      lod_chunk_setup<<<1, 64, 0, st>>>(P->ctr, P->stamp, P->epoch, p ? 0 : 1);
+      VY_LAUNCHED();
+    }
+    if (!p) {
+      ProfScope ps(VY_STAGE_LOD_TRAVERSE, st);
+      // persistent workgroups (two fit a CU with 72 KB of LDS each)
+      const int blocks = (int)(P->n_chunks < 512 ? P->n_chunks : 512);
+      lod_chunk_stream<<<blocks, 256, 0, st>>>(A, L, P->epoch, o->fbits, o->cbits, o->ctr + kErr);
+      VY_LAUNCHED();
+    } else {
+      {
+        ProfScope ps(VY_STAGE_LOD_CLASSIFY, st);
+        lod_sub_identify<<<2048, 256, 0, st>>>(A, p->F[src], p->counts + src, P->epoch, cap, o->ctr + kErr);
+        VY_LAUNCHED();
+      }
+      const int blocks = (int)((P->n_sub + 255) / 256 < 2048 ? (P->n_sub + 255) / 256 : 2048);
+      for (int j = 0; j < P->max_rounds; ++j) {
+        ProfScope ps(VY_STAGE_LOD_TRAVERSE, st);
+        lod_sub_round<<<blocks, 256, 0, st>>>(A, s->lod, L, P->epoch, j, j + 1 == P->max_rounds, o->fbits, o->cbits,
+                                              o->ctr + kErr);
+        VY_LAUNCHED();
+      }
+    }
+  } else if (flat) {
     ProfScope ps(VY_STAGE_LOD_FLAT, st);
     const int64_t waves = (s->n + 63) / 64;
     const int64_t blocks = (waves + 3) / 4 < 65536 ? (waves + 3) / 4 : 65536;
@@ -747,6 +1094,201 @@ int vy_lod_cut(const vy_scene* scene, const vy_camera* cam, float tau, vy_cut* p
   }
   o->cur = dst;
   ++o->version;
+  return VY_OK;
+}
+
+static inline int32_t bits_i(float f) {
+  int32_t i;
+  memcpy(&i, &f, 4);
+  return i;
+}
+static inline float bits_f(uint32_t u) {
+  float f;
+  memcpy(&f, &u, 4);
+  return f;
+}
+
+size_t vy_scene_partition_bytes(int64_t n) {
+  if (n < 1) return 0;
+  return (size_t)n * (32 + 4 * 4 + 4 + 8 + 4 * 2 + 4 * 2) + 3 * 4 * 256 + 64 * 4 + 16 * 256;
+}
+
+int vy_partition_plan(int64_t n, const int32_t* parent, const int32_t* first_child, const int32_t* child_count,
+                      int32_t* sub_of, int32_t* local, int64_t* n_sub_out, int32_t* sub_root, int32_t* sub_rec,
+                      int32_t* chunk_sub, int64_t* n_chunks_out) {
+  if (n < 1 || !parent || !first_child || !child_count || !sub_of || !local || !n_sub_out || !sub_root ||
+      !sub_rec || !chunk_sub || !n_chunks_out)
+    return fail(VY_ERR_ARG, "vy_partition_plan: bad argument");
+  if (parent[0] != -1) return fail(VY_ERR_ARG, "vy_partition_plan: node 0 must be the root");
+  std::vector<int32_t> depth(n, 0), root_of(n, 0);
+  for (int64_t i = 1; i < n; ++i) {
+    const int32_t p = parent[i];
+    if (p < 0 || p >= i) return fail(VY_ERR_ARG, "vy_partition_plan: parents must be numbered before children");
+    depth[i] = depth[p] + 1;
+  }
+  // subtree roots at depths 0, 3, 6, ...; subtree ids by ascending root id (BFS order)
+  int64_t n_sub = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (depth[i] % 3 == 0) {
+      root_of[i] = (int32_t)i;
+      sub_of[i] = (int32_t)n_sub;
+      sub_root[n_sub++] = (int32_t)i;
+    } else {
+      root_of[i] = root_of[parent[i]];
+      sub_of[i] = sub_of[root_of[i]];
+    }
+  }
+  // nodes of each subtree in local BFS order (root, children, grandchildren)
+  int64_t r = 0;
+  for (int64_t s = 0; s < n_sub; ++s) {
+    sub_rec[s] = (int32_t)r;
+    int32_t list[kMaxSubNodes];
+    int m = 0;
+    list[m++] = sub_root[s];
+    for (int h = 0; h < m; ++h) {
+      const int32_t v = list[h];
+      if (depth[v] - depth[sub_root[s]] >= 2) continue;
+      for (int32_t k = 0; k < child_count[v]; ++k) {
+        const int32_t c = first_child[v] + k;
+        if (c <= v || c >= n || parent[c] != v) return fail(VY_ERR_ARG, "vy_partition_plan: bad child link");
+        if (m >= kMaxSubNodes) return fail(VY_ERR_ARG, "vy_partition_plan: a subtree exceeds %d nodes", kMaxSubNodes);
+        list[m++] = c;
+      }
+    }
+    for (int h = 0; h < m; ++h) local[list[h]] = (int32_t)(r + h);
+    r += m;
+  }
+  if (r != n) return fail(VY_ERR_ARG, "vy_partition_plan: the subtrees do not cover the tree");
+  sub_rec[n_sub] = (int32_t)r;
+  // greedy packing of consecutive subtrees into chunks of at most kChunkNodes
+  // nodes: the fewest chunks under the contiguity constraint
+  int64_t nc = 0, used = 0;
+  for (int64_t s = 0; s < n_sub; ++s) {
+    const int64_t sz = sub_rec[s + 1] - sub_rec[s];
+    if (nc == 0 || used + sz > kChunkNodes) {
+      chunk_sub[nc++] = (int32_t)s;
+      used = 0;
+    }
+    used += sz;
+  }
+  chunk_sub[nc] = (int32_t)n_sub;
+  *n_sub_out = n_sub;
+  *n_chunks_out = nc;
+  return VY_OK;
+}
+
+int vy_scene_partition(vy_scene* scene, void* ws, size_t bytes, void* stream) {
+  Scene* s = (Scene*)scene;
+  if (!s || s->magic != kSceneMagic || !ws) return fail(VY_ERR_ARG, "vy_scene_partition: bad argument");
+  const int64_t n = s->n;
+  if (bytes < vy_scene_partition_bytes(n))
+    return fail(VY_ERR_ARG, "vy_scene_partition: workspace %zu < %zu bytes", bytes, vy_scene_partition_bytes(n));
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<float4> lod(2 * n);
+  std::vector<int32_t> cc(n);
+  VY_HIP(hipMemcpyAsync(lod.data(), s->lod, sizeof(float4) * 2 * n, hipMemcpyDeviceToHost, st));
+  VY_HIP(hipMemcpyAsync(cc.data(), s->ccount, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+  VY_HIP(hipStreamSynchronize(st));
+  std::vector<int32_t> parent(n), fc(n), sub_of(n), local(n), sub_root(n), sub_rec(n + 1), chunk_sub(n + 1);
+  for (int64_t i = 0; i < n; ++i) {
+    parent[i] = bits_i(lod[2 * i + 1].w);
+    fc[i] = bits_i(lod[2 * i].w);
+  }
+  int64_t n_sub = 0, n_chunks = 0;
+  if (int rc = vy_partition_plan(n, parent.data(), fc.data(), cc.data(), sub_of.data(), local.data(), &n_sub,
+                                 sub_root.data(), sub_rec.data(), chunk_sub.data(), &n_chunks))
+    return rc;
+  std::vector<int32_t> chunk_of(n_sub);
+  for (int64_t c = 0; c < n_chunks; ++c)
+    for (int32_t q = chunk_sub[c]; q < chunk_sub[c + 1]; ++q) chunk_of[q] = (int32_t)c;
+  // records, subtree by subtree
+  std::vector<float4> rec(2 * n);
+  std::vector<int32_t> aux(n, -1), sub_up(n_sub);
+  std::vector<int2> dep(n_chunks);
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t k = local[i];
+    const int32_t q = sub_of[i], root = sub_root[q];
+    uint32_t lp = kMetaRootParent;
+    if (i != root) lp = (uint32_t)(local[parent[i]] - sub_rec[q]);
+    int d = 0;
+    for (int32_t v = (int32_t)i; v != root; v = parent[v]) ++d;
+    const bool internal = cc[i] > 0, bottom = internal && d == 2;
+    const uint32_t meta = lp | (internal ? 1u << 8 : 0u) | (bottom ? 1u << 9 : 0u) |
+                          ((uint32_t)(q - chunk_sub[chunk_of[q]]) << 10) |
+                          ((uint32_t)(cc[i] < 2047 ? cc[i] : 2047) << 21);
+    if (cc[i] > 2047) return fail(VY_ERR_ARG, "vy_scene_partition: a node has more than 2047 children");
+    const float4 a = lod[2 * i], b = lod[2 * i + 1];
+    rec[2 * k] = make_float4(a.x, a.y, a.z, bits_f((uint32_t)i));
+    rec[2 * k + 1] = make_float4(b.x, b.y, b.z, bits_f(meta));
+    if (bottom) aux[k] = sub_of[fc[i]];
+  }
+  int sub_levels = 1;
+  for (int64_t q = 0; q < n_sub; ++q) {
+    const int32_t root = sub_root[q];
+    sub_up[q] = parent[root];
+    if (q > 0) {
+      int d = 0;
+      for (int32_t v = root; v > 0; v = parent[v]) ++d;
+      sub_levels = std::max(sub_levels, d / 3 + 1);
+    }
+  }
+  for (int64_t c = 0; c < n_chunks; ++c) {
+    int lo = INT32_MAX, hi = -1;
+    for (int32_t q = chunk_sub[c]; q < chunk_sub[c + 1]; ++q) {
+      if (sub_up[q] < 0) continue;
+      const int32_t pc = chunk_of[sub_of[sub_up[q]]];
+      if (pc == c) continue;
+      lo = std::min(lo, pc);
+      hi = std::max(hi, pc);
+    }
+    dep[c] = hi < 0 ? make_int2(0, -1) : make_int2(lo, hi);
+  }
+  Partition* P = s->part ? s->part : new (std::nothrow) Partition();
+  if (!P) return fail(VY_ERR_ARG, "vy_scene_partition: out of host memory");
+  Carver cv(ws, bytes);
+  P->n_sub = n_sub;
+  P->n_chunks = n_chunks;
+  P->n_nodes = n;
+  P->rec = cv.take<float4>(2 * n);
+  P->aux = cv.take<int32_t>(n);
+  P->sub_of = cv.take<int32_t>(n);
+  P->sub_rec = cv.take<int32_t>(n + 1);
+  P->sub_up = cv.take<int32_t>(n);
+  P->chunk_sub = cv.take<int32_t>(n + 1);
+  P->chunk_dep = cv.take<int2>(n);
+  P->stamp = cv.take<uint32_t>(n);
+  P->done = cv.take<uint32_t>(n);
+  P->queue[0] = cv.take<int32_t>(n);
+  P->queue[1] = cv.take<int32_t>(n);
+  P->ctr = cv.take<uint32_t>(64);
+  P->epoch = 0;
+  P->max_rounds = 2 * sub_levels + 2;
+  int rc = VY_OK;
+  if (!cv.ok()) rc = fail(VY_ERR_ARG, "vy_scene_partition: workspace layout overflow");
+  hipError_t e = hipSuccess;
+  if (rc == VY_OK) {
+    e = hipMemcpyAsync(P->rec, rec.data(), sizeof(float4) * 2 * n, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(P->aux, aux.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(P->sub_of, sub_of.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(P->sub_rec, sub_rec.data(), sizeof(int32_t) * (n_sub + 1), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(P->sub_up, sub_up.data(), sizeof(int32_t) * n_sub, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(P->chunk_sub, chunk_sub.data(), sizeof(int32_t) * (n_chunks + 1), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(P->chunk_dep, dep.data(), sizeof(int2) * n_chunks, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemsetAsync(P->stamp, 0, sizeof(uint32_t) * n, st);
+    if (e == hipSuccess) e = hipMemsetAsync(P->done, 0, sizeof(uint32_t) * n, st);
+    if (e == hipSuccess) e = hipMemsetAsync(P->ctr, 0, 64 * 4, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) rc = fail(VY_ERR_HIP, "vy_scene_partition: %s", hipGetErrorString(e));
+  }
+  if (rc != VY_OK) {
+    if (!s->part) delete P;
+    return rc;
+  }
+  s->part = P;
   return VY_OK;
 }
 

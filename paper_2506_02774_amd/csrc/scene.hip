@@ -209,6 +209,7 @@ int vy_scene_free(vy_scene* scene) {
   if (!s) return VY_OK;
   if (s->magic != kSceneMagic) return fail(VY_ERR_ARG, "vy_scene_free: not a scene");
   s->magic = 0;
+  delete s->part;
   free(s);
   return VY_OK;
 }

@@ -76,6 +76,29 @@ struct Scene {
   int levels;        // tree depth + 1 (computed at upload)
   int32_t* scratch;  // small device scratch for validate
   uint64_t params_version;  // bumped by each vy_scene_update_gaussians
+  struct Partition* part;   // subtree partition (vy_scene_partition), or null
+};
+
+// Height-2 subtrees of the LoD tree (a root at depth 0, 3, 6, ... with its
+// children and grandchildren) in BFS order of their roots, their nodes stored
+// subtree after subtree, and chunks of consecutive subtrees of at most
+// kChunkNodes nodes (Section 4.1, "LoD Tree Partitioning").
+constexpr int kChunkNodes = 2048;
+struct Partition {
+  int64_t n_sub, n_chunks, n_nodes;
+  float4* rec;          // 2 per node, subtree-major: {lo.xyz, node id}, {hi.xyz, meta}
+  int32_t* aux;         // per record: first child subtree (bottom internal nodes), else -1
+  int32_t* sub_of;      // per node: its subtree
+  int32_t* sub_rec;     // per subtree: first record [n_sub + 1]
+  int32_t* sub_up;      // per subtree: the tree parent of its root (-1 at the top)
+  int32_t* chunk_sub;   // per chunk: first subtree [n_chunks + 1]
+  int2* chunk_dep;      // per chunk: the range of earlier chunks holding parents of its subtrees
+  uint32_t* stamp;      // per subtree: search epoch when reached or visited
+  uint32_t* done;       // per chunk: search epoch when streamed
+  int32_t* queue[2];    // subtree queues of the temporal rounds [n_sub each]
+  uint32_t* ctr;        // device counters
+  uint32_t epoch;       // host: last search epoch
+  int max_rounds;       // subtree levels + 1
 };
 
 struct Cut {

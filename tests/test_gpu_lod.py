@@ -158,3 +158,67 @@ def test_errors(tiny):
     assert e.value.code == vy.VY_ERR_ARG
     with pytest.raises(vy.VoyagerError):
         vy.vy_lod_cut(sc, cam, -1.0)
+
+
+def _same(a, b):
+    return np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_chunked_traversal_agrees(tiny):
+    """VY_CUT_CHUNKED (Section 4.1: streamed chunks of height-2 subtrees for a
+    full search, Algorithm 1 per subtree with TOP/BOTTOM for a temporal one)
+    gives the default cut bit for bit: full searches, temporal searches along
+    camera changes, and temporal searches from arbitrary frontiers."""
+    vy, sc, host = tiny
+    sc.partition()
+    C = vy.VY_CUT_CHUNKED
+    cams = random_cameras(scenegen.CONFIGS["tiny"], 6, 41)
+    for cam in cams:
+        for tau in (0.0, 0.7, 2.0, 16.0, 1e30):
+            assert _same(vy.vy_lod_cut(sc, cam, tau, mode=C).ids(), vy.vy_lod_cut(sc, cam, tau).ids()), tau
+    q = vy.vy_lod_cut(sc, cams[0], 2.0, mode=C)
+    for cam in cams[1:] + cams[:2]:
+        q = vy.vy_lod_cut(sc, cam, 2.0, prev=q, out=q, mode=C)
+        assert _same(q.ids(), vy.vy_lod_cut(sc, cam, 2.0).ids())
+    leaves = np.nonzero(host.child_count == 0)[0]
+    seeds = {"root": np.array([0]), "leaves": leaves, "other": vy.vy_lod_cut(sc, cams[0], 7.0).ids()[0]}
+    for name, F0 in seeds.items():
+        for cam in cams[1:4]:
+            for tau in (0.5, 2.0, 9.0):
+                st = vy.Cut(sc)
+                st.set_frontier(F0)
+                out = vy.vy_lod_cut(sc, cam, tau, prev=st, mode=C)
+                assert _same(out.ids(), vy.vy_lod_cut(sc, cam, tau).ids()), (name, tau)
+
+
+def test_chunked_traversal_on_a_larger_city():
+    vy = require_gpu()
+    cfg = scenegen.scaled_config("med", 200_000)
+    host = scenegen.make_city(cfg)
+    sc = vy.Scene(host)
+    sc.partition()
+    cams = scenegen.walkthrough(cfg, frames=12, width=640, height=360)
+    state = None
+    for i, cam in enumerate(cams):
+        state = vy.vy_lod_cut(sc, cam, 2.0, prev=state, out=state, mode=vy.VY_CUT_CHUNKED) if state is not None \
+            else vy.vy_lod_cut(sc, cam, 2.0, mode=vy.VY_CUT_CHUNKED)
+        a = state.ids()
+        b = vy.vy_lod_cut(sc, cam, 2.0).ids()
+        c = vy.vy_lod_cut(sc, cam, 2.0, mode=vy.VY_CUT_CHUNKED).ids()
+        assert _same(a, b) and _same(b, c), i
+
+
+def test_chunked_mode_errors(tiny):
+    vy, sc, host = tiny
+    cam = scenegen.identity_camera(32, 32)
+    fresh = vy.Scene(scenegen.make_city(scenegen.scaled_config("tiny", 500)))
+    with pytest.raises(vy.VoyagerError) as e:          # no partition
+        vy.vy_lod_cut(fresh, cam, 1.0, mode=vy.VY_CUT_CHUNKED)
+    assert e.value.code == vy.VY_ERR_STATE
+    with pytest.raises(vy.VoyagerError) as e:
+        vy.vy_lod_cut(sc, cam, 1.0, mode=vy.VY_CUT_CHUNKED | vy.VY_CUT_DFS)
+    assert e.value.code == vy.VY_ERR_ARG
+    one = vy.Scene(scenegen.tree_from_arrays([-1], [-1], [0], [[-1, -1, 4]], [[1, 1, 6]], mean=[[0, 0, 5]]))
+    one.partition()
+    F, C = vy.vy_lod_cut(one, scenegen.identity_camera(32, 32), 1.0, mode=vy.VY_CUT_CHUNKED).ids()
+    assert F.tolist() == [0] and C.tolist() == [0]
