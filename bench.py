@@ -281,11 +281,32 @@ def main():
             ablation[f"tau={tau:g}"] = row
             log(f"ablation tau={tau:g}: " + ", ".join(f"{k} {v['fps']:.0f}" for k, v in row.items()))
 
-    # --------- LoD traversal: workgroup breadth-first (default) vs per-thread depth-first
+    # --------- LoD traversal: workgroup breadth-first (default), per-thread depth-first,
+    # and the subtree-chunk traversal of Section 4.1 over the scene's partition
     traversal = {}
+    t0p = time.perf_counter()
+    scene.partition()
+    torch.cuda.synchronize()
+    traversal["partition_build_s"] = round(time.perf_counter() - t0p, 2)
+    log(f"subtree partition built in {traversal['partition_build_s']} s")
+    # the chunked searches give the default cut on every frame (temporal and full)
+    chk = dict(frames=0, mismatch=0)
+    a_cut, b_cut = vy.Cut(scene), vy.Cut(scene)
+    for i, cam in enumerate(cams):
+        vy.vy_lod_cut(scene, cam, args.tau, prev=a_cut if i else None, out=a_cut, mode=vy.VY_CUT_CHUNKED)
+        vy.vy_lod_cut(scene, cam, args.tau, out=b_cut)
+        fa, fb = a_cut.ids(), b_cut.ids()
+        chk["mismatch"] += 0 if (np.array_equal(fa[0], fb[0]) and np.array_equal(fa[1], fb[1])) else 1
+        if i % 10 == 0:
+            fc = vy.vy_lod_cut(scene, cam, args.tau, out=b_cut, mode=vy.VY_CUT_CHUNKED).ids()
+            chk["mismatch"] += 0 if (np.array_equal(fc[0], fb[0]) and np.array_equal(fc[1], fb[1])) else 1
+        chk["frames"] += 1
+    del a_cut, b_cut
+    traversal["chunked_equals_default"] = chk
+    log(f"chunked traversal == default: {chk}")
     for name, temporal, filt in (("temporal+filter", True, True), ("full+unfiltered", False, False)):
         row = {}
-        for tname, mode in (("bfs", 0), ("dfs", vy.VY_CUT_DFS)):
+        for tname, mode in (("bfs", 0), ("dfs", vy.VY_CUT_DFS), ("chunked", vy.VY_CUT_CHUNKED)):
             r = timed(vy, torch, scene, cams, args.tau, temporal, filt, state, full_cut, ctx, img, mode=mode)
             vy.profile_begin(64 * K + 64)
             frame_loop(vy, torch, scene, cams, args.tau, temporal, filt, state, full_cut, ctx, img, per_frame=False,
