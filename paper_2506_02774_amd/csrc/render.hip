@@ -857,6 +857,7 @@ __global__ __launch_bounds__(256) void plan_heavy(const uint2* __restrict__ rang
 // e^(-5.55 k / m), k = 0..m, over the effective range [-5.55, 0] of rho, read
 // at the nearest node, index round(rho / -5.55 * m) (clamped to m; alpha is
 // below alpha* there for theta <= 1). The table lives in LDS.
+constexpr int kTransposedMax = 4;   // live pixels of a band at most for the entry-parallel walk
 constexpr int kLutMax = 128;
 constexpr double kLutRange = 5.55;
 struct ExpLut {
@@ -1039,6 +1040,106 @@ VY_DEV void blend_sparse(const Stage& S, int w, int jj, uint64_t mk, uint32_t b0
   }
 }
 
+// Few pixels of the band still blend (the tail of a long list, where most
+// pixels have stopped): each such pixel in turn, the lanes evaluate the
+// chunk's entries [jj, jj + m) at that pixel in parallel, one entry per lane
+// (pixel rule, rho, Eq. 4, alpha: the float operations of the per-pixel walk),
+// and the pixel's sequential blend then runs over the entries that pass, in
+// list order, on wave-uniform copies of its state (the same operations in the
+// same order as blend_sparse: bitwise the same result).
+VY_DEV float rl(float v, int k) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k)); }
+VY_DEV uint32_t rl(uint32_t v, int k) { return (uint32_t)__builtin_amdgcn_readlane((int)v, k); }
+VY_DEV int32_t rl(int32_t v, int k) { return __builtin_amdgcn_readlane(v, k); }
+
+template <bool FILTER, bool SAVE, bool LUT>
+VY_DEV void blend_transposed(const Stage& S, int w, int jj, int m, uint32_t b0, float fxp, float fyp, PixAcc& A,
+                             const ExpLut& L) {
+  const int l = (int)(threadIdx.x & 63);
+  float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0, q2 = q0;
+  uint32_t e = 0;
+  if (l < m) {
+    e = S.list[w][jj + l];
+    q0 = S.r0[w][jj + l];
+    q1 = S.r1[w][jj + l];
+    q2 = S.r2[w][jj + l];
+  }
+  uint64_t alive = __ballot(!A.done);
+  while (alive) {
+    const int p = __builtin_ctzll(alive);
+    alive &= alive - 1ull;
+    const float fx = rl(fxp, p), fy = rl(fyp, p);
+    bool ok = false;
+    float al = 0.f;
+    if (l < m) {
+      const float dx = q0.x - fx, dy = q0.y - fy;
+      const bool cov = fabsf(dx) <= q2.w && fabsf(dy) <= q1.w;   // the pixel rule
+      const float power = fminf(fmaf(dx, fmaf(q0.z, dx, q0.w * dy), (q1.x * dy) * dy), 0.f);
+      bool o = cov;
+      if (FILTER) o = o & (power >= q1.z);                       // Eq. 4 before the exponential
+      al = fminf(kAlphaMax, q1.y * exp_rho<LUT>(power, L));
+      ok = o & (al >= kAlphaMin);
+    }
+    uint64_t okm = __ballot(ok);
+    // pixel p's state, the same in every lane
+    float Tt = rl(A.Tt, p), C0 = rl(A.C0, p), C1 = rl(A.C1, p), C2 = rl(A.C2, p);
+    float Tb = rl(A.Tb, p), Cb0 = rl(A.Cb0, p), Cb1 = rl(A.Cb1, p), Cb2 = rl(A.Cb2, p);
+    int32_t nt = rl(A.nt, p), nb = rl(A.nb, p);
+    uint32_t stop_pos = rl(A.stop_pos, p), last = rl(A.last, p), cur_key = rl(A.cur_key, p);
+    bool done = false;
+    while (okm) {
+      const int k = __builtin_ctzll(okm);
+      okm &= okm - 1ull;
+      const float a = rl(al, k);
+      const uint32_t ek = rl(e, k);
+      const float4 c = S.r2[w][jj + k];
+      const uint32_t key = ek >> 8;
+      if (key != cur_key) {
+        C0 = fmaf(Tt, Cb0, C0);
+        C1 = fmaf(Tt, Cb1, C1);
+        C2 = fmaf(Tt, Cb2, C2);
+        Tt = Tt * Tb;
+        nt += nb;
+        Tb = 1.f;
+        Cb0 = Cb1 = Cb2 = 0.f;
+        nb = 0;
+        cur_key = key;
+      }
+      const float Tn = Tb * (1.f - a);
+      const bool stop = Tt * Tn < kTMin;
+      const float wgt = stop ? 0.f : a * Tb;
+      Cb0 = fmaf(wgt, c.x, Cb0);
+      Cb1 = fmaf(wgt, c.y, Cb1);
+      Cb2 = fmaf(wgt, c.z, Cb2);
+      Tb = stop ? Tb : Tn;
+      nb += stop ? 0 : 1;
+      if (SAVE) {
+        last = stop ? last : b0 + (ek & 255u);
+        stop_pos = stop ? b0 + (ek & 255u) : stop_pos;
+      }
+      if (stop) {
+        done = true;
+        break;
+      }
+    }
+    if (l == p) {
+      A.Tt = Tt;
+      A.C0 = C0;
+      A.C1 = C1;
+      A.C2 = C2;
+      A.Tb = Tb;
+      A.Cb0 = Cb0;
+      A.Cb1 = Cb1;
+      A.Cb2 = Cb2;
+      A.nt = nt;
+      A.nb = nb;
+      A.stop_pos = stop_pos;
+      A.last = last;
+      A.cur_key = cur_key;
+      A.done = done;
+    }
+  }
+}
+
 // Coverage masks of band-list entries [jj, jj + m) for the wave's pixels: bit
 // k of lane (c, r) is set when entry jj + k passes the pixel rule at the pixel
 // centre (xa + c, ya + r).
@@ -1078,7 +1179,13 @@ VY_DEV void walk_chunk(const Stage& S, int w, int jc, int mc, uint32_t b0, float
   if (!SPLIT && walk != 1) {
     // small pixel boxes (far Gaussians) cover few pixels of the band: then
     // every pixel walks only its own entries of this chunk
-    if (__ballot(!A.done) == 0ull) return;
+    const uint64_t live = __ballot(!A.done);
+    if (live == 0ull) return;
+    // the tail of a long list, where few pixels still blend: entry-parallel walk per pixel
+    if (walk == 0 && __popcll(live) <= kTransposedMax) {
+      blend_transposed<FILTER, SAVE, LUT>(S, w, jc, mc, b0, fxp, fyp, A, L);
+      return;
+    }
     uint64_t mk = cover_masks(S, w, jc, mc, xa, ya, (int)(threadIdx.x & 63));
     if (A.done) mk = 0ull;
     // the busiest pixel's entry count (0..64), by a binary search over
@@ -1222,10 +1329,13 @@ VY_DEV void pix_init(PixAcc& A, bool inside) {
 
 // Wave-level blend of one 16x4 band of a heavy tile, with no workgroup
 // barriers, so that the bands of a tile finish independently: the wave walks
-// the tile's pairs in chunks of 128 (two per lane) with the records of the next
-// chunk and the cut positions of the one after in flight, compacts the entries
+// the tile's pairs in chunks of 64 * kBandParts (kBandParts per lane) with the
+// records of the next chunk and the cut positions of the one after in flight, compacts the entries
 // whose pixel box may reach the band into its LDS region, and blends them as
 // the workgroup walk does (same rules, bitwise the same pixels).
+constexpr int kBandParts = 4;   // a band job stages 64 * kBandParts pairs per step (at most 256: its LDS list)
+static_assert(kBandParts >= 1 && kBandParts <= 4, "the band list holds 256 entries");
+
 template <bool FILTER, bool SAVE, bool LUT>
 VY_DEV void blend_band(Stage& S, int w, int tx, int ty, int band, uint32_t pb, uint32_t pe,
                        const uint32_t* __restrict__ tval, const float4* __restrict__ pg0,
@@ -1240,12 +1350,16 @@ VY_DEV void blend_band(Stage& S, int w, int tx, int ty, int band, uint32_t pb, u
   const SplitOut so{};
   const float fxp = px + 0.5f, fyp = py + 0.5f;
   const float xa = tx * kTileSize + 0.5f, ya = ty * kTileSize + band * 4 + 0.5f;
-  // chunks of 2 x 64 pairs: lane l holds pairs b0 + l and b0 + 64 + l
-  float4 na[2], nb[2], nc[2];
-  uint32_t g1[2] = {0u, 0u};
+  // chunks of kBandParts x 64 pairs: lane l holds pairs b0 + h * 64 + l; the
+  // records of the next chunk and the cut positions of the one after are in
+  // flight while a chunk is blended
+  constexpr int NP = kBandParts, CH = 64 * kBandParts;
+  float4 na[NP], nb[NP], nc[NP];
+  uint32_t g1[NP];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
+  for (int h = 0; h < NP; ++h) {
     na[h] = nb[h] = nc[h] = make_float4(0.f, 0.f, 0.f, 0.f);
+    g1[h] = 0u;
     const uint32_t p0 = pb + h * 64 + l;
     if (p0 < pe) {
       uint32_t g = tval[p0];
@@ -1254,52 +1368,53 @@ VY_DEV void blend_band(Stage& S, int w, int tx, int ty, int band, uint32_t pb, u
       nb[h] = pg1[g];
       nc[h] = pg2[g];
     }
-    const uint32_t p1 = pb + 128 + h * 64 + l;
+    const uint32_t p1 = pb + CH + h * 64 + l;
     if (p1 < pe) {
       g1[h] = tval[p1];
       if (g1[h] >= n_g) g1[h] = 0;
     }
   }
-  for (uint32_t b0 = pb; b0 < pe; b0 += 128) {
+  for (uint32_t b0 = pb; b0 < pe; b0 += CH) {
     if (__ballot(!A.done) == 0ull) break;
-    bool hit[2];
-    float4 a[2], b[2], c[2];
+    bool hit[NP];
+    float4 a[NP], b[NP], c[NP];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < NP; ++h) {
       a[h] = na[h];
       b[h] = nb[h];
       c[h] = nc[h];
       hit[h] = b0 + h * 64 + l < pe && band_hit(a[h].x, a[h].y, c[h].w, xa, ya);
     }
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {   // records of the next chunk, cut positions of the one after
-      if (b0 + 128 + h * 64 + l < pe) {
+    for (int h = 0; h < NP; ++h) {   // records of the next chunk, cut positions of the one after
+      if (b0 + CH + h * 64 + l < pe) {
         na[h] = pg0[g1[h]];
         nb[h] = pg1[g1[h]];
         nc[h] = pg2[g1[h]];
       }
-      if (b0 + 256 + h * 64 + l < pe) {
-        g1[h] = tval[b0 + 256 + h * 64 + l];
+      if (b0 + 2 * CH + h * 64 + l < pe) {
+        g1[h] = tval[b0 + 2 * CH + h * 64 + l];
         if (g1[h] >= n_g) g1[h] = 0;
       }
     }
-    const uint64_t bal0 = __ballot(hit[0]), bal1 = __ballot(hit[1]);
-    const uint32_t c0 = (uint32_t)__popcll(bal0);
+    uint32_t base = 0;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < NP; ++h) {
+      const uint64_t bal = __ballot(hit[h]);
       if (hit[h]) {
-        const uint32_t pos = (h ? c0 : 0u) + (uint32_t)__popcll((h ? bal1 : bal0) & lanemask_lt());
+        const uint32_t pos = base + (uint32_t)__popcll(bal & lanemask_lt());
         const uint32_t ex = __float_as_uint(c[h].w);
         S.list[w][pos] = (depth_bin(b[h].w) << 8) | (uint32_t)(h * 64 + l);
         S.r0[w][pos] = a[h];
         S.r1[w][pos] = make_float4(b[h].x, b[h].y, b[h].z, (float)(ex >> 16));
         S.r2[w][pos] = make_float4(c[h].x, c[h].y, c[h].z, (float)(ex & 0xFFFFu));
       }
+      base += (uint32_t)__popcll(bal);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int cnt = (int)(c0 + (uint32_t)__popcll(bal1));
+    const int cnt = (int)base;
     for (int jc = 0; jc < cnt; jc += 64) {
       if (__ballot(!A.done) == 0ull) break;
       walk_chunk<FILTER, false, SAVE, LUT>(S, w, jc, cnt - jc < 64 ? cnt - jc : 64, b0, xa, ya, fxp, fyp, A, so, walk,
