@@ -41,7 +41,7 @@ def frustum_planes(cam):
     fx, fy, cx, cy = (float(np.float32(v)) for v in (cam.fx, cam.fy, cam.cx, cam.cy))
     W, H = float(cam.width), float(cam.height)
     nc = np.array([[fx, 0.0, cx], [-fx, 0.0, W - cx], [0.0, fy, cy], [0.0, -fy, H - cy], [0.0, 0.0, 1.0]])
-    nw = nc @ R          # row i = (R^T nc_i)^T
+    nw = np.einsum("ij,jk->ik", nc, R)   # row i = (R^T nc_i)^T; einsum, not BLAS (see predicates)
     d = np.array([0.0, 0.0, 0.0, 0.0, float(np.float32(cam.near))])
     return nw, d
 
@@ -58,8 +58,11 @@ def predicates(scene, cam, tau: float, ids=None):
     for k in range(5):
         n = nw[k]
         pv = np.where(n >= 0, hi, lo)
-        s = (pv - pos) @ n - d[k]
-        scale = np.abs(pv - pos) @ np.abs(n) + abs(d[k])
+        # dot products as einsum sums (numpy's own loops): predicates_threaded
+        # runs this on several threads, and numpy's threaded OpenBLAS has
+        # returned wrong products to concurrent callers
+        s = np.einsum("nj,j->n", pv - pos, n) - d[k]
+        scale = np.einsum("nj,j->n", np.abs(pv - pos), np.abs(n)) + abs(d[k])
         vis &= s >= 0
         near_plane |= np.abs(s) <= NEAR_REL * scale
     ext = np.max(hi - lo, axis=1)

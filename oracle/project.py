@@ -63,7 +63,11 @@ def project(scene, ids, cam):
     fx, fy, cx, cy, near = (float(np.float32(v)) for v in (cam.fx, cam.fy, cam.cx, cam.cy, cam.near))
     W, H = float(cam.width), float(cam.height)
     mu = scene.mean[ids].astype(np.float64)
-    xc = (mu - pos) @ R.T
+    # Products written as einsum sums: numpy's einsum runs its own loops,
+    # never the BLAS library, which project_threaded must not enter from
+    # several threads at once (numpy's threaded OpenBLAS has returned wrong
+    # products to concurrent callers).
+    xc = np.einsum("nj,ij->ni", mu - pos, R)     # R (mu - pos)
     x, y, z = xc[:, 0], xc[:, 1], xc[:, 2]
     valid = z > near
     zs = np.where(valid, z, 1.0)
@@ -76,8 +80,8 @@ def project(scene, ids, cam):
     J[:, 0, 2] = -fx * u / zs
     J[:, 1, 1] = fy / zs
     J[:, 1, 2] = -fy * v / zs
-    T = J @ R
-    S2 = T @ S3 @ np.transpose(T, (0, 2, 1))
+    T = np.einsum("nij,jk->nik", J, R)            # J R
+    S2 = np.einsum("nik,nlk->nil", np.einsum("nij,njk->nik", T, S3), T)   # (T S3) T^T
     a = S2[:, 0, 0] + LOWPASS
     b = S2[:, 0, 1]
     c = S2[:, 1, 1] + LOWPASS

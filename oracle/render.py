@@ -147,7 +147,7 @@ def render_pixels(proj, px, py, bg=(0.0, 0.0, 0.0), order=None, amb_alpha=2e-4, 
         first_stop = stop & ~np.concatenate([np.zeros((P, 1), bool), stop[:, :-1]], axis=1)
         active = use & ~stop                        # blended
         w = np.where(active, a * Tbefore, 0.0)
-        C += w @ rgb_g[s:e]
+        C += np.einsum("pk,kc->pc", w, rgb_g[s:e])   # einsum's own loops, not BLAS (threads)
         ncon += active.sum(axis=1)
         if signature:
             sig += np.where(active, hv[None, s:e], np.uint64(0)).sum(axis=1, dtype=np.uint64)

@@ -230,3 +230,31 @@ def test_threaded_oracle_equals_serial():
     q4 = lod.predicates_threaded(city, cams[1], 2.0, threads=4, chunk=5000)
     for k in q1:
         assert np.array_equal(q1[k], q4[k]), k
+
+
+def test_threaded_oracle_is_deterministic_with_large_chunks():
+    """Chunks large enough for a multithreaded BLAS to split them, on 8
+    threads at once, four times over: projection, blend and the LoD
+    predicates stay bitwise those of one thread (no helper may hand products
+    to a BLAS that returns wrong results to concurrent callers)."""
+    from oracle import lod
+    n, W, H = 1_000_000, 64, 48
+    sc = scenegen.random_gaussians(n, 21, W, H, depth_range=(2, 40), scale_range=(-4.0, -1.0))
+    cam = scenegen.look_camera([0.3, -0.2, -0.5], 0.05, 0.02, W, H)
+    ids = np.arange(n)
+    p1 = project.project(sc, ids, cam)
+    q1 = lod.predicates(sc, cam, 2.0)
+    tiles = [0, 5, 11]
+    keep = np.nonzero(p1["valid"])[0][:60_000]
+    sub = {k: v[keep] for k, v in p1.items()}
+    a = render.render_image(sub, W, H, tiles=tiles)
+    for _ in range(4):
+        p8 = project.project_threaded(sc, ids, cam, threads=8, chunk=1 << 18)
+        for k in p1:
+            assert np.array_equal(p1[k], p8[k]), k
+        q8 = lod.predicates_threaded(sc, cam, 2.0, threads=8, chunk=1 << 18)
+        for k in q1:
+            assert np.array_equal(q1[k], q8[k]), k
+        b = render.render_image(sub, W, H, tiles=tiles, threads=8, chunk=4096)
+        for k in a:
+            assert np.array_equal(a[k], b[k], equal_nan=True), k
