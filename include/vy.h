@@ -12,8 +12,17 @@
  *                 "Rasterization", optionally with the preemptive alpha-filtering
  *                 of Section 4.2 (Eq. 3 and Eq. 4 moved to culling/projection)
  *                 and the lookup-table exponential of Eq. 5;
+ *   vy_render_batch - the frames of several viewers (scenes, cameras, image
+ *                 sizes) rendered with one launch per stage, each image
+ *                 bitwise the one vy_render gives alone;
+ *   vy_render_noalloc - vy_render with its scratch in a static device array,
+ *                 for callers that cannot allocate;
  *   vy_render_backward - gradients of a rendered image with respect to the
  *                 cut's Gaussians (the adjoint of vy_render);
+ *   vy_scene_partition - the height-2 subtree partition of Section 4.1 ("LoD
+ *                 Tree Partitioning"), which VY_CUT_CHUNKED traverses;
+ *   vy_scene_update_gaussians - new Gaussian parameters over the same tree
+ *                 (training);
  *   inspection, stage timing and vy_measure_peaks - for tests and rooflines.
  * vy_serve.h builds two runtimes on these calls: a multi-viewer server and a
  * walkthrough renderer that keeps several frames of one camera path in flight.

@@ -163,14 +163,11 @@ VY_DEV float3 sh_colour(const float* __restrict__ c, float x, float y, float z) 
 }
 
 // Maximum of rho(d) = A d_x^2 + B d_x d_y + C d_y^2 (A, C < 0: the power of a
-// Gaussian, d = pixel centre - mean) over the pixel centres of tile (tx, ty):
-// the exact maximum over the continuous rectangle spanned by those centres
-// (0 if the mean is inside, else the best of the four edges, each a 1-D
-// concave quadratic maximised at its clamped vertex).
-VY_DEV float tile_rho_max(float mx, float my, float A, float B, float C, int tx, int ty, int W, int H) {
-  const float x0 = tx * kTileSize + 0.5f, y0 = ty * kTileSize + 0.5f;
-  const float x1 = fminf((float)(tx * kTileSize + kTileSize), (float)W) - 0.5f;
-  const float y1 = fminf((float)(ty * kTileSize + kTileSize), (float)H) - 0.5f;
+// Gaussian, d = pixel centre - mean) over pixel centres spanning [x0, x1] x
+// [y0, y1] (a tile, or the band of a band job): the exact maximum over the
+// continuous rectangle (0 if the mean is inside, else the best of the four
+// edges, each a 1-D concave quadratic maximised at its clamped vertex).
+VY_DEV float rect_rho_max(float mx, float my, float A, float B, float C, float x0, float y0, float x1, float y1) {
   if (mx >= x0 && mx <= x1 && my >= y0 && my <= y1) return 0.f;
   const float dx0 = x0 - mx, dx1 = x1 - mx, dy0 = y0 - my, dy1 = y1 - my;
   float best = -INFINITY;
@@ -185,6 +182,13 @@ VY_DEV float tile_rho_max(float mx, float my, float A, float B, float C, int tx,
     best = fmaxf(best, (A * dx * dx + C * dy * dy) + B * dx * dy);
   }
   return fminf(best, 0.f);
+}
+
+VY_DEV float tile_rho_max(float mx, float my, float A, float B, float C, int tx, int ty, int W, int H) {
+  const float x0 = tx * kTileSize + 0.5f, y0 = ty * kTileSize + 0.5f;
+  const float x1 = fminf((float)(tx * kTileSize + kTileSize), (float)W) - 0.5f;
+  const float y1 = fminf((float)(ty * kTileSize + kTileSize), (float)H) - 0.5f;
+  return rect_rho_max(mx, my, A, B, C, x0, y0, x1, y1);
 }
 
 // Pair-level preemptive test (Eq. 4 moved to binning, Section 4.2): keep tile t
@@ -657,7 +661,12 @@ __global__ __launch_bounds__(256) void tile_ranges(const uint32_t* __restrict__ 
 // pixel box (half-extents in pg2.w, beyond which no pixel is blended) reaches
 // it.
 constexpr uint32_t kTierMin[3] = {16384, 4096, 1024};   // tiles blended first, heaviest tier first
-constexpr int kBandWGs = 256;   // workgroups whose waves blend the two heaviest tiers band by band
+constexpr int kBandWGs = 320;   // workgroups whose waves blend the two heaviest tiers band by band
+// Band jobs of the two heaviest tiers are halves of bands (8x4 pixels): the
+// horizon's Gaussians are a few pixels wide, so half a band sees about two
+// thirds of the band's entries, and the longest job (the kernel's critical
+// path) walks correspondingly fewer.
+constexpr bool kHalfBands = true;
 constexpr int kMaxBins = 256;
 constexpr uint32_t kMaxHeavy = 2048;
 constexpr uint32_t kMaxJobsPerTile = 64;
@@ -675,12 +684,13 @@ VY_DEV uint32_t depth_bin(float z) { return __float_as_uint(z) >> 19; }
 // pairs bit for bit.
 //
 // Can the pixel box (half-extents packed in `ext` as rx | ry << 16) hold a
-// pixel centre of the 16x4 band starting at (xa, ya)? A half-pixel slack makes
-// this a superset of the pixel rule under rounding.
-VY_DEV bool band_hit(float mx, float my, float ext, float xa, float ya) {
+// pixel centre of the band starting at (xa, ya), `xw` + 1 pixels wide (16, or
+// 8 for half a band) and 4 high? A half-pixel slack makes this a superset of
+// the pixel rule under rounding.
+VY_DEV bool band_hit(float mx, float my, float ext, float xa, float ya, float xw = 15.f) {
   const uint32_t e = __float_as_uint(ext);
   const float rx = (float)(e & 0xFFFFu) + 0.5f, ry = (float)(e >> 16) + 0.5f;
-  return (mx + rx >= xa) && (mx - rx <= xa + 15.f) && (my + ry >= ya) && (my - ry <= ya + 3.f);
+  return (mx + rx >= xa) && (mx - rx <= xa + xw) && (my + ry >= ya) && (my - ry <= ya + 3.f);
 }
 
 // LDS staging of pairs [b0, min(b0 + 256, pe)) of a tile: per band, the
@@ -1327,8 +1337,11 @@ VY_DEV void pix_init(PixAcc& A, bool inside) {
   A.lb = 0;
 }
 
-// Wave-level blend of one 16x4 band of a heavy tile, with no workgroup
-// barriers, so that the bands of a tile finish independently: the wave walks
+// Wave-level blend of one 16x4 band of a heavy tile (or, for half >= 0, of
+// its left or right 8x4 half: the lanes of the other half start as finished
+// pixels and entries are kept for the half's pixels only, which changes no
+// pixel's result), with no workgroup barriers, so that the bands of a tile
+// finish independently: the wave walks
 // the tile's pairs in chunks of 64 * kBandParts (kBandParts per lane) with the
 // records of the next chunk and the cut positions of the one after in flight, compacts the entries
 // whose pixel box may reach the band into its LDS region, and blends them as
@@ -1337,28 +1350,32 @@ constexpr int kBandParts = 4;   // a band job stages 64 * kBandParts pairs per s
 static_assert(kBandParts >= 1 && kBandParts <= 4, "the band list holds 256 entries");
 
 template <bool FILTER, bool SAVE, bool LUT>
-VY_DEV void blend_band(Stage& S, int w, int tx, int ty, int band, uint32_t pb, uint32_t pe,
+VY_DEV void blend_band(Stage& S, int w, int tx, int ty, int band, int half, uint32_t pb, uint32_t pe,
                        const uint32_t* __restrict__ tval, const float4* __restrict__ pg0,
-                       const float4* __restrict__ pg1, const float4* __restrict__ pg2, uint32_t n_g, const RCam& cam,
+                       const float4* __restrict__ pg1, const float4* __restrict__ pg2,
+                       const float* __restrict__ prelax, uint32_t n_g, const RCam& cam,
                        float* __restrict__ img, float* __restrict__ Tout, int32_t* __restrict__ Nout,
                        int32_t* __restrict__ Eout, int32_t* __restrict__ Lout, int walk, const ExpLut& L) {
   const int l = (int)(threadIdx.x & 63);
   const int px = tx * kTileSize + (l & 15), py = ty * kTileSize + band * 4 + (l >> 4);
-  const bool inside = px < cam.W && py < cam.H;
+  const bool inside = px < cam.W && py < cam.H && (half < 0 || (l & 15) >> 3 == half);
   PixAcc A;
   pix_init(A, inside);
   const SplitOut so{};
   const float fxp = px + 0.5f, fyp = py + 0.5f;
   const float xa = tx * kTileSize + 0.5f, ya = ty * kTileSize + band * 4 + 0.5f;
+  const float xh = half > 0 ? xa + 8.f : xa, xw = half < 0 ? 15.f : 7.f;   // the pixels this job blends
   // chunks of kBandParts x 64 pairs: lane l holds pairs b0 + h * 64 + l; the
   // records of the next chunk and the cut positions of the one after are in
   // flight while a chunk is blended
   constexpr int NP = kBandParts, CH = 64 * kBandParts;
   float4 na[NP], nb[NP], nc[NP];
+  float nr[NP];   // rounding allowances of rho (filter only)
   uint32_t g1[NP];
 #pragma unroll
   for (int h = 0; h < NP; ++h) {
     na[h] = nb[h] = nc[h] = make_float4(0.f, 0.f, 0.f, 0.f);
+    nr[h] = 1.f;
     g1[h] = 0u;
     const uint32_t p0 = pb + h * 64 + l;
     if (p0 < pe) {
@@ -1367,6 +1384,7 @@ VY_DEV void blend_band(Stage& S, int w, int tx, int ty, int band, uint32_t pb, u
       na[h] = pg0[g];
       nb[h] = pg1[g];
       nc[h] = pg2[g];
+      if (FILTER) nr[h] = prelax[g];
     }
     const uint32_t p1 = pb + CH + h * 64 + l;
     if (p1 < pe) {
@@ -1383,7 +1401,15 @@ VY_DEV void blend_band(Stage& S, int w, int tx, int ty, int band, uint32_t pb, u
       a[h] = na[h];
       b[h] = nb[h];
       c[h] = nc[h];
-      hit[h] = b0 + h * 64 + l < pe && band_hit(a[h].x, a[h].y, c[h].w, xa, ya);
+      hit[h] = b0 + h * 64 + l < pe && band_hit(a[h].x, a[h].y, c[h].w, xh, ya, xw);
+      // with the filter, Eq. 4 over the job's pixel centres as for tiles: an
+      // entry whose rho stays below the threshold at every one of them fails
+      // the per-pixel test everywhere, so dropping it changes no pixel; the
+      // test runs here once per entry, in parallel over the lanes, instead of
+      // once per entry of the sequential walk
+      if (FILTER && hit[h] && nr[h] < 0.25f)
+        hit[h] = rect_rho_max(a[h].x, a[h].y, a[h].z, a[h].w, b[h].x, xh, ya, xh + xw, ya + 3.f) * (1.f - nr[h]) >=
+                 b[h].z;
     }
 #pragma unroll
     for (int h = 0; h < NP; ++h) {   // records of the next chunk, cut positions of the one after
@@ -1391,6 +1417,7 @@ VY_DEV void blend_band(Stage& S, int w, int tx, int ty, int band, uint32_t pb, u
         na[h] = pg0[g1[h]];
         nb[h] = pg1[g1[h]];
         nc[h] = pg2[g1[h]];
+        if (FILTER) nr[h] = prelax[g1[h]];
       }
       if (b0 + 2 * CH + h * 64 + l < pe) {
         g1[h] = tval[b0 + 2 * CH + h * 64 + l];
@@ -1432,7 +1459,8 @@ VY_DEV void blend_band(Stage& S, int w, int tx, int ty, int band, uint32_t pb, u
 template <bool FILTER, bool SAVE, bool LUT, bool BATCH>
 __global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ ranges, const uint32_t* __restrict__ tval,
                                                   const float4* __restrict__ pg0, const float4* __restrict__ pg1,
-                                                  const float4* __restrict__ pg2, RCam cam, int ntiles,
+                                                  const float4* __restrict__ pg2, const float* __restrict__ prelax,
+                                                  RCam cam, int ntiles,
                                                   const uint32_t* __restrict__ tile_flag,
                                                   const uint32_t* __restrict__ tiers,
                                                   const uint32_t* __restrict__ heavy_rec,
@@ -1463,16 +1491,18 @@ __global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ rang
   const uint32_t n0 = ctr[C_NTIER], n1 = ctr[C_NTIER + 1], n2 = ctr[C_NTIER + 2];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   if ((int)blockIdx.x < band_wgs) {
-    // the first band_wgs workgroups: every wave takes (tile, band) jobs of the
-    // two heaviest tiers on its own, at the highest issue priority
-    const uint32_t nband = 4u * (n0 + n1);
+    // the first band_wgs workgroups: every wave takes (tile, band[, half])
+    // jobs of the two heaviest tiers on its own, at the highest issue priority
+    constexpr uint32_t kJobShift = kHalfBands ? 3 : 2;   // jobs per tile: 8 halves or 4 bands
+    const uint32_t nband = (n0 + n1) << kJobShift;
     __builtin_amdgcn_s_setprio(3);
     for (;;) {
       uint32_t jb = 0;
       if (l == 0) jb = fetch_add(ctr + C_BAND_TICKET, 1u);
       jb = (uint32_t)__builtin_amdgcn_readfirstlane(jb);
       if (jb >= nband) break;
-      const uint32_t k = jb >> 2;
+      const uint32_t k = jb >> kJobShift;
+      const int band = (int)((jb >> (kJobShift - 2)) & 3u), half = kHalfBands ? (int)(jb & 1u) : -1;
       const uint32_t tile = k < n0 ? tiers[k] : tiers[(size_t)ntiles + (k - n0)];
       const uint2 rg = ranges[tile];
       uint32_t pb = rg.x, pe = rg.y;
@@ -1487,8 +1517,8 @@ __global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ rang
         vimg = views[v].img;
         lt = tile - s_toff[v];
       }
-      blend_band<FILTER, SAVE, LUT>(S, w, (int)lt % vc.tiles_x, (int)lt / vc.tiles_x, (int)(jb & 3u), pb, pe,
-                                    tval, pg0, pg1, pg2, n_g, vc, vimg, Tout, Nout, Eout, Lout, walk, L);
+      blend_band<FILTER, SAVE, LUT>(S, w, (int)lt % vc.tiles_x, (int)lt / vc.tiles_x, band, half, pb, pe, tval, pg0,
+                                    pg1, pg2, prelax, n_g, vc, vimg, Tout, Nout, Eout, Lout, walk, L);
     }
     __builtin_amdgcn_s_setprio(0);
     return;
@@ -2752,9 +2782,9 @@ int vy_render_batch(const vy_view* views, int32_t n, const vy_render_opts* opts,
     const RCam none{};
 #define VY_BLEND_BATCH(F, LT)                                                                                    \
   blend_jobs<F, false, LT, true><<<band_wgs + 2048, 256, 0, st>>>(                                             \
-      c->ranges, c->tval[0], c->pg0, c->pg1, c->pg2, none, ntiles, c->tile_flag, c->tiers, nullptr, nullptr,    \
-      nullptr, nullptr, c->ctr, gcap, pcap, nullptr, nullptr, nullptr, nullptr, nullptr, walk, band_wgs, lut_m, \
-      b->d_views, n)
+      c->ranges, c->tval[0], c->pg0, c->pg1, c->pg2, c->prelax, none, ntiles, c->tile_flag, c->tiers, nullptr,   \
+      nullptr, nullptr, nullptr, c->ctr, gcap, pcap, nullptr, nullptr, nullptr, nullptr, nullptr, walk,         \
+      band_wgs, lut_m, b->d_views, n)
     if (filter) {
       if (lut_m > 0) VY_BLEND_BATCH(true, true); else VY_BLEND_BATCH(true, false);
     } else {
@@ -2915,9 +2945,9 @@ static int render_impl(const vy_scene* scene, const vy_cut* cut, const vy_camera
     ProfScope ps(VY_STAGE_BLEND, st);
 #define VY_BLEND_JOBS(F, S, LT)                                                                                 \
   blend_jobs<F, S, LT, false><<<band_wgs + 2048, 256, 0, st>>>(                                                 \
-      c->ranges, c->tval[0], c->pg0, c->pg1, c->pg2, rc, ntiles, c->tile_flag, c->tiers, c->heavy_rec, c->jobs, \
-      c->bin_c, c->bin_n, c->ctr, gcap, pcap, image, c->T_final, c->n_contrib, c->n_eval, c->last_contrib, walk,  \
-      band_wgs, lut_m, nullptr, 0)
+      c->ranges, c->tval[0], c->pg0, c->pg1, c->pg2, c->prelax, rc, ntiles, c->tile_flag, c->tiers, c->heavy_rec, \
+      c->jobs, c->bin_c, c->bin_n, c->ctr, gcap, pcap, image, c->T_final, c->n_contrib, c->n_eval,              \
+      c->last_contrib, walk, band_wgs, lut_m, nullptr, 0)
 #define VY_BLEND(F, S)                                                                                          \
   do {                                                                                                          \
     if (lut_m > 0) VY_BLEND_JOBS(F, S, true); else VY_BLEND_JOBS(F, S, false);                                  \
