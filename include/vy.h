@@ -268,6 +268,17 @@ typedef struct vy_render_opts {
                            exact one (filtered and unfiltered still agree bit
                            for bit: the preemptive check keeps a margin of half
                            an interval more). Not with split_min_pairs > 0. */
+  int32_t band_jobs;    /* with walk = 0, how the tiles of more than 4096 pairs
+                           are cut into wave jobs: 1 (latency) halves of 16x4
+                           bands on more dedicated workgroups, the shortest
+                           frame when frames run one at a time; 2 (throughput)
+                           whole bands on fewer workgroups, less work in all,
+                           faster when frames overlap; 0 (default) 1 for
+                           vy_render, 2 for vy_render_batch, and in
+                           vy_serve.h 2 when frames overlap (vy_walkthrough
+                           with depth > 1, a server with several frames in
+                           flight). The image is bitwise the same for any
+                           value; other values are refused (VY_ERR_ARG). */
 } vy_render_opts;
 
 typedef struct vy_render_ctx vy_render_ctx;

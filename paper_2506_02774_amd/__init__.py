@@ -51,7 +51,8 @@ class vy_scene_desc(ctypes.Structure):
 
 class vy_render_opts(ctypes.Structure):
     _fields_ = [("alpha_filter", ctypes.c_int32), ("bg", ctypes.c_float * 3), ("save_state", ctypes.c_int32),
-                ("split_min_pairs", ctypes.c_int32), ("walk", ctypes.c_int32), ("lut_entries", ctypes.c_int32)]
+                ("split_min_pairs", ctypes.c_int32), ("walk", ctypes.c_int32), ("lut_entries", ctypes.c_int32),
+                ("band_jobs", ctypes.c_int32)]
 
 
 class vy_grads(ctypes.Structure):
@@ -479,14 +480,15 @@ def vy_lod_cut(scene: Scene, cam, tau: float, prev: Cut | None = None, out: Cut 
 
 
 def vy_render(scene: Scene, cut: Cut, cam, ctx: RenderContext, image=None, alpha_filter=False,
-              bg=(0.0, 0.0, 0.0), save_state=False, split_min_pairs=0, walk=0, lut_entries=0, stream=None):
+              bg=(0.0, 0.0, 0.0), save_state=False, split_min_pairs=0, walk=0, lut_entries=0, band_jobs=0,
+              stream=None):
     """Enqueue rendering of `cut` into `image` (torch float32 [3, H, W] on the device)."""
     import torch
     if image is None:
         image = torch.empty((3, int(cam.height), int(cam.width)), dtype=torch.float32, device="cuda")
     if image.dtype != torch.float32 or not image.is_contiguous() or tuple(image.shape) != (3, cam.height, cam.width):
         raise VoyagerError(VY_ERR_ARG, "image must be a contiguous float32 tensor of shape (3, H, W)")
-    o = _render_opts(alpha_filter, bg, save_state, split_min_pairs, walk, lut_entries)
+    o = _render_opts(alpha_filter, bg, save_state, split_min_pairs, walk, lut_entries, band_jobs)
     c = make_camera(cam)
     check(lib().vy_render(scene.handle, cut.handle, ctypes.byref(c), ctypes.byref(o),
                           ctypes.c_void_p(image.data_ptr()), ctx.handle, _stream(stream)), "vy_render")
@@ -529,7 +531,7 @@ class BatchContext:
 
 
 def vy_render_batch(views, ctx: BatchContext, alpha_filter=False, bg=(0.0, 0.0, 0.0), walk=0, lut_entries=0,
-                    stream=None):
+                    band_jobs=0, stream=None):
     """Enqueue one batched render of `views`: (scene, cut, cam, image) tuples,
     image a contiguous float32 [3, H, W] device tensor. Returns the images."""
     import torch
@@ -543,7 +545,7 @@ def vy_render_batch(views, ctx: BatchContext, alpha_filter=False, bg=(0.0, 0.0, 
         arr[i].cut = cut.handle.value if isinstance(cut.handle, ctypes.c_void_p) else cut.handle
         arr[i].cam = make_camera(cam)
         arr[i].image = image.data_ptr()
-    o = _render_opts(alpha_filter, bg, False, 0, walk, lut_entries)
+    o = _render_opts(alpha_filter, bg, False, 0, walk, lut_entries, band_jobs)
     check(lib().vy_render_batch(arr, n, ctypes.byref(o), ctx.handle, _stream(stream)), "vy_render_batch")
     return [v[3] for v in views]
 
@@ -576,7 +578,7 @@ NOALLOC_MAX_WIDTH, NOALLOC_MAX_HEIGHT = 1280, 720
 
 
 def vy_render_noalloc(scene: Scene, cut: Cut, cam, image=None, counts=None, alpha_filter=False,
-                      bg=(0.0, 0.0, 0.0), walk=0, lut_entries=0, stream=None):
+                      bg=(0.0, 0.0, 0.0), walk=0, lut_entries=0, band_jobs=0, stream=None):
     """Enqueue rendering of `cut` into `image` with the library's static
     scratch instead of a context (no allocation inside the call). `counts`: a
     device int32/uint32 tensor of 4 elements receiving {pairs needed,
@@ -589,7 +591,7 @@ def vy_render_noalloc(scene: Scene, cut: Cut, cam, image=None, counts=None, alph
         raise VoyagerError(VY_ERR_ARG, "image must be a contiguous float32 tensor of shape (3, H, W)")
     if counts is not None and (counts.numel() < 4 or counts.element_size() != 4 or not counts.is_contiguous()):
         raise VoyagerError(VY_ERR_ARG, "counts must be a contiguous 32-bit tensor of at least 4 elements")
-    o = _render_opts(alpha_filter, bg, False, 0, walk, lut_entries)
+    o = _render_opts(alpha_filter, bg, False, 0, walk, lut_entries, band_jobs)
     c = make_camera(cam)
     check(lib().vy_render_noalloc(scene.handle, cut.handle, ctypes.byref(c), ctypes.byref(o),
                                   ctypes.c_void_p(image.data_ptr()),
@@ -611,7 +613,8 @@ def measure_peaks(stream=None):
     return dict(fma_fp32_tflops=f.value, exp_f32_gops=e.value)
 
 
-def _render_opts(alpha_filter=False, bg=(0.0, 0.0, 0.0), save_state=False, split_min_pairs=0, walk=0, lut_entries=0):
+def _render_opts(alpha_filter=False, bg=(0.0, 0.0, 0.0), save_state=False, split_min_pairs=0, walk=0, lut_entries=0,
+                 band_jobs=0):
     o = vy_render_opts()
     o.alpha_filter = 1 if alpha_filter else 0
     for i in range(3):
@@ -620,12 +623,13 @@ def _render_opts(alpha_filter=False, bg=(0.0, 0.0, 0.0), save_state=False, split
     o.split_min_pairs = int(split_min_pairs)
     o.walk = int(walk)
     o.lut_entries = int(lut_entries)
+    o.band_jobs = int(band_jobs)
     return o
 
 
 def vy_walkthrough(scene: Scene, cams, tau: float, cuts, ctxs, images, streams=None, prev: Cut | None = None,
                    mode: int = VY_CUT_FRONTIER, alpha_filter=False, bg=(0.0, 0.0, 0.0), walk=0, lut_entries=0,
-                   stats=None, frame_ms=False, stream=None):
+                   band_jobs=0, stats=None, frame_ms=False, stream=None):
     """Enqueue the frames of a camera path with len(cuts) frames in flight.
     Frame i searches its cut from frame i-1's (from `prev` for frame 0, a full
     search when None) into cuts[i % depth] and renders it with ctxs[i % depth]
@@ -654,7 +658,7 @@ def vy_walkthrough(scene: Scene, cams, tau: float, cuts, ctxs, images, streams=N
     if stats is not None and stats.numel() * stats.element_size() < 32 * n:
         raise VoyagerError(VY_ERR_ARG, "stats needs 32 bytes per frame")
     cam_arr = (vy_camera * max(1, n))(*[make_camera(c) for c in cams])
-    o = _render_opts(alpha_filter, bg, False, 0, walk, lut_entries)
+    o = _render_opts(alpha_filter, bg, False, 0, walk, lut_entries, band_jobs)
     P = ctypes.c_void_p
     cut_arr = (P * depth)(*[c.handle for c in cuts])
     ctx_arr = (P * depth)(*[c.handle for c in ctxs])

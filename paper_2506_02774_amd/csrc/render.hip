@@ -661,12 +661,16 @@ __global__ __launch_bounds__(256) void tile_ranges(const uint32_t* __restrict__ 
 // pixel box (half-extents in pg2.w, beyond which no pixel is blended) reaches
 // it.
 constexpr uint32_t kTierMin[3] = {16384, 4096, 1024};   // tiles blended first, heaviest tier first
-constexpr int kBandWGs = 320;   // workgroups whose waves blend the two heaviest tiers band by band
-// Band jobs of the two heaviest tiers are halves of bands (8x4 pixels): the
-// horizon's Gaussians are a few pixels wide, so half a band sees about two
-// thirds of the band's entries, and the longest job (the kernel's critical
-// path) walks correspondingly fewer.
-constexpr bool kHalfBands = true;
+// Workgroups whose waves blend the two heaviest tiers band by band, for the two
+// layouts of vy_render_opts.band_jobs. Latency: jobs are halves of bands (8x4
+// pixels) on 320 workgroups; the horizon's Gaussians are a few pixels wide, so
+// half a band sees about two thirds of the band's entries and the longest job
+// (one frame's critical path) walks correspondingly fewer. Throughput: whole
+// bands on 128 workgroups, which spends less work in all (each job scans its
+// tile's list once per band rather than once per half) and leaves more of the
+// chip to the tile jobs of frames that overlap.
+constexpr int kBandWGsLatency = 320;
+constexpr int kBandWGsThroughput = 128;
 constexpr int kMaxBins = 256;
 constexpr uint32_t kMaxHeavy = 2048;
 constexpr uint32_t kMaxJobsPerTile = 64;
@@ -1469,7 +1473,8 @@ __global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ rang
                                                   uint32_t n_pairs_cap, float* __restrict__ img,
                                                   float* __restrict__ Tout, int32_t* __restrict__ Nout,
                                                   int32_t* __restrict__ Eout, int32_t* __restrict__ Lout, int walk,
-                                                  int band_wgs, int lut_m, const BView* __restrict__ views, int nv) {
+                                                  int band_wgs, int half_bands, int lut_m,
+                                                  const BView* __restrict__ views, int nv) {
   __shared__ Stage S;
   __shared__ uint32_t s_job;
   __shared__ float s_lut[LUT ? kLutMax + 1 : 1];
@@ -1493,16 +1498,16 @@ __global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ rang
   if ((int)blockIdx.x < band_wgs) {
     // the first band_wgs workgroups: every wave takes (tile, band[, half])
     // jobs of the two heaviest tiers on its own, at the highest issue priority
-    constexpr uint32_t kJobShift = kHalfBands ? 3 : 2;   // jobs per tile: 8 halves or 4 bands
-    const uint32_t nband = (n0 + n1) << kJobShift;
+    const uint32_t shift = half_bands ? 3u : 2u;   // jobs per tile: 8 halves or 4 bands
+    const uint32_t nband = (n0 + n1) << shift;
     __builtin_amdgcn_s_setprio(3);
     for (;;) {
       uint32_t jb = 0;
       if (l == 0) jb = fetch_add(ctr + C_BAND_TICKET, 1u);
       jb = (uint32_t)__builtin_amdgcn_readfirstlane(jb);
       if (jb >= nband) break;
-      const uint32_t k = jb >> kJobShift;
-      const int band = (int)((jb >> (kJobShift - 2)) & 3u), half = kHalfBands ? (int)(jb & 1u) : -1;
+      const uint32_t k = jb >> shift;
+      const int band = (int)((jb >> (shift - 2u)) & 3u), half = half_bands ? (int)(jb & 1u) : -1;
       const uint32_t tile = k < n0 ? tiers[k] : tiers[(size_t)ntiles + (k - n0)];
       const uint2 rg = ranges[tile];
       uint32_t pb = rg.x, pe = rg.y;
@@ -2652,6 +2657,10 @@ int vy_render_batch(const vy_view* views, int32_t n, const vy_render_opts* opts,
     return fail(VY_ERR_ARG, "vy_render_batch: save_state and split tiles are for single frames (vy_render)");
   const int walk = opts ? opts->walk : 0;
   if (walk < 0 || walk > 2) return fail(VY_ERR_ARG, "vy_render_batch: walk must be 0, 1 or 2");
+  const int band_jobs = opts ? opts->band_jobs : 0;
+  if (band_jobs < 0 || band_jobs > 2) return fail(VY_ERR_ARG, "vy_render_batch: band_jobs must be 0, 1 or 2");
+  // a batch is throughput work: the whole-band layout unless asked otherwise
+  const bool half_bands = band_jobs == 1;
   if (opts && (opts->lut_entries < 0 || opts->lut_entries > kLutMax))
     return fail(VY_ERR_ARG, "vy_render_batch: lut_entries must be 0..%d", kLutMax);
   RenderCtx* c = &b->c;
@@ -2770,7 +2779,7 @@ int vy_render_batch(const vy_view* views, int32_t n, const vy_render_opts* opts,
     tile_ranges<<<blocks, 256, 0, st>>>(c->tkey[0], c->ctr, c->ranges, (uint32_t)ntiles);
     VY_LAUNCHED();
   }
-  const int band_wgs = walk == 0 ? kBandWGs : 0;
+  const int band_wgs = walk != 0 ? 0 : half_bands ? kBandWGsLatency : kBandWGsThroughput;
   {
     ProfScope ps(VY_STAGE_BLEND_PLAN, st);
     plan_tiles<<<imin(cdiv(ntiles, 256), 64), 256, 0, st>>>(c->ranges, ntiles, c->tile_flag, nullptr, c->tiers,
@@ -2784,7 +2793,7 @@ int vy_render_batch(const vy_view* views, int32_t n, const vy_render_opts* opts,
   blend_jobs<F, false, LT, true><<<band_wgs + 2048, 256, 0, st>>>(                                             \
       c->ranges, c->tval[0], c->pg0, c->pg1, c->pg2, c->prelax, none, ntiles, c->tile_flag, c->tiers, nullptr,   \
       nullptr, nullptr, nullptr, c->ctr, gcap, pcap, nullptr, nullptr, nullptr, nullptr, nullptr, walk,         \
-      band_wgs, lut_m, b->d_views, n)
+      band_wgs, half_bands, lut_m, b->d_views, n)
     if (filter) {
       if (lut_m > 0) VY_BLEND_BATCH(true, true); else VY_BLEND_BATCH(true, false);
     } else {
@@ -2821,6 +2830,9 @@ static int render_impl(const vy_scene* scene, const vy_cut* cut, const vy_camera
   const bool save = opts && opts->save_state;
   const int walk = opts ? opts->walk : 0;
   if (walk < 0 || walk > 2) return fail(VY_ERR_ARG, "vy_render: walk must be 0, 1 or 2");
+  const int band_jobs = opts ? opts->band_jobs : 0;
+  if (band_jobs < 0 || band_jobs > 2) return fail(VY_ERR_ARG, "vy_render: band_jobs must be 0, 1 or 2");
+  const bool half_bands = band_jobs != 2;   // one frame: the latency layout unless asked otherwise
   if (opts && (opts->lut_entries < 0 || opts->lut_entries > kLutMax))
     return fail(VY_ERR_ARG, "vy_render: lut_entries must be 0..%d", kLutMax);
   if (opts && opts->lut_entries > 0 && opts->split_min_pairs > 0)
@@ -2917,7 +2929,7 @@ static int render_impl(const vy_scene* scene, const vy_cut* cut, const vy_camera
   }
   // splitting tiles by depth bins gives up early termination; it is off unless asked for
   // automatic walk: the two heaviest tiers are blended band by band by waves of their own
-  const int band_wgs = walk == 0 ? kBandWGs : 0;
+  const int band_wgs = walk != 0 ? 0 : half_bands ? kBandWGsLatency : kBandWGsThroughput;
   const bool split_on = opts && opts->split_min_pairs > 0;
   if (split_on && !c->split) return fail(VY_ERR_ARG, "vy_render: this context has no room for split tiles");
   const int lut_m = opts ? opts->lut_entries : 0;
@@ -2947,7 +2959,7 @@ static int render_impl(const vy_scene* scene, const vy_cut* cut, const vy_camera
   blend_jobs<F, S, LT, false><<<band_wgs + 2048, 256, 0, st>>>(                                                 \
       c->ranges, c->tval[0], c->pg0, c->pg1, c->pg2, c->prelax, rc, ntiles, c->tile_flag, c->tiers, c->heavy_rec, \
       c->jobs, c->bin_c, c->bin_n, c->ctr, gcap, pcap, image, c->T_final, c->n_contrib, c->n_eval,              \
-      c->last_contrib, walk, band_wgs, lut_m, nullptr, 0)
+      c->last_contrib, walk, band_wgs, half_bands, lut_m, nullptr, 0)
 #define VY_BLEND(F, S)                                                                                          \
   do {                                                                                                          \
     if (lut_m > 0) VY_BLEND_JOBS(F, S, true); else VY_BLEND_JOBS(F, S, false);                                  \

@@ -494,6 +494,7 @@ struct HipExec {
       vy_render_opts o;
       memset(&o, 0, sizeof(o));
       o.alpha_filter = ss.alpha_filter;
+      if (n_streams > 1) o.band_jobs = 2;   // frames of several streams overlap: the throughput layout
       rc = vy_render(ss.scene, r.cut, &q.cam, &o, image, r.ctx, st);
     }
     if (rc == VY_OK) rc = render_frame_finish(r.cut, r.ctx, image, ss.width, ss.height, stats + i, st);

@@ -11,6 +11,7 @@
 // context and image slot (frame i uses slot i mod depth), and every launch of
 // a slot goes to that slot's stream, so the work of one slot is ordered by its
 // stream alone.
+#include <cstring>
 #include <vector>
 
 #include "vy_common.hpp"
@@ -68,6 +69,12 @@ extern "C" int vy_walkthrough(const vy_scene* scene, const vy_camera* cams, int6
   if ((full_mode & ~(VY_CUT_FLAT | VY_CUT_DFS | VY_WALK_FULL_EACH)) != 0)
     return fail(VY_ERR_ARG, "vy_walkthrough: unknown mode %d", full_mode);
   if (n_frames == 0) return VY_OK;
+  // frames in flight overlap: unless the caller chose, heavy tiles take the
+  // band-job layout that spends the least work in all
+  vy_render_opts ropts;
+  memset(&ropts, 0, sizeof(ropts));
+  if (opts) ropts = *opts;
+  if (ropts.band_jobs == 0 && depth > 1) ropts.band_jobs = 2;
   // every frame searched from the root (no chain between frames), or the temporal chain
   const bool each_full = (full_mode & VY_WALK_FULL_EACH) != 0;
   const int cut_mode = full_mode & ~VY_WALK_FULL_EACH;
@@ -116,7 +123,7 @@ extern "C" int vy_walkthrough(const vy_scene* scene, const vy_camera* cams, int6
       break;
     }
     float* image = images[i % n_images];
-    err = vy_render(scene, cuts[k], &cams[i], opts, image, ctxs[k], st);
+    err = vy_render(scene, cuts[k], &cams[i], &ropts, image, ctxs[k], st);
     if (err == VY_OK && stats)
       err = render_frame_finish(cuts[k], ctxs[k], image, cams[i].width, cams[i].height, stats + i, st);
     if (err == VY_OK && frame_ms) {

@@ -189,14 +189,17 @@ def test_walks_are_bitwise_identical(tiny, tiny_cams, filt):
                 assert np.array_equal(a, b)
     with pytest.raises(vy.VoyagerError):
         vy.vy_render(sc, cut, tiny_cams[0], ctx, walk=3)
+    with pytest.raises(vy.VoyagerError):
+        vy.vy_render(sc, cut, tiny_cams[0], ctx, band_jobs=3)
 
 
 @pytest.mark.parametrize("n,dim", [(60000, 0.0), (60000, 4.0), (130000, 0.0), (130000, 4.0), (130000, 8.0)])
 def test_heavy_tiles_band_jobs(n, dim):
     """Tiles with more than 4096 pairs are blended band by band by separate
-    waves in the automatic mode; the image equals the workgroup walks bit for
-    bit (with and without the filter) and matches the oracle. `dim` lowers the
-    opacity logits so that pixels stop later or never."""
+    waves in the automatic mode, as halves of bands (band_jobs 1, the default
+    of vy_render) or whole bands (band_jobs 2); the image equals the workgroup
+    walks bit for bit (with and without the filter) and matches the oracle.
+    `dim` lowers the opacity logits so that pixels stop later or never."""
     vy = require_gpu()
     W, H = 64, 48
     leaves = scenegen.random_gaussians(n, 11, W, H, depth_range=(1.0, 60.0), scale_range=(-4.0, -1.0))
@@ -213,6 +216,8 @@ def test_heavy_tiles_band_jobs(n, dim):
         for walk in (0, 1, 2):
             imgs[filt, walk] = vy.vy_render(sc, cut, cam, ctx, alpha_filter=filt, walk=walk).cpu().numpy()
             vy.check(ctx.status()[0])
+        for bj in (1, 2):
+            imgs[filt, 0, bj] = vy.vy_render(sc, cut, cam, ctx, alpha_filter=filt, band_jobs=bj).cpu().numpy()
         keys, vals, ranges = ctx.pairs(W, H)
         longest[filt] = int((ranges[:, 1] - ranges[:, 0]).max())
     assert longest[False] > (8192 if n > 100000 else 4096) and (dim > 0 or longest[True] > 4096), longest

@@ -290,7 +290,7 @@ def test_struct_layouts_match_the_header(tmp_path):
                              "batch_gaussians", "batch_pairs"],
         "vy_camera": ["R", "pos", "fx", "fy", "cx", "cy", "width", "height", "znear"],
         "vy_view": ["scene", "cut", "cam", "image"],
-        "vy_render_opts": ["alpha_filter", "bg", "save_state", "split_min_pairs", "walk", "lut_entries"],
+        "vy_render_opts": ["alpha_filter", "bg", "save_state", "split_min_pairs", "walk", "lut_entries", "band_jobs"],
         "vy_grads": ["mean", "log_scale", "quat", "opacity_logit", "sh", "mean2d", "quat_raw"],
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "vy_serve.h"', "int main(void) {"]
