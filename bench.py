@@ -416,7 +416,7 @@ def main():
         ops = BLEND_OPS_EVAL * avg["evals"] + BLEND_OPS_EXP * avg["contribs"]
         ops_per_launch = ops * K / dom_n
         achieved = ops_per_launch / (launch_ms * 1e-3) / 1e12
-        roofline = dict(kernel="blend_jobs<true,false,false>", bound="alu", achieved=round(achieved, 3),
+        roofline = dict(kernel="blend_jobs<true,false,false,false>", bound="alu", achieved=round(achieved, 3),
                         peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s", frac=round(achieved / FP32_VECTOR_PEAK_TFLOPS, 5),
                         traffic=traffic, peak_unpacked=FP32_UNPACKED_PEAK_TFLOPS,
                         frac_of_unpacked=round(achieved / FP32_UNPACKED_PEAK_TFLOPS, 5),

@@ -4,7 +4,7 @@
         per-kernel calls / average / total time (markdown table)
 
     python -m paper_2506_02774_amd.rocprof_summary traffic FETCH_DIR/run_counter_collection.csv \
-        WRITE_DIR/run_counter_collection.csv --copy-mib 1024 --kernel 'blend_jobs<true, false, false>' --stage blend
+        WRITE_DIR/run_counter_collection.csv --copy-mib 1024 --kernel 'blend_jobs<true, false, false, false>' --stage blend
 
         HBM traffic per dispatch from FETCH_SIZE and WRITE_SIZE (KiB per
         dispatch), each scaled by the factor that makes the reference copy
@@ -122,12 +122,12 @@ def main():
     b.add_argument("write_csv")
     b.add_argument("--copy-mib", type=int, default=1024)
     b.add_argument("--copy-regex", default=r"AUnaryFunctor.*MulFunctor|AUnaryFunctor")
-    b.add_argument("--kernel", default="blend_jobs<true, false, false>")
+    b.add_argument("--kernel", default="blend_jobs<true, false, false, false>")
     b.add_argument("--stage", default="blend")
     b.add_argument("--source", default=os.path.join(HERE, "csrc", "render.hip"))
     c = sub.add_parser("counters")
     c.add_argument("csv", nargs="+")
-    c.add_argument("--kernels", default="blend_jobs<true, false, false>")
+    c.add_argument("--kernels", default="blend_jobs<true, false, false, false>")
     args = ap.parse_args()
     if args.cmd == "stats":
         stats(args.csv, args.top)
