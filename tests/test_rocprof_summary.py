@@ -14,7 +14,7 @@ from paper_2506_02774_amd import rocprof_summary as rs  # noqa: E402
 
 COPY = "void at::native::vectorized_elementwise_kernel<4, at::native::AUnaryFunctor<float, float, float, " \
        "at::native::binary_internal::MulFunctor<float> >, std::array<char*, 2ul> >(int, float)"
-BLEND = "void (anonymous namespace)::blend_jobs<true, false, false>(unsigned int const*, int)"
+BLEND = "void (anonymous namespace)::blend_jobs<true, false, false, false>(unsigned int const*, int)"
 
 
 def _csv(path, rows):
@@ -26,7 +26,7 @@ def _csv(path, rows):
 
 
 def test_short_names():
-    assert rs.short(BLEND) == "blend_jobs<true, false, false>"
+    assert rs.short(BLEND) == "blend_jobs<true, false, false, false>"
     assert rs.short("void (anonymous namespace)::project<true>(int const*)") == "project<true>"
 
 
@@ -54,9 +54,9 @@ def test_counter_table(tmp_path):
     old = sys.stdout
     sys.stdout = out
     try:
-        rs.counters([str(f)], ["blend_jobs<true, false, false>", "absent"])
+        rs.counters([str(f)], ["blend_jobs<true, false, false, false>", "absent"])
     finally:
         sys.stdout = old
     lines = out.getvalue().splitlines()
     assert lines[0] == "| kernel | dispatches | SQ_INSTS_VALU | SQ_WAVES |"
-    assert lines[2] == "| `blend_jobs<true, false, false>` | 2 | 8 | 200 |" and len(lines) == 3
+    assert lines[2] == "| `blend_jobs<true, false, false, false>` | 2 | 8 | 200 |" and len(lines) == 3
