@@ -410,7 +410,8 @@ __global__ __launch_bounds__(256) void lod_bfs(const int32_t* __restrict__ in_q,
 // of the partitions before it (at most a few thousand words, read from L2)
 // instead of waiting on a look-back chain across the partitions.
 // A partition is read as 4 rounds of 256 consecutive words (one per thread);
-// each round's ids are gathered in LDS and written out with coalesced stores.
+// each wave gathers its words' ids of a round in LDS and writes them out with
+// coalesced stores.
 // The 8 per-thread counts (2 bitmaps x 4 rounds, each <= 32) are scanned in
 // one pass as 16-bit fields of 4 words (a partition's totals stay below 2^16).
 constexpr int kWordsPerThread = 4, kWordsPerPart = 256 * kWordsPerThread;
@@ -538,6 +539,10 @@ __global__ __launch_bounds__(256) void lod_compact(int64_t n_words, uint32_t* __
     }
   }
   __syncthreads();
+  // each wave stages the ids of its 64 words of a round in its own LDS slice
+  // and writes them as one contiguous, coalesced range: no workgroup barriers
+  const uint32_t ln = lane();
+  int32_t* slice = s_ids + (threadIdx.x >> 6) * (64 * 32);
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     int32_t* out = (q == 0 ? Fout : Cout) + s_ex[q];
@@ -545,17 +550,27 @@ __global__ __launch_bounds__(256) void lod_compact(int64_t n_words, uint32_t* __
 #pragma unroll
     for (int k = 0; k < kWordsPerThread; ++k) {
       const int64_t w = base + k * 256 + threadIdx.x;
-      uint32_t m = wd[q][k], o = off[q][k];
+      uint32_t m = wd[q][k];
+      // the wave's first offset (lane 0's: the scan is ascending over threads)
+      // and its id count (the last lane's offset plus its bits)
+      const uint32_t o0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)off[q][k]);
+      const uint32_t oe = off[q][k] + (uint32_t)__popc(m);
+      const uint32_t n = (uint32_t)__builtin_amdgcn_readlane((int)oe, 63) - o0;
+      uint32_t o = off[q][k] - o0;
       while (m) {
         const int b = __ffs(m) - 1;
         m &= m - 1;
-        s_ids[o++] = (int32_t)(w * 32 + b);
+        slice[o++] = (int32_t)(w * 32 + b);
       }
-      __syncthreads();
-      for (uint32_t i = threadIdx.x; i < rt[q][k]; i += 256) out[r0 + i] = s_ids[i];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (uint32_t i = ln; i < n; i += 64) out[r0 + o0 + i] = slice[i];
       r0 += rt[q][k];
       if (wd[q][k]) (q == 0 ? fbits : cbits)[w] = 0u;
-      __syncthreads();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
   if (part == n_parts - 1 && threadIdx.x == 0) {
