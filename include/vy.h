@@ -253,13 +253,14 @@ typedef struct vy_render_opts {
                               splitting). The image is bitwise the same for any
                               value; splitting forgoes early termination. */
   int32_t walk;         /* how a band of 16x4 pixels walks its tile list: 0 (auto)
-                           per chunk of 64 entries, all pixels together when
-                           most entries cover most pixels, else each pixel over
-                           its own entries, and tiles with more than 4096 pairs
-                           are blended band by band by waves of their own;
-                           1: always together; 2: always per pixel (1 and 2
-                           blend every tile with one workgroup). The image is
-                           bitwise the same for any value. */
+                           each pixel over its own entries, and once at most 4
+                           pixels of the band still blend, a chunk's entries in
+                           parallel for one pixel at a time; tiles with more
+                           than 4096 pairs are blended band by band by waves of
+                           their own (band_jobs); 1: all pixels together over
+                           every entry; 2: each pixel over its own entries (1
+                           and 2 blend every tile with one workgroup). The
+                           image is bitwise the same for any value. */
   int32_t lut_entries;  /* 0: alpha uses the exponential. m in 1..128: the
                            lookup table of Section 4.2 (Eq. 5): e^rho is read
                            from m + 1 values e^(-5.55 k / m), k = 0..m, at

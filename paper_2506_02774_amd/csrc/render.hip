@@ -1185,14 +1185,15 @@ VY_DEV uint64_t cover_masks(const Stage& S, int w, int jj, int m, float xa, floa
 
 // Blend band-list entries [jc, jc + mc) (mc <= 64) of the wave's LDS region
 // w, tile-list positions counted from b0, for the band whose first pixel
-// centre is (xa, ya): per pixel (each lane over its own entries) when most
-// entries cover few pixels of the band, else all pixels together.
+// centre is (xa, ya). walk 0 (automatic) and 2: per pixel, each lane over its
+// own entries, and (walk 0) entry-parallel once at most kTransposedMax pixels
+// are live; walk 1, and split jobs: all pixels together. (On the full-scale
+// walkthrough the per-pixel walk measured faster than the together walk also
+// on chunks whose busiest pixel covers most of the entries.)
 template <bool FILTER, bool SPLIT, bool SAVE, bool LUT>
 VY_DEV void walk_chunk(const Stage& S, int w, int jc, int mc, uint32_t b0, float xa, float ya, float fxp, float fyp,
                        PixAcc& A, const SplitOut& so, int walk, const ExpLut& L) {
   if (!SPLIT && walk != 1) {
-    // small pixel boxes (far Gaussians) cover few pixels of the band: then
-    // every pixel walks only its own entries of this chunk
     const uint64_t live = __ballot(!A.done);
     if (live == 0ull) return;
     // the tail of a long list, where few pixels still blend: entry-parallel walk per pixel
@@ -1202,20 +1203,8 @@ VY_DEV void walk_chunk(const Stage& S, int w, int jc, int mc, uint32_t b0, float
     }
     uint64_t mk = cover_masks(S, w, jc, mc, xa, ya, (int)(threadIdx.x & 63));
     if (A.done) mk = 0ull;
-    // the busiest pixel's entry count (0..64), by a binary search over
-    // ballots: wave-uniform, and no LDS round trips on the critical path
-    const int pc = __popcll(mk);
-    int mx = 0;
-#pragma unroll
-    for (int b = 6; b >= 0; --b)
-      if (__ballot(pc >= (mx | (1 << b))) != 0ull) mx |= 1 << b;
-    // per pixel when the busiest pixel needs under 70 % of the chunk (an
-    // entry of the per-pixel walk costs about twice one of the band walk,
-    // which needs fewer steps: measured best between 60 and 80 %)
-    if (walk == 2 || mx * 10 < mc * 7) {
-      blend_sparse<FILTER, SAVE, LUT>(S, w, jc, mk, b0, fxp, fyp, A, L);
-      return;
-    }
+    blend_sparse<FILTER, SAVE, LUT>(S, w, jc, mk, b0, fxp, fyp, A, L);
+    return;
   }
   for (int jj = jc; jj < jc + mc; jj += 4) {
     if (__ballot(!A.done) == 0ull) return;   // the whole band has terminated
