@@ -406,8 +406,20 @@ int vy_render_status(vy_render_ctx* ctx, int64_t* n_pairs, int64_t* n_visible, v
 int vy_render_saved(const vy_render_ctx* ctx, const float** T_final, const int32_t** n_contrib,
                     const int32_t** n_eval, const int32_t** last_contrib, const float** mean2d);
 
+/* Device pointers to the last frame's sorted pairs ([n_pairs] each): the tile
+ * key (tile id in bits 0..15; above it the pair's pixel box within the tile,
+ * 4 bits each: first and last column, first and last row that may hold a
+ * pixel centre the Gaussian reaches) and the cut position of the Gaussian;
+ * and the tile ranges ([tiles] uint2, begin and end in the pair list). */
 int vy_render_pairs(const vy_render_ctx* ctx, const uint32_t** tile_keys, const uint32_t** cut_pos,
                     const uint32_t** ranges);
+/* Device pointers to the projected records of the cut ([n] float4 each, cut
+ * order: mean2d and rho coefficients A, B; C, theta, filter threshold,
+ * depth; rgb and the packed pixel half-extents) and the binning records
+ * ([n] uint4: tile rect x0 | y0 << 16, x1 | y1 << 16, kept-tile mask, and the
+ * pair count; for rects of at most 32 tiles (mask != 0) the count is the low
+ * 8 bits and the pixel box of vy_render_pairs' keys, for the rect's first and
+ * last tiles, the 16 bits above it). */
 int vy_render_projected(const vy_render_ctx* ctx, const float** rec0, const float** rec1, const float** rec2,
                         const uint32_t** bin_rec);
 

@@ -420,8 +420,11 @@ class RenderContext:
             out.append(Lc)
         return tuple(out)
 
-    def pairs(self, width, height):
-        """Last frame's sorted pairs (tile ids, cut positions) and tile ranges (synchronises)."""
+    def pairs(self, width, height, raw=False):
+        """Last frame's sorted pairs (tile ids, cut positions) and tile ranges
+        (synchronises). The device keys hold the tile id in their low 16 bits
+        and the pair's pixel box within the tile above it; `raw` returns them
+        whole, else the tile ids."""
         rc, n_pairs, n_vis = self.status()
         check(rc, "vy_render_status")
         pk, pv, pr = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
@@ -435,7 +438,7 @@ class RenderContext:
             _copy_d2h(keys, pk.value)
             _copy_d2h(vals, pv.value)
         _copy_d2h(ranges, pr.value)
-        return keys, vals, ranges
+        return (keys if raw else keys & np.uint32(0xFFFF)), vals, ranges
 
     def projected(self, n):
         """Projected records of the first n cut positions (synchronises): rec0, rec1,

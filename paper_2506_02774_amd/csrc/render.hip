@@ -200,6 +200,38 @@ VY_DEV bool tile_keep(const float4 p0, const float4 p1, float relax, int tx, int
   return rm * (1.f - relax) >= p1.z;
 }
 
+// The pixel box of a Gaussian (centre (mx, my), half-extents rx, ry) within
+// the first and last tile columns and rows of its tile rect [x0, x1] x [y0, y1]:
+// the first column of tile x0 and the last of tile x1 (and likewise for
+// rows) that may hold a pixel centre passing the pixel rule, with one pixel
+// of slack for rounding (a superset), clamped to the tile. 4 bits each:
+// first column | last column << 4 | first row << 8 | last row << 12. Tiles
+// between the first and last take every column (row); a pair's key carries
+// its own tile's range (pair_emit), so that band jobs can tell which pairs
+// may reach their band from the sorted keys alone.
+VY_DEV uint32_t pixel_box(float mx, float my, float rx, float ry, int x0, int y0, int x1, int y1) {
+  const int px0 = (int)floorf(mx - rx - 1.5f), px1 = (int)ceilf(mx + rx + 0.5f);
+  const int py0 = (int)floorf(my - ry - 1.5f), py1 = (int)ceilf(my + ry + 0.5f);
+  const uint32_t a = (uint32_t)min(max(px0 - x0 * kTileSize, 0), kTileSize - 1);
+  const uint32_t b = (uint32_t)min(max(px1 - x1 * kTileSize, 0), kTileSize - 1);
+  const uint32_t c = (uint32_t)min(max(py0 - y0 * kTileSize, 0), kTileSize - 1);
+  const uint32_t d = (uint32_t)min(max(py1 - y1 * kTileSize, 0), kTileSize - 1);
+  return a | (b << 4) | (c << 8) | (d << 12);
+}
+constexpr uint32_t kWholeTileBox = 0xF0F0u;   // columns 0..15, rows 0..15
+
+// The pair count of a binning record's (mask, count word): rects of at most
+// kBigArea tiles (mask != 0) keep the count in the low 8 bits and the pixel
+// box above it; big rects keep the whole word for their count.
+VY_DEV uint32_t rec_count(uint2 mask_count) { return mask_count.x ? (mask_count.y & 0xFFu) : mask_count.y; }
+
+// The pixel box of a pair's tile (tx, ty) as key bits 16..31 (pair_emit).
+VY_DEV uint32_t pair_box_bits(uint32_t box, int tx, int ty, int x0, int y0, int x1, int y1) {
+  const uint32_t lx = tx == x0 ? (box & 15u) : 0u, hx = tx == x1 ? ((box >> 4) & 15u) : 15u;
+  const uint32_t ly = ty == y0 ? ((box >> 8) & 15u) : 0u, hy = ty == y1 ? ((box >> 12) & 15u) : 15u;
+  return (lx | (hx << 4) | (ly << 8) | (hy << 12)) << 16;
+}
+
 // One cut Gaussian (cut position i, node id `node`): EWA projection, SH
 // colour, pixel extents, tile rect and (FILTER) the Eq. 4 tests; writes its
 // records at position i and returns its depth key (0xFFFFFFFF when culled) and
@@ -217,7 +249,7 @@ VY_DEV uint32_t project_one(uint32_t i, int32_t node, const float4* __restrict__
   bool valid = z > cam.near;
   uint32_t count = 0, mask = 0, key = 0xFFFFFFFFu;
   float4 o0 = make_float4(0, 0, 0, 0), o1 = make_float4(0, 0, 0, 0), o2 = make_float4(0, 0, 0, 0);
-  uint32_t r0 = 0, r1 = 0;
+  uint32_t r0 = 0, r1 = 0, box = 0;
   float relax = 0.f;
   if (valid) {
     // Sigma3 = M M^T with M = Rq diag(s)
@@ -306,15 +338,16 @@ VY_DEV uint32_t project_one(uint32_t i, int32_t node, const float4* __restrict__
           }
           if (count == 0) valid = false;
           else key = __float_as_uint(z);
+          if (valid && area <= kBigArea) box = pixel_box(mx, my, rx, ry, x0, y0, x1, y1);
         }
       }
     }
   }
-  if (!valid) count = mask = 0;
+  if (!valid) count = mask = box = 0;
   pg0[i] = o0;
   pg1[i] = o1;
   pg2[i] = o2;
-  prec[i] = make_uint4(r0, r1, mask, count);
+  prec[i] = make_uint4(r0, r1, mask, count | (box << 8));
   prelax[i] = relax;
   *count_out = count;
   return key;
@@ -495,7 +528,7 @@ __global__ __launch_bounds__(256) void pair_emit(const uint32_t* __restrict__ so
       uint32_t v = 0;
       if (i < n) {
         const uint32_t g = sorted_val[i];
-        v = g < n_g ? prec[g].w : 0u;
+        if (g < n_g) v = rec_count(reinterpret_cast<const uint2*>(prec + g)[1]);
       }
       s_v[k * 256 + threadIdx.x] = v;
     }
@@ -521,13 +554,14 @@ __global__ __launch_bounds__(256) void pair_emit(const uint32_t* __restrict__ so
       const uint32_t g = sorted_val[i];
       if (g >= n_g) continue;
       const uint4 r = prec[g];
-      if (r.w == 0) continue;
+      if (rec_count(make_uint2(r.z, r.w)) == 0) continue;
       uint32_t o = s_v[k * 256 + threadIdx.x];
       if (r.z == 0) {   // big: emit_big writes its pairs
         offsets[g] = o;
         continue;
       }
-      const int x0 = r.x & 0xFFFF, y0 = r.x >> 16, w = (int)(r.y & 0xFFFF) - x0 + 1;
+      const int x0 = r.x & 0xFFFF, y0 = r.x >> 16, x1 = r.y & 0xFFFF, y1 = r.y >> 16, w = x1 - x0 + 1;
+      const uint32_t box = r.w >> 8;
       const uint64_t wmask = (1ull << w) - 1ull;
       uint64_t bits = r.z;
       int tx_n = tiles_x;
@@ -544,7 +578,7 @@ __global__ __launch_bounds__(256) void pair_emit(const uint32_t* __restrict__ so
           rb &= rb - 1;
           const uint32_t t = tbase + (uint32_t)(ty * tx_n + x0 + b);
           if (o < cap) {
-            tkey[o] = t;
+            tkey[o] = t | pair_box_bits(box, x0 + b, ty, x0, y0, x1, y1);
             tval[o] = g;
             atomicAdd(&s_hist[0][t & m0], 1u);
             atomicAdd(&s_hist[1][(t >> bits0) & 255u], 1u);
@@ -611,7 +645,7 @@ __global__ __launch_bounds__(256) void emit_big(const uint32_t* __restrict__ big
       const uint32_t pos = o + block_excl_scan256(keep ? 1u : 0u, s_scan, &tot);
       if (keep && pos < cap) {
         const uint32_t t = tbase + (uint32_t)(ty * tiles_x + tx);
-        tkey[pos] = t;
+        tkey[pos] = t | (kWholeTileBox << 16);
         tval[pos] = g;
         atomicAdd(&s_hist[0][t & m0], 1u);
         atomicAdd(&s_hist[1][(t >> bits0) & 255u], 1u);
@@ -630,10 +664,10 @@ __global__ __launch_bounds__(256) void tile_ranges(const uint32_t* __restrict__ 
                                                    uint2* __restrict__ ranges, uint32_t ntiles) {
   const uint32_t n = ctr[C_NPAIRS];
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const uint32_t t = key[i];
+    const uint32_t t = key[i] & 0xFFFFu;   // the tile id (the pixel box above it)
     if (t >= ntiles) continue;
-    if (i == 0 || key[i - 1] != t) ranges[t].x = i;
-    if (i + 1 == n || key[i + 1] != t) ranges[t].y = i + 1;
+    if (i == 0 || (key[i - 1] & 0xFFFFu) != t) ranges[t].x = i;
+    if (i + 1 == n || (key[i + 1] & 0xFFFFu) != t) ranges[t].y = i + 1;
   }
 }
 

@@ -128,7 +128,8 @@ def test_sorted_pairs(frame, filt):
     vy.vy_render(sc, cut, cam, ctx, alpha_filter=filt)
     keys, vals, ranges = ctx.pairs(cam.width, cam.height)
     r0, r1, r2, br = ctx.projected(len(C))
-    lo, hi, mask, count = br[:, 0], br[:, 1], br[:, 2], br[:, 3]
+    lo, hi, mask = br[:, 0], br[:, 1], br[:, 2]
+    count = np.where(mask != 0, br[:, 3] & 0xFF, br[:, 3])   # small rects: the pixel box above the count
     tx_n = (cam.width + 15) // 16
     # ranges partition the pair list by tile, in tile order
     nz = ranges[:, 1] > ranges[:, 0]
@@ -170,3 +171,23 @@ def test_sorted_pairs(frame, filt):
             k = (t // tx_n - y0) * w[g] + (t % tx_n - x0)
             bits[g] = bits.get(g, 0) | (1 << int(k))
     assert all(bits.get(int(g), 0) == int(mask[g]) for g in np.nonzero(small)[0])
+    # each key's pixel box (bits 16..31: first and last column, first and last
+    # row) holds every pixel of its tile where the blend's pixel rule, evaluated
+    # in float32 as the blend does, lets the Gaussian in
+    raw, _, _ = ctx.pairs(cam.width, cam.height, raw=True)
+    assert np.array_equal(raw & 0xFFFF, keys)
+    box = raw >> 16
+    lx, hx, ly, hy = box & 15, (box >> 4) & 15, (box >> 8) & 15, (box >> 12) & 15
+    tx, ty = (keys % tx_n).astype(np.int64), (keys // tx_n).astype(np.int64)
+    ext = np.ascontiguousarray(r2[vals, 3]).view(np.uint32)
+    rx, ry = (ext & 0xFFFF).astype(np.float32), (ext >> 16).astype(np.float32)
+    mx, my = r0[vals, 0].astype(np.float32), r0[vals, 1].astype(np.float32)
+    c = np.arange(16)
+    cx = (tx[:, None] * 16 + c[None, :]).astype(np.float32) + np.float32(0.5)
+    cy = (ty[:, None] * 16 + c[None, :]).astype(np.float32) + np.float32(0.5)
+    okx = np.abs(mx[:, None] - cx) <= rx[:, None]
+    oky = np.abs(my[:, None] - cy) <= ry[:, None]
+    assert not (okx & ((c[None, :] < lx[:, None]) | (c[None, :] > hx[:, None]))).any()
+    assert not (oky & ((c[None, :] < ly[:, None]) | (c[None, :] > hy[:, None]))).any()
+    # and it is not the whole tile for most pairs (the far city's Gaussians are small)
+    assert ((hx - lx) < 15).mean() > 0.3, ((hx - lx) < 15).mean()
