@@ -1481,10 +1481,160 @@ VY_DEV void blend_band(Stage& S, int w, int tx, int ty, int band, int half, uint
   if (inside) pixel_out<SAVE>(A, cam, px, py, pb, pe, img, Tout, Nout, Eout, Lout);
 }
 
+// Band job over candidate batches (with the filter, without saved state).
+// The sorted tile keys carry each pair's pixel box within its tile, so the
+// wave first scans keys and cut positions, coalesced and two bulks of 256
+// ahead, for the pairs whose box meets the job's pixels, and gathers the
+// random 48-byte records of those candidates only, a batch of 192..256 at a
+// time, while it walks the previous batch. A sparse band (few of its tile's
+// pairs reach it, and its pixels stop late) then pays one record-gather
+// latency per batch of candidates instead of one per 256 pairs of its list.
+// Each batch is tested (pixel box, Eq. 4) and compacted exactly as in
+// blend_band, in list order, so every pixel's result is bitwise the same.
+constexpr int kCandBulk = 4;   // blocks of 64 keys per bulk
+
+template <bool LUT>
+VY_DEV void blend_band_keys(Stage& S, uint32_t* __restrict__ cand, int w, int tx, int ty, int band, int half,
+                            uint32_t pb, uint32_t pe, const uint32_t* __restrict__ tkey,
+                            const uint32_t* __restrict__ tval, const float4* __restrict__ pg0,
+                            const float4* __restrict__ pg1, const float4* __restrict__ pg2,
+                            const float* __restrict__ prelax, uint32_t n_g, const RCam& cam,
+                            float* __restrict__ img, int walk, const ExpLut& L) {
+  const int l = (int)(threadIdx.x & 63);
+  const int px = tx * kTileSize + (l & 15), py = ty * kTileSize + band * 4 + (l >> 4);
+  const bool inside = px < cam.W && py < cam.H && (half < 0 || (l & 15) >> 3 == half);
+  PixAcc A;
+  pix_init(A, inside);
+  const SplitOut so{};
+  const float fxp = px + 0.5f, fyp = py + 0.5f;
+  const float xa = tx * kTileSize + 0.5f, ya = ty * kTileSize + band * 4 + 0.5f;
+  const float xh = half > 0 ? xa + 8.f : xa, xw = half < 0 ? 15.f : 7.f;
+  // the job's pixels in tile-local columns and rows, for the key boxes
+  const uint32_t cxl = half > 0 ? 8u : 0u, cxh = half == 0 ? 7u : 15u;
+  const uint32_t ryl = (uint32_t)band * 4u, ryh = ryl + 3u;
+  // key bulks: a = the one being scanned (block qi next), b = the one after
+  uint32_t ka[kCandBulk], va[kCandBulk], kb[kCandBulk], vb[kCandBulk];
+  uint32_t bulk = pb;   // first position of bulk a
+  int qi = 0;
+#pragma unroll
+  for (int q = 0; q < kCandBulk; ++q) {
+    const uint32_t p0 = pb + q * 64 + l, p1 = p0 + 64 * kCandBulk;
+    ka[q] = p0 < pe ? tkey[p0] : 0u;
+    va[q] = p0 < pe ? tval[p0] : 0u;
+    kb[q] = p1 < pe ? tkey[p1] : 0u;
+    vb[q] = p1 < pe ? tval[p1] : 0u;
+  }
+  // collects the next batch of candidates' cut positions into cand[0, n)
+  auto assemble = [&]() -> int {
+    int n = 0;
+    for (;;) {
+      const uint32_t sp = bulk + (uint32_t)qi * 64u;
+      if (sp >= pe) break;
+      uint32_t k = ka[0], v = va[0];
+#pragma unroll
+      for (int q = 1; q < kCandBulk; ++q) {
+        k = qi == q ? ka[q] : k;
+        v = qi == q ? va[q] : v;
+      }
+      const uint32_t bx = k >> 16;
+      const bool c = sp + l < pe && (bx & 15u) <= cxh && ((bx >> 4) & 15u) >= cxl && ((bx >> 8) & 15u) <= ryh &&
+                     (bx >> 12) >= ryl;
+      const uint64_t bal = __ballot(c);
+      const int m = __popcll(bal);
+      if (n + m > 256) break;   // this block opens the next batch
+      if (c) cand[n + __popcll(bal & lanemask_lt())] = v;
+      n += m;
+      if (++qi == kCandBulk) {   // bulk a done: b becomes a, the one after b is loaded
+        qi = 0;
+        bulk += 64u * kCandBulk;
+#pragma unroll
+        for (int q = 0; q < kCandBulk; ++q) {
+          ka[q] = kb[q];
+          va[q] = vb[q];
+          const uint32_t p = bulk + 64u * kCandBulk + q * 64 + l;
+          kb[q] = p < pe ? tkey[p] : 0u;
+          vb[q] = p < pe ? tval[p] : 0u;
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    return n;
+  };
+  // records of a batch's candidates: lane l holds slots h * 64 + l
+  float4 qa[kBandParts], qb[kBandParts], qc[kBandParts];
+  float qr[kBandParts];
+#pragma unroll
+  for (int h = 0; h < kBandParts; ++h) {
+    qa[h] = qb[h] = qc[h] = make_float4(0.f, 0.f, 0.f, 0.f);
+    qr[h] = 1.f;
+  }
+  auto gather = [&](int n) {
+#pragma unroll
+    for (int h = 0; h < kBandParts; ++h) {
+      const int j = h * 64 + l;
+      if (j < n) {
+        uint32_t g = cand[j];
+        if (g >= n_g) g = 0;
+        qa[h] = pg0[g];
+        qb[h] = pg1[g];
+        qc[h] = pg2[g];
+        qr[h] = prelax[g];
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();   // cand is read before the next assembly overwrites it
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+  int cnt = assemble();
+  gather(cnt);
+  while (cnt > 0) {
+    if (__ballot(!A.done) == 0ull) break;
+    // the batch's exact tests and compaction, in list order
+    uint32_t base = 0;
+#pragma unroll
+    for (int h = 0; h < kBandParts; ++h) {
+      const int j = h * 64 + l;
+      bool hit = j < cnt && band_hit(qa[h].x, qa[h].y, qc[h].w, xh, ya, xw);
+      if (hit && qr[h] < 0.25f)   // Eq. 4 over the job's pixel centres, as in blend_band
+        hit = rect_rho_max(qa[h].x, qa[h].y, qa[h].z, qa[h].w, qb[h].x, xh, ya, xh + xw, ya + 3.f) * (1.f - qr[h]) >=
+              qb[h].z;
+      const uint64_t bal = __ballot(hit);
+      if (hit) {
+        const uint32_t pos = base + (uint32_t)__popcll(bal & lanemask_lt());
+        const uint32_t ex = __float_as_uint(qc[h].w);
+        S.list[w][pos] = (depth_bin(qb[h].w) << 8) | (uint32_t)j;
+        S.r0[w][pos] = qa[h];
+        S.r1[w][pos] = make_float4(qb[h].x, qb[h].y, qb[h].z, (float)(ex >> 16));
+        S.r2[w][pos] = make_float4(qc[h].x, qc[h].y, qc[h].z, (float)(ex & 0xFFFFu));
+      }
+      base += (uint32_t)__popcll(bal);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // the next batch's candidates, and their records in flight during the walk
+    const int next = assemble();
+    gather(next);
+    const int m = (int)base;
+    for (int jc = 0; jc < m; jc += 64) {
+      if (__ballot(!A.done) == 0ull) break;
+      walk_chunk<true, false, false, LUT>(S, w, jc, m - jc < 64 ? m - jc : 64, 0u, xa, ya, fxp, fyp, A, so, walk, L);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    cnt = next;
+  }
+  if (inside) pixel_out<false>(A, cam, px, py, pb, pe, img, nullptr, nullptr, nullptr, nullptr);
+}
+
 // BATCH: the tiles are the global tiles of a batch of views (ntiles in all);
 // each job finds its view (camera, image) from the views' first tiles.
 template <bool FILTER, bool SAVE, bool LUT, bool BATCH>
-__global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ ranges, const uint32_t* __restrict__ tval,
+__global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ ranges, const uint32_t* __restrict__ tkey,
+                                                  const uint32_t* __restrict__ tval,
                                                   const float4* __restrict__ pg0, const float4* __restrict__ pg1,
                                                   const float4* __restrict__ pg2, const float* __restrict__ prelax,
                                                   RCam cam, int ntiles,
@@ -1502,6 +1652,7 @@ __global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ rang
   __shared__ uint32_t s_job;
   __shared__ float s_lut[LUT ? kLutMax + 1 : 1];
   __shared__ uint32_t s_toff[BATCH ? kMaxViews + 1 : 1];
+  __shared__ uint32_t s_cand[FILTER && !SAVE ? 4 * 256 : 1];   // band jobs' candidate batches, per wave
   ExpLut L{s_lut, 0.f, 0};
   if (LUT) {
     // table values in double, rounded once to float
@@ -1545,8 +1696,13 @@ __global__ __launch_bounds__(256) void blend_jobs(const uint2* __restrict__ rang
         vimg = views[v].img;
         lt = tile - s_toff[v];
       }
-      blend_band<FILTER, SAVE, LUT>(S, w, (int)lt % vc.tiles_x, (int)lt / vc.tiles_x, band, half, pb, pe, tval, pg0,
-                                    pg1, pg2, prelax, n_g, vc, vimg, Tout, Nout, Eout, Lout, walk, L);
+      if (FILTER && !SAVE)
+        blend_band_keys<LUT>(S, s_cand + (FILTER && !SAVE ? w * 256 : 0), w, (int)lt % vc.tiles_x,
+                             (int)lt / vc.tiles_x, band, half, pb, pe, tkey, tval, pg0, pg1, pg2, prelax, n_g, vc,
+                             vimg, walk, L);
+      else
+        blend_band<FILTER, SAVE, LUT>(S, w, (int)lt % vc.tiles_x, (int)lt / vc.tiles_x, band, half, pb, pe, tval,
+                                      pg0, pg1, pg2, prelax, n_g, vc, vimg, Tout, Nout, Eout, Lout, walk, L);
     }
     __builtin_amdgcn_s_setprio(0);
     return;
@@ -2814,9 +2970,9 @@ int vy_render_batch(const vy_view* views, int32_t n, const vy_render_opts* opts,
     const RCam none{};
 #define VY_BLEND_BATCH(F, LT)                                                                                    \
   blend_jobs<F, false, LT, true><<<band_wgs + 2048, 256, 0, st>>>(                                             \
-      c->ranges, c->tval[0], c->pg0, c->pg1, c->pg2, c->prelax, none, ntiles, c->tile_flag, c->tiers, nullptr,   \
-      nullptr, nullptr, nullptr, c->ctr, gcap, pcap, nullptr, nullptr, nullptr, nullptr, nullptr, walk,         \
-      band_wgs, half_bands, lut_m, b->d_views, n)
+      c->ranges, c->tkey[0], c->tval[0], c->pg0, c->pg1, c->pg2, c->prelax, none, ntiles, c->tile_flag,         \
+      c->tiers, nullptr, nullptr, nullptr, nullptr, c->ctr, gcap, pcap, nullptr, nullptr, nullptr, nullptr,      \
+      nullptr, walk, band_wgs, half_bands, lut_m, b->d_views, n)
     if (filter) {
       if (lut_m > 0) VY_BLEND_BATCH(true, true); else VY_BLEND_BATCH(true, false);
     } else {
@@ -2980,9 +3136,9 @@ static int render_impl(const vy_scene* scene, const vy_cut* cut, const vy_camera
     ProfScope ps(VY_STAGE_BLEND, st);
 #define VY_BLEND_JOBS(F, S, LT)                                                                                 \
   blend_jobs<F, S, LT, false><<<band_wgs + 2048, 256, 0, st>>>(                                                 \
-      c->ranges, c->tval[0], c->pg0, c->pg1, c->pg2, c->prelax, rc, ntiles, c->tile_flag, c->tiers, c->heavy_rec, \
-      c->jobs, c->bin_c, c->bin_n, c->ctr, gcap, pcap, image, c->T_final, c->n_contrib, c->n_eval,              \
-      c->last_contrib, walk, band_wgs, half_bands, lut_m, nullptr, 0)
+      c->ranges, c->tkey[0], c->tval[0], c->pg0, c->pg1, c->pg2, c->prelax, rc, ntiles, c->tile_flag, c->tiers,  \
+      c->heavy_rec, c->jobs, c->bin_c, c->bin_n, c->ctr, gcap, pcap, image, c->T_final, c->n_contrib,            \
+      c->n_eval, c->last_contrib, walk, band_wgs, half_bands, lut_m, nullptr, 0)
 #define VY_BLEND(F, S)                                                                                          \
   do {                                                                                                          \
     if (lut_m > 0) VY_BLEND_JOBS(F, S, true); else VY_BLEND_JOBS(F, S, false);                                  \
