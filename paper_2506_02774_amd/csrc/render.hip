@@ -203,15 +203,20 @@ VY_DEV bool tile_keep(const float4 p0, const float4 p1, float relax, int tx, int
 // The pixel box of a Gaussian (centre (mx, my), half-extents rx, ry) within
 // the first and last tile columns and rows of its tile rect [x0, x1] x [y0, y1]:
 // the first column of tile x0 and the last of tile x1 (and likewise for
-// rows) that may hold a pixel centre passing the pixel rule, with one pixel
-// of slack for rounding (a superset), clamped to the tile. 4 bits each:
+// rows) that may hold a pixel centre passing the pixel rule, clamped to the
+// tile. Column px passes when |mx - (px + 0.5)| <= rx, so the columns are
+// ceil(mx - rx - 0.5) .. floor(mx + rx - 0.5). The slack, 1/8 px plus
+// 2^-19 (|mx| + rx), is over 4x the rounding of these sums and of the rule's
+// own difference (about 2^-22 (|mx| + rx + 2^15) in all), so the box is a
+// superset at any centre and extent. 4 bits each:
 // first column | last column << 4 | first row << 8 | last row << 12. Tiles
 // between the first and last take every column (row); a pair's key carries
 // its own tile's range (pair_emit), so that band jobs can tell which pairs
 // may reach their band from the sorted keys alone.
 VY_DEV uint32_t pixel_box(float mx, float my, float rx, float ry, int x0, int y0, int x1, int y1) {
-  const int px0 = (int)floorf(mx - rx - 1.5f), px1 = (int)ceilf(mx + rx + 0.5f);
-  const int py0 = (int)floorf(my - ry - 1.5f), py1 = (int)ceilf(my + ry + 0.5f);
+  const float sx = 0.125f + (fabsf(mx) + rx) * 0x1p-19f, sy = 0.125f + (fabsf(my) + ry) * 0x1p-19f;
+  const int px0 = (int)ceilf(mx - rx - 0.5f - sx), px1 = (int)floorf(mx + rx - 0.5f + sx);
+  const int py0 = (int)ceilf(my - ry - 0.5f - sy), py1 = (int)floorf(my + ry - 0.5f + sy);
   const uint32_t a = (uint32_t)min(max(px0 - x0 * kTileSize, 0), kTileSize - 1);
   const uint32_t b = (uint32_t)min(max(px1 - x1 * kTileSize, 0), kTileSize - 1);
   const uint32_t c = (uint32_t)min(max(py0 - y0 * kTileSize, 0), kTileSize - 1);
