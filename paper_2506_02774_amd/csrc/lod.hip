@@ -492,13 +492,33 @@ __global__ __launch_bounds__(256) void lod_compact(int64_t n_words, uint32_t* __
   __shared__ int32_t s_ids[256 * 32];
   const uint32_t part = blockIdx.x;
   if (threadIdx.x < 2) s_ex[threadIdx.x] = 0u;
+  // the partition's bitmap words, in flight while the offsets are summed
+  const int64_t base = (int64_t)part * kWordsPerPart;
+  uint32_t wd[2][kWordsPerThread];
+#pragma unroll
+  for (int k = 0; k < kWordsPerThread; ++k) {
+    const int64_t w = base + k * 256 + threadIdx.x;
+    wd[0][k] = w < n_words ? fbits[w] : 0u;
+    wd[1][k] = w < n_words ? cbits[w] : 0u;
+  }
   __syncthreads();
   {
-    // the offsets of this partition's ids: totals of the partitions before it
+    // the offsets of this partition's ids: totals of the partitions before it,
+    // eight loads per thread in flight at a time
+    const uint2* __restrict__ pt = reinterpret_cast<const uint2*>(part_tot);
     uint32_t pa = 0u, pb = 0u;
-    for (uint32_t j = threadIdx.x; j < part; j += 256) {
-      pa += part_tot[2 * (size_t)j];
-      pb += part_tot[2 * (size_t)j + 1];
+    for (uint32_t j0 = threadIdx.x; j0 < part; j0 += 256 * 8) {
+      uint2 t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const uint32_t j = j0 + 256u * u;
+        t[u] = j < part ? pt[j] : make_uint2(0u, 0u);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        pa += t[u].x;
+        pb += t[u].y;
+      }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -509,14 +529,6 @@ __global__ __launch_bounds__(256) void lod_compact(int64_t n_words, uint32_t* __
       atomicAdd(&s_ex[0], pa);
       atomicAdd(&s_ex[1], pb);
     }
-  }
-  const int64_t base = (int64_t)part * kWordsPerPart;
-  uint32_t wd[2][kWordsPerThread];
-#pragma unroll
-  for (int k = 0; k < kWordsPerThread; ++k) {
-    const int64_t w = base + k * 256 + threadIdx.x;
-    wd[0][k] = w < n_words ? fbits[w] : 0u;
-    wd[1][k] = w < n_words ? cbits[w] : 0u;
   }
   // fields: .x = F rounds 0 | 1 << 16, .y = F rounds 2 | 3, .z/.w the same for C
   const uint4 cnt4 = make_uint4((uint32_t)__popc(wd[0][0]) | ((uint32_t)__popc(wd[0][1]) << 16),
