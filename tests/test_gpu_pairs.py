@@ -171,9 +171,17 @@ def test_sorted_pairs(frame, filt):
             k = (t // tx_n - y0) * w[g] + (t % tx_n - x0)
             bits[g] = bits.get(g, 0) | (1 << int(k))
     assert all(bits.get(int(g), 0) == int(mask[g]) for g in np.nonzero(small)[0])
-    # each key's pixel box (bits 16..31: first and last column, first and last
-    # row) holds every pixel of its tile where the blend's pixel rule, evaluated
-    # in float32 as the blend does, lets the Gaussian in
+    lx, hx, mx = check_key_boxes(ctx, cam, keys, vals, r0, r2)
+    # and it is not the whole tile for most pairs (the far city's Gaussians are small)
+    assert ((hx - lx) < 15).mean() > 0.3, ((hx - lx) < 15).mean()
+
+
+def check_key_boxes(ctx, cam, keys, vals, r0, r2):
+    """Each key's pixel box (bits 16..31: first and last column, first and
+    last row) holds every pixel of its tile where the blend's pixel rule,
+    evaluated in float32 as the blend does, lets the Gaussian in. Returns the
+    boxes' first and last columns and the pairs' centres' x."""
+    tx_n = (cam.width + 15) // 16
     raw, _, _ = ctx.pairs(cam.width, cam.height, raw=True)
     assert np.array_equal(raw & 0xFFFF, keys)
     box = raw >> 16
@@ -189,5 +197,44 @@ def test_sorted_pairs(frame, filt):
     oky = np.abs(my[:, None] - cy) <= ry[:, None]
     assert not (okx & ((c[None, :] < lx[:, None]) | (c[None, :] > hx[:, None]))).any()
     assert not (oky & ((c[None, :] < ly[:, None]) | (c[None, :] > hy[:, None]))).any()
-    # and it is not the whole tile for most pairs (the far city's Gaussians are small)
-    assert ((hx - lx) < 15).mean() > 0.3, ((hx - lx) < 15).mean()
+    return lx, hx, mx
+
+
+@pytest.mark.parametrize("filt", [False, True])
+def test_key_boxes_far_centres(filt):
+    """Key boxes of Gaussians centred far outside the image (up to about
+    27 000 pixels to the side) whose long, thin footprints still reach into
+    it: the rounding slack of the box grows with the centre's magnitude, and
+    the boxes stay supersets of the pixel rule there too."""
+    vy = require_gpu()
+    W, H = 64, 48
+    rng = np.random.default_rng(33)
+    n = 4000
+    z = rng.uniform(2.0, 12.0, n)
+    u = rng.choice([-1.0, 1.0], n) * np.exp(rng.uniform(np.log(2.0), np.log(500.0), n))   # x / z
+    v = rng.uniform(-0.4, 0.4, n)
+    x = u * z
+    mean = np.stack([x, v * z, z], 1).astype(np.float32)
+    # axis-aligned, long in x (about a third of the distance to the image's
+    # centre line, so that 3.33 sigma reaches back into the image or just
+    # misses it) and thin in y and z
+    ls = np.stack([np.log(np.abs(x) * rng.uniform(0.28, 0.4, n)),
+                   rng.uniform(-3.0, -1.5, n), rng.uniform(-3.0, -1.5, n)], 1).astype(np.float32)
+    q = np.tile(np.array([1.0, 0.0, 0.0, 0.0], np.float32), (n, 1))
+    lg = rng.uniform(1.0, 4.0, n).astype(np.float32)
+    shc = rng.normal(0, 0.2, (n, 16, 3)).astype(np.float32)
+    shc[:, 0] += 0.5
+    host = scenegen.build_hierarchy(dict(mean=mean, log_scale=ls, quat=q, opacity_logit=lg, sh=shc))
+    cam = scenegen.identity_camera(W, H)
+    sc = vy.Scene(host)
+    ctx = vy.RenderContext(sc.n, W, H, 1 << 22)
+    cut = vy.vy_lod_cut(sc, cam, 0.0)
+    F, C = cut.ids()
+    vy.vy_render(sc, cut, cam, ctx, alpha_filter=filt)
+    vy.check(ctx.status()[0])
+    keys, vals, ranges = ctx.pairs(W, H)
+    r0, r1, r2, br = ctx.projected(len(C))
+    lx, hx, mx = check_key_boxes(ctx, cam, keys, vals, r0, r2)
+    far = np.abs(mx) > 5000.0
+    print(f"{len(keys)} pairs, {int(far.sum())} of centres beyond 5000 px (max {np.abs(mx).max():.0f})", flush=True)
+    assert far.sum() > 50
