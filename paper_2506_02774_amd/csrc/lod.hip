@@ -415,6 +415,7 @@ __global__ __launch_bounds__(256) void lod_bfs(const int32_t* __restrict__ in_q,
 // The 8 per-thread counts (2 bitmaps x 4 rounds, each <= 32) are scanned in
 // one pass as 16-bit fields of 4 words (a partition's totals stay below 2^16).
 constexpr int kWordsPerThread = 4, kWordsPerPart = 256 * kWordsPerThread;
+static_assert(kWordsPerPart * 32 <= 65536, "lod_compact stages a partition's ids as 16-bit offsets");
 
 VY_DEV uint4 block_excl_scan256_x4(uint4 v, uint4* sh, uint4* total) {
   const uint32_t l = lane(), w = threadIdx.x >> 6;
@@ -489,7 +490,9 @@ __global__ __launch_bounds__(256) void lod_compact(int64_t n_words, uint32_t* __
                                                    const uint32_t* __restrict__ part_tot, uint32_t n_parts) {
   __shared__ uint4 s_scan4[4];
   __shared__ uint32_t s_ex[2];
-  __shared__ int32_t s_ids[256 * 32];
+  // ids staged as 16-bit offsets into the partition's 32768 node ids: 16 KB,
+  // so that every partition of a large tree is resident at once
+  __shared__ uint16_t s_ids[256 * 32];
   const uint32_t part = blockIdx.x;
   if (threadIdx.x < 2) s_ex[threadIdx.x] = 0u;
   // the partition's bitmap words, in flight while the offsets are summed
@@ -554,7 +557,8 @@ __global__ __launch_bounds__(256) void lod_compact(int64_t n_words, uint32_t* __
   // each wave stages the ids of its 64 words of a round in its own LDS slice
   // and writes them as one contiguous, coalesced range: no workgroup barriers
   const uint32_t ln = lane();
-  int32_t* slice = s_ids + (threadIdx.x >> 6) * (64 * 32);
+  uint16_t* slice = s_ids + (threadIdx.x >> 6) * (64 * 32);
+  const int32_t id0 = (int32_t)(base * 32);   // the partition's first node id
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     int32_t* out = (q == 0 ? Fout : Cout) + s_ex[q];
@@ -569,15 +573,16 @@ __global__ __launch_bounds__(256) void lod_compact(int64_t n_words, uint32_t* __
       const uint32_t oe = off[q][k] + (uint32_t)__popc(m);
       const uint32_t n = (uint32_t)__builtin_amdgcn_readlane((int)oe, 63) - o0;
       uint32_t o = off[q][k] - o0;
+      const uint32_t wl = (uint32_t)(k * 256 + threadIdx.x) * 32u;   // the word's first local id
       while (m) {
         const int b = __ffs(m) - 1;
         m &= m - 1;
-        slice[o++] = (int32_t)(w * 32 + b);
+        slice[o++] = (uint16_t)(wl + (uint32_t)b);
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      for (uint32_t i = ln; i < n; i += 64) out[r0 + o0 + i] = slice[i];
+      for (uint32_t i = ln; i < n; i += 64) out[r0 + o0 + i] = id0 + (int32_t)slice[i];
       r0 += rt[q][k];
       if (wd[q][k]) (q == 0 ? fbits : cbits)[w] = 0u;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
