@@ -574,15 +574,31 @@ __global__ __launch_bounds__(256) void lod_compact(int64_t n_words, uint32_t* __
       const uint32_t n = (uint32_t)__builtin_amdgcn_readlane((int)oe, 63) - o0;
       uint32_t o = off[q][k] - o0;
       const uint32_t wl = (uint32_t)(k * 256 + threadIdx.x) * 32u;   // the word's first local id
-      while (m) {
-        const int b = __ffs(m) - 1;
-        m &= m - 1;
-        slice[o++] = (uint16_t)(wl + (uint32_t)b);
+      if (m == 0xFFFFFFFFu) {
+        // a full word (dense parts of the cut): its 32 consecutive ids at once
+#pragma unroll
+        for (int b = 0; b < 32; ++b) slice[o + b] = (uint16_t)(wl + (uint32_t)b);
+      } else {
+        while (m) {
+          const int b = __ffs(m) - 1;
+          m &= m - 1;
+          slice[o++] = (uint16_t)(wl + (uint32_t)b);
+        }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      for (uint32_t i = ln; i < n; i += 64) out[r0 + o0 + i] = id0 + (int32_t)slice[i];
+      // the staged range to memory, four LDS reads per lane in flight
+      int32_t* dst = out + r0 + o0;
+      uint32_t i = ln;
+      for (; i + 192u < n; i += 256u) {
+        const int32_t a0 = slice[i], a1 = slice[i + 64u], a2 = slice[i + 128u], a3 = slice[i + 192u];
+        dst[i] = id0 + a0;
+        dst[i + 64u] = id0 + a1;
+        dst[i + 128u] = id0 + a2;
+        dst[i + 192u] = id0 + a3;
+      }
+      for (; i < n; i += 64u) dst[i] = id0 + (int32_t)slice[i];
       r0 += rt[q][k];
       if (wd[q][k]) (q == 0 ? fbits : cbits)[w] = 0u;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
