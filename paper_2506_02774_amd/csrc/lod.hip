@@ -414,7 +414,11 @@ __global__ __launch_bounds__(256) void lod_bfs(const int32_t* __restrict__ in_q,
 // coalesced stores.
 // The 8 per-thread counts (2 bitmaps x 4 rounds, each <= 32) are scanned in
 // one pass as 16-bit fields of 4 words (a partition's totals stay below 2^16).
-constexpr int kWordsPerThread = 4, kWordsPerPart = 256 * kWordsPerThread;
+// 3 words per thread: 1465 partitions of 24576 nodes for a 36M-node tree,
+// all resident at once, with the densest partition's ids spread over
+// fewer words than with 4 (1099 partitions) or 2 (2198, a second round)
+constexpr int kWordsPerThread = 3, kWordsPerPart = 256 * kWordsPerThread;
+static_assert(kWordsPerThread <= 4, "lod_compact packs two words' counts per 16-bit pair of a uint4 field");
 static_assert(kWordsPerPart * 32 <= 65536, "lod_compact stages a partition's ids as 16-bit offsets");
 
 VY_DEV uint4 block_excl_scan256_x4(uint4 v, uint4* sh, uint4* total) {
@@ -534,10 +538,12 @@ __global__ __launch_bounds__(256) void lod_compact(int64_t n_words, uint32_t* __
     }
   }
   // fields: .x = F rounds 0 | 1 << 16, .y = F rounds 2 | 3, .z/.w the same for C
-  const uint4 cnt4 = make_uint4((uint32_t)__popc(wd[0][0]) | ((uint32_t)__popc(wd[0][1]) << 16),
-                                (uint32_t)__popc(wd[0][2]) | ((uint32_t)__popc(wd[0][3]) << 16),
-                                (uint32_t)__popc(wd[1][0]) | ((uint32_t)__popc(wd[1][1]) << 16),
-                                (uint32_t)__popc(wd[1][2]) | ((uint32_t)__popc(wd[1][3]) << 16));
+  uint32_t f4[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int k = 0; k < kWordsPerThread; ++k) f4[2 * q + (k >> 1)] |= (uint32_t)__popc(wd[q][k]) << (16 * (k & 1));
+  const uint4 cnt4 = make_uint4(f4[0], f4[1], f4[2], f4[3]);
   uint4 tot4;
   const uint4 off4 = block_excl_scan256_x4(cnt4, s_scan4, &tot4);
   uint32_t off[2][kWordsPerThread], rt[2][kWordsPerThread], tot[2];
@@ -550,7 +556,9 @@ __global__ __launch_bounds__(256) void lod_compact(int64_t n_words, uint32_t* __
         off[q][k] = (o[2 * q + (k >> 1)] >> (16 * (k & 1))) & 0xFFFFu;
         rt[q][k] = (t[2 * q + (k >> 1)] >> (16 * (k & 1))) & 0xFFFFu;
       }
-      tot[q] = rt[q][0] + rt[q][1] + rt[q][2] + rt[q][3];
+      tot[q] = 0u;
+#pragma unroll
+      for (int k = 0; k < kWordsPerThread; ++k) tot[q] += rt[q][k];
     }
   }
   __syncthreads();
