@@ -405,15 +405,15 @@ __global__ __launch_bounds__(256) void lod_bfs(const int32_t* __restrict__ in_q,
 }
 
 // Compaction of the F and C bitmaps into ascending ids over partitions of
-// 1024 words, zeroing the bitmaps as they are read: a first launch counts
+// 768 words, zeroing the bitmaps as they are read: a first launch counts
 // every partition's bits, and each partition of the second sums the counts
 // of the partitions before it (at most a few thousand words, read from L2)
 // instead of waiting on a look-back chain across the partitions.
-// A partition is read as 4 rounds of 256 consecutive words (one per thread);
-// each wave gathers its words' ids of a round in LDS and writes them out with
-// coalesced stores.
-// The 8 per-thread counts (2 bitmaps x 4 rounds, each <= 32) are scanned in
-// one pass as 16-bit fields of 4 words (a partition's totals stay below 2^16).
+// A partition is read as 3 rounds of 256 consecutive words (one per thread);
+// each wave gathers its words' ids of a round in LDS, as 16-bit offsets into
+// the partition, and writes them out with coalesced stores.
+// The 6 per-thread counts (2 bitmaps x 3 rounds, each <= 32) are scanned in
+// one pass as 16-bit fields of 4 words (a round's totals stay below 2^16).
 // 3 words per thread: 1465 partitions of 24576 nodes for a 36M-node tree,
 // all resident at once, with the densest partition's ids spread over
 // fewer words than with 4 (1099 partitions) or 2 (2198, a second round)
@@ -537,7 +537,7 @@ __global__ __launch_bounds__(256) void lod_compact(int64_t n_words, uint32_t* __
       atomicAdd(&s_ex[1], pb);
     }
   }
-  // fields: .x = F rounds 0 | 1 << 16, .y = F rounds 2 | 3, .z/.w the same for C
+  // fields: .x = F rounds 0 | 1 << 16, .y = F round 2 (| 3 << 16 with 4 rounds), .z/.w the same for C
   uint32_t f4[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
   for (int q = 0; q < 2; ++q)
