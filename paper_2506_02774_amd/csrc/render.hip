@@ -668,11 +668,33 @@ __global__ __launch_bounds__(256) void emit_big(const uint32_t* __restrict__ big
 __global__ __launch_bounds__(256) void tile_ranges(const uint32_t* __restrict__ key, const uint32_t* ctr,
                                                    uint2* __restrict__ ranges, uint32_t ntiles) {
   const uint32_t n = ctr[C_NPAIRS];
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const uint32_t t = key[i] & 0xFFFFu;   // the tile id (the pixel box above it)
-    if (t >= ntiles) continue;
-    if (i == 0 || (key[i - 1] & 0xFFFFu) != t) ranges[t].x = i;
-    if (i + 1 == n || (key[i + 1] & 0xFFFFu) != t) ranges[t].y = i + 1;
+  const uint32_t nq = (n + 3u) / 4u;
+  // four consecutive keys per thread with one 16-byte load, and the keys on
+  // either side of them: one memory latency per thread
+  for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
+    const uint32_t i0 = 4u * q;
+    uint32_t k[6];
+    if (i0 + 4u <= n) {
+      const uint4 v = reinterpret_cast<const uint4*>(key)[q];
+      k[1] = v.x;
+      k[2] = v.y;
+      k[3] = v.z;
+      k[4] = v.w;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) k[1 + j] = i0 + j < n ? key[i0 + j] : 0u;
+    }
+    k[0] = i0 > 0 ? key[i0 - 1u] : 0u;
+    k[5] = i0 + 4u < n ? key[i0 + 4u] : 0u;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t i = i0 + j;
+      if (i >= n) break;
+      const uint32_t t = k[1 + j] & 0xFFFFu;   // the tile id (the pixel box above it)
+      if (t >= ntiles) continue;
+      if (i == 0 || (k[j] & 0xFFFFu) != t) ranges[t].x = i;
+      if (i + 1 == n || (k[2 + j] & 0xFFFFu) != t) ranges[t].y = i + 1;
+    }
   }
 }
 
@@ -2959,7 +2981,7 @@ int vy_render_batch(const vy_view* views, int32_t n, const vy_render_opts* opts,
   }
   {
     ProfScope ps(VY_STAGE_RANGES, st);
-    const int blocks = imin(cdiv(c->max_pairs, 256), 4096);
+    const int blocks = imin(cdiv(c->max_pairs, 1024), 4096);
     tile_ranges<<<blocks, 256, 0, st>>>(c->tkey[0], c->ctr, c->ranges, (uint32_t)ntiles);
     VY_LAUNCHED();
   }
@@ -3107,7 +3129,7 @@ static int render_impl(const vy_scene* scene, const vy_cut* cut, const vy_camera
   }
   {
     ProfScope ps(VY_STAGE_RANGES, st);
-    const int blocks = imin(cdiv(c->max_pairs, 256), 4096);
+    const int blocks = imin(cdiv(c->max_pairs, 1024), 4096);
     tile_ranges<<<blocks, 256, 0, st>>>(c->tkey[0], c->ctr, c->ranges, (uint32_t)ntiles);
     VY_LAUNCHED();
   }
