@@ -832,14 +832,23 @@ __global__ __launch_bounds__(256) void plan_tiles(const uint2* __restrict__ rang
         f = h + 2;
       }
     }
-    if (f == 0) {
-      for (int k = 0; k < 3; ++k)
-        if (len > kTierMin[k]) {
-          tiers[(size_t)k * ntiles + fetch_add(ctr + C_NTIER + k, 1u)] = (uint32_t)t;
-          f = 1;
-          break;
-        }
+    // the tier (the first threshold the tile's list exceeds), appended with
+    // one atomic per wave and tier (the order within a tier does not matter)
+    int tier = -1;
+    if (f == 0)
+      for (int k = 2; k >= 0; --k)
+        if (len > kTierMin[k]) tier = k;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const uint64_t bal = __ballot(tier == k);
+      if (bal == 0ull) continue;
+      const int leader = __builtin_ctzll(bal);
+      uint32_t slot0 = 0;
+      if ((int)lane() == leader) slot0 = fetch_add(ctr + C_NTIER + k, (uint32_t)__popcll(bal));
+      slot0 = (uint32_t)__shfl((int)slot0, leader, 64);
+      if (tier == k) tiers[(size_t)k * ntiles + slot0 + (uint32_t)__popcll(bal & lanemask_lt())] = (uint32_t)t;
     }
+    if (tier >= 0) f = 1;
     tile_flag[t] = f;
   }
 }
