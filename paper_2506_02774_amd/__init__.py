@@ -204,6 +204,23 @@ def make_camera(cam) -> vy_camera:
     return c
 
 
+def make_cameras(cams):
+    """A ctypes array of vy_camera for a sequence of cameras, the fields of each
+    as make_camera() sets them (float32 rounding, int32 sizes, znear default
+    0.2), filled through one numpy buffer (the struct is 19 packed 4-byte
+    fields) rather than field by field."""
+    n = len(cams)
+    buf = np.empty((max(1, n), 19), np.float32)
+    if n:
+        buf[:n, 0:9] = np.asarray([np.asarray(c.R, np.float32).reshape(9) for c in cams], np.float32)
+        buf[:n, 9:12] = np.asarray([np.asarray(c.pos, np.float32).reshape(3) for c in cams], np.float32)
+        buf[:n, 12:16] = np.asarray([(c.fx, c.fy, c.cx, c.cy) for c in cams], np.float64).astype(np.float32)
+        buf[:n, 18] = np.asarray([getattr(c, "near", 0.2) for c in cams], np.float64).astype(np.float32)
+        buf[:n].view(np.int32)[:, 16:18] = np.asarray([(int(c.width), int(c.height)) for c in cams], np.int32)
+    assert ctypes.sizeof(vy_camera) == 19 * 4
+    return (vy_camera * max(1, n)).from_buffer_copy(buf)
+
+
 def _dev(a, dtype, device):
     import torch
     return torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dtype)
@@ -654,13 +671,13 @@ def vy_walkthrough(scene: Scene, cams, tau: float, cuts, ctxs, images, streams=N
     for im in images:
         if im.dtype != torch.float32 or not im.is_contiguous() or im.dim() != 3 or im.shape[0] != 3:
             raise VoyagerError(VY_ERR_ARG, "images must be contiguous float32 tensors of shape (3, H, W)")
+    shapes = [(int(im.shape[1]), int(im.shape[2])) for im in images]
     for i, cam in enumerate(cams):
-        im = images[i % len(images)]
-        if (im.shape[1], im.shape[2]) != (cam.height, cam.width):
+        if shapes[i % len(images)] != (cam.height, cam.width):
             raise VoyagerError(VY_ERR_ARG, f"frame {i}: image shape differs from the camera's size")
     if stats is not None and stats.numel() * stats.element_size() < 32 * n:
         raise VoyagerError(VY_ERR_ARG, "stats needs 32 bytes per frame")
-    cam_arr = (vy_camera * max(1, n))(*[make_camera(c) for c in cams])
+    cam_arr = make_cameras(cams)
     o = _render_opts(alpha_filter, bg, False, 0, walk, lut_entries, band_jobs)
     P = ctypes.c_void_p
     cut_arr = (P * depth)(*[c.handle for c in cuts])

@@ -127,3 +127,24 @@ def test_noalloc_rejects_before_touching_the_gpu():
     o.save_state = 1
     assert L.vy_render_noalloc(None, None, ctypes.byref(c), ctypes.byref(o), img, None, None) == vy.VY_ERR_ARG
     assert L.vy_render_noalloc(None, None, None, None, img, None, None) == vy.VY_ERR_ARG
+
+
+def test_camera_array_matches_single_cameras():
+    """make_cameras (one numpy buffer for a whole camera path) gives the same
+    vy_camera bytes as make_camera per camera: float32 rounding of the
+    intrinsics, int32 sizes, the default near plane, any camera-like object."""
+    import numpy as np
+    import scenegen
+    import paper_2506_02774_amd as vy
+
+    class Cam:
+        pass
+
+    c = Cam()
+    c.R, c.pos = np.eye(3) * 0.5, [1.0, -2.0, 3.25]
+    c.fx, c.fy, c.cx, c.cy, c.width, c.height = 100.123456789, 99.5, 32.25, 16, 64, 48
+    cams = list(scenegen.walkthrough(scenegen.CONFIGS["tiny"])) + [
+        scenegen.identity_camera(64, 48), scenegen.look_camera([0.0, 0.0, 50.0], 0.3, -0.2, 100, 37), c]
+    one = (vy.vy_camera * len(cams))(*[vy.make_camera(x) for x in cams])
+    assert bytes(vy.make_cameras(cams)) == bytes(one)
+    assert len(bytes(vy.make_cameras([]))) == ctypes.sizeof(vy.vy_camera)
